@@ -1,0 +1,164 @@
+"""Benchmark: one Baum-Welch E-step over the batched ragged workload.
+
+Workload: 1024 sequences with lengths uniform in {500..5000}, N = 8 Gamma
+states (shape U[1,10], scale U[0.5,3]), sticky A (a_ii = 0.95), FP32
+observations resident in device memory.  One step = one full E-step
+(parameter staging, emission log-densities, forward and backward
+recursions, posteriors and the pooled sufficient statistics).
+
+Prints one JSON line with the throughput in state transitions per second
+(sum_b T_b * N^2 per E-step), the plain one-thread-per-sequence GPU method
+on the same data, the dominant kernel's roofline figures and the FP64 CPU
+oracle timed on the host.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP32_VALU_TFLOPS = 157.3   # MI355X FP32 vector, spec sheet
+METRIC = "E-step state-transitions/s (B*T*N^2) vs plain GPU; p50/p99 decode latency"
+
+
+def kernel_table(records, steps):
+    agg = {}
+    for name, ms in records:
+        a = agg.setdefault(name, [0.0, 0])
+        a[0] += ms
+        a[1] += 1
+    return {k: {"ms_total": v[0], "launches": v[1], "ms_avg": v[0] / v[1],
+                "ms_per_step": v[0] / steps} for k, v in agg.items()}
+
+
+def algorithmic_flops(name, w):
+    """FLOPs of the method's arithmetic for one launch of kernel `name`."""
+    n = w.model.n_states
+    steps = w.total_steps
+    if name == "chunk_stats":
+        # forward alpha*A, backward A*w and the xi outer product: 3 FMA per transition
+        return 6.0 * steps * n * n
+    if name == "chunk_product":
+        # chunk transfer matrices: N^3 FMA per step after each sequence's first
+        return 2.0 * (steps - w.n_seq) * n ** 3
+    return None
+
+
+def cpu_baseline(w, reps=2):
+    import oracle
+    oracle._load()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        oracle.estep(w.model, w.offsets, w.obs)
+    dt = time.perf_counter() - t0
+    return {"value": reps * w.transitions / dt, "unit": "transitions/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"full workload ({w.n_seq} sequences, {w.total_steps} steps) x{reps}, "
+                      f"FP64 oracle, 1 thread, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--prec", default="f32", choices=["f32", "f64"])
+    ap.add_argument("--plain-steps", type=int, default=2)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; multi-GPU sharding of the "
+                                   "sequence batch is described but not built"}))
+        sys.exit(2)
+
+    import torch
+    import paper_2605_29208_amd as h
+    import workloads
+
+    w = workloads.config2()
+    dm = h.DeviceModel.from_model(w.model)
+    db = h.DeviceBatch(w.obs, w.offsets, dtype=np.float32 if args.prec == "f32" else np.float64)
+    prec = args.prec
+    ws = h._ws(h.hmm_workspace_size("estep", dm, db, prec))
+    S = h.hmm_stats_len(dm)
+    stats = torch.empty(S, dtype=torch.float64, device="cuda")
+    loglik = torch.empty(w.n_seq, dtype=torch.float64, device="cuda")
+    status = torch.empty(w.n_seq, dtype=torch.int32, device="cuda")
+
+    def step(p=prec, wsp=ws):
+        h.hmm_estep_stats(dm, db, p, stats, loglik, status, wsp)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    h.hmm_profile_enable(True)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record()
+    for _ in range(args.steps):
+        step()
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / args.steps
+    recs = h.hmm_profile_records()
+    h.hmm_profile_enable(False)
+    kt = kernel_table(recs, args.steps)
+    assert (status.cpu().numpy() == 0).all()
+
+    # plain GPU method (one thread per sequence, literal log-sum-exp) on the same data
+    pprec = "plain_" + prec
+    pws = h._ws(h.hmm_workspace_size("estep", dm, db, pprec))
+    step(pprec, pws)
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for _ in range(args.plain_steps):
+        step(pprec, pws)
+    t1.record()
+    torch.cuda.synchronize()
+    plain_ms = t0.elapsed_time(t1) / args.plain_steps
+    del pws
+
+    value = w.transitions / (ms / 1e3)
+    dom = max(kt, key=lambda k: kt[k]["ms_total"])
+    fl = algorithmic_flops(dom, w)
+    roof = None
+    if fl is not None:
+        ach = fl / (kt[dom]["ms_avg"] / 1e3) / 1e12
+        roof = {"bound": "alu", "kernel": dom, "achieved": ach, "peak": PEAK_FP32_VALU_TFLOPS,
+                "unit": "TFLOP/s", "frac": ach / PEAK_FP32_VALU_TFLOPS, "traffic": None,
+                "kernel_ms_avg": kt[dom]["ms_avg"]}
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "transitions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if prec == "f32" else "f64",
+        "data": "synthetic",
+        "config": {"workload": "batched ragged E-step: B=1024, T~U{500..5000}, N=8 Gamma, "
+                               "FP32 obs", "global_batch": w.n_seq, "total_steps": w.total_steps,
+                   "transitions_per_step": w.transitions, "precision": prec},
+        "plain_gpu": {"value": w.transitions / (plain_ms / 1e3), "ms_per_step": plain_ms,
+                      "speedup": plain_ms / ms},
+        "roofline": roof,
+        "kernels": kt,
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(w)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,303 @@
+"""Python binding of libhmmgpu (MI355X / gfx950 HMM inference).
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels of libhmmgpu.so.  PyTorch supplies device memory and the stream.
+The raw functions carry the C names (hmm_estep_stats, ...); the small
+helpers below them allocate outputs and workspace and call the raw ones.
+
+Importing this module requires the built library; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhmmgpu.so")
+
+# enums of include/hmm_gpu.h
+HMM_OK, HMM_ERR_ARG, HMM_ERR_UNSUPPORTED, HMM_ERR_WORKSPACE, HMM_ERR_DEVICE, \
+    HMM_ERR_PARAMS_UNSET, HMM_ERR_NUMERIC = range(7)
+FAMILY = {"gaussian": 0, "gamma": 1, "student_t": 2, "poisson": 3, "diag": 4, "full": 5,
+          "table": 6}
+PREC = {"f64": 0, "f32": 1, "bf16_scaled": 2, "f16_scaled": 3, "plain_f32": 4, "plain_f64": 5}
+OP = {"emission": 0, "forward_backward": 1, "estep": 2, "viterbi": 3, "posterior_decode": 4}
+
+EXPORTED = [
+    "hmm_version", "hmm_last_error", "hmm_stats_len", "hmm_workspace_size",
+    "hmm_emission_logpdf", "hmm_forward_backward", "hmm_estep_stats", "hmm_viterbi",
+    "hmm_posterior_decode", "hmm_mstep_default_opts", "hmm_mstep_transitions",
+    "hmm_mstep_gaussian", "hmm_mstep_gamma", "hmm_mstep_student_t", "hmm_mstep_poisson",
+    "hmm_mstep_diag_gaussian", "hmm_mstep_full_gaussian", "hmm_set_chunk_len",
+    "hmm_profile_enable", "hmm_profile_count", "hmm_profile_get", "hmm_profile_reset",
+]
+
+
+class HmmError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"hmm status {status}: {msg}")
+        self.status = status
+
+
+class HmmModelC(ctypes.Structure):
+    _fields_ = [("n_states", ctypes.c_int32), ("dim", ctypes.c_int32),
+                ("family", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("log_pi", ctypes.c_void_p), ("log_A", ctypes.c_void_p),
+                ("theta", ctypes.c_void_p)]
+
+
+class HmmBatchC(ctypes.Structure):
+    _fields_ = [("n_seq", ctypes.c_int64), ("offsets", ctypes.c_void_p),
+                ("h_offsets", ctypes.c_void_p), ("obs", ctypes.c_void_p),
+                ("obs_f64", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class HmmMstepOptsC(ctypes.Structure):
+    _fields_ = [("eps_collapse", ctypes.c_double), ("ridge", ctypes.c_double),
+                ("gamma_rtol", ctypes.c_double), ("nu_tol", ctypes.c_double),
+                ("nu_min", ctypes.c_double), ("nu_max", ctypes.c_double),
+                ("max_iter", ctypes.c_int32), ("t_nu_printed", ctypes.c_int32)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2605_29208_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, i32, i64, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
+    MP, BP = ctypes.POINTER(HmmModelC), ctypes.POINTER(HmmBatchC)
+    OPP = ctypes.POINTER(HmmMstepOptsC)
+    sig = {
+        "hmm_version": ([], ctypes.c_char_p),
+        "hmm_last_error": ([], ctypes.c_char_p),
+        "hmm_stats_len": ([MP], sz),
+        "hmm_workspace_size": ([ctypes.c_int, MP, BP, ctypes.c_int, ctypes.POINTER(sz)], ctypes.c_int),
+        "hmm_emission_logpdf": ([MP, BP, ctypes.c_int, P, P, sz, P], ctypes.c_int),
+        "hmm_forward_backward": ([MP, BP, ctypes.c_int, P, P, P, P, sz, P], ctypes.c_int),
+        "hmm_estep_stats": ([MP, BP, ctypes.c_int, P, P, P, P, sz, P], ctypes.c_int),
+        "hmm_viterbi": ([MP, BP, ctypes.c_int, P, P, P, sz, P], ctypes.c_int),
+        "hmm_posterior_decode": ([MP, BP, ctypes.c_int, P, P, P, sz, P], ctypes.c_int),
+        "hmm_mstep_default_opts": ([OPP], None),
+        "hmm_mstep_transitions": ([MP, P, OPP, P, P, P], ctypes.c_int),
+        "hmm_set_chunk_len": ([i32], ctypes.c_int),
+        "hmm_profile_enable": ([i32], ctypes.c_int),
+        "hmm_profile_count": ([], i32),
+        "hmm_profile_get": ([i32, ctypes.POINTER(ctypes.c_char_p), ctypes.POINTER(ctypes.c_float)],
+                            ctypes.c_int),
+        "hmm_profile_reset": ([], ctypes.c_int),
+    }
+    for fam in ("gaussian", "gamma", "student_t", "poisson", "diag_gaussian", "full_gaussian"):
+        sig[f"hmm_mstep_{fam}"] = ([MP, P, OPP, P, P, P, P], ctypes.c_int)
+    for name, (args, res) in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = res
+    return lib
+
+
+_lib = _load()
+
+
+def version() -> str:
+    return _lib.hmm_version().decode()
+
+
+def last_error() -> str:
+    return _lib.hmm_last_error().decode()
+
+
+def _check(st):
+    if st != HMM_OK:
+        raise HmmError(st, last_error())
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+# --------------------------------------------------------------------------
+# device-resident model and batch
+# --------------------------------------------------------------------------
+
+class DeviceModel:
+    """lambda = (log pi, log A, theta) as FP64 device tensors."""
+
+    def __init__(self, family, n_states, dim, log_pi, log_A, theta, device="cuda"):
+        import torch
+        self.family, self.n_states, self.dim = family, int(n_states), int(dim)
+        f64 = dict(dtype=torch.float64, device=device)
+        self.log_pi = torch.as_tensor(np.asarray(log_pi, dtype=np.float64)).to(**f64).contiguous()
+        self.log_A = torch.as_tensor(np.asarray(log_A, dtype=np.float64)).to(**f64).contiguous()
+        self.theta = None if theta is None else \
+            torch.as_tensor(np.asarray(theta, dtype=np.float64)).to(**f64).contiguous()
+        self.c = HmmModelC(self.n_states, self.dim, FAMILY[family], 0,
+                           self.log_pi.data_ptr(), self.log_A.data_ptr(),
+                           None if self.theta is None else self.theta.data_ptr())
+
+    @classmethod
+    def from_model(cls, m, device="cuda"):
+        return cls(m.family, m.n_states, m.dim, m.log_pi, m.log_A, m.theta, device)
+
+    def refresh(self):
+        self.c.log_pi = self.log_pi.data_ptr()
+        self.c.log_A = self.log_A.data_ptr()
+        self.c.theta = None if self.theta is None else self.theta.data_ptr()
+
+
+class DeviceBatch:
+    """A ragged batch: observations [sum T, D] (float32 or float64) and offsets."""
+
+    def __init__(self, obs, offsets, device="cuda", dtype=np.float32):
+        import torch
+        offsets = np.ascontiguousarray(offsets, dtype=np.int64)
+        self.h_offsets = offsets
+        self.offsets = torch.as_tensor(offsets).to(device)
+        obs = np.ascontiguousarray(obs, dtype=dtype)
+        self.obs = torch.as_tensor(obs).to(device).contiguous()
+        self.n_seq = len(offsets) - 1
+        self.total = int(offsets[-1])
+        self.c = HmmBatchC(self.n_seq, self.offsets.data_ptr(),
+                           self.h_offsets.ctypes.data_as(ctypes.c_void_p).value,
+                           self.obs.data_ptr(), 1 if dtype == np.float64 else 0, 0)
+
+    @classmethod
+    def from_workload(cls, w, dtype=np.float32, device="cuda"):
+        return cls(w.obs, w.offsets, device, dtype)
+
+
+# --------------------------------------------------------------------------
+# raw C calls (same names as the C ABI)
+# --------------------------------------------------------------------------
+
+def hmm_stats_len(model: DeviceModel) -> int:
+    return int(_lib.hmm_stats_len(ctypes.byref(model.c)))
+
+
+def hmm_workspace_size(op, model: DeviceModel, batch: DeviceBatch, prec) -> int:
+    out = ctypes.c_size_t()
+    _check(_lib.hmm_workspace_size(OP[op], ctypes.byref(model.c), ctypes.byref(batch.c),
+                                   PREC[prec], ctypes.byref(out)))
+    return out.value
+
+
+def hmm_emission_logpdf(model, batch, prec, log_b, ws, stream=None):
+    _check(_lib.hmm_emission_logpdf(ctypes.byref(model.c), ctypes.byref(batch.c), PREC[prec],
+                                    _ptr(log_b), _ptr(ws), _nbytes(ws), _stream(stream)))
+
+
+def hmm_forward_backward(model, batch, prec, loglik, gamma, seq_status, ws, stream=None):
+    _check(_lib.hmm_forward_backward(ctypes.byref(model.c), ctypes.byref(batch.c), PREC[prec],
+                                     _ptr(loglik), _ptr(gamma), _ptr(seq_status), _ptr(ws),
+                                     _nbytes(ws), _stream(stream)))
+
+
+def hmm_estep_stats(model, batch, prec, stats, loglik, seq_status, ws, stream=None):
+    _check(_lib.hmm_estep_stats(ctypes.byref(model.c), ctypes.byref(batch.c), PREC[prec],
+                                _ptr(stats), _ptr(loglik), _ptr(seq_status), _ptr(ws),
+                                _nbytes(ws), _stream(stream)))
+
+
+def hmm_viterbi(model, batch, prec, path, path_logp, ws, stream=None):
+    _check(_lib.hmm_viterbi(ctypes.byref(model.c), ctypes.byref(batch.c), PREC[prec],
+                            _ptr(path), _ptr(path_logp), _ptr(ws), _nbytes(ws), _stream(stream)))
+
+
+def hmm_posterior_decode(model, batch, prec, path, loglik, ws, stream=None):
+    _check(_lib.hmm_posterior_decode(ctypes.byref(model.c), ctypes.byref(batch.c), PREC[prec],
+                                     _ptr(path), _ptr(loglik), _ptr(ws), _nbytes(ws),
+                                     _stream(stream)))
+
+
+def hmm_set_chunk_len(steps: int):
+    _check(_lib.hmm_set_chunk_len(int(steps)))
+
+
+def hmm_profile_enable(on: bool):
+    _check(_lib.hmm_profile_enable(1 if on else 0))
+
+
+def hmm_profile_reset():
+    _check(_lib.hmm_profile_reset())
+
+
+def hmm_profile_records():
+    """[(kernel name, milliseconds)] of the kernels recorded since the last reset."""
+    out = []
+    for i in range(_lib.hmm_profile_count()):
+        name = ctypes.c_char_p()
+        ms = ctypes.c_float()
+        _check(_lib.hmm_profile_get(i, ctypes.byref(name), ctypes.byref(ms)))
+        out.append((name.value.decode(), ms.value))
+    return out
+
+
+def _nbytes(t):
+    return 0 if t is None else t.numel() * t.element_size()
+
+
+def _ws(nbytes):
+    import torch
+    # torch's caching allocator returns 256-byte aligned blocks
+    return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device="cuda")
+
+
+# --------------------------------------------------------------------------
+# helpers that allocate outputs
+# --------------------------------------------------------------------------
+
+def _rdtype(prec):
+    import torch
+    return torch.float64 if prec in ("f64", "plain_f64") else torch.float32
+
+
+def estep_stats(model: DeviceModel, batch: DeviceBatch, prec="f32", ws=None, stream=None):
+    import torch
+    S = hmm_stats_len(model)
+    stats = torch.empty(S, dtype=torch.float64, device="cuda")
+    loglik = torch.empty(max(batch.n_seq, 1), dtype=torch.float64, device="cuda")
+    status = torch.empty(max(batch.n_seq, 1), dtype=torch.int32, device="cuda")
+    if ws is None:
+        ws = _ws(hmm_workspace_size("estep", model, batch, prec))
+    hmm_estep_stats(model, batch, prec, stats, loglik, status, ws, stream)
+    return stats, loglik[:batch.n_seq], status[:batch.n_seq]
+
+
+def forward_backward(model, batch, prec="f32", want_gamma=True, ws=None, stream=None):
+    import torch
+    loglik = torch.empty(max(batch.n_seq, 1), dtype=torch.float64, device="cuda")
+    status = torch.empty(max(batch.n_seq, 1), dtype=torch.int32, device="cuda")
+    gamma = torch.empty((max(batch.total, 1), model.n_states), dtype=_rdtype(prec),
+                        device="cuda") if want_gamma else None
+    if ws is None:
+        ws = _ws(hmm_workspace_size("forward_backward", model, batch, prec))
+    hmm_forward_backward(model, batch, prec, loglik, gamma, status, ws, stream)
+    g = gamma[:batch.total] if gamma is not None else None
+    return loglik[:batch.n_seq], g, status[:batch.n_seq]
+
+
+def emission_logpdf(model, batch, prec="f32", ws=None, stream=None):
+    import torch
+    out = torch.empty((max(batch.total, 1), model.n_states), dtype=_rdtype(prec), device="cuda")
+    if ws is None:
+        ws = _ws(hmm_workspace_size("emission", model, batch, prec))
+    hmm_emission_logpdf(model, batch, prec, out, ws, stream)
+    return out[:batch.total]
+
+
+def posterior_decode(model, batch, prec="f32", ws=None, stream=None):
+    import torch
+    path = torch.empty(max(batch.total, 1), dtype=torch.int32, device="cuda")
+    loglik = torch.empty(max(batch.n_seq, 1), dtype=torch.float64, device="cuda")
+    if ws is None:
+        ws = _ws(hmm_workspace_size("posterior_decode", model, batch, prec))
+    hmm_posterior_decode(model, batch, prec, path, loglik, ws, stream)
+    return path[:batch.total], loglik[:batch.n_seq]

@@ -1,0 +1,463 @@
+// abi.cpp -- extern "C" entry points: argument validation on the host,
+// workspace planning, parameter staging and dispatch to the kernels.
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "hmm_internal.hpp"
+
+using namespace hmmk;
+
+namespace {
+
+thread_local std::string g_err;
+std::atomic<int> g_chunk_len{0};
+
+hmm_status fail(hmm_status st, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+hmm_status ok() {
+    g_err.clear();
+    return HMM_OK;
+}
+
+inline size_t a256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+int family_k(int family, int D) {
+    switch (family) {
+    case HMM_GAUSSIAN: return 2;
+    case HMM_GAMMA: return 3;
+    case HMM_STUDENT_T: return 4;
+    case HMM_POISSON: return 1;
+    case HMM_DIAG_GAUSSIAN: return 2 * D;
+    case HMM_FULL_GAUSSIAN: return D + D * (D + 1) / 2;
+    case HMM_TABLE: return 0;
+    default: return -1;
+    }
+}
+
+bool is_f64(hmm_precision p) { return p == HMM_PREC_F64 || p == HMM_PREC_PLAIN_F64; }
+bool is_plain(hmm_precision p) { return p == HMM_PREC_PLAIN_F32 || p == HMM_PREC_PLAIN_F64; }
+
+struct Checked {
+    int N, D, fam;
+    int64_t B, total, Tmax;
+    const int64_t *h_off;
+};
+
+hmm_status check_model(const hmm_model *m) {
+    if (!m) return fail(HMM_ERR_ARG, "model is NULL");
+    if (m->n_states < 1 || m->n_states > 1024)
+        return fail(HMM_ERR_ARG, "n_states %d outside [1, 1024]", m->n_states);
+    if (m->family < HMM_GAUSSIAN || m->family > HMM_TABLE)
+        return fail(HMM_ERR_ARG, "unknown family %d", m->family);
+    if (m->reserved != 0) return fail(HMM_ERR_ARG, "model.reserved must be 0");
+    const bool scalar = m->family <= HMM_POISSON;
+    if (scalar && m->dim != 1) return fail(HMM_ERR_ARG, "scalar family needs dim == 1 (got %d)", m->dim);
+    if (m->family == HMM_TABLE && m->dim != m->n_states)
+        return fail(HMM_ERR_ARG, "table family needs dim == n_states");
+    if ((m->family == HMM_DIAG_GAUSSIAN || m->family == HMM_FULL_GAUSSIAN) &&
+        (m->dim < 1 || m->dim > 64))
+        return fail(HMM_ERR_ARG, "multivariate dim %d outside [1, 64]", m->dim);
+    if (!m->log_pi || !m->log_A) return fail(HMM_ERR_ARG, "log_pi / log_A is NULL");
+    if (m->family != HMM_TABLE && !m->theta)
+        return fail(HMM_ERR_PARAMS_UNSET, "emission parameters (theta) are not set");
+    return HMM_OK;
+}
+
+hmm_status check_batch(const hmm_batch *b, const hmm_model *m, Checked *c) {
+    hmm_status st = check_model(m);
+    if (st != HMM_OK) return st;
+    if (!b) return fail(HMM_ERR_ARG, "batch is NULL");
+    if (b->n_seq < 0) return fail(HMM_ERR_ARG, "n_seq < 0");
+    if (b->reserved != 0) return fail(HMM_ERR_ARG, "batch.reserved must be 0");
+    if (b->obs_f64 != 0 && b->obs_f64 != 1) return fail(HMM_ERR_ARG, "obs_f64 must be 0 or 1");
+    c->N = m->n_states;
+    c->D = m->dim;
+    c->fam = m->family;
+    c->B = b->n_seq;
+    c->total = 0;
+    c->Tmax = 0;
+    c->h_off = b->h_offsets;
+    if (b->n_seq == 0) return HMM_OK;
+    if (!b->offsets || !b->h_offsets || !b->obs)
+        return fail(HMM_ERR_ARG, "offsets / h_offsets / obs is NULL");
+    if (b->h_offsets[0] != 0) return fail(HMM_ERR_ARG, "offsets[0] must be 0");
+    for (int64_t i = 0; i < b->n_seq; ++i) {
+        int64_t T = b->h_offsets[i + 1] - b->h_offsets[i];
+        if (T < 1) return fail(HMM_ERR_ARG, "sequence %lld has length %lld (must be >= 1)",
+                                (long long)i, (long long)T);
+        if (T > c->Tmax) c->Tmax = T;
+    }
+    c->total = b->h_offsets[b->n_seq];
+    if (c->Tmax > (int64_t)1 << 30) return fail(HMM_ERR_ARG, "sequence longer than 2^30 steps");
+    return HMM_OK;
+}
+
+// ---------------------------------------------------------------- planning
+struct Plan {
+    bool f64 = false, plain = false, chunked = false;
+    int G = 0, L = 0, C = 0, nblk = 0;
+    int64_t S = 0;
+    size_t staged = 0, cbase = 0, P = 0, rexp = 0, clog = 0, F = 0, Gb = 0, partial = 0;
+    size_t ll = 0, st = 0, gam = 0;
+    size_t logB = 0, alpha = 0, beta = 0, ps = 0;
+    size_t total = 0;
+};
+
+int default_chunk_len(bool f64) {
+    int v = g_chunk_len.load();
+    if (v == 0) return f64 ? 16 : 32;
+    if (f64 && v > 32) return 32;
+    return v;
+}
+
+hmm_status make_plan(hmm_op op, const Checked &c, hmm_precision prec, Plan *p) {
+    if (prec == HMM_PREC_BF16_SCALED || prec == HMM_PREC_F16_SCALED)
+        return fail(HMM_ERR_UNSUPPORTED, "scaled low-precision recursions are not built");
+    if (prec < HMM_PREC_F64 || prec > HMM_PREC_PLAIN_F64)
+        return fail(HMM_ERR_ARG, "unknown precision %d", (int)prec);
+    p->f64 = is_f64(prec);
+    p->plain = is_plain(prec);
+    const size_t r = p->f64 ? 8 : 4;
+    const int N = c.N;
+    p->S = 1 + 2 * (int64_t)N + (int64_t)N * N + (int64_t)N * family_k(c.fam, c.D);
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off += a256(bytes);
+        return o;
+    };
+    p->staged = take(staged_bytes(N, c.D, c.fam, p->f64));
+    if (op == HMM_OP_EMISSION) {
+        p->total = off;
+        return HMM_OK;
+    }
+    if (op == HMM_OP_VITERBI) return fail(HMM_ERR_UNSUPPORTED, "Viterbi is not built yet");
+    if (op != HMM_OP_FORWARD_BACKWARD && op != HMM_OP_ESTEP && op != HMM_OP_POSTERIOR_DECODE)
+        return fail(HMM_ERR_ARG, "unknown op %d", (int)op);
+    p->ll = take((size_t)c.B * 8);
+    p->st = take((size_t)c.B * 4);
+    if (op == HMM_OP_POSTERIOR_DECODE) p->gam = take((size_t)c.total * N * r);
+    if (p->plain) {
+        p->logB = take((size_t)c.total * N * r);
+        p->alpha = take((size_t)c.total * N * r);
+        p->beta = take((size_t)c.total * N * r);
+        p->ps = take(((size_t)c.B * p->S + (size_t)c.B) * 8);
+    } else {
+        const bool scalar = c.fam <= HMM_POISSON || c.fam == HMM_TABLE;
+        if (!(N <= 8 && scalar))
+            return fail(HMM_ERR_UNSUPPORTED,
+                        "batched path: this build covers N <= 8 with scalar or table emissions "
+                        "(N = %d, family %d); use a PLAIN precision",
+                        N, c.fam);
+        p->chunked = true;
+        p->G = N <= 4 ? 4 : 8;
+        p->L = default_chunk_len(p->f64);
+        int64_t C = 0;
+        for (int64_t b = 0; b < c.B; ++b) {
+            int64_t T = c.h_off[b + 1] - c.h_off[b];
+            C += (T + p->L - 1) / p->L;
+        }
+        if (C > INT32_MAX / 64) return fail(HMM_ERR_UNSUPPORTED, "too many chunks");
+        p->C = (int)C;
+        const int gpb = (BLOCK / 64) * (64 / p->G);
+        int64_t nb = (C + gpb - 1) / gpb;
+        p->nblk = (int)(nb < 1 ? 1 : (nb > 2048 ? 2048 : nb));
+        p->cbase = take((size_t)(c.B + 1) * 4);
+        p->P = take((size_t)C * p->G * p->G * r);
+        p->rexp = take((size_t)C * p->G * 4);
+        p->clog = take((size_t)C * 8);
+        p->F = take((size_t)C * p->G * r);
+        p->Gb = take((size_t)C * p->G * r);
+        p->partial = take((size_t)p->nblk * p->S * 8);
+    }
+    p->total = off;
+    return HMM_OK;
+}
+
+hmm_status check_ws(const Plan &p, void *ws, size_t ws_bytes) {
+    if (ws_bytes < p.total)
+        return fail(HMM_ERR_WORKSPACE, "workspace of %zu bytes is smaller than the %zu required",
+                    ws_bytes, p.total);
+    if (p.total > 0 && !ws) return fail(HMM_ERR_WORKSPACE, "workspace pointer is NULL");
+    if (((uintptr_t)ws & 255) != 0) return fail(HMM_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+    return HMM_OK;
+}
+
+hmm_status device_check(const char *what) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(HMM_ERR_DEVICE, "%s: %s", what, hipGetErrorString(e));
+    return ok();
+}
+
+RawModel raw(const hmm_model *m) {
+    return RawModel{m->n_states, m->dim, m->family, m->log_pi, m->log_A, m->theta};
+}
+
+template <typename R>
+hmm_status run_posterior_path(const hmm_model *m, const hmm_batch *b, const Checked &c,
+                              const Plan &p, char *ws, double *loglik, int32_t *status,
+                              void *gamma_out, double *stats, hipStream_t s) {
+    StagedModel<R> sm;
+    launch_stage<R>(raw(m), ws + p.staged, &sm, s);
+    double *ll = loglik ? loglik : (double *)(ws + p.ll);
+    int32_t *st = status ? status : (int32_t *)(ws + p.st);
+    ObsDesc od{b->obs, b->obs_f64, c.B, b->offsets};
+    if (c.B == 0) {
+        if (stats) launch_reduce_stats(nullptr, 0, p.S, ll, st, 0, stats, s);
+        return device_check("estep (empty batch)");
+    }
+    hmm_status r;
+    if (p.plain) {
+        PlainBuffers pb{ws + p.logB, ws + p.alpha, ws + p.beta, (double *)(ws + p.ps)};
+        r = run_plain<R>(sm, od, pb, ll, st, gamma_out, stats, p.S, s);
+    } else {
+        ChunkBuffers cb;
+        cb.L = p.L;
+        cb.C = p.C;
+        cb.G = p.G;
+        cb.nblk_stats = p.nblk;
+        cb.cbase = (int *)(ws + p.cbase);
+        cb.P = ws + p.P;
+        cb.rexp = (int *)(ws + p.rexp);
+        cb.clog = (double *)(ws + p.clog);
+        cb.F = ws + p.F;
+        cb.Gb = ws + p.Gb;
+        cb.partial = (double *)(ws + p.partial);
+        launch_plan_chunks(b->offsets, c.B, p.L, cb.cbase, s);
+        r = run_chunked<R>(sm, od, cb, ll, st, gamma_out, stats, p.S, s);
+    }
+    if (r != HMM_OK) return fail(r, "unsupported configuration");
+    return device_check("E-step kernels");
+}
+
+// ---------------------------------------------------------------- profiling
+struct ProfRec {
+    const char *name;
+    hipEvent_t a, b;
+};
+thread_local bool g_prof_on = false;
+thread_local std::vector<ProfRec> g_prof;
+thread_local std::vector<hipEvent_t> g_event_pool;
+thread_local size_t g_pool_used = 0;
+
+hipEvent_t pool_event() {
+    if (g_pool_used == g_event_pool.size()) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        g_event_pool.push_back(e);
+    }
+    return g_event_pool[g_pool_used++];
+}
+
+}  // namespace
+
+namespace hmmk {
+void prof_begin(const char *name, hipStream_t s) {
+    if (!g_prof_on) return;
+    ProfRec r{name, pool_event(), pool_event()};
+    if (r.a) hipEventRecord(r.a, s);
+    g_prof.push_back(r);
+}
+void prof_end(hipStream_t s) {
+    if (!g_prof_on || g_prof.empty()) return;
+    if (g_prof.back().b) hipEventRecord(g_prof.back().b, s);
+}
+}  // namespace hmmk
+
+namespace hmmk {
+void launch_argmax_rows(const void *gamma, bool f64, int64_t rows, int N, int32_t *path,
+                        hipStream_t s);
+}
+
+extern "C" {
+
+const char *hmm_version(void) { return "hmmgpu 0.1.0 (gfx950)"; }
+
+const char *hmm_last_error(void) { return g_err.c_str(); }
+
+size_t hmm_stats_len(const hmm_model *model) {
+    if (check_model(model) != HMM_OK) return 0;
+    int k = family_k(model->family, model->dim);
+    int64_t N = model->n_states;
+    return (size_t)(1 + 2 * N + N * N + N * k);
+}
+
+hmm_status hmm_workspace_size(hmm_op op, const hmm_model *model, const hmm_batch *batch,
+                              hmm_precision prec, size_t *bytes) {
+    if (!bytes) return fail(HMM_ERR_ARG, "bytes is NULL");
+    Checked c;
+    hmm_status st = check_batch(batch, model, &c);
+    if (st != HMM_OK) return st;
+    Plan p;
+    st = make_plan(op, c, prec, &p);
+    if (st != HMM_OK) return st;
+    *bytes = p.total;
+    return ok();
+}
+
+hmm_status hmm_emission_logpdf(const hmm_model *model, const hmm_batch *batch, hmm_precision prec,
+                               void *log_b, void *ws, size_t ws_bytes, void *stream) {
+    Checked c;
+    hmm_status st = check_batch(batch, model, &c);
+    if (st != HMM_OK) return st;
+    Plan p;
+    if ((st = make_plan(HMM_OP_EMISSION, c, prec, &p)) != HMM_OK) return st;
+    if ((st = check_ws(p, ws, ws_bytes)) != HMM_OK) return st;
+    if (c.total > 0 && !log_b) return fail(HMM_ERR_ARG, "log_b is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    ObsDesc od{batch->obs, batch->obs_f64, c.B, batch->offsets};
+    if (p.f64) {
+        StagedModel<double> sm;
+        launch_stage<double>(raw(model), (char *)ws + p.staged, &sm, s);
+        run_emission<double>(sm, od, c.total, (double *)log_b, s);
+    } else {
+        StagedModel<float> sm;
+        launch_stage<float>(raw(model), (char *)ws + p.staged, &sm, s);
+        run_emission<float>(sm, od, c.total, (float *)log_b, s);
+    }
+    return device_check("emission kernel");
+}
+
+hmm_status hmm_forward_backward(const hmm_model *model, const hmm_batch *batch,
+                                hmm_precision prec, double *loglik, void *gamma,
+                                int32_t *seq_status, void *ws, size_t ws_bytes, void *stream) {
+    Checked c;
+    hmm_status st = check_batch(batch, model, &c);
+    if (st != HMM_OK) return st;
+    Plan p;
+    if ((st = make_plan(HMM_OP_FORWARD_BACKWARD, c, prec, &p)) != HMM_OK) return st;
+    if ((st = check_ws(p, ws, ws_bytes)) != HMM_OK) return st;
+    if (c.B > 0 && !loglik) return fail(HMM_ERR_ARG, "loglik is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    if (p.f64)
+        return run_posterior_path<double>(model, batch, c, p, (char *)ws, loglik, seq_status,
+                                          gamma, nullptr, s);
+    return run_posterior_path<float>(model, batch, c, p, (char *)ws, loglik, seq_status, gamma,
+                                     nullptr, s);
+}
+
+hmm_status hmm_estep_stats(const hmm_model *model, const hmm_batch *batch, hmm_precision prec,
+                           double *stats, double *loglik, int32_t *seq_status, void *ws,
+                           size_t ws_bytes, void *stream) {
+    Checked c;
+    hmm_status st = check_batch(batch, model, &c);
+    if (st != HMM_OK) return st;
+    Plan p;
+    if ((st = make_plan(HMM_OP_ESTEP, c, prec, &p)) != HMM_OK) return st;
+    if ((st = check_ws(p, ws, ws_bytes)) != HMM_OK) return st;
+    if (!stats) return fail(HMM_ERR_ARG, "stats is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    if (p.f64)
+        return run_posterior_path<double>(model, batch, c, p, (char *)ws, loglik, seq_status,
+                                          nullptr, stats, s);
+    return run_posterior_path<float>(model, batch, c, p, (char *)ws, loglik, seq_status, nullptr,
+                                     stats, s);
+}
+
+hmm_status hmm_posterior_decode(const hmm_model *model, const hmm_batch *batch,
+                                hmm_precision prec, int32_t *path, double *loglik, void *ws,
+                                size_t ws_bytes, void *stream) {
+    Checked c;
+    hmm_status st = check_batch(batch, model, &c);
+    if (st != HMM_OK) return st;
+    Plan p;
+    if ((st = make_plan(HMM_OP_POSTERIOR_DECODE, c, prec, &p)) != HMM_OK) return st;
+    if ((st = check_ws(p, ws, ws_bytes)) != HMM_OK) return st;
+    if (c.total > 0 && !path) return fail(HMM_ERR_ARG, "path is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    char *w = (char *)ws;
+    void *gam = w + p.gam;
+    if (p.f64) st = run_posterior_path<double>(model, batch, c, p, w, loglik, nullptr, gam, nullptr, s);
+    else st = run_posterior_path<float>(model, batch, c, p, w, loglik, nullptr, gam, nullptr, s);
+    if (st != HMM_OK) return st;
+    if (c.total > 0) launch_argmax_rows(gam, p.f64, c.total, c.N, path, s);
+    return device_check("posterior decode");
+}
+
+hmm_status hmm_viterbi(const hmm_model *model, const hmm_batch *batch, hmm_precision prec,
+                       int32_t *path, double *path_logp, void *ws, size_t ws_bytes, void *stream) {
+    (void)model; (void)batch; (void)prec; (void)path; (void)path_logp; (void)ws; (void)ws_bytes;
+    (void)stream;
+    return fail(HMM_ERR_UNSUPPORTED, "Viterbi is not built yet");
+}
+
+void hmm_mstep_default_opts(hmm_mstep_opts *o) {
+    if (!o) return;
+    o->eps_collapse = 1e-8;
+    o->ridge = 1e-6;
+    o->gamma_rtol = 1e-12;
+    o->nu_tol = 1e-6;
+    o->nu_min = 0.5;
+    o->nu_max = 1e4;
+    o->max_iter = 100;
+    o->t_nu_printed = 0;
+}
+
+#define HMM_MSTEP_STUB(name)                                                                   \
+    hmm_status name(const hmm_model *model, const double *stats, const hmm_mstep_opts *opts,    \
+                    double *theta_out, int32_t *collapsed, int32_t *iters, void *stream) {      \
+        (void)model; (void)stats; (void)opts; (void)theta_out; (void)collapsed; (void)iters;    \
+        (void)stream;                                                                          \
+        return fail(HMM_ERR_UNSUPPORTED, #name " is not built yet");                           \
+    }
+HMM_MSTEP_STUB(hmm_mstep_gaussian)
+HMM_MSTEP_STUB(hmm_mstep_gamma)
+HMM_MSTEP_STUB(hmm_mstep_student_t)
+HMM_MSTEP_STUB(hmm_mstep_poisson)
+HMM_MSTEP_STUB(hmm_mstep_diag_gaussian)
+HMM_MSTEP_STUB(hmm_mstep_full_gaussian)
+
+hmm_status hmm_mstep_transitions(const hmm_model *model, const double *stats,
+                                 const hmm_mstep_opts *opts, double *log_pi_out,
+                                 double *log_A_out, void *stream) {
+    (void)model; (void)stats; (void)opts; (void)log_pi_out; (void)log_A_out; (void)stream;
+    return fail(HMM_ERR_UNSUPPORTED, "hmm_mstep_transitions is not built yet");
+}
+
+hmm_status hmm_profile_enable(int32_t on) {
+    g_prof_on = on != 0;
+    g_prof.clear();
+    g_pool_used = 0;
+    return ok();
+}
+
+int32_t hmm_profile_count(void) { return (int32_t)g_prof.size(); }
+
+hmm_status hmm_profile_get(int32_t i, const char **name, float *ms) {
+    if (i < 0 || i >= (int32_t)g_prof.size() || !name || !ms)
+        return fail(HMM_ERR_ARG, "profile record %d does not exist", i);
+    *name = g_prof[i].name;
+    hipError_t e = hipEventSynchronize(g_prof[i].b);
+    if (e == hipSuccess) e = hipEventElapsedTime(ms, g_prof[i].a, g_prof[i].b);
+    if (e != hipSuccess) return fail(HMM_ERR_DEVICE, "profile event: %s", hipGetErrorString(e));
+    return ok();
+}
+
+hmm_status hmm_profile_reset(void) {
+    g_prof.clear();
+    g_pool_used = 0;
+    return ok();
+}
+
+hmm_status hmm_set_chunk_len(int32_t steps) {
+    if (steps != 0 && steps != 16 && steps != 32 && steps != 64)
+        return fail(HMM_ERR_ARG, "chunk length must be 0, 16, 32 or 64");
+    g_chunk_len.store(steps);
+    return ok();
+}
+
+}  // extern "C"

@@ -1,0 +1,271 @@
+// dev_common.hpp -- device helpers shared by the HIP kernels of the library:
+// DPP lane-group primitives, per-state emission constants, scalar emission
+// log-densities and the per-state sufficient-statistic terms.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "hmm_internal.hpp"
+
+namespace hmmk {
+
+// ---------------------------------------------------------------------------
+// DPP control words (CDNA data-parallel-primitive encoding)
+// ---------------------------------------------------------------------------
+enum : int {
+    DPP_QP_X1 = 0xB1,          // quad_perm [1,0,3,2]: lane ^ 1 inside each quad
+    DPP_QP_X2 = 0x4E,          // quad_perm [2,3,0,1]: lane ^ 2
+    DPP_QP_X3 = 0x1B,          // quad_perm [3,2,1,0]: lane ^ 3
+    DPP_HALF_MIRROR = 0x141    // row_half_mirror: lane p <-> 7 - p inside each 8 lanes
+};
+
+template <int CTRL>
+__device__ __forceinline__ int dpp_i(int v) {
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, true);
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp_v(float v) {
+    return __builtin_bit_cast(float, dpp_i<CTRL>(__builtin_bit_cast(int, v)));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_v(double v) {
+    uint64_t u = __builtin_bit_cast(uint64_t, v);
+    uint32_t lo = (uint32_t)dpp_i<CTRL>((int)(uint32_t)u);
+    uint32_t hi = (uint32_t)dpp_i<CTRL>((int)(uint32_t)(u >> 32));
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+// Lane-group of G consecutive lanes (G = 4 or 8); position p = lane % G.
+// Source k of position p: k < 4 -> p ^ k; k >= 4 -> 7 - (p ^ (k - 4)).
+// For G = 8 the eight sources of every position are the eight lanes of its
+// group; for G = 4 the first four are the four lanes of its quad.
+__host__ __device__ constexpr int grp_src(int p, int k) {
+    return k < 4 ? (p ^ k) : (7 - (p ^ (k - 4)));
+}
+// inverse: the k with grp_src(p, k) == i
+__host__ __device__ constexpr int grp_inv(int p, int i) {
+    return ((i ^ p) < 4) ? (i ^ p) : (4 + ((7 - i) ^ p));
+}
+
+// x_k = value of x held by source k of this lane
+template <int G, typename R>
+__device__ __forceinline__ void grp_gather(R x, R (&out)[G]) {
+    out[0] = x;
+    out[1] = dpp_v<DPP_QP_X1>(x);
+    out[2] = dpp_v<DPP_QP_X2>(x);
+    out[3] = dpp_v<DPP_QP_X3>(x);
+    if constexpr (G == 8) {
+        R m = dpp_v<DPP_HALF_MIRROR>(x);
+        out[4] = m;
+        out[5] = dpp_v<DPP_QP_X1>(m);
+        out[6] = dpp_v<DPP_QP_X2>(m);
+        out[7] = dpp_v<DPP_QP_X3>(m);
+    }
+}
+
+// sum_k x[src_k] * c[k]
+template <int G, typename R>
+__device__ __forceinline__ R grp_dot(R x, const R (&c)[G]) {
+    R s = x * c[0];
+    s = fma(dpp_v<DPP_QP_X1>(x), c[1], s);
+    s = fma(dpp_v<DPP_QP_X2>(x), c[2], s);
+    s = fma(dpp_v<DPP_QP_X3>(x), c[3], s);
+    if constexpr (G == 8) {
+        R m = dpp_v<DPP_HALF_MIRROR>(x);
+        s = fma(m, c[4], s);
+        s = fma(dpp_v<DPP_QP_X1>(m), c[5], s);
+        s = fma(dpp_v<DPP_QP_X2>(m), c[6], s);
+        s = fma(dpp_v<DPP_QP_X3>(m), c[7], s);
+    }
+    return s;
+}
+
+// U[k] += x[src_k] * w
+template <int G, typename R>
+__device__ __forceinline__ void grp_outer_acc(R x, R w, R (&U)[G]) {
+    U[0] = fma(x, w, U[0]);
+    U[1] = fma(dpp_v<DPP_QP_X1>(x), w, U[1]);
+    U[2] = fma(dpp_v<DPP_QP_X2>(x), w, U[2]);
+    U[3] = fma(dpp_v<DPP_QP_X3>(x), w, U[3]);
+    if constexpr (G == 8) {
+        R m = dpp_v<DPP_HALF_MIRROR>(x);
+        U[4] = fma(m, w, U[4]);
+        U[5] = fma(dpp_v<DPP_QP_X1>(m), w, U[5]);
+        U[6] = fma(dpp_v<DPP_QP_X2>(m), w, U[6]);
+        U[7] = fma(dpp_v<DPP_QP_X3>(m), w, U[7]);
+    }
+}
+
+template <int G, typename R>
+__device__ __forceinline__ R grp_max(R v) {
+    v = fmax(v, dpp_v<DPP_QP_X1>(v));
+    v = fmax(v, dpp_v<DPP_QP_X2>(v));
+    if constexpr (G == 8) v = fmax(v, dpp_v<DPP_HALF_MIRROR>(v));
+    return v;
+}
+template <int G, typename R>
+__device__ __forceinline__ R grp_sum(R v) {
+    v = v + dpp_v<DPP_QP_X1>(v);
+    v = v + dpp_v<DPP_QP_X2>(v);
+    if constexpr (G == 8) v = v + dpp_v<DPP_HALF_MIRROR>(v);
+    return v;
+}
+template <int G>
+__device__ __forceinline__ int grp_max_i(int v) {
+    v = max(v, dpp_i<DPP_QP_X1>(v));
+    v = max(v, dpp_i<DPP_QP_X2>(v));
+    if constexpr (G == 8) v = max(v, dpp_i<DPP_HALF_MIRROR>(v));
+    return v;
+}
+
+// wave-wide integer maximum (used once per kernel for uniform trip counts)
+__device__ __forceinline__ int wave_max_i(int v) {
+    for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+// binary exponent helpers: x = m * 2^e with |m| in [1/2, 1); exponent of 0 is 0
+__device__ __forceinline__ int fexp(float x) { return __builtin_amdgcn_frexp_expf(x); }
+__device__ __forceinline__ int fexp(double x) { return __builtin_amdgcn_frexp_exp(x); }
+__device__ __forceinline__ float fldexp(float x, int e) { return __builtin_amdgcn_ldexpf(x, e); }
+__device__ __forceinline__ double fldexp(double x, int e) { return __builtin_amdgcn_ldexp(x, e); }
+
+__device__ __forceinline__ float fexp_e(float x) { return __expf(x); }
+__device__ __forceinline__ double fexp_e(double x) { return exp(x); }
+__device__ __forceinline__ float flog(float x) { return __logf(x); }
+__device__ __forceinline__ double flog(double x) { return log(x); }
+__device__ __forceinline__ float flog1p(float x) { return log1pf(x); }
+__device__ __forceinline__ double flog1p(double x) { return log1p(x); }
+__device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double frcp(double x) { return 1.0 / x; }
+
+template <typename R> __device__ __forceinline__ R neg_inf() { return -__builtin_inf(); }
+
+// ---------------------------------------------------------------------------
+// observations
+// ---------------------------------------------------------------------------
+struct ObsRef {
+    const void *p;
+    int f64;
+};
+template <typename R>
+__device__ __forceinline__ R load_obs(const ObsRef &o, int64_t idx) {
+    if (o.f64) return (R)((const double *)o.p)[idx];
+    return (R)((const float *)o.p)[idx];
+}
+
+// ---------------------------------------------------------------------------
+// scalar emission families (compile-time family)
+//
+// Per-state constants ep[8] (filled by the staging kernel from theta):
+//   GAUSSIAN   ep0 = mu, ep1 = -1/(2 var), ep2 = -log(2 pi var)/2
+//              log b = ep2 + ep1 (y - mu)^2
+//   GAMMA      ep0 = a log(rate) - lgamma(a), ep1 = a - 1, ep2 = -rate
+//              log b = ep0 + ep1 log y + ep2 y          (y > 0, else -inf)
+//   STUDENT_T  ep0 = mu, ep1 = 1/(nu s^2), ep2 = -(nu+1)/2,
+//              ep3 = lgamma((nu+1)/2) - lgamma(nu/2) - log(nu pi s^2)/2, ep4 = (nu+1)/nu
+//              log b = ep3 + ep2 log1p(ep1 (y - mu)^2);  u = ep4 / (1 + ep1 (y-mu)^2)
+//   POISSON    ep0 = log(lambda), ep1 = -lambda
+//              log b = y ep0 + ep1 - lgamma(y + 1)      (y a non-negative integer)
+//              The state-independent -lgamma(y+1) is returned separately in
+//              FP64 ("common") so the single-precision values stay small.
+//   TABLE      log b is read from the observation table [sum T, N].
+// ---------------------------------------------------------------------------
+template <typename R>
+struct StateConsts {
+    R c0, c1, c2, c3, c4;
+};
+
+template <typename R>
+__device__ __forceinline__ StateConsts<R> load_consts(const R *ep, int j, bool live) {
+    StateConsts<R> s;
+    if (live) {
+        s.c0 = ep[j * EP_STRIDE + 0];
+        s.c1 = ep[j * EP_STRIDE + 1];
+        s.c2 = ep[j * EP_STRIDE + 2];
+        s.c3 = ep[j * EP_STRIDE + 3];
+        s.c4 = ep[j * EP_STRIDE + 4];
+    } else {
+        s.c0 = s.c1 = s.c2 = s.c3 = s.c4 = (R)0;
+    }
+    return s;
+}
+
+// per-step observation: y (scalar families) and whether it is finite
+template <typename R>
+struct Emit {
+    R ell;          // log b_j(y_t) without the state-independent part
+    double common;  // state-independent part (Poisson: -lgamma(y+1)); 0 otherwise
+    bool bad;       // non-finite observation
+};
+
+template <int FAM, typename R>
+__device__ __forceinline__ Emit<R> emit_scalar(R y, const StateConsts<R> &k, bool live) {
+    Emit<R> e;
+    e.common = 0.0;
+    e.bad = !isfinite(y);
+    if constexpr (FAM == HMM_GAUSSIAN) {
+        R d = y - k.c0;
+        e.ell = fma(k.c1, d * d, k.c2);
+    } else if constexpr (FAM == HMM_GAMMA) {
+        e.ell = (y > (R)0) ? fma(k.c2, y, fma(k.c1, flog(y), k.c0)) : neg_inf<R>();
+    } else if constexpr (FAM == HMM_STUDENT_T) {
+        R d = y - k.c0;
+        e.ell = fma(k.c2, flog1p(k.c1 * d * d), k.c3);
+    } else if constexpr (FAM == HMM_POISSON) {
+        bool ok = (y >= (R)0) && (floor(y) == y);
+        e.ell = ok ? fma(y, k.c0, k.c1) : neg_inf<R>();
+        e.common = ok ? -lgamma((double)y + 1.0) : 0.0;
+    } else {
+        e.ell = y;   // table: the value itself is log b
+    }
+    if (!live) e.ell = neg_inf<R>();
+    return e;
+}
+
+// number of family-statistic slots per state
+template <int FAM>
+__host__ __device__ constexpr int fam_k() {
+    return FAM == HMM_GAUSSIAN ? 2 : FAM == HMM_GAMMA ? 3 : FAM == HMM_STUDENT_T ? 4
+         : FAM == HMM_POISSON ? 1 : 0;
+}
+
+// acc[k] += g * term_k(y) for one state (compile-time family)
+template <int FAM, typename R, int K>
+__device__ __forceinline__ void fam_accumulate(R g, R y, const StateConsts<R> &k, R (&acc)[K]) {
+    if constexpr (FAM == HMM_GAUSSIAN) {
+        R d = y - k.c0;
+        R gd = g * d;
+        acc[0] += gd;
+        acc[1] = fma(gd, d, acc[1]);
+    } else if constexpr (FAM == HMM_GAMMA) {
+        R gy = g * y;
+        acc[0] += gy;
+        acc[1] = fma(g, flog(y), acc[1]);
+        acc[2] = fma(gy, y, acc[2]);
+    } else if constexpr (FAM == HMM_STUDENT_T) {
+        R d = y - k.c0;
+        R q = k.c1 * d * d;
+        R u = k.c4 * frcp((R)1 + q);
+        R gu = g * u;
+        acc[0] += gu;
+        acc[1] = fma(gu, d, acc[1]);
+        acc[2] = fma(gu * d, d, acc[2]);
+        acc[3] = fma(g, flog(u) - u, acc[3]);
+    } else if constexpr (FAM == HMM_POISSON) {
+        acc[0] = fma(g, y, acc[0]);
+    }
+}
+
+// locate the sequence b owning chunk c: largest b with cbase[b] <= c
+__device__ __forceinline__ int find_seq(const int *cbase, int nseq, int c) {
+    int lo = 0, hi = nseq - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (cbase[mid] <= c) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+}  // namespace hmmk

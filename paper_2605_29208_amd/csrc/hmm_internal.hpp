@@ -1,0 +1,100 @@
+// hmm_internal.hpp -- internal declarations shared by the host runtime
+// (abi.cpp) and the kernel translation units: staged-parameter layout,
+// kernel argument blocks and launcher prototypes.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "hmm_gpu.h"
+
+namespace hmmk {
+
+constexpr int EP_STRIDE = 8;       // per-state emission-constant slots
+constexpr int BLOCK = 256;         // threads per block of every kernel
+
+// Parameters staged on the device once per call (section 3.2 notes that log A
+// is prepared once per training iteration; the linear A, pi and the per-state
+// emission constants are prepared the same way).  R = float or double.
+template <typename R>
+struct StagedModel {
+    int N, D, family;
+    const R *pi;        // [N]      exp(log pi)
+    const R *A;         // [N*N]    exp(log A), row i = from state i
+    const R *lpi;       // [N]      log pi in R
+    const R *lA;        // [N*N]    log A in R
+    const R *ep;        // [N*EP_STRIDE] emission constants
+    const R *mv;        // multivariate constants: diag [mu(N*D), -1/(2 var)(N*D)],
+                        // full [mu(N*D), Linv(N*D*D)] (Linv lower, row-major)
+    const int *perr;    // parameter-domain flag written by the staging kernel
+};
+
+// Raw (not yet staged) model, FP64 device pointers from the ABI.
+struct RawModel {
+    int N, D, family;
+    const double *log_pi, *log_A, *theta;
+};
+
+struct ObsDesc {
+    const void *obs;
+    int obs_f64;
+    int64_t nseq;
+    const int64_t *offsets;   // device [B+1]
+};
+
+// Optional per-kernel timing: when enabled with hmm_profile_enable, every
+// launcher brackets its kernel with hipEvents recorded on the launch stream.
+void prof_begin(const char *name, hipStream_t s);
+void prof_end(hipStream_t s);
+struct ProfScope {
+    hipStream_t s;
+    ProfScope(const char *name, hipStream_t st) : s(st) { prof_begin(name, st); }
+    ~ProfScope() { prof_end(s); }
+};
+
+// byte sizes of the staged region for precision R
+size_t staged_bytes(int N, int D, int family, bool f64);
+
+// ----- launchers (each defined in the kernel translation unit) -----
+template <typename R>
+void launch_stage(const RawModel &m, void *region, StagedModel<R> *out, hipStream_t s);
+
+void launch_plan_chunks(const int64_t *offsets, int64_t nseq, int L, int *cbase, hipStream_t s);
+
+// batched small-N path (G = 4 or 8 lanes per chunk)
+struct ChunkBuffers {
+    int L, C, G, nblk_stats;
+    int *cbase;          // [B+1]
+    void *P;             // [C*G*G] R
+    int *rexp;           // [C*G]
+    double *clog;        // [C]
+    void *F;             // [C*G] R  alpha at each chunk end (normalised)
+    void *Gb;            // [C*G] R  beta at each chunk end (normalised)
+    double *partial;     // [nblk_stats * S]
+};
+template <typename R>
+hmm_status run_chunked(const StagedModel<R> &m, const ObsDesc &o, const ChunkBuffers &cb,
+                       double *loglik, int32_t *status, void *gamma_out, double *stats,
+                       int64_t stats_len, hipStream_t s);
+
+// plain path (one thread per sequence, literal log-sum-exp)
+struct PlainBuffers {
+    void *logB, *alpha, *beta;   // [sum T * N] R
+    double *ps;                  // [B * S] per-sequence statistics
+};
+template <typename R>
+hmm_status run_plain(const StagedModel<R> &m, const ObsDesc &o, const PlainBuffers &pb,
+                     double *loglik, int32_t *status, void *gamma_out, double *stats,
+                     int64_t stats_len, hipStream_t s);
+
+// emission table
+template <typename R>
+hmm_status run_emission(const StagedModel<R> &m, const ObsDesc &o, int64_t total_steps,
+                        R *out, hipStream_t s);
+
+// fixed-order reduction of per-block partial statistics + log-likelihood sum
+void launch_reduce_stats(const double *partial, int nparts, int64_t S, const double *loglik,
+                         const int32_t *status, int64_t nseq, double *stats, hipStream_t s);
+
+}  // namespace hmmk

@@ -1,0 +1,251 @@
+// k_stage.hip -- parameter staging, chunk planning and the fixed-order
+// reduction of partial statistics.
+#include <math.h>
+
+#include "dev_common.hpp"
+#include "hmm_internal.hpp"
+
+namespace hmmk {
+
+static inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+static size_t mv_count(int N, int D, int family) {
+    if (family == HMM_DIAG_GAUSSIAN) return (size_t)2 * N * D;
+    if (family == HMM_FULL_GAUSSIAN) return (size_t)N * D + (size_t)N * D * D;
+    return 0;
+}
+
+size_t staged_bytes(int N, int D, int family, bool f64) {
+    size_t r = f64 ? 8 : 4;
+    size_t n = (size_t)N, nn = n * n;
+    return align256(n * r) * 2 + align256(nn * r) * 2 + align256(n * EP_STRIDE * r) +
+           align256(mv_count(N, D, family) * r + r) + 256;
+}
+
+// One block.  Computes linear and log probabilities in R, the per-state
+// emission constants (see dev_common.hpp for their meaning) and, for the
+// multivariate families, the location vectors and -1/(2 var) or L^{-1}.
+template <typename R>
+__global__ __launch_bounds__(BLOCK) void k_stage(RawModel m, R *pi, R *A, R *lpi, R *lA, R *ep,
+                                                 R *mv, int *perr) {
+    const int N = m.N, D = m.D;
+    int bad = 0;
+    for (int j = threadIdx.x; j < N; j += blockDim.x) {
+        double l = m.log_pi[j];
+        pi[j] = (R)exp(l);
+        lpi[j] = (R)l;
+    }
+    for (int k = threadIdx.x; k < N * N; k += blockDim.x) {
+        double l = m.log_A[k];
+        A[k] = (R)exp(l);
+        lA[k] = (R)l;
+    }
+    const double *th = m.theta;
+    const double kLog2Pi = 1.8378770664093454835606594728112;
+    for (int j = threadIdx.x; j < N; j += blockDim.x) {
+        double c[EP_STRIDE] = {0, 0, 0, 0, 0, 0, 0, 0};
+        switch (m.family) {
+        case HMM_GAUSSIAN: {
+            double mu = th[j], var = th[N + j];
+            bad |= !(var > 0.0) || !isfinite(mu);
+            c[0] = mu;
+            c[1] = -0.5 / var;
+            c[2] = -0.5 * log(2.0 * M_PI * var);
+            break;
+        }
+        case HMM_GAMMA: {
+            double a = th[j], b = th[N + j];
+            bad |= !(a > 0.0) || !(b > 0.0);
+            c[0] = a * log(b) - lgamma(a);
+            c[1] = a - 1.0;
+            c[2] = -b;
+            break;
+        }
+        case HMM_STUDENT_T: {
+            double mu = th[j], s = th[N + j], nu = th[2 * N + j];
+            bad |= !(s > 0.0) || !(nu > 0.0) || !isfinite(mu);
+            c[0] = mu;
+            c[1] = 1.0 / (nu * s * s);
+            c[2] = -0.5 * (nu + 1.0);
+            c[3] = lgamma(0.5 * (nu + 1.0)) - lgamma(0.5 * nu) - 0.5 * log(nu * M_PI * s * s);
+            c[4] = (nu + 1.0) / nu;
+            break;
+        }
+        case HMM_POISSON: {
+            double lam = th[j];
+            bad |= !(lam > 0.0);
+            c[0] = log(lam);
+            c[1] = -lam;
+            break;
+        }
+        case HMM_DIAG_GAUSSIAN: {
+            double s = 0.0;
+            for (int d = 0; d < D; ++d) {
+                double mu = th[(size_t)j * D + d], var = th[(size_t)N * D + (size_t)j * D + d];
+                bad |= !(var > 0.0) || !isfinite(mu);
+                s += -0.5 * log(2.0 * M_PI * var);
+                mv[(size_t)j * D + d] = (R)mu;
+                mv[(size_t)N * D + (size_t)j * D + d] = (R)(-0.5 / var);
+            }
+            c[0] = s;
+            break;
+        }
+        case HMM_FULL_GAUSSIAN: {
+            const double *L = th + (size_t)N * D + (size_t)j * D * D;
+            R *Li = mv + (size_t)N * D + (size_t)j * D * D;
+            double logdet = 0.0;
+            for (int d = 0; d < D; ++d) {
+                mv[(size_t)j * D + d] = (R)th[(size_t)j * D + d];
+                bad |= !(L[d * D + d] > 0.0);
+                logdet += log(L[d * D + d]);
+            }
+            // L^{-1} column by column: solve L x = e_col by forward substitution (FP64)
+            for (int col = 0; col < D; ++col) {
+                double x[64];
+                for (int r = 0; r < D; ++r) {
+                    if (r < col) { x[r] = 0.0; continue; }
+                    double acc = (r == col) ? 1.0 : 0.0;
+                    for (int q = col; q < r; ++q) acc -= L[r * D + q] * x[q];
+                    x[r] = acc / L[r * D + r];
+                }
+                for (int r = 0; r < D; ++r) Li[r * D + col] = (R)x[r];
+            }
+            c[0] = -logdet - 0.5 * D * kLog2Pi;
+            break;
+        }
+        default:
+            break;
+        }
+        for (int k = 0; k < EP_STRIDE; ++k) ep[j * EP_STRIDE + k] = (R)c[k];
+    }
+    int any = __syncthreads_or(bad);
+    if (threadIdx.x == 0) *perr = any;
+}
+
+template <typename R>
+void launch_stage(const RawModel &m, void *region, StagedModel<R> *out, hipStream_t s) {
+    size_t r = sizeof(R);
+    size_t n = (size_t)m.N, nn = n * n;
+    char *p = (char *)region;
+    R *pi = (R *)p; p += align256(n * r);
+    R *lpi = (R *)p; p += align256(n * r);
+    R *A = (R *)p; p += align256(nn * r);
+    R *lA = (R *)p; p += align256(nn * r);
+    R *ep = (R *)p; p += align256(n * EP_STRIDE * r);
+    R *mv = (R *)p; p += align256(mv_count(m.N, m.D, m.family) * r + r);
+    int *perr = (int *)p;
+    {
+        ProfScope ps("stage", s);
+        hipLaunchKernelGGL(k_stage<R>, dim3(1), dim3(BLOCK), 0, s, m, pi, A, lpi, lA, ep, mv, perr);
+    }
+    out->N = m.N;
+    out->D = m.D;
+    out->family = m.family;
+    out->pi = pi;
+    out->A = A;
+    out->lpi = lpi;
+    out->lA = lA;
+    out->ep = ep;
+    out->mv = mv;
+    out->perr = perr;
+}
+
+template void launch_stage<float>(const RawModel &, void *, StagedModel<float> *, hipStream_t);
+template void launch_stage<double>(const RawModel &, void *, StagedModel<double> *, hipStream_t);
+
+// cbase[b] = sum_{b' < b} ceil(T_b' / L); single block exclusive scan.
+__global__ __launch_bounds__(1024) void k_plan_chunks(const int64_t *offsets, int64_t nseq, int L,
+                                                      int *cbase) {
+    __shared__ int sh[1024];
+    int carry = 0;
+    for (int64_t base = 0; base < nseq; base += 1024) {
+        int64_t b = base + threadIdx.x;
+        int n = 0;
+        if (b < nseq) {
+            int64_t T = offsets[b + 1] - offsets[b];
+            n = (int)((T + L - 1) / L);
+        }
+        sh[threadIdx.x] = n;
+        __syncthreads();
+        for (int o = 1; o < 1024; o <<= 1) {   // Hillis-Steele inclusive scan
+            int v = (threadIdx.x >= (unsigned)o) ? sh[threadIdx.x - o] : 0;
+            __syncthreads();
+            sh[threadIdx.x] += v;
+            __syncthreads();
+        }
+        if (b < nseq) cbase[b] = carry + sh[threadIdx.x] - n;
+        int tot = sh[1023];
+        __syncthreads();
+        carry += tot;
+    }
+    if (threadIdx.x == 0) cbase[nseq] = carry;
+}
+
+void launch_plan_chunks(const int64_t *offsets, int64_t nseq, int L, int *cbase, hipStream_t s) {
+    ProfScope ps("plan_chunks", s);
+    hipLaunchKernelGGL(k_plan_chunks, dim3(1), dim3(1024), 0, s, offsets, nseq, L, cbase);
+}
+
+// stats[s] = sum over parts of partial[p*S + s] (s >= 1) in a fixed order;
+// stats[0] = sum of loglik[b] over sequences with status 0.
+__global__ __launch_bounds__(BLOCK) void k_reduce_stats(const double *partial, int nparts, int64_t S,
+                                                       const double *loglik, const int32_t *status,
+                                                       int64_t nseq, double *stats) {
+    __shared__ double sh[BLOCK];
+    const int64_t s = blockIdx.x;
+    double acc = 0.0;
+    if (s == 0) {
+        for (int64_t b = threadIdx.x; b < nseq; b += BLOCK)
+            if (status[b] == 0) acc += loglik[b];
+    } else {
+        for (int p = threadIdx.x; p < nparts; p += BLOCK) acc += partial[(int64_t)p * S + s];
+    }
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int o = BLOCK / 2; o > 0; o >>= 1) {
+        if (threadIdx.x < (unsigned)o) sh[threadIdx.x] += sh[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) stats[s] = sh[0];
+}
+
+void launch_reduce_stats(const double *partial, int nparts, int64_t S, const double *loglik,
+                         const int32_t *status, int64_t nseq, double *stats, hipStream_t s) {
+    ProfScope ps("reduce_stats", s);
+    hipLaunchKernelGGL(k_reduce_stats, dim3((unsigned)S), dim3(BLOCK), 0, s, partial, nparts, S,
+                       loglik, status, nseq, stats);
+}
+
+}  // namespace hmmk
+
+namespace hmmk {
+
+// posterior decoding: path[r] = lowest argmax_j gamma[r, j]
+template <typename R>
+__global__ __launch_bounds__(BLOCK) void k_argmax_rows(const R *g, int64_t rows, int N,
+                                                      int32_t *path) {
+    const int64_t r = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (r >= rows) return;
+    const R *row = g + r * N;
+    int q = 0;
+    R best = row[0];
+    for (int j = 1; j < N; ++j)
+        if (row[j] > best) {
+            best = row[j];
+            q = j;
+        }
+    path[r] = q;
+}
+
+void launch_argmax_rows(const void *gamma, bool f64, int64_t rows, int N, int32_t *path,
+                        hipStream_t s) {
+    dim3 grid((unsigned)((rows + BLOCK - 1) / BLOCK));
+    if (f64)
+        hipLaunchKernelGGL(k_argmax_rows<double>, grid, dim3(BLOCK), 0, s, (const double *)gamma,
+                           rows, N, path);
+    else
+        hipLaunchKernelGGL(k_argmax_rows<float>, grid, dim3(BLOCK), 0, s, (const float *)gamma,
+                           rows, N, path);
+}
+
+}  // namespace hmmk

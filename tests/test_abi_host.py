@@ -1,0 +1,108 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every function the header declares, and rejects bad arguments on the host
+before anything is enqueued.  Device pointers here are placeholders that the
+library must never dereference on these paths."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    txt = open(os.path.join(ROOT, "include", "hmm_gpu.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(hmm_[a-z0-9_]+)\s*\(", txt)))
+
+
+@pytest.fixture(scope="module")
+def h():
+    import paper_2605_29208_amd as h
+    return h
+
+
+def test_exports_every_declared_symbol(h):
+    lib = ctypes.CDLL(h.LIB_PATH)
+    names = header_functions()
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(h.EXPORTED)
+
+
+def fake_model(h, n=3, family="gaussian", dim=1, theta=True):
+    return h.HmmModelC(n, dim, h.FAMILY[family], 0, 0x1000, 0x2000, 0x3000 if theta else None)
+
+
+def fake_batch(h, lengths, f64=0):
+    offs = np.zeros(len(lengths) + 1, dtype=np.int64)
+    offs[1:] = np.cumsum(lengths)
+    b = h.HmmBatchC(len(lengths), 0x4000, offs.ctypes.data_as(ctypes.c_void_p).value, 0x5000, f64, 0)
+    return b, offs
+
+
+def ws_size(h, op, m, b, prec):
+    out = ctypes.c_size_t()
+    st = h._lib.hmm_workspace_size(h.OP[op], ctypes.byref(m), ctypes.byref(b), h.PREC[prec],
+                                   ctypes.byref(out))
+    return st, out.value
+
+
+def test_stats_len(h):
+    m = fake_model(h, 3, "gaussian")
+    assert h._lib.hmm_stats_len(ctypes.byref(m)) == 1 + 3 + 9 + 3 + 3 * 2
+    m = fake_model(h, 8, "gamma")
+    assert h._lib.hmm_stats_len(ctypes.byref(m)) == 1 + 8 + 64 + 8 + 8 * 3
+    m = fake_model(h, 4, "full", dim=5)
+    assert h._lib.hmm_stats_len(ctypes.byref(m)) == 1 + 4 + 16 + 4 + 4 * (5 + 15)
+    m = fake_model(h, 0, "gaussian")
+    assert h._lib.hmm_stats_len(ctypes.byref(m)) == 0
+
+
+def test_workspace_size_and_validation(h):
+    m = fake_model(h, 8, "gamma")
+    b, offs = fake_batch(h, [100, 64, 1])
+    st, n = ws_size(h, "estep", m, b, "f32")
+    assert st == h.HMM_OK and n > 0
+    st, n2 = ws_size(h, "estep", m, b, "plain_f32")
+    assert st == h.HMM_OK and n2 > 0
+    # zero-length sequence
+    b0, _ = fake_batch(h, [5, 0, 3])
+    st, _ = ws_size(h, "estep", m, b0, "f32")
+    assert st == h.HMM_ERR_ARG and "length" in h.last_error()
+    # theta unset
+    mu = fake_model(h, 8, "gamma", theta=False)
+    st, _ = ws_size(h, "estep", mu, b, "f32")
+    assert st == h.HMM_ERR_PARAMS_UNSET
+    # bad n_states / family / dim
+    for bad in (fake_model(h, 0), fake_model(h, 2000), h.HmmModelC(3, 1, 42, 0, 1, 2, 3),
+                fake_model(h, 3, "gaussian", dim=2), fake_model(h, 3, "table", dim=2)):
+        st, _ = ws_size(h, "estep", bad, b, "f32")
+        assert st == h.HMM_ERR_ARG
+    # scaled precisions are reserved
+    st, _ = ws_size(h, "estep", m, b, "bf16_scaled")
+    assert st == h.HMM_ERR_UNSUPPORTED
+
+
+def test_calls_reject_small_workspace_on_host(h):
+    m = fake_model(h, 3, "gaussian")
+    b, offs = fake_batch(h, [10, 20])
+    st = h._lib.hmm_estep_stats(ctypes.byref(m), ctypes.byref(b), h.PREC["f32"],
+                                ctypes.c_void_p(0x6000), None, None, ctypes.c_void_p(0x7000),
+                                16, None)
+    assert st == h.HMM_ERR_WORKSPACE
+    st = h._lib.hmm_estep_stats(ctypes.byref(m), ctypes.byref(b), h.PREC["f32"], None, None,
+                                None, ctypes.c_void_p(0x7000), 1 << 40, None)
+    assert st == h.HMM_ERR_ARG   # stats is NULL
+
+
+def test_default_opts_and_chunk_len(h):
+    o = h.HmmMstepOptsC()
+    h._lib.hmm_mstep_default_opts(ctypes.byref(o))
+    assert o.eps_collapse == 1e-8 and o.ridge == 1e-6 and o.nu_tol == 1e-6 and o.max_iter == 100
+    assert h._lib.hmm_set_chunk_len(7) == h.HMM_ERR_ARG
+    assert h._lib.hmm_set_chunk_len(16) == h.HMM_OK
+    assert h._lib.hmm_set_chunk_len(0) == h.HMM_OK

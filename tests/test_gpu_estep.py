@@ -1,0 +1,236 @@
+"""GPU parity of the E-step paths (batched FP32/FP64 and plain FP32/FP64)
+against the FP64 oracle, called through the C ABI.
+
+Inputs are the seeded synthetic workloads; sizes span several chunks and a
+ragged tail.  The full batched-ragged workload (1024 Gamma sequences, N=8)
+is also run at its real size with the launch configuration the benchmark
+times, and checked on sampled sequences plus exact identities.
+"""
+import numpy as np
+import pytest
+import torch  # noqa: F401  (imported at collection, outside the per-test time limit)
+
+import oracle
+import workloads
+from tests.parity import TOL, assert_loglik_close, assert_stats_close, family_k
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def h():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_2605_29208_amd as h
+    return h
+
+
+def run_estep(h, w, prec, model=None, obs=None):
+    m = model if model is not None else w.model
+    dm = h.DeviceModel.from_model(m)
+    dt = np.float64 if prec in ("f64", "plain_f64") else np.float32
+    db = h.DeviceBatch(w.obs if obs is None else obs, w.offsets, dtype=dt)
+    stats, ll, st = h.estep_stats(dm, db, prec)
+    import torch
+    torch.cuda.synchronize()
+    return stats.cpu().numpy(), ll.cpu().numpy(), st.cpu().numpy()
+
+
+def oracle_ref(w, model=None, obs=None, logB=None):
+    m = model if model is not None else w.model
+    return oracle.estep(m, w.offsets, w.obs if obs is None else obs, logB=logB)
+
+
+PRECS = ["f32", "f64", "plain_f32", "plain_f64"]
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_config1_estep(h, prec):
+    w = workloads.config1()
+    m0 = workloads.perturb(w.model, np.random.default_rng(1))
+    ref = oracle_ref(w, m0)
+    stats, ll, st = run_estep(h, w, prec, m0)
+    assert list(st) == [0]
+    assert_loglik_close(ll, ref["loglik"], TOL[prec], f"config1 {prec}")
+    assert_stats_close(stats, ref["stats"], 3, 2, TOL[prec], f"config1 {prec}")
+
+
+LENGTHS = [1, 2, 15, 16, 17, 31, 32, 33, 64, 65, 100, 257, 500]
+
+
+@pytest.mark.parametrize("fam", ["gaussian", "gamma", "student_t", "poisson"])
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 5, 8])
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_batched_families_ragged(h, fam, n, prec):
+    w = workloads.random_workload(fam, n, 1, LENGTHS, 100 + n)
+    ref = oracle_ref(w)
+    stats, ll, st = run_estep(h, w, prec)
+    assert np.array_equal(st, ref["status"])
+    assert_loglik_close(ll, ref["loglik"], TOL[prec], f"{fam} N={n} {prec}")
+    assert_stats_close(stats, ref["stats"], n, family_k(fam), TOL[prec], f"{fam} N={n} {prec}")
+
+
+@pytest.mark.parametrize("fam,n,d", [("gaussian", 3, 1), ("gamma", 8, 1), ("student_t", 5, 1),
+                                     ("poisson", 4, 1), ("diag", 6, 3), ("full", 4, 3),
+                                     ("gaussian", 20, 1)])
+@pytest.mark.parametrize("prec", ["plain_f32", "plain_f64"])
+def test_plain_families(h, fam, n, d, prec):
+    w = workloads.random_workload(fam, n, d, [1, 7, 40, 129], 200 + n)
+    ref = oracle_ref(w)
+    stats, ll, st = run_estep(h, w, prec)
+    assert np.array_equal(st, ref["status"])
+    assert_loglik_close(ll, ref["loglik"], TOL[prec], f"plain {fam} {prec}")
+    assert_stats_close(stats, ref["stats"], n, family_k(fam, d), TOL[prec], f"plain {fam} {prec}")
+
+
+@pytest.mark.parametrize("chunk", [16, 32])
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_chunk_length_setting(h, chunk, prec):
+    w = workloads.random_workload("gamma", 8, 1, [3, 40, 300, 1001], 300)
+    ref = oracle_ref(w)
+    h.hmm_set_chunk_len(chunk)
+    try:
+        stats, ll, st = run_estep(h, w, prec)
+    finally:
+        h.hmm_set_chunk_len(0)
+    assert_loglik_close(ll, ref["loglik"], TOL[prec], f"L={chunk}")
+    assert_stats_close(stats, ref["stats"], 8, 3, TOL[prec], f"L={chunk}")
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64", "plain_f32"])
+def test_config2_subset(h, prec):
+    w = workloads.config2().subset(np.arange(0, 1024, 32))
+    ref = oracle_ref(w)
+    stats, ll, st = run_estep(h, w, prec)
+    assert (st == 0).all()
+    assert_loglik_close(ll, ref["loglik"], TOL[prec], f"config2 subset {prec}")
+    assert_stats_close(stats, ref["stats"], 8, 3, TOL[prec], f"config2 subset {prec}")
+
+
+def test_config2_full_size(h):
+    """All 1024 sequences in the benchmark's launch configuration: sampled
+    sequences against the oracle, plus identities that hold at any size."""
+    w = workloads.config2()
+    stats, ll, st = run_estep(h, w, "f32")
+    assert (st == 0).all()
+    rng = np.random.default_rng(5)
+    pick = np.sort(rng.choice(1024, 12, replace=False))
+    sub = w.subset(pick)
+    ref = oracle_ref(sub)
+    assert_loglik_close(ll[pick], ref["loglik"], TOL["f32"], "config2 sampled")
+    N = 8
+    g1 = stats[1:1 + N]
+    xi = stats[1 + N:1 + N + N * N]
+    gs = stats[1 + N + N * N:1 + 2 * N + N * N]
+    assert abs(g1.sum() - 1024) < 1e-4 * 1024
+    assert abs(gs.sum() - w.total_steps) < 1e-4 * w.total_steps
+    assert abs(xi.sum() - (w.total_steps - 1024)) < 1e-4 * w.total_steps
+    assert abs(stats[0] - ll.sum()) < 1e-9 * abs(stats[0])
+    # the FP64 batched path agrees with the FP32 one on every pooled statistic
+    s64, ll64, _ = run_estep(h, w, "f64")
+    assert_loglik_close(ll, ll64, TOL["f32"], "config2 f32 vs f64")
+    assert_stats_close(stats, s64, N, 3, TOL["f32"], "config2 f32 vs f64")
+
+
+def test_status_codes_and_exclusion(h):
+    w = workloads.random_workload("gamma", 4, 1, [50, 60, 70, 80], 400)
+    obs = w.obs.copy()
+    obs[w.offsets[1] + 5] = np.nan          # non-finite observation -> status 2
+    obs[w.offsets[2] + 3] = -1.0            # outside the Gamma support -> status 1
+    ref = oracle_ref(w, obs=obs)
+    for prec in ("f32", "f64", "plain_f32"):
+        stats, ll, st = run_estep(h, w, prec, obs=obs)
+        assert list(st) == list(ref["status"]) == [0, 2, 1, 0], (prec, st)
+        assert ll[2] == -np.inf and np.isnan(ll[1])
+        assert_stats_close(stats, ref["stats"], 4, 3, TOL[prec], f"status {prec}")
+
+
+def test_parameter_domain_error(h):
+    w = workloads.random_workload("gaussian", 3, 1, [20, 30], 410)
+    m = w.model.copy()
+    m.theta[3 + 1] = -1.0                   # a negative variance
+    for prec in ("f32", "plain_f64"):
+        stats, ll, st = run_estep(h, w, prec, model=m)
+        assert (st == 4).all()
+        assert np.all(stats == 0)
+
+
+def test_determinism_and_batch_invariance(h):
+    w = workloads.random_workload("gaussian", 5, 1, [300, 1000, 77, 4000, 1], 420)
+    a = run_estep(h, w, "f32")
+    b = run_estep(h, w, "f32")
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+    for k in (1, 3):
+        alone = run_estep(h, w.subset([k]), "f32")
+        assert alone[1][0] == a[1][k]
+
+
+def test_empty_batch(h):
+    import torch
+    w = workloads.random_workload("gamma", 4, 1, [10], 430)
+    dm = h.DeviceModel.from_model(w.model)
+    db = h.DeviceBatch(np.zeros((0, 1)), np.zeros(1, dtype=np.int64))
+    for prec in ("f32", "plain_f32"):
+        stats, ll, st = h.estep_stats(dm, db, prec)
+        torch.cuda.synchronize()
+        assert np.all(stats.cpu().numpy() == 0)
+
+
+@pytest.mark.parametrize("fam,n,d", [("gaussian", 3, 1), ("gamma", 4, 1), ("student_t", 3, 1),
+                                     ("poisson", 5, 1), ("diag", 3, 4), ("full", 3, 4)])
+def test_emission_table_vs_oracle(h, fam, n, d):
+    import torch
+    w = workloads.random_workload(fam, n, d, [37, 5], 440)
+    ref = oracle.emission(fam, n, d, w.model.theta, w.obs)
+    dm = h.DeviceModel.from_model(w.model)
+    for prec, tol in (("f64", 1e-12), ("f32", 2e-5)):
+        dt = np.float64 if prec == "f64" else np.float32
+        db = h.DeviceBatch(w.obs, w.offsets, dtype=dt)
+        out = h.emission_logpdf(dm, db, prec)
+        torch.cuda.synchronize()
+        got = out.cpu().numpy().astype(np.float64)
+        err = np.abs(got - ref) / np.maximum(np.abs(ref), 1.0)
+        assert err.max() <= tol, (prec, err.max())
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64", "plain_f64"])
+def test_table_family(h, prec):
+    """Log-emission tables given directly (any discrete or user-evaluated family)."""
+    rng = np.random.default_rng(450)
+    n = 4
+    lengths = [3, 33, 90]
+    T = sum(lengths)
+    logB = np.log(rng.dirichlet(np.ones(6), size=n).T[rng.integers(0, 6, T)])   # [T, n]
+    offs = np.concatenate([[0], np.cumsum(lengths)])
+    base = workloads.make_model("gaussian", n, 1, rng)
+    m = workloads.Model("table", n, n, base.log_pi, base.log_A, np.zeros(0))
+    ref = oracle.estep(m, offs, None, logB=logB)
+    dm = h.DeviceModel("table", n, n, m.log_pi, m.log_A, None)
+    dt = np.float64 if prec in ("f64", "plain_f64") else np.float32
+    db = h.DeviceBatch(logB, offs, dtype=dt)
+    import torch
+    stats, ll, st = h.estep_stats(dm, db, prec)
+    torch.cuda.synchronize()
+    assert_loglik_close(ll.cpu().numpy(), ref["loglik"], TOL[prec], "table")
+    assert_stats_close(stats.cpu().numpy(), ref["stats"], n, 0, TOL[prec], "table")
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_gamma_posteriors_and_posterior_decode(h, prec):
+    import torch
+    w = workloads.random_workload("student_t", 5, 1, [1, 45, 300], 460)
+    ref = oracle.estep(w.model, w.offsets, w.obs, want_gamma=True)
+    dm = h.DeviceModel.from_model(w.model)
+    dt = np.float64 if prec == "f64" else np.float32
+    db = h.DeviceBatch(w.obs, w.offsets, dtype=dt)
+    ll, gam, st = h.forward_backward(dm, db, prec)
+    path, _ = h.posterior_decode(dm, db, prec)
+    torch.cuda.synchronize()
+    g = gam.cpu().numpy().astype(np.float64)
+    atol = 1e-12 if prec == "f64" else 2e-6
+    assert np.abs(g - ref["gamma"]).max() <= atol * 10
+    rp = oracle.posterior_decode(ref["gamma"])
+    p = path.cpu().numpy()
+    srt = np.sort(ref["gamma"], axis=1)
+    gap = srt[:, -1] - srt[:, -2]
+    assert np.all((p == rp) | (gap < 1e-5))
