@@ -224,6 +224,27 @@ __device__ __forceinline__ Emit<R> emit_scalar(R y, const StateConsts<R> &k, boo
     return e;
 }
 
+// Arithmetic type of the emission evaluation.  Poisson log-densities are of
+// the size of y log(lambda) (hundreds for counts near 100), so in the
+// single-precision path they are evaluated, shifted by their per-step maximum
+// and summed into the log offset in FP64; only the shifted difference is
+// rounded to the recursion's type.
+template <int FAM, typename R>
+struct EmitTraits {
+    using T = R;
+};
+template <typename R>
+struct EmitTraits<HMM_POISSON, R> {
+    using T = double;
+};
+
+template <int FAM, typename R>
+__device__ __forceinline__ const typename EmitTraits<FAM, R>::T *consts_ptr(
+    const StagedModel<R> &m) {
+    if constexpr (FAM == HMM_POISSON) return m.ep64;
+    else return m.ep;
+}
+
 // number of family-statistic slots per state
 template <int FAM>
 __host__ __device__ constexpr int fam_k() {
@@ -232,10 +253,10 @@ __host__ __device__ constexpr int fam_k() {
 }
 
 // acc[k] += g * term_k(y) for one state (compile-time family)
-template <int FAM, typename R, int K>
-__device__ __forceinline__ void fam_accumulate(R g, R y, const StateConsts<R> &k, R (&acc)[K]) {
+template <int FAM, typename R, int K, typename KT>
+__device__ __forceinline__ void fam_accumulate(R g, R y, const StateConsts<KT> &k, R (&acc)[K]) {
     if constexpr (FAM == HMM_GAUSSIAN) {
-        R d = y - k.c0;
+        R d = y - (R)k.c0;
         R gd = g * d;
         acc[0] += gd;
         acc[1] = fma(gd, d, acc[1]);
@@ -245,9 +266,9 @@ __device__ __forceinline__ void fam_accumulate(R g, R y, const StateConsts<R> &k
         acc[1] = fma(g, flog(y), acc[1]);
         acc[2] = fma(gy, y, acc[2]);
     } else if constexpr (FAM == HMM_STUDENT_T) {
-        R d = y - k.c0;
-        R q = k.c1 * d * d;
-        R u = k.c4 * frcp((R)1 + q);
+        R d = y - (R)k.c0;
+        R q = (R)k.c1 * d * d;
+        R u = (R)k.c4 * frcp((R)1 + q);
         R gu = g * u;
         acc[0] += gu;
         acc[1] = fma(gu, d, acc[1]);

@@ -25,6 +25,7 @@ struct StagedModel {
     const R *lpi;       // [N]      log pi in R
     const R *lA;        // [N*N]    log A in R
     const R *ep;        // [N*EP_STRIDE] emission constants
+    const double *ep64; // the same constants in FP64 (families evaluated in FP64)
     const R *mv;        // multivariate constants: diag [mu(N*D), -1/(2 var)(N*D)],
                         // full [mu(N*D), Linv(N*D*D)] (Linv lower, row-major)
     const int *perr;    // parameter-domain flag written by the staging kernel

@@ -95,7 +95,8 @@ __global__ __launch_bounds__(BLOCK) void k_chunk_product(ChunkGeom g, StagedMode
     }
     const int nmax = wave_max_i(nsteps);
     const bool live = lj < N;
-    const StateConsts<R> k = load_consts(m.ep, lj, live);
+    using ET = typename EmitTraits<FAM, R>::T;
+    const StateConsts<ET> k = load_consts(consts_ptr<FAM, R>(m), lj, live);
 
     // emissions of the chunk: row group li takes steps ts + li, ts + li + G, ...
     double msum = 0.0;
@@ -104,9 +105,9 @@ __global__ __launch_bounds__(BLOCK) void k_chunk_product(ChunkGeom g, StagedMode
         const int tt = base + li;
         const bool act = tt < nsteps;
         R v = act ? load_step<FAM, R>(g.obs, off + ts + tt, lj, N, live) : (R)1;
-        Emit<R> em = emit_step<FAM, R>(v, k, live);
-        R mx = grp_max<G, R>(em.ell);
-        R e = (em.ell == neg_inf<R>()) ? (R)0 : fexp_e(em.ell - mx);
+        Emit<ET> em = emit_step<FAM, ET>((ET)v, k, live);
+        ET mx = grp_max<G, ET>(em.ell);
+        R e = (em.ell == neg_inf<ET>()) ? (R)0 : fexp_e((R)(em.ell - mx));
         bool gbad = grp_max_i<G>((act && em.bad) ? 1 : 0) > 0;
         if (act) {
             esh[slot][tt][lj] = e;
@@ -174,11 +175,12 @@ __global__ __launch_bounds__(BLOCK) void k_chunk_scan(ChunkGeom g, StagedModel<R
 
     if (blockIdx.y == 0) {
         // forward: alpha_0 = pi o e_0, then alpha_{end(c)} = alpha_{end(c-1)} P_c
-        const StateConsts<R> k = load_consts(m.ep, p, live);
+        using ET = typename EmitTraits<FAM, R>::T;
+        const StateConsts<ET> k = load_consts(consts_ptr<FAM, R>(m), p, live);
         R v0 = valid ? load_step<FAM, R>(g.obs, off, p, N, live) : (R)1;
-        Emit<R> em = emit_step<FAM, R>(v0, k, live);
-        R mx = grp_max<G, R>(em.ell);
-        R e = (em.ell == neg_inf<R>()) ? (R)0 : fexp_e(em.ell - mx);
+        Emit<ET> em = emit_step<FAM, ET>((ET)v0, k, live);
+        ET mx = grp_max<G, ET>(em.ell);
+        R e = (em.ell == neg_inf<ET>()) ? (R)0 : fexp_e((R)(em.ell - mx));
         R f = (live ? m.pi[p] : (R)0) * e;
         double logS = (double)mx + em.common;
         bool bad = grp_max_i<G>(em.bad ? 1 : 0) > 0;
@@ -269,7 +271,8 @@ __global__ __launch_bounds__(BLOCK) void k_chunk_stats(ChunkGeom g, StagedModel<
     const int sub = lane / G, p = lane % G, grp = wave * GPW + sub;
     const int N = m.N;
     const bool live = p < N;
-    const StateConsts<R> k = load_consts(m.ep, p, live);
+    using ET = typename EmitTraits<FAM, R>::T;
+    const StateConsts<ET> k = load_consts(consts_ptr<FAM, R>(m), p, live);
     R coefC[G], coefR[G];
 #pragma unroll
     for (int q = 0; q < G; ++q) {
@@ -309,10 +312,10 @@ __global__ __launch_bounds__(BLOCK) void k_chunk_stats(ChunkGeom g, StagedModel<
         for (int tt = 0; tt < L; ++tt) {
             const bool act = valid && tt >= tt0;
             R v = act ? load_step<FAM, R>(g.obs, off + t0 + (tt - tt0), p, N, live) : (R)1;
-            Emit<R> em = emit_step<FAM, R>(v, k, live);
-            R mx = grp_max<G, R>(em.ell);
+            Emit<ET> em = emit_step<FAM, ET>((ET)v, k, live);
+            ET mx = grp_max<G, ET>(em.ell);
             y[tt] = v;
-            e[tt] = (act && em.ell != neg_inf<R>()) ? fexp_e(em.ell - mx) : (R)0;
+            e[tt] = (act && em.ell != neg_inf<ET>()) ? fexp_e((R)(em.ell - mx)) : (R)0;
         }
         const R ap = (valid && !first) ? Fi[(size_t)(c - 1) * G + p] : (R)0;
 

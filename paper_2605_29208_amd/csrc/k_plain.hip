@@ -13,23 +13,31 @@
 
 namespace hmmk {
 
-// log b_j(y_t) without the state-independent part, for any family (runtime).
+// log b_j(y_t) without the state-independent part, for any family (runtime),
+// returned in FP64.  Poisson is evaluated from the FP64 constants (its values
+// are of the size of y log lambda); the other families in R.
 template <typename R>
-__device__ R emission_any(const StagedModel<R> &m, const ObsRef &o, int64_t row, int j,
-                          double *common, bool *bad) {
+__device__ double emission_any(const StagedModel<R> &m, const ObsRef &o, int64_t row, int j,
+                               double *common, bool *bad) {
     const int N = m.N, D = m.D;
     switch (m.family) {
     case HMM_GAUSSIAN:
     case HMM_GAMMA:
-    case HMM_STUDENT_T:
-    case HMM_POISSON: {
+    case HMM_STUDENT_T: {
         R y = load_obs<R>(o, row);
         StateConsts<R> k = load_consts(m.ep, j, true);
         Emit<R> e;
         if (m.family == HMM_GAUSSIAN) e = emit_scalar<HMM_GAUSSIAN, R>(y, k, true);
         else if (m.family == HMM_GAMMA) e = emit_scalar<HMM_GAMMA, R>(y, k, true);
-        else if (m.family == HMM_STUDENT_T) e = emit_scalar<HMM_STUDENT_T, R>(y, k, true);
-        else e = emit_scalar<HMM_POISSON, R>(y, k, true);
+        else e = emit_scalar<HMM_STUDENT_T, R>(y, k, true);
+        *common = e.common;
+        *bad = e.bad;
+        return (double)e.ell;
+    }
+    case HMM_POISSON: {
+        double y = load_obs<double>(o, row);
+        StateConsts<double> k = load_consts(m.ep64, j, true);
+        Emit<double> e = emit_scalar<HMM_POISSON, double>(y, k, true);
         *common = e.common;
         *bad = e.bad;
         return e.ell;
@@ -45,7 +53,7 @@ __device__ R emission_any(const StagedModel<R> &m, const ObsRef &o, int64_t row,
         }
         *common = 0.0;
         *bad = b;
-        return s;
+        return (double)s;
     }
     case HMM_FULL_GAUSSIAN: {
         const R *mu = m.mv + (size_t)j * D;
@@ -63,13 +71,13 @@ __device__ R emission_any(const StagedModel<R> &m, const ObsRef &o, int64_t row,
         for (int c = 0; c < D; ++c) b |= !isfinite(load_obs<R>(o, row * D + c));
         *common = 0.0;
         *bad = b;
-        return m.ep[j * EP_STRIDE] - (R)0.5 * q;
+        return (double)(m.ep[j * EP_STRIDE] - (R)0.5 * q);
     }
     default: {   // table
         R v = load_obs<R>(o, row * N + j);
         *common = 0.0;
         *bad = isnan(v) || (v > (R)0 && isinf(v));
-        return v;
+        return (double)v;
     }
     }
 }
@@ -84,9 +92,8 @@ __global__ __launch_bounds__(BLOCK) void k_emission_table(StagedModel<R> m, ObsR
     const int j = (int)(idx % m.N);
     double common;
     bool bad;
-    R v = emission_any<R>(m, o, row, j, &common, &bad);
-    double full = (double)v + common;
-    out[idx] = bad ? (R)__builtin_nan("") : (R)full;
+    double v = emission_any<R>(m, o, row, j, &common, &bad);
+    out[idx] = bad ? (R)__builtin_nan("") : (R)(v + common);
 }
 
 template <typename R>
@@ -117,13 +124,19 @@ __global__ __launch_bounds__(64) void k_plain_emission(StagedModel<R> m, ObsRef 
     double cs = 0.0;
     bool badany = false;
     for (int64_t t = 0; t < T; ++t) {
-        double common = 0.0;
+        // store log b shifted by its per-step maximum; the shift joins the FP64 offset
+        double common = 0.0, mx = -__builtin_inf();
         for (int j = 0; j < N; ++j) {
             bool bad;
-            logB[(off + t) * N + j] = emission_any<R>(m, o, off + t, j, &common, &bad);
+            mx = fmax(mx, emission_any<R>(m, o, off + t, j, &common, &bad));
             badany |= bad;
         }
-        cs += common;
+        for (int j = 0; j < N; ++j) {
+            bool bad;
+            double v = emission_any<R>(m, o, off + t, j, &common, &bad);
+            logB[(off + t) * N + j] = (mx == -__builtin_inf()) ? (R)v : (R)(v - mx);
+        }
+        cs += common + ((mx == -__builtin_inf()) ? 0.0 : mx);
     }
     comsum[b] = cs;
     status[b] = *m.perr ? 4 : (badany ? 2 : 0);

@@ -19,7 +19,7 @@ size_t staged_bytes(int N, int D, int family, bool f64) {
     size_t r = f64 ? 8 : 4;
     size_t n = (size_t)N, nn = n * n;
     return align256(n * r) * 2 + align256(nn * r) * 2 + align256(n * EP_STRIDE * r) +
-           align256(mv_count(N, D, family) * r + r) + 256;
+           align256(n * EP_STRIDE * 8) + align256(mv_count(N, D, family) * r + r) + 256;
 }
 
 // One block.  Computes linear and log probabilities in R, the per-state
@@ -27,7 +27,7 @@ size_t staged_bytes(int N, int D, int family, bool f64) {
 // multivariate families, the location vectors and -1/(2 var) or L^{-1}.
 template <typename R>
 __global__ __launch_bounds__(BLOCK) void k_stage(RawModel m, R *pi, R *A, R *lpi, R *lA, R *ep,
-                                                 R *mv, int *perr) {
+                                                 double *ep64, R *mv, int *perr) {
     const int N = m.N, D = m.D;
     int bad = 0;
     for (int j = threadIdx.x; j < N; j += blockDim.x) {
@@ -116,7 +116,10 @@ __global__ __launch_bounds__(BLOCK) void k_stage(RawModel m, R *pi, R *A, R *lpi
         default:
             break;
         }
-        for (int k = 0; k < EP_STRIDE; ++k) ep[j * EP_STRIDE + k] = (R)c[k];
+        for (int k = 0; k < EP_STRIDE; ++k) {
+            ep[j * EP_STRIDE + k] = (R)c[k];
+            ep64[j * EP_STRIDE + k] = c[k];
+        }
     }
     int any = __syncthreads_or(bad);
     if (threadIdx.x == 0) *perr = any;
@@ -132,11 +135,13 @@ void launch_stage(const RawModel &m, void *region, StagedModel<R> *out, hipStrea
     R *A = (R *)p; p += align256(nn * r);
     R *lA = (R *)p; p += align256(nn * r);
     R *ep = (R *)p; p += align256(n * EP_STRIDE * r);
+    double *ep64 = (double *)p; p += align256(n * EP_STRIDE * 8);
     R *mv = (R *)p; p += align256(mv_count(m.N, m.D, m.family) * r + r);
     int *perr = (int *)p;
     {
         ProfScope ps("stage", s);
-        hipLaunchKernelGGL(k_stage<R>, dim3(1), dim3(BLOCK), 0, s, m, pi, A, lpi, lA, ep, mv, perr);
+        hipLaunchKernelGGL(k_stage<R>, dim3(1), dim3(BLOCK), 0, s, m, pi, A, lpi, lA, ep, ep64, mv,
+                           perr);
     }
     out->N = m.N;
     out->D = m.D;
@@ -146,6 +151,7 @@ void launch_stage(const RawModel &m, void *region, StagedModel<R> *out, hipStrea
     out->lpi = lpi;
     out->lA = lA;
     out->ep = ep;
+    out->ep64 = ep64;
     out->mv = mv;
     out->perr = perr;
 }

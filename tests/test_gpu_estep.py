@@ -12,7 +12,7 @@ import torch  # noqa: F401  (imported at collection, outside the per-test time l
 
 import oracle
 import workloads
-from tests.parity import TOL, assert_loglik_close, assert_stats_close, family_k
+from tests.parity import TOL, assert_loglik_close, assert_stats_close
 
 pytestmark = pytest.mark.gpu
 
@@ -52,7 +52,7 @@ def test_config1_estep(h, prec):
     stats, ll, st = run_estep(h, w, prec, m0)
     assert list(st) == [0]
     assert_loglik_close(ll, ref["loglik"], TOL[prec], f"config1 {prec}")
-    assert_stats_close(stats, ref["stats"], 3, 2, TOL[prec], f"config1 {prec}")
+    assert_stats_close(stats, ref["stats"], 3, "gaussian", TOL[prec], f"config1 {prec}")
 
 
 LENGTHS = [1, 2, 15, 16, 17, 31, 32, 33, 64, 65, 100, 257, 500]
@@ -67,7 +67,7 @@ def test_batched_families_ragged(h, fam, n, prec):
     stats, ll, st = run_estep(h, w, prec)
     assert np.array_equal(st, ref["status"])
     assert_loglik_close(ll, ref["loglik"], TOL[prec], f"{fam} N={n} {prec}")
-    assert_stats_close(stats, ref["stats"], n, family_k(fam), TOL[prec], f"{fam} N={n} {prec}")
+    assert_stats_close(stats, ref["stats"], n, fam, TOL[prec], f"{fam} N={n} {prec}")
 
 
 @pytest.mark.parametrize("fam,n,d", [("gaussian", 3, 1), ("gamma", 8, 1), ("student_t", 5, 1),
@@ -80,7 +80,7 @@ def test_plain_families(h, fam, n, d, prec):
     stats, ll, st = run_estep(h, w, prec)
     assert np.array_equal(st, ref["status"])
     assert_loglik_close(ll, ref["loglik"], TOL[prec], f"plain {fam} {prec}")
-    assert_stats_close(stats, ref["stats"], n, family_k(fam, d), TOL[prec], f"plain {fam} {prec}")
+    assert_stats_close(stats, ref["stats"], n, fam, TOL[prec], f"plain {fam} {prec}", d=d)
 
 
 @pytest.mark.parametrize("chunk", [16, 32])
@@ -94,7 +94,7 @@ def test_chunk_length_setting(h, chunk, prec):
     finally:
         h.hmm_set_chunk_len(0)
     assert_loglik_close(ll, ref["loglik"], TOL[prec], f"L={chunk}")
-    assert_stats_close(stats, ref["stats"], 8, 3, TOL[prec], f"L={chunk}")
+    assert_stats_close(stats, ref["stats"], 8, "gamma", TOL[prec], f"L={chunk}")
 
 
 @pytest.mark.parametrize("prec", ["f32", "f64", "plain_f32"])
@@ -104,7 +104,7 @@ def test_config2_subset(h, prec):
     stats, ll, st = run_estep(h, w, prec)
     assert (st == 0).all()
     assert_loglik_close(ll, ref["loglik"], TOL[prec], f"config2 subset {prec}")
-    assert_stats_close(stats, ref["stats"], 8, 3, TOL[prec], f"config2 subset {prec}")
+    assert_stats_close(stats, ref["stats"], 8, "gamma", TOL[prec], f"config2 subset {prec}")
 
 
 def test_config2_full_size(h):
@@ -129,7 +129,7 @@ def test_config2_full_size(h):
     # the FP64 batched path agrees with the FP32 one on every pooled statistic
     s64, ll64, _ = run_estep(h, w, "f64")
     assert_loglik_close(ll, ll64, TOL["f32"], "config2 f32 vs f64")
-    assert_stats_close(stats, s64, N, 3, TOL["f32"], "config2 f32 vs f64")
+    assert_stats_close(stats, s64, N, "gamma", TOL["f32"], "config2 f32 vs f64")
 
 
 def test_status_codes_and_exclusion(h):
@@ -142,7 +142,7 @@ def test_status_codes_and_exclusion(h):
         stats, ll, st = run_estep(h, w, prec, obs=obs)
         assert list(st) == list(ref["status"]) == [0, 2, 1, 0], (prec, st)
         assert ll[2] == -np.inf and np.isnan(ll[1])
-        assert_stats_close(stats, ref["stats"], 4, 3, TOL[prec], f"status {prec}")
+        assert_stats_close(stats, ref["stats"], 4, "gamma", TOL[prec], f"status {prec}")
 
 
 def test_parameter_domain_error(h):
