@@ -111,7 +111,9 @@ struct Plan {
     bool f64 = false, plain = false, chunked = false;
     int G = 0, L = 0, C = 0, nblk = 0;
     int64_t S = 0;
-    size_t staged = 0, cbase = 0, P = 0, rexp = 0, clog = 0, F = 0, Gb = 0, partial = 0;
+    size_t staged = 0, cbase = 0, frec = 0, brec = 0, F = 0, Gb = 0, partial = 0;
+    int SS = 16, SC = 0;   // chunks per superchunk, number of superchunks
+    size_t sbase = 0, sfrec = 0, sbrec = 0, Fs = 0, Gs = 0, cdesc = 0, sdesc = 0;
     size_t ll = 0, st = 0, gam = 0;
     size_t logB = 0, alpha = 0, beta = 0, ps = 0;
     size_t total = 0;
@@ -119,7 +121,7 @@ struct Plan {
 
 int default_chunk_len(bool f64) {
     int v = g_chunk_len.load();
-    if (v == 0) return f64 ? 16 : 32;
+    if (v == 0) return 16;
     if (f64 && v > 32) return 32;
     return v;
 }
@@ -166,23 +168,33 @@ hmm_status make_plan(hmm_op op, const Checked &c, hmm_precision prec, Plan *p) {
         p->chunked = true;
         p->G = N <= 4 ? 4 : 8;
         p->L = default_chunk_len(p->f64);
-        int64_t C = 0;
+        int64_t C = 0, SC = 0;
         for (int64_t b = 0; b < c.B; ++b) {
             int64_t T = c.h_off[b + 1] - c.h_off[b];
-            C += (T + p->L - 1) / p->L;
+            int64_t nc = (T + p->L - 1) / p->L;
+            C += nc;
+            SC += (nc + p->SS - 1) / p->SS;
         }
+        p->SC = (int)SC;
         if (C > INT32_MAX / 64) return fail(HMM_ERR_UNSUPPORTED, "too many chunks");
         p->C = (int)C;
         const int gpb = (BLOCK / 64) * (64 / p->G);
         int64_t nb = (C + gpb - 1) / gpb;
         p->nblk = (int)(nb < 1 ? 1 : (nb > 2048 ? 2048 : nb));
         p->cbase = take((size_t)(c.B + 1) * 4);
-        p->P = take((size_t)C * p->G * p->G * r);
-        p->rexp = take((size_t)C * p->G * 4);
-        p->clog = take((size_t)C * 8);
-        p->F = take((size_t)C * p->G * r);
-        p->Gb = take((size_t)C * p->G * r);
+        p->frec = take((size_t)C * p->G * chunk_rec_bytes(p->f64, p->G));
+        p->brec = take((size_t)C * p->G * chunk_rec_bytes(p->f64, p->G));
+        p->F = take((size_t)(C + 1) * p->G * r);    // + one sink slot
+        p->Gb = take((size_t)(C + 1) * p->G * r);
         p->partial = take((size_t)p->nblk * p->S * 8);
+        const size_t rb = chunk_rec_bytes(p->f64, p->G);
+        p->sbase = take((size_t)(c.B + 1) * 4);
+        p->cdesc = take((size_t)C * sizeof(ChunkDesc));
+        p->sdesc = take((size_t)SC * sizeof(SuperDesc));
+        p->sfrec = take((size_t)SC * p->G * rb);
+        p->sbrec = take((size_t)SC * p->G * rb);
+        p->Fs = take((size_t)(SC + 1) * p->G * r);
+        p->Gs = take((size_t)(SC + 1) * p->G * r);
     }
     p->total = off;
     return HMM_OK;
@@ -231,13 +243,23 @@ hmm_status run_posterior_path(const hmm_model *m, const hmm_batch *b, const Chec
         cb.G = p.G;
         cb.nblk_stats = p.nblk;
         cb.cbase = (int *)(ws + p.cbase);
-        cb.P = ws + p.P;
-        cb.rexp = (int *)(ws + p.rexp);
-        cb.clog = (double *)(ws + p.clog);
+        cb.fwdrec = ws + p.frec;
+        cb.bwdrec = ws + p.brec;
         cb.F = ws + p.F;
         cb.Gb = ws + p.Gb;
         cb.partial = (double *)(ws + p.partial);
-        launch_plan_chunks(b->offsets, c.B, p.L, cb.cbase, s);
+        cb.S = p.SS;
+        cb.SC = p.SC;
+        cb.sbase = (int *)(ws + p.sbase);
+        cb.sfwdrec = ws + p.sfrec;
+        cb.sbwdrec = ws + p.sbrec;
+        cb.Fs = ws + p.Fs;
+        cb.Gs = ws + p.Gs;
+        cb.cdesc = (ChunkDesc *)(ws + p.cdesc);
+        cb.sdesc = (SuperDesc *)(ws + p.sdesc);
+        launch_plan_chunks(b->offsets, c.B, p.L, p.SS, cb.cbase, cb.sbase, s);
+        launch_chunk_desc(b->offsets, c.B, p.L, p.SS, cb.cbase, cb.sbase, p.C, p.SC, cb.cdesc,
+                          cb.sdesc, s);
         r = run_chunked<R>(sm, od, cb, ll, st, gamma_out, stats, p.S, s);
     }
     if (r != HMM_OK) return fail(r, "unsupported configuration");

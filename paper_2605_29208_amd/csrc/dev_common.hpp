@@ -111,6 +111,21 @@ __device__ __forceinline__ R grp_sum(R v) {
     if constexpr (G == 8) v = v + dpp_v<DPP_HALF_MIRROR>(v);
     return v;
 }
+// maximum of non-negative values: for IEEE floats >= 0 the bit patterns order
+// like the values, so an unsigned integer maximum needs no NaN canonicalisation
+template <int G>
+__device__ __forceinline__ float grp_max_pos(float v) {
+    unsigned u = __builtin_bit_cast(unsigned, v);
+    u = max(u, (unsigned)dpp_i<DPP_QP_X1>((int)u));
+    u = max(u, (unsigned)dpp_i<DPP_QP_X2>((int)u));
+    if constexpr (G == 8) u = max(u, (unsigned)dpp_i<DPP_HALF_MIRROR>((int)u));
+    return __builtin_bit_cast(float, u);
+}
+template <int G>
+__device__ __forceinline__ double grp_max_pos(double v) {
+    return grp_max<G, double>(v);
+}
+
 template <int G>
 __device__ __forceinline__ int grp_max_i(int v) {
     v = max(v, dpp_i<DPP_QP_X1>(v));
@@ -253,8 +268,10 @@ __host__ __device__ constexpr int fam_k() {
 }
 
 // acc[k] += g * term_k(y) for one state (compile-time family)
+// ly = log y (used by the Gamma family only)
 template <int FAM, typename R, int K, typename KT>
-__device__ __forceinline__ void fam_accumulate(R g, R y, const StateConsts<KT> &k, R (&acc)[K]) {
+__device__ __forceinline__ void fam_accumulate(R g, R y, R ly, const StateConsts<KT> &k,
+                                               R (&acc)[K]) {
     if constexpr (FAM == HMM_GAUSSIAN) {
         R d = y - (R)k.c0;
         R gd = g * d;
@@ -263,7 +280,7 @@ __device__ __forceinline__ void fam_accumulate(R g, R y, const StateConsts<KT> &
     } else if constexpr (FAM == HMM_GAMMA) {
         R gy = g * y;
         acc[0] += gy;
-        acc[1] = fma(g, flog(y), acc[1]);
+        acc[1] = fma(g, ly, acc[1]);
         acc[2] = fma(gy, y, acc[2]);
     } else if constexpr (FAM == HMM_STUDENT_T) {
         R d = y - (R)k.c0;

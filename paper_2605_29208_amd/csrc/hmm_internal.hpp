@@ -29,6 +29,8 @@ struct StagedModel {
     const R *mv;        // multivariate constants: diag [mu(N*D), -1/(2 var)(N*D)],
                         // full [mu(N*D), Linv(N*D*D)] (Linv lower, row-major)
     const int *perr;    // parameter-domain flag written by the staging kernel
+    const R *A8;        // [8*8] exp(log A) zero-padded to 8 states (small-N kernels)
+    const int *nrm;     // steps between rescalings of forward-type products (1, 2 or 4)
 };
 
 // Raw (not yet staged) model, FP64 device pointers from the ABI.
@@ -61,19 +63,53 @@ size_t staged_bytes(int N, int D, int family, bool f64);
 template <typename R>
 void launch_stage(const RawModel &m, void *region, StagedModel<R> *out, hipStream_t s);
 
-void launch_plan_chunks(const int64_t *offsets, int64_t nseq, int L, int *cbase, hipStream_t s);
+// Per-chunk and per-superchunk descriptors, written once per call so the
+// kernels find their sequence with a single load.
+struct __align__(16) ChunkDesc {
+    int64_t off;    // first observation row of the owning sequence
+    int b;          // owning sequence
+    int t0;         // first step of the chunk inside the sequence
+    int len;        // steps in the chunk (<= L)
+    int pad0;
+    int64_t pad1;
+};
+struct __align__(16) SuperDesc {
+    int64_t off;    // first observation row of the owning sequence
+    int b;          // owning sequence
+    int lo;         // first chunk of the superchunk
+    int n;          // chunks in the superchunk (<= S)
+    int head;       // 1 if it is the sequence's first superchunk
+    int64_t pad;
+};
+void launch_chunk_desc(const int64_t *offsets, int64_t nseq, int L, int S, const int *cbase,
+                       const int *sbase, int C, int SC, ChunkDesc *cdesc, SuperDesc *sdesc,
+                       hipStream_t s);
+
+// cbase[b] = chunks before sequence b (L steps each); sbase[b] = superchunks
+// (S chunks each) before sequence b; both [B+1]
+void launch_plan_chunks(const int64_t *offsets, int64_t nseq, int L, int S, int *cbase,
+                        int *sbase, hipStream_t s);
 
 // batched small-N path (G = 4 or 8 lanes per chunk)
 struct ChunkBuffers {
     int L, C, G, nblk_stats;
+    int S, SC;           // chunks per superchunk, number of superchunks
     int *cbase;          // [B+1]
-    void *P;             // [C*G*G] R
-    int *rexp;           // [C*G]
-    double *clog;        // [C]
+    int *sbase;          // [B+1]
+    ChunkDesc *cdesc;    // [C]
+    SuperDesc *sdesc;    // [SC]
+    void *sfwdrec;       // [SC*G] superchunk records
+    void *sbwdrec;       // [SC*G]
+    void *Fs;            // [SC*G] R  alpha at each superchunk end
+    void *Gs;            // [SC*G] R  beta at each superchunk end
+    void *fwdrec;        // [C*G] records: column of P_c, row exponent, chunk log shift
+    void *bwdrec;        // [C*G] records: row of P_c, row exponent
     void *F;             // [C*G] R  alpha at each chunk end (normalised)
     void *Gb;            // [C*G] R  beta at each chunk end (normalised)
     double *partial;     // [nblk_stats * S]
 };
+// bytes of one transfer-matrix record (see k_chunk.hip)
+size_t chunk_rec_bytes(bool f64, int G);
 template <typename R>
 hmm_status run_chunked(const StagedModel<R> &m, const ObsDesc &o, const ChunkBuffers &cb,
                        double *loglik, int32_t *status, void *gamma_out, double *stats,

@@ -33,12 +33,12 @@ struct ChunkGeom {
     int64_t nseq;
     const int64_t *offsets;
     const int *cbase;
+    const ChunkDesc *cdesc;
     int L;
     int C;
     ObsRef obs;
 };
 
-constexpr int LMAX = 64;
 constexpr int NEG_EXP = INT_MIN / 4;
 
 // one observation (scalar families) or one log b_j entry (table family)
@@ -64,196 +64,460 @@ __device__ __forceinline__ Emit<R> emit_step(R v, const StateConsts<R> &k, bool 
     }
 }
 
-// ---------------------------------------------------------------- phase 1
-template <typename R, int G, int FAM>
-__global__ __launch_bounds__(BLOCK) void k_chunk_product(ChunkGeom g, StagedModel<R> m,
-                                                         R *__restrict__ Pout,
-                                                         int *__restrict__ rexp,
-                                                         double *__restrict__ clog) {
-    constexpr int GG = G * G;
-    constexpr int CPW = 64 / GG;
-    constexpr int CPB = (BLOCK / 64) * CPW;
-    __shared__ R esh[CPB][LMAX][G];
-    __shared__ double msh[CPB][G];
+// Transfer-matrix records read by the boundary scan.  Lane p of a sequence
+// reads one record per chunk with a few 16-byte loads:
+//   FwdRec (forward scan, lane = column p): coef[k] = P_c[src(p,k)][p],
+//          r = binary exponent of row p, clog = the chunk's summed log shifts;
+//   BwdRec (backward scan, lane = row p):   coef[k] = P_c[p][src(p,k)], r as above.
+template <typename R, int G>
+struct __align__(16) FwdRec {
+    R coef[G];
+    int r;
+    int pad;
+    double clog;
+};
+template <typename R, int G>
+struct __align__(16) BwdRec {
+    R coef[G];
+    int r;
+    int pad;
+    double clog;
+};
 
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int sub = lane / GG, li = (lane % GG) / G, lj = lane % G;
-    const int slot = wave * CPW + sub;
+size_t chunk_rec_bytes(bool f64, int G) {
+    size_t a = f64 ? (G == 8 ? sizeof(FwdRec<double, 8>) : sizeof(FwdRec<double, 4>))
+                   : (G == 8 ? sizeof(FwdRec<float, 8>) : sizeof(FwdRec<float, 4>));
+    size_t b = f64 ? (G == 8 ? sizeof(BwdRec<double, 8>) : sizeof(BwdRec<double, 4>))
+                   : (G == 8 ? sizeof(BwdRec<float, 8>) : sizeof(BwdRec<float, 4>));
+    return a > b ? a : b;
+}
+
+// ---------------------------------------------------------------- phase 1
+// One lane per row of a chunk's transfer matrix (G lanes per chunk): the
+// lane keeps its row in registers and multiplies it by A diag(e_t) with A
+// uniform across the block, so the product needs no lane exchange at all.
+// The chunk's emissions e_t(j) are first tabulated in LDS, lane i taking the
+// steps i, i + G, ... (all states of a step in one lane, so the per-step
+// maximum is a local reduction).
+template <typename R, int G, int L, int FAM>
+__global__ __launch_bounds__(BLOCK) void k_chunk_product(ChunkGeom g, StagedModel<R> m,
+                                                         const R *__restrict__ A8,
+                                                         FwdRec<R, G> *__restrict__ frec,
+                                                         BwdRec<R, G> *__restrict__ brec) {
+    constexpr int CPB = BLOCK / G;   // chunks per block
+    __shared__ R esh[CPB][L][G];
+    __shared__ double msh[CPB][G];
+    __shared__ R psh[CPB][G][G + 1];
+
+    const int li = threadIdx.x % G;
+    const int slot = threadIdx.x / G;
     const int c = blockIdx.x * CPB + slot;
     const bool valid = c < g.C;
     const int N = m.N;
     int64_t off = 0;
     int ts = 0, nsteps = 0;
     if (valid) {
-        int b = find_seq(g.cbase, (int)g.nseq, c);
-        off = g.offsets[b];
-        int T = (int)(g.offsets[b + 1] - off);
-        int t0 = (c - g.cbase[b]) * g.L;
-        int t1 = min(t0 + g.L, T);
-        ts = max(t0, 1);
-        nsteps = max(t1 - ts, 0);
+        const ChunkDesc d = g.cdesc[c];
+        off = d.off;
+        ts = max(d.t0, 1);
+        nsteps = max(d.t0 + d.len - ts, 0);
     }
-    const int nmax = wave_max_i(nsteps);
-    const bool live = lj < N;
     using ET = typename EmitTraits<FAM, R>::T;
-    const StateConsts<ET> k = load_consts(consts_ptr<FAM, R>(m), lj, live);
+    const ET *ep = consts_ptr<FAM, R>(m);
 
-    // emissions of the chunk: row group li takes steps ts + li, ts + li + G, ...
+    // emissions: e_t(j) = exp(log b_j(y_t) - max_j log b_j(y_t))
     double msum = 0.0;
     bool bad = false;
-    for (int base = 0; base < nmax; base += G) {
-        const int tt = base + li;
-        const bool act = tt < nsteps;
-        R v = act ? load_step<FAM, R>(g.obs, off + ts + tt, lj, N, live) : (R)1;
-        Emit<ET> em = emit_step<FAM, ET>((ET)v, k, live);
-        ET mx = grp_max<G, ET>(em.ell);
-        R e = (em.ell == neg_inf<ET>()) ? (R)0 : fexp_e((R)(em.ell - mx));
-        bool gbad = grp_max_i<G>((act && em.bad) ? 1 : 0) > 0;
-        if (act) {
-            esh[slot][tt][lj] = e;
-            msum += (double)mx + em.common;
-            bad |= gbad;
+    for (int tt = li; tt < nsteps; tt += G) {
+        const int64_t row = off + ts + tt;
+        ET ell[G];
+        ET mx = neg_inf<ET>();
+        double common = 0.0;
+#pragma unroll
+        for (int j = 0; j < G; ++j) {
+            const bool live = j < N;
+            R v = load_step<FAM, R>(g.obs, row, j, N, live);
+            StateConsts<ET> k = load_consts(ep, j, live);
+            Emit<ET> em = emit_step<FAM, ET>((ET)v, k, live);
+            ell[j] = em.ell;
+            mx = fmax(mx, em.ell);
+            bad |= em.bad;
+            common = em.common;
         }
+#pragma unroll
+        for (int j = 0; j < G; ++j)
+            esh[slot][tt][j] = (ell[j] == neg_inf<ET>()) ? (R)0 : fexp_e((R)(ell[j] - mx));
+        msum += (double)mx + common;
     }
-    if (lj == 0) msh[slot][li] = bad ? __builtin_nan("") : msum;
+    msh[slot][li] = bad ? __builtin_nan("") : msum;
+    R a[G][G];
+#pragma unroll
+    for (int k = 0; k < G; ++k)
+#pragma unroll
+        for (int j = 0; j < G; ++j) a[k][j] = A8[k * 8 + j];
+    const int nrm = *m.nrm;
     __syncthreads();
 
-    R coef[G];
+    R rowv[G];
 #pragma unroll
-    for (int q = 0; q < G; ++q) {
-        int i = grp_src(lj, q);
-        coef[q] = (live && i < N) ? m.A[i * N + lj] : (R)0;
-    }
-    R P = (li == lj && live) ? (R)1 : (R)0;
+    for (int j = 0; j < G; ++j) rowv[j] = (j == li && li < N) ? (R)1 : (R)0;
     int r = 0;
-    for (int s = 0; s < nmax; ++s) {
-        const bool act = s < nsteps;
-        R e = esh[slot][act ? s : 0][lj];
-        R v = grp_dot<G, R>(P, coef) * e;
-        int ex = fexp(grp_max<G, R>(v));
-        v = fldexp(v, -ex);
-        if (act) {
-            P = v;
-            r += ex;
+    for (int s = 0; s < nsteps; ++s) {
+        R e[G];
+#pragma unroll
+        for (int j = 0; j < G; ++j) e[j] = esh[slot][s][j];
+        R nv[G];
+#pragma unroll
+        for (int j = 0; j < G; ++j) {
+            R acc = rowv[0] * a[0][j];
+#pragma unroll
+            for (int k = 1; k < G; ++k) acc = fma(rowv[k], a[k][j], acc);
+            nv[j] = acc * e[j];
         }
+        const bool rescale = ((s + 1) % nrm == 0) || (s + 1 == nsteps);
+        int ex = 0;
+        if (rescale) {
+            R mxv = nv[0];
+#pragma unroll
+            for (int j = 1; j < G; ++j) mxv = fmax(mxv, nv[j]);
+            ex = fexp(mxv);
+        }
+#pragma unroll
+        for (int j = 0; j < G; ++j) rowv[j] = rescale ? fldexp(nv[j], -ex) : nv[j];
+        r += ex;
     }
+    // transpose through LDS into the two record layouts
+#pragma unroll
+    for (int j = 0; j < G; ++j) psh[slot][li][j] = rowv[j];
+    __syncthreads();
     if (valid) {
-        Pout[(size_t)c * GG + li * G + lj] = P;
-        if (lj == 0) rexp[(size_t)c * G + li] = r;
-        if (li == 0 && lj == 0) {
-            double t = 0.0;
-            for (int q = 0; q < G; ++q) t += msh[slot][q];
-            clog[c] = t;
+        double cl = 0.0;
+        for (int q = 0; q < G; ++q) cl += msh[slot][q];
+        FwdRec<R, G> f;
+        BwdRec<R, G> bw;
+#pragma unroll
+        for (int k = 0; k < G; ++k) {
+            f.coef[k] = psh[slot][grp_src(li, k)][li];
+            bw.coef[k] = psh[slot][li][grp_src(li, k)];
         }
+        f.r = r;
+        f.pad = 0;
+        f.clog = cl;
+        bw.r = r;
+        bw.pad = 0;
+        bw.clog = cl;
+        frec[(size_t)c * G + li] = f;
+        brec[(size_t)c * G + li] = bw;
+    }
+}
+
+// ---------------------------------------------------------------- phase 1b
+// Products of S consecutive chunk matrices ("superchunks"), one G-lane group
+// per superchunk, lane = row.  Each chunk matrix is scattered into LDS in
+// natural order; the lane then multiplies its row by it, combining the
+// per-row binary exponents exactly.  Output records have the same layout as
+// the chunk records, so the boundary scan below runs on either level.
+template <typename R, int G>
+__global__ __launch_bounds__(BLOCK) void k_super_product(const SuperDesc *__restrict__ sdesc, int SC,
+                                                         int S, const FwdRec<R, G> *__restrict__ frec,
+                                                         const BwdRec<R, G> *__restrict__ brec,
+                                                         FwdRec<R, G> *__restrict__ sfrec,
+                                                         BwdRec<R, G> *__restrict__ sbrec) {
+    constexpr int GPB = BLOCK / G;
+    __shared__ R psh[GPB][G][G + 1];
+    __shared__ int rsh[GPB][G];
+    __shared__ double csh[GPB];
+    const int li = threadIdx.x % G;
+    const int slot = threadIdx.x / G;
+    const int k = blockIdx.x * GPB + slot;
+    const bool valid = k < SC;
+    int c0 = 0, nc = 0;
+    if (valid) {
+        const SuperDesc d = sdesc[k];
+        c0 = d.lo;
+        nc = d.n;
+    }
+    R rv[G];
+#pragma unroll
+    for (int j = 0; j < G; ++j) rv[j] = (R)0;
+    int E = 0;
+    double cl = 0.0;
+    // records are loaded one chunk ahead; indices are clamped into the
+    // superchunk so every load is in bounds and unconditional
+    constexpr int PFS = 4;
+    const int last = valid ? c0 + nc - 1 : 0;
+    BwdRec<R, G> ring[PFS];
+#pragma unroll
+    for (int q = 0; q < PFS; ++q) ring[q] = brec[(size_t)min(c0 + q, last) * G + li];
+    for (int it = 0; it < S; ++it) {
+        const bool act = valid && it < nc;
+        BwdRec<R, G> rec = ring[0];
+#pragma unroll
+        for (int q = 0; q + 1 < PFS; ++q) ring[q] = ring[q + 1];
+        ring[PFS - 1] = brec[(size_t)min(c0 + it + PFS, last) * G + li];
+        if (act) {
+#pragma unroll
+            for (int q = 0; q < G; ++q) psh[slot][li][grp_src(li, q)] = rec.coef[q];
+            rsh[slot][li] = rec.r;
+            cl += rec.clog;
+        }
+        __syncthreads();
+        if (act) {
+            if (it == 0) {
+#pragma unroll
+                for (int j = 0; j < G; ++j) rv[j] = psh[slot][li][j];
+                E = rsh[slot][li];
+            } else {
+                int Rm = NEG_EXP;
+#pragma unroll
+                for (int q = 0; q < G; ++q)
+                    if (rv[q] > (R)0) Rm = max(Rm, fexp(rv[q]) + rsh[slot][q]);
+                if (Rm != NEG_EXP) {
+                    R nv[G];
+#pragma unroll
+                    for (int j = 0; j < G; ++j) nv[j] = (R)0;
+#pragma unroll
+                    for (int q = 0; q < G; ++q) {
+                        R wq = (rv[q] > (R)0) ? fldexp(rv[q], rsh[slot][q] - Rm) : (R)0;
+#pragma unroll
+                        for (int j = 0; j < G; ++j) nv[j] = fma(wq, psh[slot][q][j], nv[j]);
+                    }
+                    R mx = nv[0];
+#pragma unroll
+                    for (int j = 1; j < G; ++j) mx = fmax(mx, nv[j]);
+                    const int ex = fexp(mx);
+#pragma unroll
+                    for (int j = 0; j < G; ++j) rv[j] = fldexp(nv[j], -ex);
+                    E += Rm + ex;
+                }
+            }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int j = 0; j < G; ++j) psh[slot][li][j] = rv[j];
+    if (li == 0) csh[slot] = cl;
+    __syncthreads();
+    if (valid) {
+        FwdRec<R, G> f;
+        BwdRec<R, G> bw;
+#pragma unroll
+        for (int q = 0; q < G; ++q) {
+            f.coef[q] = psh[slot][grp_src(li, q)][li];
+            bw.coef[q] = psh[slot][li][grp_src(li, q)];
+        }
+        f.r = E;
+        f.pad = 0;
+        f.clog = csh[slot];
+        bw.r = E;
+        bw.pad = 0;
+        bw.clog = csh[slot];
+        sfrec[(size_t)k * G + li] = f;
+        sbrec[(size_t)k * G + li] = bw;
     }
 }
 
 // ---------------------------------------------------------------- phase 2
+// Serial scans over records, G lanes per segment.  EXPAND = false: a segment
+// is a sequence and the records are its superchunks (boundary vectors at
+// superchunk ends, log-likelihood, status).  EXPAND = true: a segment is a
+// superchunk and the records are its chunks, started from the superchunk
+// boundaries found by the first pass.  The records of the next PF steps are
+// kept in flight (software prefetch).
+struct ScanGeom {
+    int64_t nseq;
+    const int64_t *offsets;
+    const int *cbase;    // [B+1] chunks per sequence (prefix)
+    const int *sbase;    // [B+1] superchunks per sequence (prefix)
+    int S;               // chunks per superchunk
+    int SC;              // number of superchunks
+    int C;               // number of chunks
+    const SuperDesc *sdesc;
+    ObsRef obs;
+};
+
+// alpha_0 = pi o e_0 of sequence b, rescaled; returns its log offset and flags
 template <typename R, int G, int FAM>
-__global__ __launch_bounds__(BLOCK) void k_chunk_scan(ChunkGeom g, StagedModel<R> m,
-                                                      const R *__restrict__ P,
-                                                      const int *__restrict__ rexp,
-                                                      const double *__restrict__ clog,
+__device__ __forceinline__ R alpha0(const StagedModel<R> &m, const ObsRef &obs, int64_t off,
+                                    bool valid, int p, double *logS, int *E, bool *bad) {
+    const int N = m.N;
+    const bool live = p < N;
+    using ET = typename EmitTraits<FAM, R>::T;
+    const StateConsts<ET> k = load_consts(consts_ptr<FAM, R>(m), p, live);
+    R v0 = valid ? load_step<FAM, R>(obs, off, p, N, live) : (R)1;
+    Emit<ET> em = emit_step<FAM, ET>((ET)v0, k, live);
+    ET mx = grp_max<G, ET>(em.ell);
+    R e = (em.ell == neg_inf<ET>()) ? (R)0 : fexp_e((R)(em.ell - mx));
+    R f = (live ? m.pi[p] : (R)0) * e;
+    *logS = (double)mx + em.common;
+    *bad = grp_max_i<G>(em.bad ? 1 : 0) > 0;
+    const int ex0 = fexp(grp_max_pos<G>(f));
+    *E = ex0;
+    return fldexp(f, -ex0);
+}
+
+template <typename R, int G, int FAM, int PF, bool EXPAND>
+__global__ __launch_bounds__(BLOCK) void k_chunk_scan(ScanGeom g, StagedModel<R> m,
+                                                      const FwdRec<R, G> *__restrict__ frec,
+                                                      const BwdRec<R, G> *__restrict__ brec,
+                                                      const R *__restrict__ Fs,
+                                                      const R *__restrict__ Gs,
                                                       R *__restrict__ Fo, R *__restrict__ Go,
                                                       double *__restrict__ loglik,
                                                       int32_t *__restrict__ status) {
-    constexpr int GG = G * G, SPW = 64 / G;
+    constexpr int SPW = 64 / G;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int sub = lane / G, p = lane % G;
-    const int64_t b = ((int64_t)blockIdx.x * (BLOCK / 64) + wave) * SPW + sub;
-    const bool valid = b < g.nseq;
-    const int N = m.N;
-    int cb = 0, nch = 0;
-    int64_t off = 0;
+    const int64_t seg = ((int64_t)blockIdx.x * (BLOCK / 64) + wave) * SPW + sub;
+    const bool valid = seg < (EXPAND ? (int64_t)g.SC : g.nseq);
+    const bool live = p < m.N;
+    int lo = 0, n = 0;
+    int64_t b = 0;
+    bool head = true;   // EXPAND: the segment is its sequence's first superchunk
+    // outputs of a lane group past the last segment go to the sink slot after
+    // the last record, so every store is unconditional
+    const int sink = EXPAND ? g.C : g.SC;
     if (valid) {
-        cb = g.cbase[b];
-        nch = g.cbase[b + 1] - cb;
-        off = g.offsets[b];
+        if (EXPAND) {
+            const SuperDesc d = g.sdesc[seg];
+            b = d.b;
+            lo = d.lo;
+            n = d.n;
+            head = d.head != 0;
+        } else {
+            b = seg;
+            lo = g.sbase[b];
+            n = g.sbase[b + 1] - lo;
+        }
     }
-    const int nmax = wave_max_i(nch);
-    const bool live = p < N;
+    const int nmax = wave_max_i(n);
 
     if (blockIdx.y == 0) {
-        // forward: alpha_0 = pi o e_0, then alpha_{end(c)} = alpha_{end(c-1)} P_c
-        using ET = typename EmitTraits<FAM, R>::T;
-        const StateConsts<ET> k = load_consts(consts_ptr<FAM, R>(m), p, live);
-        R v0 = valid ? load_step<FAM, R>(g.obs, off, p, N, live) : (R)1;
-        Emit<ET> em = emit_step<FAM, ET>((ET)v0, k, live);
-        ET mx = grp_max<G, ET>(em.ell);
-        R e = (em.ell == neg_inf<ET>()) ? (R)0 : fexp_e((R)(em.ell - mx));
-        R f = (live ? m.pi[p] : (R)0) * e;
-        double logS = (double)mx + em.common;
-        bool bad = grp_max_i<G>(em.bad ? 1 : 0) > 0;
-        int ex0 = fexp(grp_max<G, R>(f));
-        f = fldexp(f, -ex0);
-        int64_t E = ex0;
-        for (int s = 0; s < nmax; ++s) {
-            const bool act = s < nch;
-            const int c = act ? cb + s : 0;
-            R coef[G];
+        // forward: f <- f P_c over the segment's records
+        double logS = 0.0;
+        int E0 = 0;
+        bool bad = false;
+        const int64_t off = valid ? g.offsets[b] : 0;
+        R f;
+        if (!EXPAND || head) {
+            f = alpha0<R, G, FAM>(m, g.obs, off, valid, p, &logS, &E0, &bad);
+        } else {
+            f = (R)0;
+        }
+        if (EXPAND && !head && valid) f = Fs[(size_t)(seg - 1) * G + p];
+        int64_t E = E0;
+        // loads run PF records ahead with indices clamped into the segment
+        // (always in bounds, so they need no branch and their waits stay exact)
+        const int lastf = lo + max(n - 1, 0);
+        const int64_t fsl = valid ? -1 : (int64_t)sink;   // store slot override
+        FwdRec<R, G> ring[PF];
 #pragma unroll
-            for (int q = 0; q < G; ++q)
-                coef[q] = act ? P[(size_t)c * GG + grp_src(p, q) * G + p] : (R)0;
-            const int rr = act ? rexp[(size_t)c * G + p] : 0;
-            const double cl = act ? clog[c] : 0.0;
-            const int ce = (f > (R)0) ? fexp(f) + rr : NEG_EXP;
-            const int Rm = grp_max_i<G>(ce);
-            R w = (f > (R)0) ? fldexp(f, rr - Rm) : (R)0;
-            R v = grp_dot<G, R>(w, coef);
-            int ev = fexp(grp_max<G, R>(v));
-            v = fldexp(v, -ev);
-            if (act) {
-                f = v;
-                E += (int64_t)Rm + ev;
-                logS += cl;
-                if (valid) Fo[(size_t)c * G + p] = v;
+        for (int q = 0; q < PF; ++q) ring[q] = frec[(size_t)min(lo + q, lastf) * G + p];
+        for (int s0 = 0; s0 < nmax; s0 += PF) {
+#pragma unroll
+            for (int q = 0; q < PF; ++q) {
+                const int s = s0 + q;
+                const bool act = s < n;
+                const FwdRec<R, G> cur = ring[q];
+                ring[q] = frec[(size_t)min(lo + s + PF, lastf) * G + p];
+                const int rr = act ? cur.r : 0;
+                const int ce = (f > (R)0) ? fexp(f) + rr : NEG_EXP;
+                const int Rm = grp_max_i<G>(ce);
+                R w = (f > (R)0 && act) ? fldexp(f, rr - Rm) : (R)0;
+                R coef[G];
+#pragma unroll
+                for (int kk = 0; kk < G; ++kk) coef[kk] = cur.coef[kk];
+                R v = grp_dot<G, R>(w, coef);
+                int ev = fexp(grp_max_pos<G>(v));
+                v = fldexp(v, -ev);
+                if (act) {
+                    f = v;
+                    E += (int64_t)Rm + ev;
+                    logS += cur.clog;
+                }
+                const int64_t slot_f = fsl >= 0 ? fsl : (int64_t)min(lo + s, lastf);
+                Fo[(size_t)slot_f * G + p] = f;
             }
         }
-        R tot = grp_sum<G, R>(f);
-        if (valid && p == 0) {
-            double ll;
-            int st;
-            if (*m.perr) {
-                ll = __builtin_nan("");
-                st = 4;
-            } else if (bad || isnan(logS)) {
-                ll = __builtin_nan("");
-                st = 2;
-            } else if (!(tot > (R)0) || isinf(logS)) {
-                ll = -__builtin_inf();
-                st = 1;
-            } else {
-                ll = logS + (double)E * 0.69314718055994530942 + log((double)tot);
-                st = 0;
+        if (!EXPAND) {
+            R tot = grp_sum<G, R>(f);
+            if (valid && p == 0) {
+                double ll;
+                int st;
+                if (*m.perr) {
+                    ll = __builtin_nan("");
+                    st = 4;
+                } else if (bad || isnan(logS)) {
+                    ll = __builtin_nan("");
+                    st = 2;
+                } else if (!(tot > (R)0) || isinf(logS)) {
+                    ll = -__builtin_inf();
+                    st = 1;
+                } else {
+                    ll = logS + (double)E * 0.69314718055994530942 + log((double)tot);
+                    st = 0;
+                }
+                loglik[b] = ll;
+                status[b] = st;
             }
-            loglik[b] = ll;
-            status[b] = st;
         }
     } else {
-        // backward: beta_{T-1} = 1, beta_{end(c-1)} = P_c beta_{end(c)}
+        // backward: g <- P_c g, from the segment's last record down to its second
         R gv = live ? (R)1 : (R)0;
-        if (valid) Go[(size_t)(cb + nch - 1) * G + p] = gv;
-        for (int s = 0; s + 1 < nmax; ++s) {
-            const bool act = s + 1 < nch;
-            const int c = act ? cb + nch - 1 - s : 0;
-            R coef[G];
+        if (EXPAND && valid) gv = Gs[(size_t)seg * G + p];
+        const int64_t gsl = valid ? -1 : (int64_t)sink;
+        Go[(size_t)(gsl >= 0 ? gsl : (int64_t)(lo + n - 1)) * G + p] = gv;
+        const int nb = n - 1;
+        const int top = lo + max(n - 1, 0);
+        BwdRec<R, G> ring[PF];
 #pragma unroll
-            for (int q = 0; q < G; ++q)
-                coef[q] = act ? P[(size_t)c * GG + p * G + grp_src(p, q)] : (R)0;
-            const int rr = act ? rexp[(size_t)c * G + p] : 0;
-            R v = grp_dot<G, R>(gv, coef);
-            const int ce = (v > (R)0) ? fexp(v) + rr : NEG_EXP;
-            const int Rm = grp_max_i<G>(ce);
-            v = (v > (R)0) ? fldexp(v, rr - Rm) : (R)0;
-            if (act) {
-                gv = v;
-                if (valid) Go[(size_t)(c - 1) * G + p] = v;
+        for (int q = 0; q < PF; ++q) ring[q] = brec[(size_t)max(top - q, lo) * G + p];
+        for (int s0 = 0; s0 + 1 < nmax; s0 += PF) {
+#pragma unroll
+            for (int q = 0; q < PF; ++q) {
+                const int s = s0 + q;
+                const bool act = s < nb;
+                const BwdRec<R, G> cur = ring[q];
+                ring[q] = brec[(size_t)max(top - (s + PF), lo) * G + p];
+                R coef[G];
+#pragma unroll
+                for (int kk = 0; kk < G; ++kk) coef[kk] = act ? cur.coef[kk] : (R)0;
+                const int rr = act ? cur.r : 0;
+                R v = grp_dot<G, R>(gv, coef);
+                const int ce = (v > (R)0) ? fexp(v) + rr : NEG_EXP;
+                const int Rm = grp_max_i<G>(ce);
+                v = (v > (R)0) ? fldexp(v, rr - Rm) : (R)0;
+                if (act) gv = v;
+                const int64_t slot_g = gsl >= 0 ? gsl : (int64_t)max(top - 1 - s, lo);
+                Go[(size_t)slot_g * G + p] = gv;
             }
         }
     }
 }
 
 // ---------------------------------------------------------------- phase 3
+// One chunk per G-lane group (lane = state), 64/G chunks per wave.  Per round:
+//  1. the chunk's emission factors e_t(j) are tabulated in LDS, lane p taking
+//     the steps p, p + G, ... (all states of a step in one lane, so the
+//     per-step maximum is local), together with y_t and log y_t;
+//  2. each lane copies its own state's column e_t(p) into registers;
+//  3. forward from the boundary alpha_{end(c-1)} (or pi o e_0), keeping the
+//     alpha history in the same LDS table;
+//  4. backward from the boundary beta_{end(c)}, forming gamma and xi and the
+//     family statistics.
+// The chunk occupies slots tt0 .. L-1 of the L-step frame (tt0 = L - length),
+// so a short final chunk is aligned to the end of the frame.
+template <typename R, int G, int L, int FAM>
+struct StatsLds {
+    static constexpr int GPB = (BLOCK / 64) * (64 / G);
+    static constexpr int K = fam_k<FAM>();
+    static constexpr int NV = G + 2 + K;
+    static constexpr size_t tab = sizeof(R) * GPB * L * G;
+    static constexpr size_t ysz = sizeof(R) * GPB * L * 2;
+    static constexpr size_t red = sizeof(double) * GPB * G * NV;
+    static constexpr size_t bytes = (2 * tab + ysz) > red ? (2 * tab + ysz) : red;
+};
+
 template <typename R, int G, int L, int FAM, bool WG>
 __global__ __launch_bounds__(BLOCK) void k_chunk_stats(ChunkGeom g, StagedModel<R> m,
                                                        const R *__restrict__ Fi,
@@ -261,18 +525,23 @@ __global__ __launch_bounds__(BLOCK) void k_chunk_stats(ChunkGeom g, StagedModel<
                                                        const int32_t *__restrict__ status,
                                                        double *__restrict__ partial,
                                                        R *__restrict__ gamma_out, int64_t S) {
-    constexpr int K = fam_k<FAM>();
+    using LD = StatsLds<R, G, L, FAM>;
+    constexpr int K = LD::K;
     constexpr int KK = K > 0 ? K : 1;
-    constexpr int GPW = 64 / G, GPB = (BLOCK / 64) * GPW;
-    constexpr int NV = G + 2 + K;
-    __shared__ double red[GPB][G][NV];
+    constexpr int GPW = 64 / G, GPB = LD::GPB;
+    constexpr int NV = LD::NV;
+    __shared__ __align__(16) unsigned char lds_raw[LD::bytes];
+    R (*tab)[L][G] = reinterpret_cast<R (*)[L][G]>(lds_raw);             // e_t(j)
+    R (*atab)[L][G] = reinterpret_cast<R (*)[L][G]>(lds_raw + LD::tab);  // alpha history
+    R (*ysh)[L][2] = reinterpret_cast<R (*)[L][2]>(lds_raw + 2 * LD::tab);
 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int sub = lane / G, p = lane % G, grp = wave * GPW + sub;
     const int N = m.N;
     const bool live = p < N;
     using ET = typename EmitTraits<FAM, R>::T;
-    const StateConsts<ET> k = load_consts(consts_ptr<FAM, R>(m), p, live);
+    const ET *ep = consts_ptr<FAM, R>(m);
+    const StateConsts<ET> k = load_consts(ep, p, live);
     R coefC[G], coefR[G];
 #pragma unroll
     for (int q = 0; q < G; ++q) {
@@ -281,6 +550,7 @@ __global__ __launch_bounds__(BLOCK) void k_chunk_stats(ChunkGeom g, StagedModel<
         coefR[q] = (live && i < N) ? m.A[p * N + i] : (R)0;
     }
     const R pi_p = live ? m.pi[p] : (R)0;
+    const int nrm = *m.nrm;
 
     double xacc[G], g1acc = 0.0, gsacc = 0.0, facc[KK];
 #pragma unroll
@@ -297,93 +567,126 @@ __global__ __launch_bounds__(BLOCK) void k_chunk_stats(ChunkGeom g, StagedModel<
         int64_t off = 0;
         bool use = false;
         if (valid) {
-            int b = find_seq(g.cbase, (int)g.nseq, c);
-            off = g.offsets[b];
-            int T = (int)(g.offsets[b + 1] - off);
-            t0 = (c - g.cbase[b]) * L;
-            len = min(L, T - t0);
-            use = status[b] == 0;
+            const ChunkDesc d = g.cdesc[c];
+            off = d.off;
+            t0 = d.t0;
+            len = d.len;
+            use = status[d.b] == 0;
         }
-        const int tt0 = L - len;       // the chunk occupies register slots tt0 .. L-1
+        const int tt0 = L - len;
         const bool first = (t0 == 0);
 
-        R y[L], e[L], al[L];
-#pragma unroll
-        for (int tt = 0; tt < L; ++tt) {
+        // 1. emission table (lane p takes frame slots p, p + G, ...)
+        for (int tt = p; tt < L; tt += G) {
             const bool act = valid && tt >= tt0;
-            R v = act ? load_step<FAM, R>(g.obs, off + t0 + (tt - tt0), p, N, live) : (R)1;
-            Emit<ET> em = emit_step<FAM, ET>((ET)v, k, live);
-            ET mx = grp_max<G, ET>(em.ell);
-            y[tt] = v;
-            e[tt] = (act && em.ell != neg_inf<ET>()) ? fexp_e((R)(em.ell - mx)) : (R)0;
-        }
-        const R ap = (valid && !first) ? Fi[(size_t)(c - 1) * G + p] : (R)0;
-
-        // forward inside the chunk from its boundary
+            const int64_t row = off + t0 + (tt - tt0);
+            ET ell[G];
+            ET mx = neg_inf<ET>();
+            R y1 = (R)1;
 #pragma unroll
+            for (int j = 0; j < G; ++j) {
+                const bool lj = j < N;
+                R v = act ? load_step<FAM, R>(g.obs, row, j, N, lj) : (R)1;
+                if (j == 0) y1 = v;
+                Emit<ET> em = emit_step<FAM, ET>((ET)v, load_consts(ep, j, lj), lj);
+                ell[j] = em.ell;
+                mx = fmax(mx, em.ell);
+            }
+#pragma unroll
+            for (int j = 0; j < G; ++j)
+                tab[grp][tt][j] =
+                    (act && ell[j] != neg_inf<ET>()) ? fexp_e((R)(ell[j] - mx)) : (R)0;
+            ysh[grp][tt][0] = y1;
+            ysh[grp][tt][1] = (FAM == HMM_GAMMA && y1 > (R)0) ? flog(y1) : (R)0;
+        }
+        __syncthreads();
+
+        // 3. forward from the chunk's boundary; alpha history into LDS
+        const R ap = (valid && !first) ? Fi[(size_t)(c - 1) * G + p] : (R)0;
+        R start;
+        {
+            R v = pi_p * tab[grp][tt0][p];
+            start = fldexp(v, -fexp(grp_max_pos<G>(v)));
+        }
+        R acur = ap;
+#pragma unroll 4
         for (int tt = 0; tt < L; ++tt) {
-            const R xin = (tt == tt0 || tt == 0) ? ap : al[tt > 0 ? tt - 1 : 0];
-            R v = e[tt] * grp_dot<G, R>(xin, coefC);
-            if (first && tt == tt0) v = pi_p * e[tt];
-            int ex = fexp(grp_max<G, R>(v));
-            al[tt] = fldexp(v, -ex);
+            const R xin = (tt == tt0) ? ap : acur;
+            R v = tab[grp][tt][p] * grp_dot<G, R>(xin, coefC);
+            if (first && tt == tt0) v = start;
+            if ((tt % nrm) == nrm - 1 || tt == L - 1) v = fldexp(v, -fexp(grp_max_pos<G>(v)));
+            acur = v;
+            atab[grp][tt][p] = v;
         }
 
+        // 4. backward
         R U[G], gs = (R)0, g1 = (R)0, fa[KK];
 #pragma unroll
         for (int q = 0; q < G; ++q) U[q] = (R)0;
 #pragma unroll
         for (int q = 0; q < KK; ++q) fa[q] = (R)0;
-
         R bcur = valid ? Gi[(size_t)c * G + p] : (R)0;
+        const bool own = use && live;
         {   // gamma at the chunk's last step
-            R h = al[L - 1] * bcur;
+            R h = acur * bcur;
             R Z = grp_sum<G, R>(h);
-            R gm = h * frcp(Z);
-            const int tg = t0 + len - 1;
-            if (use && live) {
-                gs += gm;
-                if constexpr (K > 0) fam_accumulate<FAM, R, KK>(gm, y[L - 1], k, fa);
-                if (tg == 0) g1 += gm;
-                if constexpr (WG) gamma_out[(off + tg) * N + p] = gm;
+            R gm = own ? h * frcp(Z) : (R)0;
+            gs += gm;
+            if constexpr (K > 0)
+                fam_accumulate<FAM, R, KK>(gm, ysh[grp][L - 1][0], ysh[grp][L - 1][1], k, fa);
+            g1 += (first && tt0 == L - 1) ? gm : (R)0;
+            if constexpr (WG) {
+                if (own) gamma_out[(off + t0 + len - 1) * N + p] = gm;
             }
         }
-#pragma unroll
+        // beta_{t-1}(i) = sum_j a_ij e_t(j) beta_t(j).  Lane i gathers
+        // w_j = e_t(j) beta_t(j) from its group once and uses it twice: for
+        // beta_{t-1}(i) and for xi_t(i, j) = alpha_{t-1}(i) a_ij w_j / Z_t, where
+        // Z_t = sum_i alpha_{t-1}(i) beta_{t-1}(i) also normalises gamma_{t-1}.
+#pragma unroll 4
         for (int tt = L - 1; tt >= 0; --tt) {
             const bool trans = (tt > tt0) || (tt == tt0 && !first);
-            R w = e[tt] * bcur;
-            R bp = grp_dot<G, R>(w, coefR);
-            const R xprev = (tt == tt0 || tt == 0) ? ap : al[tt > 0 ? tt - 1 : 0];
+            R w = tab[grp][tt][p] * bcur;
+            R wg[G];
+            grp_gather<G, R>(w, wg);
+            R bp = wg[0] * coefR[0];
+#pragma unroll
+            for (int q = 1; q < G; ++q) bp = fma(wg[q], coefR[q], bp);
+            const R xprev = (tt == tt0 || tt == 0) ? ap : atab[grp][tt > 0 ? tt - 1 : 0][p];
             R h = xprev * bp;
             R Z = grp_sum<G, R>(h);
             R rz = frcp(Z);
-            const bool acc = use && trans;
-            R wr = acc ? w * rz : (R)0;
-            grp_outer_acc<G, R>(xprev, wr, U);
+            const R xr = (use && trans) ? xprev * rz : (R)0;
+#pragma unroll
+            for (int q = 0; q < G; ++q) U[q] = fma(xr, wg[q], U[q]);
             if (tt > 0) {
-                if (use && live && tt > tt0) {
-                    R gm = h * rz;
-                    const int tg = t0 + (tt - 1 - tt0);
-                    gs += gm;
-                    if constexpr (K > 0) fam_accumulate<FAM, R, KK>(gm, y[tt - 1], k, fa);
-                    if (tg == 0) g1 += gm;
-                    if constexpr (WG) gamma_out[(off + tg) * N + p] = gm;
+                const bool ok = own && tt > tt0;
+                R gm = ok ? h * rz : (R)0;
+                gs += gm;
+                if constexpr (K > 0)
+                    fam_accumulate<FAM, R, KK>(gm, ysh[grp][tt - 1][0], ysh[grp][tt - 1][1], k,
+                                               fa);
+                g1 += (first && tt - 1 == tt0) ? gm : (R)0;
+                if constexpr (WG) {
+                    if (ok) gamma_out[(off + t0 + (tt - 1 - tt0)) * N + p] = gm;
                 }
             }
-            int ex = fexp(grp_max<G, R>(bp));
+            int ex = fexp(grp_max_pos<G>(bp));
             if (trans) bcur = fldexp(bp, -ex);
         }
         if (use && live) {
 #pragma unroll
-            for (int q = 0; q < G; ++q) xacc[q] += (double)(U[q] * coefC[q]);
+            for (int q = 0; q < G; ++q) xacc[q] += (double)(U[q] * coefR[q]);
             gsacc += (double)gs;
             g1acc += (double)g1;
 #pragma unroll
             for (int q = 0; q < KK; ++q) facc[q] += (double)fa[q];
         }
+        __syncthreads();
     }
 
-    // fixed-order reduction over the block's lane groups
+    // fixed-order reduction over the block's lane groups (reusing the LDS)
+    double (*red)[G][NV] = reinterpret_cast<double (*)[G][NV]>(lds_raw);
 #pragma unroll
     for (int q = 0; q < G; ++q) red[grp][p][q] = xacc[q];
     red[grp][p][G] = g1acc;
@@ -399,8 +702,8 @@ __global__ __launch_bounds__(BLOCK) void k_chunk_stats(ChunkGeom g, StagedModel<
         } else if (s < 1 + N + (int64_t)N * N) {
             int q = (int)(s - 1 - N);
             int i = q / N, j = q % N;
-            pp = j;
-            slot = grp_inv(j, i);
+            pp = i;
+            slot = grp_inv(i, j);
         } else if (s < 1 + 2 * N + (int64_t)N * N) {
             pp = (int)(s - 1 - N - (int64_t)N * N);
             slot = G + 1;
@@ -430,26 +733,59 @@ static void launch_phase3(int nblk, const ChunkGeom &geom, const StagedModel<R> 
                            geom, m, F, Gb, status, partial, gamma_out, S);
 }
 
+template <typename R, int G, int FAM, int L>
+static void launch_product(int C, const ChunkGeom &geom, const StagedModel<R> &m,
+                           FwdRec<R, G> *fr, BwdRec<R, G> *br, hipStream_t s) {
+    constexpr int CPB = BLOCK / G;
+    hipLaunchKernelGGL((k_chunk_product<R, G, L, FAM>), dim3((C + CPB - 1) / CPB), dim3(BLOCK), 0,
+                       s, geom, m, m.A8, fr, br);
+}
+
 template <typename R, int G, int FAM>
 static hmm_status run_chunked_g(const StagedModel<R> &m, const ObsDesc &o, const ChunkBuffers &cb,
                                 double *loglik, int32_t *status, R *gamma_out, double *stats,
                                 int64_t S, hipStream_t s) {
-    ChunkGeom geom{o.nseq, o.offsets, cb.cbase, cb.L, cb.C, ObsRef{o.obs, o.obs_f64}};
-    constexpr int CPB = (BLOCK / 64) * (64 / (G * G));
+    ChunkGeom geom{o.nseq, o.offsets, cb.cbase, cb.cdesc, cb.L, cb.C, ObsRef{o.obs, o.obs_f64}};
     constexpr int SPB = (BLOCK / 64) * (64 / G);
-    R *P = (R *)cb.P;
+    auto *fr = (FwdRec<R, G> *)cb.fwdrec;
+    auto *br = (BwdRec<R, G> *)cb.bwdrec;
     R *F = (R *)cb.F;
     R *Gb = (R *)cb.Gb;
     {
         ProfScope ps("chunk_product", s);
-        hipLaunchKernelGGL((k_chunk_product<R, G, FAM>), dim3((cb.C + CPB - 1) / CPB), dim3(BLOCK),
-                           0, s, geom, m, P, cb.rexp, cb.clog);
+        switch (cb.L) {
+        case 16: launch_product<R, G, FAM, 16>(cb.C, geom, m, fr, br, s); break;
+        case 32: launch_product<R, G, FAM, 32>(cb.C, geom, m, fr, br, s); break;
+        case 64: launch_product<R, G, FAM, 64>(cb.C, geom, m, fr, br, s); break;
+        default: return HMM_ERR_UNSUPPORTED;
+        }
+    }
+    ScanGeom sg{o.nseq,  o.offsets, cb.cbase, cb.sbase, cb.S,
+                cb.SC,   cb.C,      cb.sdesc, ObsRef{o.obs, o.obs_f64}};
+    auto *sfr = (FwdRec<R, G> *)cb.sfwdrec;
+    auto *sbr = (BwdRec<R, G> *)cb.sbwdrec;
+    R *Fs = (R *)cb.Fs;
+    R *Gs = (R *)cb.Gs;
+    {
+        ProfScope ps("super_product", s);
+        constexpr int GPB = BLOCK / G;
+        hipLaunchKernelGGL((k_super_product<R, G>), dim3((cb.SC + GPB - 1) / GPB), dim3(BLOCK), 0, s,
+                           (const SuperDesc *)cb.sdesc, cb.SC, cb.S, (const FwdRec<R, G> *)fr,
+                           (const BwdRec<R, G> *)br, sfr, sbr);
     }
     {
         ProfScope ps("chunk_scan", s);
-        hipLaunchKernelGGL((k_chunk_scan<R, G, FAM>), dim3((unsigned)((o.nseq + SPB - 1) / SPB), 2),
-                           dim3(BLOCK), 0, s, geom, m, (const R *)P, (const int *)cb.rexp,
-                           (const double *)cb.clog, F, Gb, loglik, status);
+        hipLaunchKernelGGL((k_chunk_scan<R, G, FAM, 8, false>),
+                           dim3((unsigned)((o.nseq + SPB - 1) / SPB), 2), dim3(BLOCK), 0, s, sg, m,
+                           (const FwdRec<R, G> *)sfr, (const BwdRec<R, G> *)sbr, (const R *)nullptr,
+                           (const R *)nullptr, Fs, Gs, loglik, status);
+    }
+    {
+        ProfScope ps("chunk_expand", s);
+        hipLaunchKernelGGL((k_chunk_scan<R, G, FAM, 8, true>),
+                           dim3((unsigned)((cb.SC + SPB - 1) / SPB), 2), dim3(BLOCK), 0, s, sg, m,
+                           (const FwdRec<R, G> *)fr, (const BwdRec<R, G> *)br, (const R *)Fs,
+                           (const R *)Gs, F, Gb, loglik, status);
     }
     switch (cb.L) {
     case 16:

@@ -19,7 +19,8 @@ size_t staged_bytes(int N, int D, int family, bool f64) {
     size_t r = f64 ? 8 : 4;
     size_t n = (size_t)N, nn = n * n;
     return align256(n * r) * 2 + align256(nn * r) * 2 + align256(n * EP_STRIDE * r) +
-           align256(n * EP_STRIDE * 8) + align256(mv_count(N, D, family) * r + r) + 256;
+           align256(n * EP_STRIDE * 8) + align256(mv_count(N, D, family) * r + r) + 256 +
+           align256(64 * r) + 256;
 }
 
 // One block.  Computes linear and log probabilities in R, the per-state
@@ -27,9 +28,17 @@ size_t staged_bytes(int N, int D, int family, bool f64) {
 // multivariate families, the location vectors and -1/(2 var) or L^{-1}.
 template <typename R>
 __global__ __launch_bounds__(BLOCK) void k_stage(RawModel m, R *pi, R *A, R *lpi, R *lA, R *ep,
-                                                 double *ep64, R *mv, int *perr) {
+                                                 double *ep64, R *mv, int *perr, R *A8, int *nrm) {
     const int N = m.N, D = m.D;
     int bad = 0;
+    __shared__ double amin_sh[BLOCK];
+    double amin = 1.0;
+    for (int k = threadIdx.x; k < N * N; k += blockDim.x) amin = fmin(amin, exp(m.log_A[k]));
+    amin_sh[threadIdx.x] = amin;
+    for (int k = threadIdx.x; k < 64; k += blockDim.x) {
+        int i = k / 8, j = k % 8;
+        A8[k] = (i < N && j < N) ? (R)exp(m.log_A[i * N + j]) : (R)0;
+    }
     for (int j = threadIdx.x; j < N; j += blockDim.x) {
         double l = m.log_pi[j];
         pi[j] = (R)exp(l);
@@ -122,7 +131,18 @@ __global__ __launch_bounds__(BLOCK) void k_stage(RawModel m, R *pi, R *A, R *lpi
         }
     }
     int any = __syncthreads_or(bad);
-    if (threadIdx.x == 0) *perr = any;
+    if (threadIdx.x == 0) {
+        *perr = any;
+        double a = 1.0;
+        for (int t = 0; t < BLOCK; ++t) a = fmin(a, amin_sh[t]);
+        // A product of forward-type steps (row vector times A diag(e), max e = 1)
+        // grows by at most N <= 8 and shrinks by at most min a_ij per step, so
+        // rescaling every 4 steps keeps single precision in range when
+        // min a_ij >= 2^-25 (2^-200 for double).
+        const double lim4 = sizeof(R) == 4 ? 0x1p-25 : 0x1p-200;
+        const double lim2 = sizeof(R) == 4 ? 0x1p-50 : 0x1p-400;
+        *nrm = (N <= 8 && a >= lim4) ? 4 : ((N <= 8 && a >= lim2) ? 2 : 1);
+    }
 }
 
 template <typename R>
@@ -137,11 +157,13 @@ void launch_stage(const RawModel &m, void *region, StagedModel<R> *out, hipStrea
     R *ep = (R *)p; p += align256(n * EP_STRIDE * r);
     double *ep64 = (double *)p; p += align256(n * EP_STRIDE * 8);
     R *mv = (R *)p; p += align256(mv_count(m.N, m.D, m.family) * r + r);
-    int *perr = (int *)p;
+    int *perr = (int *)p; p += 256;
+    R *A8 = (R *)p; p += align256(64 * r);
+    int *nrm = (int *)p;
     {
         ProfScope ps("stage", s);
         hipLaunchKernelGGL(k_stage<R>, dim3(1), dim3(BLOCK), 0, s, m, pi, A, lpi, lA, ep, ep64, mv,
-                           perr);
+                           perr, A8, nrm);
     }
     out->N = m.N;
     out->D = m.D;
@@ -154,42 +176,102 @@ void launch_stage(const RawModel &m, void *region, StagedModel<R> *out, hipStrea
     out->ep64 = ep64;
     out->mv = mv;
     out->perr = perr;
+    out->A8 = A8;
+    out->nrm = nrm;
 }
 
 template void launch_stage<float>(const RawModel &, void *, StagedModel<float> *, hipStream_t);
 template void launch_stage<double>(const RawModel &, void *, StagedModel<double> *, hipStream_t);
 
-// cbase[b] = sum_{b' < b} ceil(T_b' / L); single block exclusive scan.
-__global__ __launch_bounds__(1024) void k_plan_chunks(const int64_t *offsets, int64_t nseq, int L,
-                                                      int *cbase) {
-    __shared__ int sh[1024];
-    int carry = 0;
-    for (int64_t base = 0; base < nseq; base += 1024) {
-        int64_t b = base + threadIdx.x;
-        int n = 0;
-        if (b < nseq) {
-            int64_t T = offsets[b + 1] - offsets[b];
-            n = (int)((T + L - 1) / L);
-        }
-        sh[threadIdx.x] = n;
+// cbase[b] = sum_{b' < b} ceil(T_b' / L) and sbase[b] = sum_{b' < b}
+// ceil(nchunks_b' / S); single block, exclusive scans in tiles of 1024.
+__device__ __forceinline__ int block_incl_scan(int v, int *sh) {
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {   // Hillis-Steele inclusive scan
+        int u = (threadIdx.x >= (unsigned)o) ? sh[threadIdx.x - o] : 0;
         __syncthreads();
-        for (int o = 1; o < 1024; o <<= 1) {   // Hillis-Steele inclusive scan
-            int v = (threadIdx.x >= (unsigned)o) ? sh[threadIdx.x - o] : 0;
-            __syncthreads();
-            sh[threadIdx.x] += v;
-            __syncthreads();
-        }
-        if (b < nseq) cbase[b] = carry + sh[threadIdx.x] - n;
-        int tot = sh[1023];
+        sh[threadIdx.x] += u;
         __syncthreads();
-        carry += tot;
     }
-    if (threadIdx.x == 0) cbase[nseq] = carry;
+    return sh[threadIdx.x];
 }
 
-void launch_plan_chunks(const int64_t *offsets, int64_t nseq, int L, int *cbase, hipStream_t s) {
+__global__ __launch_bounds__(1024) void k_plan_chunks(const int64_t *offsets, int64_t nseq, int L,
+                                                      int S, int *cbase, int *sbase) {
+    __shared__ int sh[1024];
+    int carry_c = 0, carry_s = 0;
+    for (int64_t base = 0; base < nseq; base += 1024) {
+        int64_t b = base + threadIdx.x;
+        int nc = 0, ns = 0;
+        if (b < nseq) {
+            int64_t T = offsets[b + 1] - offsets[b];
+            nc = (int)((T + L - 1) / L);
+            ns = (nc + S - 1) / S;
+        }
+        int ic = block_incl_scan(nc, sh);
+        int tc = sh[1023];
+        __syncthreads();
+        int is = block_incl_scan(ns, sh);
+        int ts = sh[1023];
+        __syncthreads();
+        if (b < nseq) {
+            cbase[b] = carry_c + ic - nc;
+            sbase[b] = carry_s + is - ns;
+        }
+        carry_c += tc;
+        carry_s += ts;
+    }
+    if (threadIdx.x == 0) {
+        cbase[nseq] = carry_c;
+        sbase[nseq] = carry_s;
+    }
+}
+
+void launch_plan_chunks(const int64_t *offsets, int64_t nseq, int L, int S, int *cbase,
+                        int *sbase, hipStream_t s) {
     ProfScope ps("plan_chunks", s);
-    hipLaunchKernelGGL(k_plan_chunks, dim3(1), dim3(1024), 0, s, offsets, nseq, L, cbase);
+    hipLaunchKernelGGL(k_plan_chunks, dim3(1), dim3(1024), 0, s, offsets, nseq, L, S, cbase, sbase);
+}
+
+__global__ __launch_bounds__(BLOCK) void k_chunk_desc(const int64_t *offsets, int64_t nseq, int L,
+                                                      int S, const int *cbase, const int *sbase,
+                                                      int C, int SC, ChunkDesc *cdesc,
+                                                      SuperDesc *sdesc) {
+    const int i = blockIdx.x * BLOCK + threadIdx.x;
+    if (i < C) {
+        int b = find_seq(cbase, (int)nseq, i);
+        int64_t off = offsets[b];
+        int T = (int)(offsets[b + 1] - off);
+        ChunkDesc d;
+        d.off = off;
+        d.b = b;
+        d.t0 = (i - cbase[b]) * L;
+        d.len = min(L, T - d.t0);
+        d.pad0 = 0;
+        d.pad1 = 0;
+        cdesc[i] = d;
+    }
+    if (i < SC) {
+        int b = find_seq(sbase, (int)nseq, i);
+        SuperDesc d;
+        d.off = offsets[b];
+        d.b = b;
+        d.lo = cbase[b] + (i - sbase[b]) * S;
+        d.n = min(S, cbase[b + 1] - d.lo);
+        d.head = (i == sbase[b]) ? 1 : 0;
+        d.pad = 0;
+        sdesc[i] = d;
+    }
+}
+
+void launch_chunk_desc(const int64_t *offsets, int64_t nseq, int L, int S, const int *cbase,
+                       const int *sbase, int C, int SC, ChunkDesc *cdesc, SuperDesc *sdesc,
+                       hipStream_t s) {
+    ProfScope ps("chunk_desc", s);
+    const int n = C > SC ? C : SC;
+    hipLaunchKernelGGL(k_chunk_desc, dim3((n + BLOCK - 1) / BLOCK), dim3(BLOCK), 0, s, offsets,
+                       nseq, L, S, cbase, sbase, C, SC, cdesc, sdesc);
 }
 
 // stats[s] = sum over parts of partial[p*S + s] (s >= 1) in a fixed order;
