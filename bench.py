@@ -49,6 +49,16 @@ def algorithmic_flops(name, w):
     return None
 
 
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(w, reps=2):
     import oracle
     oracle._load()
@@ -59,7 +69,7 @@ def cpu_baseline(w, reps=2):
     return {"value": reps * w.transitions / dt, "unit": "transitions/s", "cores": 1,
             "kind": "oracle",
             "sample": f"full workload ({w.n_seq} sequences, {w.total_steps} steps) x{reps}, "
-                      f"FP64 oracle, 1 thread, {dt:.1f} s"}
+                      f"FP64 oracle, 1 thread on {cpu_model()}, {dt:.1f} s"}
 
 
 def main():
