@@ -293,6 +293,17 @@ def emission_logpdf(model, batch, prec="f32", ws=None, stream=None):
     return out[:batch.total]
 
 
+def viterbi(model, batch, prec="f64", ws=None, stream=None):
+    """Returns (path [sum T] int32, path log-probability [B] float64)."""
+    import torch
+    path = torch.empty(max(batch.total, 1), dtype=torch.int32, device="cuda")
+    logp = torch.empty(max(batch.n_seq, 1), dtype=torch.float64, device="cuda")
+    if ws is None:
+        ws = _ws(hmm_workspace_size("viterbi", model, batch, prec))
+    hmm_viterbi(model, batch, prec, path, logp, ws, stream)
+    return path[:batch.total], logp[:batch.n_seq]
+
+
 def posterior_decode(model, batch, prec="f32", ws=None, stream=None):
     import torch
     path = torch.empty(max(batch.total, 1), dtype=torch.int32, device="cuda")

@@ -114,6 +114,7 @@ struct Plan {
     size_t staged = 0, cbase = 0, frec = 0, brec = 0, F = 0, Gb = 0, partial = 0;
     int SS = 16, SC = 0;   // chunks per superchunk, number of superchunks
     size_t sbase = 0, sfrec = 0, sbrec = 0, Fs = 0, Gs = 0, cdesc = 0, sdesc = 0;
+    size_t vpsi = 0, vJ = 0, vqlast = 0, vqend = 0;
     size_t ll = 0, st = 0, gam = 0;
     size_t logB = 0, alpha = 0, beta = 0, ps = 0;
     size_t total = 0;
@@ -147,7 +148,23 @@ hmm_status make_plan(hmm_op op, const Checked &c, hmm_precision prec, Plan *p) {
         p->total = off;
         return HMM_OK;
     }
-    if (op == HMM_OP_VITERBI) return fail(HMM_ERR_UNSUPPORTED, "Viterbi is not built yet");
+    if (op == HMM_OP_VITERBI) {
+        if (p->plain) return fail(HMM_ERR_UNSUPPORTED, "Viterbi runs in HMM_PREC_F64 or HMM_PREC_F32");
+        if (N > 64) return fail(HMM_ERR_UNSUPPORTED, "Viterbi: this build covers N <= 64 (N = %d)", N);
+        int64_t C = 0;
+        for (int64_t b = 0; b < c.B; ++b) C += (c.h_off[b + 1] - c.h_off[b] + 63) / 64;
+        if (C > INT32_MAX / 64) return fail(HMM_ERR_UNSUPPORTED, "too many chunks");
+        p->C = (int)C;
+        p->vpsi = take((size_t)c.total * N);
+        p->vJ = take((size_t)C * N);
+        p->vqlast = take((size_t)c.B);
+        p->vqend = take((size_t)C);
+        p->cbase = take((size_t)(c.B + 1) * 4);
+        p->sbase = take((size_t)(c.B + 1) * 4);
+        p->cdesc = take((size_t)C * sizeof(ChunkDesc));
+        p->total = off;
+        return HMM_OK;
+    }
     if (op != HMM_OP_FORWARD_BACKWARD && op != HMM_OP_ESTEP && op != HMM_OP_POSTERIOR_DECODE)
         return fail(HMM_ERR_ARG, "unknown op %d", (int)op);
     p->ll = take((size_t)c.B * 8);
@@ -412,9 +429,35 @@ hmm_status hmm_posterior_decode(const hmm_model *model, const hmm_batch *batch,
 
 hmm_status hmm_viterbi(const hmm_model *model, const hmm_batch *batch, hmm_precision prec,
                        int32_t *path, double *path_logp, void *ws, size_t ws_bytes, void *stream) {
-    (void)model; (void)batch; (void)prec; (void)path; (void)path_logp; (void)ws; (void)ws_bytes;
-    (void)stream;
-    return fail(HMM_ERR_UNSUPPORTED, "Viterbi is not built yet");
+    Checked c;
+    hmm_status st = check_batch(batch, model, &c);
+    if (st != HMM_OK) return st;
+    Plan p;
+    if ((st = make_plan(HMM_OP_VITERBI, c, prec, &p)) != HMM_OK) return st;
+    if ((st = check_ws(p, ws, ws_bytes)) != HMM_OK) return st;
+    if (c.total > 0 && !path) return fail(HMM_ERR_ARG, "path is NULL");
+    if (c.B > 0 && !path_logp) return fail(HMM_ERR_ARG, "path_logp is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    char *w = (char *)ws;
+    ObsDesc od{batch->obs, batch->obs_f64, c.B, batch->offsets};
+    if (c.B == 0) return ok();
+    int *cbase = (int *)(w + p.cbase);
+    ChunkDesc *cdesc = (ChunkDesc *)(w + p.cdesc);
+    launch_plan_chunks(batch->offsets, c.B, 64, 1, cbase, (int *)(w + p.sbase), s);
+    launch_chunk_desc(batch->offsets, c.B, 64, 1, cbase, (int *)(w + p.sbase), p.C, 0, cdesc,
+                      nullptr, s);
+    uint8_t *psi = (uint8_t *)(w + p.vpsi), *J = (uint8_t *)(w + p.vJ);
+    uint8_t *ql = (uint8_t *)(w + p.vqlast), *qe = (uint8_t *)(w + p.vqend);
+    if (p.f64) {
+        StagedModel<double> sm;
+        launch_stage<double>(raw(model), w + p.staged, &sm, s);
+        run_viterbi<double>(sm, od, cbase, cdesc, p.C, psi, J, ql, qe, path, path_logp, s);
+    } else {
+        StagedModel<float> sm;
+        launch_stage<float>(raw(model), w + p.staged, &sm, s);
+        run_viterbi<float>(sm, od, cbase, cdesc, p.C, psi, J, ql, qe, path, path_logp, s);
+    }
+    return device_check("Viterbi kernels");
 }
 
 void hmm_mstep_default_opts(hmm_mstep_opts *o) {

@@ -130,6 +130,12 @@ template <typename R>
 hmm_status run_emission(const StagedModel<R> &m, const ObsDesc &o, int64_t total_steps,
                         R *out, hipStream_t s);
 
+// Viterbi (N <= 64): psi [sum T * N] bytes, J [C * N], qlast [B], qend [C]
+template <typename R>
+hmm_status run_viterbi(const StagedModel<R> &m, const ObsDesc &o, const int *cbase,
+                       const ChunkDesc *cdesc, int C, uint8_t *psi, uint8_t *J, uint8_t *qlast,
+                       uint8_t *qend, int32_t *path, double *logp, hipStream_t s);
+
 // fixed-order reduction of per-block partial statistics + log-likelihood sum
 void launch_reduce_stats(const double *partial, int nparts, int64_t S, const double *loglik,
                          const int32_t *status, int64_t nseq, double *stats, hipStream_t s);

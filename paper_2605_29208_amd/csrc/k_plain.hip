@@ -13,75 +13,6 @@
 
 namespace hmmk {
 
-// log b_j(y_t) without the state-independent part, for any family (runtime),
-// returned in FP64.  Poisson is evaluated from the FP64 constants (its values
-// are of the size of y log lambda); the other families in R.
-template <typename R>
-__device__ double emission_any(const StagedModel<R> &m, const ObsRef &o, int64_t row, int j,
-                               double *common, bool *bad) {
-    const int N = m.N, D = m.D;
-    switch (m.family) {
-    case HMM_GAUSSIAN:
-    case HMM_GAMMA:
-    case HMM_STUDENT_T: {
-        R y = load_obs<R>(o, row);
-        StateConsts<R> k = load_consts(m.ep, j, true);
-        Emit<R> e;
-        if (m.family == HMM_GAUSSIAN) e = emit_scalar<HMM_GAUSSIAN, R>(y, k, true);
-        else if (m.family == HMM_GAMMA) e = emit_scalar<HMM_GAMMA, R>(y, k, true);
-        else e = emit_scalar<HMM_STUDENT_T, R>(y, k, true);
-        *common = e.common;
-        *bad = e.bad;
-        return (double)e.ell;
-    }
-    case HMM_POISSON: {
-        double y = load_obs<double>(o, row);
-        StateConsts<double> k = load_consts(m.ep64, j, true);
-        Emit<double> e = emit_scalar<HMM_POISSON, double>(y, k, true);
-        *common = e.common;
-        *bad = e.bad;
-        return e.ell;
-    }
-    case HMM_DIAG_GAUSSIAN: {
-        R s = m.ep[j * EP_STRIDE];
-        bool b = false;
-        for (int d = 0; d < D; ++d) {
-            R y = load_obs<R>(o, row * D + d);
-            b |= !isfinite(y);
-            R dv = y - m.mv[(size_t)j * D + d];
-            s = fma(m.mv[(size_t)N * D + (size_t)j * D + d], dv * dv, s);
-        }
-        *common = 0.0;
-        *bad = b;
-        return (double)s;
-    }
-    case HMM_FULL_GAUSSIAN: {
-        const R *mu = m.mv + (size_t)j * D;
-        const R *Li = m.mv + (size_t)N * D + (size_t)j * D * D;
-        R q = (R)0;
-        bool b = false;
-        for (int r = 0; r < D; ++r) {
-            R z = (R)0;
-            for (int c = 0; c <= r; ++c) {
-                R y = load_obs<R>(o, row * D + c);
-                z = fma(Li[r * D + c], y - mu[c], z);
-            }
-            q = fma(z, z, q);
-        }
-        for (int c = 0; c < D; ++c) b |= !isfinite(load_obs<R>(o, row * D + c));
-        *common = 0.0;
-        *bad = b;
-        return (double)(m.ep[j * EP_STRIDE] - (R)0.5 * q);
-    }
-    default: {   // table
-        R v = load_obs<R>(o, row * N + j);
-        *common = 0.0;
-        *bad = isnan(v) || (v > (R)0 && isinf(v));
-        return (double)v;
-    }
-    }
-}
-
 // emission table: one thread per (step, state)
 template <typename R>
 __global__ __launch_bounds__(BLOCK) void k_emission_table(StagedModel<R> m, ObsRef o,

@@ -1,0 +1,236 @@
+// k_viterbi.hip -- Viterbi decoding (section 3.3) for N <= 64 states.
+//
+// Forward max-plus recursion, one wave per sequence, lane j = state j:
+//   delta_1(j) = log pi_j + log b_j(y_1)
+//   delta_t(j) = max_i [delta_{t-1}(i) + log a_ij] + log b_j(y_t),
+//   psi_t(j)   = the lowest i attaining the maximum (strict comparison in
+//                increasing i),
+// with every step shifted by m_t = max_j delta_t(j) and the shifts summed in
+// FP64 (an exact shift for the argmax; it keeps the values small).  The
+// additions happen in the same order as in the plain definition, so with
+// identical log b inputs the FP64 path reproduces it bit for bit.
+// psi is stored as one byte per (step, state).
+//
+// Backtrace in three kernels: per chunk of K = 64 steps a jump table
+// J_c[j] = state just before the chunk when the chunk ends in state j (the
+// chunk's psi block is staged in LDS and chased on chip); a chain over the
+// chunks of each sequence (one wave per sequence, next rows prefetched, the
+// current state wave-uniform so J_c[q] is a lane read); and a parallel fill
+// of each chunk's path from its end state.
+#include "dev_common.hpp"
+#include "hmm_internal.hpp"
+
+namespace hmmk {
+
+constexpr int VK = 64;   // steps per backtrace chunk
+
+__device__ __forceinline__ double wave_max_d(double v) {
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+__device__ __forceinline__ float wave_max_d(float v) {
+    for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+// one wave per sequence; NMAX = 8 or 64 bounds the (unrolled) predecessor loop
+template <typename R, int NMAX>
+__global__ __launch_bounds__(64) void k_vit_forward(StagedModel<R> m, ObsRef o, int64_t nseq,
+                                                    const int64_t *__restrict__ offsets,
+                                                    uint8_t *__restrict__ psi,
+                                                    double *__restrict__ logp,
+                                                    uint8_t *__restrict__ qlast) {
+    __shared__ R dsh[64];
+    const int64_t b = blockIdx.x;
+    const int j = threadIdx.x;
+    const int N = m.N;
+    const bool live = j < N;
+    const int64_t off = offsets[b], T = offsets[b + 1] - off;
+    R col[NMAX];
+#pragma unroll
+    for (int i = 0; i < NMAX; ++i) col[i] = (live && i < N) ? m.lA[i * N + j] : neg_inf<R>();
+    const R ninf = neg_inf<R>();
+    double common = 0.0;
+    bool bad = false;
+    double lb = live ? emission_any<R>(m, o, off, j, &common, &bad) : -__builtin_inf();
+    R d = live ? (R)(m.lpi[j] + (R)lb) : ninf;
+    R mx = wave_max_d(d);
+    bool dead = (mx == ninf);
+    double offset = (double)mx + common;
+    d = dead ? ninf : d - mx;
+    for (int64_t t = 1; t < T; ++t) {
+        dsh[j] = d;
+        __syncthreads();
+        R best = ninf;
+        int arg = 0;
+#pragma unroll
+        for (int i = 0; i < NMAX; ++i) {
+            if (i < N) {
+                R v = dsh[i] + col[i];
+                if (v > best) {
+                    best = v;
+                    arg = i;
+                }
+            }
+        }
+        __syncthreads();
+        bool bd = false;
+        double cm = 0.0;
+        double lt = live ? emission_any<R>(m, o, off + t, j, &cm, &bd) : -__builtin_inf();
+        bad |= bd;
+        R nd = live ? (R)(best + (R)lt) : ninf;
+        if (live) psi[(off + t) * N + j] = (uint8_t)arg;
+        R mt = wave_max_d(nd);
+        if (mt == ninf) dead = true;
+        offset += (double)mt + cm;
+        d = (mt == ninf) ? ninf : nd - mt;
+    }
+    // final state: lowest argmax
+    R best = ninf;
+    int q = 0;
+    dsh[j] = d;
+    __syncthreads();
+    if (j == 0) {
+        for (int i = 0; i < N; ++i)
+            if (dsh[i] > best) {
+                best = dsh[i];
+                q = i;
+            }
+        logp[b] = dead ? -__builtin_inf() : offset + (double)best;
+        qlast[b] = (uint8_t)(dead ? 255 : q);
+    }
+    // a non-finite observation in any lane makes the whole sequence undecodable
+    int badw = __any(bad);
+    if (j == 0 && badw) {
+        logp[b] = __builtin_nan("");
+        qlast[b] = 255;
+    }
+}
+
+// J[c][j] for chunk c covering steps [t0, t1): follow psi from (t1 - 1, j)
+// back through step t0 (t0 >= 1) or down to step 0 (first chunk).
+__global__ __launch_bounds__(64) void k_vit_jump(const ChunkDesc *__restrict__ cdesc, int N,
+                                                 const uint8_t *__restrict__ psi,
+                                                 uint8_t *__restrict__ J) {
+    __shared__ uint8_t blk[VK * 64];
+    const int c = blockIdx.x;
+    const ChunkDesc d = cdesc[c];
+    const int tid = threadIdx.x;
+    // stage the chunk's psi rows (len x N bytes)
+    const int nbytes = d.len * N;
+    const uint8_t *src = psi + (d.off + d.t0) * N;
+    for (int k = tid; k < nbytes; k += 64) blk[k] = src[k];
+    __syncthreads();
+    if (tid < N) {
+        int q = tid;
+        const int stop = d.t0 == 0 ? 1 : 0;   // psi_0 does not exist
+        for (int tt = d.len - 1; tt >= stop; --tt) q = blk[tt * N + q];
+        J[(size_t)c * N + tid] = (uint8_t)q;
+    }
+}
+
+// end state of every chunk: one wave per sequence walks its chunks backwards
+__global__ __launch_bounds__(64) void k_vit_chain(const int *__restrict__ cbase, int N,
+                                                  const uint8_t *__restrict__ qlast,
+                                                  const uint8_t *__restrict__ J,
+                                                  uint8_t *__restrict__ qend) {
+    constexpr int PF = 8;
+    const int64_t b = blockIdx.x;
+    const int lane = threadIdx.x;
+    const int c0 = cbase[b], c1 = cbase[b + 1];
+    int q = qlast[b];
+    if (q == 255) {
+        for (int c = c0 + lane; c < c1; c += 64) qend[c] = 255;
+        return;
+    }
+    int ring[PF];
+#pragma unroll
+    for (int k = 0; k < PF; ++k) {
+        const int c = max(c1 - 1 - k, c0);
+        ring[k] = lane < N ? J[(size_t)c * N + lane] : 0;
+    }
+    for (int s0 = 0; s0 < c1 - c0; s0 += PF) {
+#pragma unroll
+        for (int k = 0; k < PF; ++k) {
+            const int s = s0 + k;
+            const int c = c1 - 1 - s;
+            const int row = ring[k];
+            const int cn = max(c1 - 1 - (s + PF), c0);
+            ring[k] = lane < N ? J[(size_t)cn * N + lane] : 0;
+            if (c >= c0) {
+                if (lane == 0) qend[c] = (uint8_t)q;
+                q = __builtin_amdgcn_readlane(row, q);
+            }
+        }
+    }
+}
+
+// path of every chunk from its end state (one lane chases, the wave stages psi)
+__global__ __launch_bounds__(64) void k_vit_fill(const ChunkDesc *__restrict__ cdesc, int N,
+                                                 const uint8_t *__restrict__ psi,
+                                                 const uint8_t *__restrict__ qend,
+                                                 int32_t *__restrict__ path) {
+    __shared__ uint8_t blk[VK * 64];
+    __shared__ int32_t out[VK];
+    const int c = blockIdx.x;
+    const ChunkDesc d = cdesc[c];
+    const int tid = threadIdx.x;
+    const int nbytes = d.len * N;
+    const uint8_t *src = psi + (d.off + d.t0) * N;
+    for (int k = tid; k < nbytes; k += 64) blk[k] = src[k];
+    __syncthreads();
+    if (tid == 0) {
+        int q = qend[c];
+        if (q == 255) {
+            for (int tt = 0; tt < d.len; ++tt) out[tt] = -1;
+        } else {
+            for (int tt = d.len - 1; tt >= 0; --tt) {
+                out[tt] = q;
+                if (tt > 0 || d.t0 > 0) q = blk[tt * N + q];
+            }
+        }
+    }
+    __syncthreads();
+    if (tid < d.len) path[d.off + d.t0 + tid] = out[tid];
+}
+
+template <typename R>
+hmm_status run_viterbi(const StagedModel<R> &m, const ObsDesc &o, const int *cbase,
+                       const ChunkDesc *cdesc, int C, uint8_t *psi, uint8_t *J, uint8_t *qlast,
+                       uint8_t *qend, int32_t *path, double *logp, hipStream_t s) {
+    if (o.nseq == 0) return HMM_OK;
+    {
+        ProfScope ps("vit_forward", s);
+        if (m.N <= 8)
+            hipLaunchKernelGGL((k_vit_forward<R, 8>), dim3((unsigned)o.nseq), dim3(64), 0, s, m,
+                               ObsRef{o.obs, o.obs_f64}, o.nseq, o.offsets, psi, logp, qlast);
+        else
+            hipLaunchKernelGGL((k_vit_forward<R, 64>), dim3((unsigned)o.nseq), dim3(64), 0, s, m,
+                               ObsRef{o.obs, o.obs_f64}, o.nseq, o.offsets, psi, logp, qlast);
+    }
+    {
+        ProfScope ps("vit_jump", s);
+        hipLaunchKernelGGL(k_vit_jump, dim3((unsigned)C), dim3(64), 0, s, cdesc, m.N,
+                           (const uint8_t *)psi, J);
+    }
+    {
+        ProfScope ps("vit_chain", s);
+        hipLaunchKernelGGL(k_vit_chain, dim3((unsigned)o.nseq), dim3(64), 0, s, cbase, m.N,
+                           (const uint8_t *)qlast, (const uint8_t *)J, qend);
+    }
+    {
+        ProfScope ps("vit_fill", s);
+        hipLaunchKernelGGL(k_vit_fill, dim3((unsigned)C), dim3(64), 0, s, cdesc, m.N,
+                           (const uint8_t *)psi, (const uint8_t *)qend, path);
+    }
+    return HMM_OK;
+}
+
+template hmm_status run_viterbi<float>(const StagedModel<float> &, const ObsDesc &, const int *,
+                                       const ChunkDesc *, int, uint8_t *, uint8_t *, uint8_t *,
+                                       uint8_t *, int32_t *, double *, hipStream_t);
+template hmm_status run_viterbi<double>(const StagedModel<double> &, const ObsDesc &, const int *,
+                                        const ChunkDesc *, int, uint8_t *, uint8_t *, uint8_t *,
+                                        uint8_t *, int32_t *, double *, hipStream_t);
+
+}  // namespace hmmk
