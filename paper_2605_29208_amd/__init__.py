@@ -217,6 +217,40 @@ def hmm_posterior_decode(model, batch, prec, path, loglik, ws, stream=None):
                                      _stream(stream)))
 
 
+def default_mstep_opts(**kw) -> HmmMstepOptsC:
+    o = HmmMstepOptsC()
+    _lib.hmm_mstep_default_opts(ctypes.byref(o))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+def hmm_mstep_transitions(model, stats, opts, log_pi_out, log_A_out, stream=None):
+    _check(_lib.hmm_mstep_transitions(ctypes.byref(model.c), _ptr(stats),
+                                      None if opts is None else ctypes.byref(opts),
+                                      _ptr(log_pi_out), _ptr(log_A_out), _stream(stream)))
+
+
+MSTEP_NAMES = {"gaussian": "hmm_mstep_gaussian", "gamma": "hmm_mstep_gamma",
+               "student_t": "hmm_mstep_student_t", "poisson": "hmm_mstep_poisson",
+               "diag": "hmm_mstep_diag_gaussian", "full": "hmm_mstep_full_gaussian"}
+
+
+def hmm_mstep(model, stats, opts, theta_out, collapsed=None, iters=None, stream=None):
+    """Calls hmm_mstep_<family> for the model's family."""
+    fn = getattr(_lib, MSTEP_NAMES[model.family])
+    _check(fn(ctypes.byref(model.c), _ptr(stats), None if opts is None else ctypes.byref(opts),
+              _ptr(theta_out), _ptr(collapsed), _ptr(iters), _stream(stream)))
+
+
+def em_iteration(model, batch, prec, stats, loglik, status, ws, opts=None, stream=None):
+    """One Baum-Welch iteration, in place on the device: E-step into `stats`,
+    then the transition and emission M-steps overwrite the model tensors."""
+    hmm_estep_stats(model, batch, prec, stats, loglik, status, ws, stream)
+    hmm_mstep_transitions(model, stats, opts, model.log_pi, model.log_A, stream)
+    hmm_mstep(model, stats, opts, model.theta, None, None, stream)
+
+
 def hmm_set_chunk_len(steps: int):
     _check(_lib.hmm_set_chunk_len(int(steps)))
 

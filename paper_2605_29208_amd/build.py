@@ -20,7 +20,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libhmmgpu.so")
 ARCH = "gfx950"
 
-SOURCES = ["abi.cpp", "k_stage.hip", "k_plain.hip", "k_chunk.hip", "k_viterbi.hip"]
+SOURCES = ["abi.cpp", "k_stage.hip", "k_plain.hip", "k_chunk.hip", "k_viterbi.hip", "k_mstep.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

@@ -472,25 +472,95 @@ void hmm_mstep_default_opts(hmm_mstep_opts *o) {
     o->t_nu_printed = 0;
 }
 
-#define HMM_MSTEP_STUB(name)                                                                   \
-    hmm_status name(const hmm_model *model, const double *stats, const hmm_mstep_opts *opts,    \
-                    double *theta_out, int32_t *collapsed, int32_t *iters, void *stream) {      \
-        (void)model; (void)stats; (void)opts; (void)theta_out; (void)collapsed; (void)iters;    \
-        (void)stream;                                                                          \
-        return fail(HMM_ERR_UNSUPPORTED, #name " is not built yet");                           \
+static size_t theta_len(const hmm_model *m) {
+    const size_t N = (size_t)m->n_states, D = (size_t)m->dim;
+    switch (m->family) {
+    case HMM_GAUSSIAN:
+    case HMM_GAMMA: return 2 * N;
+    case HMM_STUDENT_T: return 3 * N;
+    case HMM_POISSON: return N;
+    case HMM_DIAG_GAUSSIAN: return 2 * N * D;
+    case HMM_FULL_GAUSSIAN: return N * D + N * D * D;
+    default: return 0;
     }
-HMM_MSTEP_STUB(hmm_mstep_gaussian)
-HMM_MSTEP_STUB(hmm_mstep_gamma)
-HMM_MSTEP_STUB(hmm_mstep_student_t)
-HMM_MSTEP_STUB(hmm_mstep_poisson)
-HMM_MSTEP_STUB(hmm_mstep_diag_gaussian)
-HMM_MSTEP_STUB(hmm_mstep_full_gaussian)
+}
+
+static hmm_status mstep_family(int family, const char *name, const hmm_model *model,
+                               const double *stats, const hmm_mstep_opts *opts, double *theta_out,
+                               int32_t *collapsed, int32_t *iters, void *stream) {
+    hmm_status st = check_model(model);
+    if (st != HMM_OK) return st;
+    if (model->family != family)
+        return fail(HMM_ERR_ARG, "%s called for a model of family %d", name, model->family);
+    if (!stats || !theta_out) return fail(HMM_ERR_ARG, "%s: stats / theta_out is NULL", name);
+    hmm_mstep_opts o;
+    if (opts) o = *opts;
+    else hmm_mstep_default_opts(&o);
+    if (!(o.max_iter >= 1) || !(o.nu_min > 0) || !(o.nu_max >= o.nu_min))
+        return fail(HMM_ERR_ARG, "%s: invalid options", name);
+    hipStream_t s = (hipStream_t)stream;
+    const size_t n = theta_len(model);
+    if (theta_out != model->theta) {
+        // states that keep their parameters (collapse guard) keep the input values
+        hipError_t e = hipMemcpyAsync(theta_out, model->theta, n * sizeof(double),
+                                      hipMemcpyDeviceToDevice, s);
+        if (e != hipSuccess) return fail(HMM_ERR_DEVICE, "%s: copy: %s", name, hipGetErrorString(e));
+    }
+    launch_mstep_emission(family, model->n_states, model->dim, model->theta, stats, o, theta_out,
+                          collapsed, iters, s);
+    return device_check(name);
+}
+
+hmm_status hmm_mstep_gaussian(const hmm_model *model, const double *stats,
+                              const hmm_mstep_opts *opts, double *theta_out, int32_t *collapsed,
+                              int32_t *iters, void *stream) {
+    return mstep_family(HMM_GAUSSIAN, "hmm_mstep_gaussian", model, stats, opts, theta_out,
+                        collapsed, iters, stream);
+}
+hmm_status hmm_mstep_gamma(const hmm_model *model, const double *stats, const hmm_mstep_opts *opts,
+                           double *theta_out, int32_t *collapsed, int32_t *iters, void *stream) {
+    return mstep_family(HMM_GAMMA, "hmm_mstep_gamma", model, stats, opts, theta_out, collapsed,
+                        iters, stream);
+}
+hmm_status hmm_mstep_student_t(const hmm_model *model, const double *stats,
+                               const hmm_mstep_opts *opts, double *theta_out, int32_t *collapsed,
+                               int32_t *iters, void *stream) {
+    return mstep_family(HMM_STUDENT_T, "hmm_mstep_student_t", model, stats, opts, theta_out,
+                        collapsed, iters, stream);
+}
+hmm_status hmm_mstep_poisson(const hmm_model *model, const double *stats,
+                             const hmm_mstep_opts *opts, double *theta_out, int32_t *collapsed,
+                             int32_t *iters, void *stream) {
+    return mstep_family(HMM_POISSON, "hmm_mstep_poisson", model, stats, opts, theta_out,
+                        collapsed, iters, stream);
+}
+hmm_status hmm_mstep_diag_gaussian(const hmm_model *model, const double *stats,
+                                   const hmm_mstep_opts *opts, double *theta_out,
+                                   int32_t *collapsed, int32_t *iters, void *stream) {
+    return mstep_family(HMM_DIAG_GAUSSIAN, "hmm_mstep_diag_gaussian", model, stats, opts,
+                        theta_out, collapsed, iters, stream);
+}
+hmm_status hmm_mstep_full_gaussian(const hmm_model *model, const double *stats,
+                                   const hmm_mstep_opts *opts, double *theta_out,
+                                   int32_t *collapsed, int32_t *iters, void *stream) {
+    if (model && model->dim > 64) return fail(HMM_ERR_UNSUPPORTED, "full covariance needs D <= 64");
+    return mstep_family(HMM_FULL_GAUSSIAN, "hmm_mstep_full_gaussian", model, stats, opts,
+                        theta_out, collapsed, iters, stream);
+}
 
 hmm_status hmm_mstep_transitions(const hmm_model *model, const double *stats,
                                  const hmm_mstep_opts *opts, double *log_pi_out,
                                  double *log_A_out, void *stream) {
-    (void)model; (void)stats; (void)opts; (void)log_pi_out; (void)log_A_out; (void)stream;
-    return fail(HMM_ERR_UNSUPPORTED, "hmm_mstep_transitions is not built yet");
+    hmm_status st = check_model(model);
+    if (st != HMM_OK) return st;
+    if (!stats || !log_pi_out || !log_A_out)
+        return fail(HMM_ERR_ARG, "hmm_mstep_transitions: NULL pointer");
+    hmm_mstep_opts o;
+    if (opts) o = *opts;
+    else hmm_mstep_default_opts(&o);
+    launch_mstep_trans(model->n_states, stats, model->log_A, o.eps_collapse, log_pi_out, log_A_out,
+                       (hipStream_t)stream);
+    return device_check("hmm_mstep_transitions");
 }
 
 hmm_status hmm_profile_enable(int32_t on) {

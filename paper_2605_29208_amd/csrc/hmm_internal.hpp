@@ -136,6 +136,13 @@ hmm_status run_viterbi(const StagedModel<R> &m, const ObsDesc &o, const int *cba
                        const ChunkDesc *cdesc, int C, uint8_t *psi, uint8_t *J, uint8_t *qlast,
                        uint8_t *qend, int32_t *path, double *logp, hipStream_t s);
 
+// M-steps (section 4), FP64 on the device
+void launch_mstep_trans(int N, const double *stats, const double *log_A_in, double eps,
+                        double *log_pi_out, double *log_A_out, hipStream_t s);
+void launch_mstep_emission(int family, int N, int D, const double *theta_in,
+                           const double *stats, const hmm_mstep_opts &o, double *theta_out,
+                           int32_t *collapsed, int32_t *iters, hipStream_t s);
+
 // fixed-order reduction of per-block partial statistics + log-likelihood sum
 void launch_reduce_stats(const double *partial, int nparts, int64_t S, const double *loglik,
                          const int32_t *status, int64_t nseq, double *stats, hipStream_t s);
