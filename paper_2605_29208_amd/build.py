@@ -1,6 +1,6 @@
 """Build libhmmgpu.so (HIP for gfx950) in-tree.
 
-    python -m paper_2605_29208_amd.build
+    python paper_2605_29208_amd/build.py
 
 Every source under csrc/ is compiled to an object with hipcc, in parallel,
 and linked into paper_2605_29208_amd/libhmmgpu.so.  Objects go to
@@ -20,7 +20,8 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libhmmgpu.so")
 ARCH = "gfx950"
 
-SOURCES = ["abi.cpp", "k_stage.hip", "k_plain.hip", "k_chunk.hip", "k_viterbi.hip", "k_mstep.hip"]
+SOURCES = ["abi.cpp", "k_stage.hip", "k_plain.hip", "k_chunk.hip", "k_viterbi.hip", "k_mstep.hip",
+           "k_wave.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

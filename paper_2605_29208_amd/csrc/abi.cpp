@@ -108,7 +108,7 @@ hmm_status check_batch(const hmm_batch *b, const hmm_model *m, Checked *c) {
 
 // ---------------------------------------------------------------- planning
 struct Plan {
-    bool f64 = false, plain = false, chunked = false;
+    bool f64 = false, plain = false, chunked = false, wave = false;
     int G = 0, L = 0, C = 0, nblk = 0;
     int64_t S = 0;
     size_t staged = 0, cbase = 0, frec = 0, brec = 0, F = 0, Gb = 0, partial = 0;
@@ -117,6 +117,7 @@ struct Plan {
     size_t vpsi = 0, vJ = 0, vqlast = 0, vqend = 0;
     size_t ll = 0, st = 0, gam = 0;
     size_t logB = 0, alpha = 0, beta = 0, ps = 0;
+    size_t red = 0;
     size_t total = 0;
 };
 
@@ -175,13 +176,34 @@ hmm_status make_plan(hmm_op op, const Checked &c, hmm_precision prec, Plan *p) {
         p->alpha = take((size_t)c.total * N * r);
         p->beta = take((size_t)c.total * N * r);
         p->ps = take(((size_t)c.B * p->S + (size_t)c.B) * 8);
+        p->red = take((size_t)reduce_scratch_len(c.B, p->S) * 8);
     } else {
         const bool scalar = c.fam <= HMM_POISSON || c.fam == HMM_TABLE;
-        if (!(N <= 8 && scalar))
+        if (!(N <= 64 && scalar))
             return fail(HMM_ERR_UNSUPPORTED,
-                        "batched path: this build covers N <= 8 with scalar or table emissions "
+                        "batched path: this build covers N <= 64 with scalar or table emissions "
                         "(N = %d, family %d); use a PLAIN precision",
                         N, c.fam);
+        if (N > 8) {
+            // per-sequence sweeps + one wave per chunk of WAVE_L steps
+            p->wave = true;
+            p->L = WAVE_L;
+            int64_t C = 0;
+            for (int64_t b = 0; b < c.B; ++b) C += (c.h_off[b + 1] - c.h_off[b] + WAVE_L - 1) / WAVE_L;
+            if (C > INT32_MAX / 64) return fail(HMM_ERR_UNSUPPORTED, "too many chunks");
+            p->C = (int)C;
+            p->nblk = wave_stats_blocks((int)C, N);
+            const int np = wave_np(N);
+            p->cbase = take((size_t)(c.B + 1) * 4);
+            p->sbase = take((size_t)(c.B + 1) * 4);
+            p->cdesc = take((size_t)C * sizeof(ChunkDesc));
+            p->F = take((size_t)C * np * r);
+            p->Gb = take((size_t)C * np * r);
+            p->partial = take((size_t)p->nblk * p->S * 8);
+            p->red = take((size_t)reduce_scratch_len(p->nblk, p->S) * 8);
+            p->total = off;
+            return HMM_OK;
+        }
         p->chunked = true;
         p->G = N <= 4 ? 4 : 8;
         p->L = default_chunk_len(p->f64);
@@ -204,6 +226,7 @@ hmm_status make_plan(hmm_op op, const Checked &c, hmm_precision prec, Plan *p) {
         p->F = take((size_t)(C + 1) * p->G * r);    // + one sink slot
         p->Gb = take((size_t)(C + 1) * p->G * r);
         p->partial = take((size_t)p->nblk * p->S * 8);
+        p->red = take((size_t)reduce_scratch_len(p->nblk, p->S) * 8);
         const size_t rb = chunk_rec_bytes(p->f64, p->G);
         p->sbase = take((size_t)(c.B + 1) * 4);
         p->cdesc = take((size_t)C * sizeof(ChunkDesc));
@@ -246,13 +269,28 @@ hmm_status run_posterior_path(const hmm_model *m, const hmm_batch *b, const Chec
     int32_t *st = status ? status : (int32_t *)(ws + p.st);
     ObsDesc od{b->obs, b->obs_f64, c.B, b->offsets};
     if (c.B == 0) {
-        if (stats) launch_reduce_stats(nullptr, 0, p.S, ll, st, 0, stats, s);
+        if (stats) launch_reduce_stats(nullptr, 0, p.S, ll, st, 0, stats, nullptr, s);
         return device_check("estep (empty batch)");
     }
     hmm_status r;
     if (p.plain) {
-        PlainBuffers pb{ws + p.logB, ws + p.alpha, ws + p.beta, (double *)(ws + p.ps)};
+        PlainBuffers pb{ws + p.logB, ws + p.alpha, ws + p.beta, (double *)(ws + p.ps),
+                        (double *)(ws + p.red)};
         r = run_plain<R>(sm, od, pb, ll, st, gamma_out, stats, p.S, s);
+    } else if (p.wave) {
+        WaveBuffers wb;
+        wb.C = p.C;
+        wb.nblk = p.nblk;
+        wb.cbase = (int *)(ws + p.cbase);
+        wb.cdesc = (ChunkDesc *)(ws + p.cdesc);
+        wb.F = ws + p.F;
+        wb.Gb = ws + p.Gb;
+        wb.partial = (double *)(ws + p.partial);
+        wb.red = (double *)(ws + p.red);
+        int *sbase = (int *)(ws + p.sbase);
+        launch_plan_chunks(b->offsets, c.B, p.L, 1, wb.cbase, sbase, s);
+        launch_chunk_desc(b->offsets, c.B, p.L, 1, wb.cbase, sbase, p.C, 0, wb.cdesc, nullptr, s);
+        r = run_wave<R>(sm, od, wb, ll, st, gamma_out, stats, p.S, s);
     } else {
         ChunkBuffers cb;
         cb.L = p.L;
@@ -265,6 +303,7 @@ hmm_status run_posterior_path(const hmm_model *m, const hmm_batch *b, const Chec
         cb.F = ws + p.F;
         cb.Gb = ws + p.Gb;
         cb.partial = (double *)(ws + p.partial);
+        cb.red = (double *)(ws + p.red);
         cb.S = p.SS;
         cb.SC = p.SC;
         cb.sbase = (int *)(ws + p.sbase);

@@ -107,6 +107,7 @@ struct ChunkBuffers {
     void *F;             // [C*G] R  alpha at each chunk end (normalised)
     void *Gb;            // [C*G] R  beta at each chunk end (normalised)
     double *partial;     // [nblk_stats * S]
+    double *red;         // reduction scratch (reduce_scratch_len doubles)
 };
 // bytes of one transfer-matrix record (see k_chunk.hip)
 size_t chunk_rec_bytes(bool f64, int G);
@@ -115,10 +116,30 @@ hmm_status run_chunked(const StagedModel<R> &m, const ObsDesc &o, const ChunkBuf
                        double *loglik, int32_t *status, void *gamma_out, double *stats,
                        int64_t stats_len, hipStream_t s);
 
+// batched path for 8 < N <= 64: per-sequence sweeps give alpha/beta at the
+// ends of chunks of WAVE_L steps, one lane group per chunk forms the statistics
+struct WaveBuffers {
+    int C, nblk;
+    int *cbase;          // [B+1]
+    ChunkDesc *cdesc;    // [C]
+    void *F;             // [C*NP] R  alpha at each chunk end (normalised)
+    void *Gb;            // [C*NP] R  beta at each chunk end (normalised)
+    double *partial;     // [nblk * S]
+    double *red;         // reduction scratch (reduce_scratch_len doubles)
+};
+constexpr int WAVE_L = 32;          // chunk length of the wave path
+int wave_np(int N);                 // lanes per group = padded state count (16, 32 or 64)
+int wave_stats_blocks(int C, int N);   // blocks (= partial rows) of the statistics kernel
+template <typename R>
+hmm_status run_wave(const StagedModel<R> &m, const ObsDesc &o, const WaveBuffers &wb,
+                    double *loglik, int32_t *status, void *gamma_out, double *stats,
+                    int64_t stats_len, hipStream_t s);
+
 // plain path (one thread per sequence, literal log-sum-exp)
 struct PlainBuffers {
     void *logB, *alpha, *beta;   // [sum T * N] R
     double *ps;                  // [B * S] per-sequence statistics
+    double *red;                 // reduction scratch (reduce_scratch_len doubles)
 };
 template <typename R>
 hmm_status run_plain(const StagedModel<R> &m, const ObsDesc &o, const PlainBuffers &pb,
@@ -143,8 +164,11 @@ void launch_mstep_emission(int family, int N, int D, const double *theta_in,
                            const double *stats, const hmm_mstep_opts &o, double *theta_out,
                            int32_t *collapsed, int32_t *iters, hipStream_t s);
 
-// fixed-order reduction of per-block partial statistics + log-likelihood sum
+// fixed-order reduction of per-block partial statistics + log-likelihood sum;
+// red is scratch of reduce_scratch_len(nparts, S) doubles
+int64_t reduce_scratch_len(int64_t nparts, int64_t S);
 void launch_reduce_stats(const double *partial, int nparts, int64_t S, const double *loglik,
-                         const int32_t *status, int64_t nseq, double *stats, hipStream_t s);
+                         const int32_t *status, int64_t nseq, double *stats, double *red,
+                         hipStream_t s);
 
 }  // namespace hmmk

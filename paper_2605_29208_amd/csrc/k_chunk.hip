@@ -808,7 +808,7 @@ static hmm_status run_chunked_g(const StagedModel<R> &m, const ObsDesc &o, const
         return HMM_ERR_UNSUPPORTED;
     }
     if (stats)
-        launch_reduce_stats(cb.partial, cb.nblk_stats, S, loglik, status, o.nseq, stats, s);
+        launch_reduce_stats(cb.partial, cb.nblk_stats, S, loglik, status, o.nseq, stats, cb.red, s);
     return HMM_OK;
 }
 

@@ -277,7 +277,7 @@ hmm_status run_plain(const StagedModel<R> &m, const ObsDesc &o, const PlainBuffe
                      hipStream_t s) {
     const unsigned nb = (unsigned)((o.nseq + 63) / 64);
     if (nb == 0) {
-        if (stats) launch_reduce_stats(pb.ps, 0, S, loglik, status, 0, stats, s);
+        if (stats) launch_reduce_stats(pb.ps, 0, S, loglik, status, 0, stats, pb.red, s);
         return HMM_OK;
     }
     ObsRef obs{o.obs, o.obs_f64};
@@ -305,7 +305,7 @@ hmm_status run_plain(const StagedModel<R> &m, const ObsDesc &o, const PlainBuffe
                            (const R *)logB, (const R *)alpha, (const R *)beta,
                            (const int32_t *)status, pb.ps, S, K, (R *)gamma_out);
     }
-    if (stats) launch_reduce_stats(pb.ps, (int)o.nseq, S, loglik, status, o.nseq, stats, s);
+    if (stats) launch_reduce_stats(pb.ps, (int)o.nseq, S, loglik, status, o.nseq, stats, pb.red, s);
     return HMM_OK;
 }
 

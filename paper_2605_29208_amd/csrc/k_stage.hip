@@ -135,13 +135,13 @@ __global__ __launch_bounds__(BLOCK) void k_stage(RawModel m, R *pi, R *A, R *lpi
         *perr = any;
         double a = 1.0;
         for (int t = 0; t < BLOCK; ++t) a = fmin(a, amin_sh[t]);
-        // A product of forward-type steps (row vector times A diag(e), max e = 1)
-        // grows by at most N <= 8 and shrinks by at most min a_ij per step, so
-        // rescaling every 4 steps keeps single precision in range when
-        // min a_ij >= 2^-25 (2^-200 for double).
+        // The largest entry of a product of forward-type steps (row vector times
+        // A diag(e), max e = 1) grows by at most N <= 1024 = 2^10 and shrinks by
+        // at most min a_ij per step, so rescaling every 4 steps keeps single
+        // precision in range when min a_ij >= 2^-25 (2^-200 for double).
         const double lim4 = sizeof(R) == 4 ? 0x1p-25 : 0x1p-200;
         const double lim2 = sizeof(R) == 4 ? 0x1p-50 : 0x1p-400;
-        *nrm = (N <= 8 && a >= lim4) ? 4 : ((N <= 8 && a >= lim2) ? 2 : 1);
+        *nrm = a >= lim4 ? 4 : (a >= lim2 ? 2 : 1);
     }
 }
 
@@ -274,34 +274,70 @@ void launch_chunk_desc(const int64_t *offsets, int64_t nseq, int L, int S, const
                        nseq, L, S, cbase, sbase, C, SC, cdesc, sdesc);
 }
 
-// stats[s] = sum over parts of partial[p*S + s] (s >= 1) in a fixed order;
-// stats[0] = sum of loglik[b] over sequences with status 0.
-__global__ __launch_bounds__(BLOCK) void k_reduce_stats(const double *partial, int nparts, int64_t S,
-                                                       const double *loglik, const int32_t *status,
-                                                       int64_t nseq, double *stats) {
-    __shared__ double sh[BLOCK];
-    const int64_t s = blockIdx.x;
+// Pooled statistics from per-part rows partial[p * S + s] (p < nparts), in a
+// fixed order so that repeated calls give identical bits.  Parts are summed in
+// groups of RED_G (pass 1, one thread per (entry, group), coalesced over
+// entries), then the groups in order (pass 2).  Entry 0 is the sum of the
+// log-likelihoods of the sequences with status 0 (a block tree of its own).
+constexpr int RED_G = 64;
+
+int64_t reduce_scratch_len(int64_t nparts, int64_t S) {
+    return nparts > RED_G ? ((nparts + RED_G - 1) / RED_G) * S : 0;
+}
+
+__global__ __launch_bounds__(BLOCK) void k_reduce_parts(const double *__restrict__ partial,
+                                                       int nparts, int64_t S,
+                                                       double *__restrict__ red) {
+    const int64_t s = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    const int g = blockIdx.y;
+    if (s >= S) return;
+    const int p1 = min(nparts, (g + 1) * RED_G);
     double acc = 0.0;
-    if (s == 0) {
+    for (int p = g * RED_G; p < p1; ++p) acc += partial[(int64_t)p * S + s];
+    red[(int64_t)g * S + s] = acc;
+}
+
+__global__ __launch_bounds__(BLOCK) void k_reduce_final(const double *__restrict__ rows, int nrows,
+                                                       int64_t S, const double *loglik,
+                                                       const int32_t *status, int64_t nseq,
+                                                       double *stats) {
+    if (blockIdx.x == gridDim.x - 1) {
+        __shared__ double sh[BLOCK];
+        double acc = 0.0;
         for (int64_t b = threadIdx.x; b < nseq; b += BLOCK)
             if (status[b] == 0) acc += loglik[b];
-    } else {
-        for (int p = threadIdx.x; p < nparts; p += BLOCK) acc += partial[(int64_t)p * S + s];
-    }
-    sh[threadIdx.x] = acc;
-    __syncthreads();
-    for (int o = BLOCK / 2; o > 0; o >>= 1) {
-        if (threadIdx.x < (unsigned)o) sh[threadIdx.x] += sh[threadIdx.x + o];
+        sh[threadIdx.x] = acc;
         __syncthreads();
+        for (int o = BLOCK / 2; o > 0; o >>= 1) {
+            if (threadIdx.x < (unsigned)o) sh[threadIdx.x] += sh[threadIdx.x + o];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) stats[0] = sh[0];
+        return;
     }
-    if (threadIdx.x == 0) stats[s] = sh[0];
+    const int64_t s = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (s < 1 || s >= S) return;
+    double acc = 0.0;
+    for (int r = 0; r < nrows; ++r) acc += rows[(int64_t)r * S + s];
+    stats[s] = acc;
 }
 
 void launch_reduce_stats(const double *partial, int nparts, int64_t S, const double *loglik,
-                         const int32_t *status, int64_t nseq, double *stats, hipStream_t s) {
+                         const int32_t *status, int64_t nseq, double *stats, double *red,
+                         hipStream_t s) {
     ProfScope ps("reduce_stats", s);
-    hipLaunchKernelGGL(k_reduce_stats, dim3((unsigned)S), dim3(BLOCK), 0, s, partial, nparts, S,
-                       loglik, status, nseq, stats);
+    const unsigned sb = (unsigned)((S + BLOCK - 1) / BLOCK);
+    const double *rows = partial;
+    int nrows = nparts;
+    if (nparts > RED_G) {
+        const int ng = (nparts + RED_G - 1) / RED_G;
+        hipLaunchKernelGGL(k_reduce_parts, dim3(sb, (unsigned)ng), dim3(BLOCK), 0, s, partial,
+                           nparts, S, red);
+        rows = red;
+        nrows = ng;
+    }
+    hipLaunchKernelGGL(k_reduce_final, dim3(sb + 1), dim3(BLOCK), 0, s, rows, nrows, S, loglik,
+                       status, nseq, stats);
 }
 
 }  // namespace hmmk
