@@ -1,7 +1,9 @@
-"""Benchmark: one Baum-Welch E-step over the batched ragged workload.
+"""Benchmark: one Baum-Welch E-step over a batch of ragged sequences.
 
-Workload: 1024 sequences with lengths uniform in {500..5000}, N = 8 Gamma
-states (shape U[1,10], scale U[0.5,3]), sticky A (a_ii = 0.95), FP32
+Default workload (--workload batched): 1024 sequences with lengths uniform in
+{500..5000}, N = 8 Gamma states (shape U[1,10], scale U[0.5,3]), sticky A
+(a_ii = 0.95).  --workload heavy: 512 sequences with log-normal lengths
+(median 3000, sigma 0.6, at most 20,000), N = 32 Student-t states.  FP32
 observations resident in device memory.  One step = one full E-step
 (parameter staging, emission log-densities, forward and backward
 recursions, posteriors and the pooled sufficient statistics).
@@ -46,7 +48,21 @@ def algorithmic_flops(name, w):
     if name == "chunk_product":
         # chunk transfer matrices: N^3 FMA per step after each sequence's first
         return 2.0 * (steps - w.n_seq) * n ** 3
+    if name == "wave_stats":
+        # chunk forward alpha*A, backward A*w and the xi outer product
+        return 6.0 * steps * n * n
+    if name == "wave_sweep":
+        # forward alpha*A and backward A*w over every sequence
+        return 4.0 * steps * n * n
     return None
+
+
+WORKLOADS = {
+    "batched": ("batched ragged E-step: B=1024, T~U{500..5000}, N=8 Gamma, FP32 obs",
+                lambda workloads: workloads.config2()),
+    "heavy": ("heavy-tailed E-step: B=512, T~lognormal(median 3000, sigma 0.6, <=20000), "
+              "N=32 Student-t, FP32 obs", lambda workloads: workloads.config4b()),
+}
 
 
 def cpu_model():
@@ -75,6 +91,7 @@ def cpu_baseline(w, reps=2):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--workload", default="batched", choices=sorted(WORKLOADS))
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--prec", default="f32", choices=["f32", "f64"])
@@ -94,7 +111,8 @@ def main():
     import workloads
 
     h.hmm_set_chunk_len(args.chunk)
-    w = workloads.config2()
+    wl_name, wl_make = WORKLOADS[args.workload]
+    w = wl_make(workloads)
     dm = h.DeviceModel.from_model(w.model)
     db = h.DeviceBatch(w.obs, w.offsets, dtype=np.float32 if args.prec == "f32" else np.float64)
     prec = args.prec
@@ -163,7 +181,8 @@ def main():
         plain_ms = t0.elapsed_time(t1) / args.plain_steps
         del pws
 
-    # Baum-Welch: FP32 E-step + FP64 Gamma Newton M-step, em_iters iterations
+    # Baum-Welch: E-step + FP64 M-step of the family (Gamma Newton, Student-t ECM),
+    # em_iters iterations
     # captured once in a HIP graph and replayed
     em = None
     if args.em_iters > 0:
@@ -225,8 +244,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f32" if prec == "f32" else "f64",
         "data": "synthetic",
-        "config": {"workload": "batched ragged E-step: B=1024, T~U{500..5000}, N=8 Gamma, "
-                               "FP32 obs", "global_batch": w.n_seq, "total_steps": w.total_steps,
+        "config": {"workload": wl_name, "global_batch": w.n_seq, "total_steps": w.total_steps,
                    "transitions_per_step": w.transitions, "precision": prec},
         "plain_gpu": None if plain_ms is None else {
             "value": w.transitions / (plain_ms / 1e3), "ms_per_step": plain_ms,

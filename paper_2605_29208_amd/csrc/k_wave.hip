@@ -87,6 +87,30 @@ __device__ __forceinline__ double grp_all(double v) {
     return v;
 }
 
+// maximum of non-negative values: for floats an unsigned maximum of the bit
+// patterns (monotone for x >= 0, and no canonicalisation of the operands)
+template <int G>
+__device__ __forceinline__ float grp_max_nn(float v) {
+    uint32_t u = __builtin_bit_cast(uint32_t, v);
+    u = max(u, (uint32_t)dpp_i<DPP_QP_X1>((int)u));
+    u = max(u, (uint32_t)dpp_i<DPP_QP_X2>((int)u));
+    u = max(u, (uint32_t)dpp_i<DPP_HALF_MIRROR>((int)u));
+    u = max(u, (uint32_t)dpp_i<DPP_ROW_MIRROR>((int)u));
+    if constexpr (G >= 32) {
+        auto r = __builtin_amdgcn_permlane16_swap(u, u, false, false);
+        u = max((uint32_t)r[0], (uint32_t)r[1]);
+    }
+    if constexpr (G == 64) {
+        auto r = __builtin_amdgcn_permlane32_swap(u, u, false, false);
+        u = max((uint32_t)r[0], (uint32_t)r[1]);
+    }
+    return __builtin_bit_cast(float, u);
+}
+template <int G>
+__device__ __forceinline__ double grp_max_nn(double v) {
+    return grp_all<G, true>(v);
+}
+
 // sum of a value over the groups of the wave (same state position), fixed order
 template <int G>
 __device__ __forceinline__ double across_groups(double v) {
@@ -167,6 +191,15 @@ __device__ __forceinline__ R lds_dot(const R *v, const R (&c)[NP]) {
     return acc0 + acc1;
 }
 
+// Orders this wave's LDS accesses around a lane exchange.  LDS instructions of
+// one wave are performed in program order, so a wavefront-scope fence (which
+// only stops the compiler from moving accesses across it) is enough between
+// the lanes' store of a vector and their broadcast reads of it: no wait for
+// the store to complete.
+__device__ __forceinline__ void wave_lds_order() {
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+}
+
 // ---------------------------------------------------------------- sweeps
 // Task 2b is the forward sweep of sequence b (alpha at chunk ends, logL and
 // status), task 2b + 1 its backward sweep (beta at chunk ends).  Loops run to
@@ -179,7 +212,6 @@ __global__ __launch_bounds__(64) void k_wave_sweep(WaveGeom g, StagedModel<R> m,
     constexpr int NG = 64 / NP;
     constexpr int VS = NP + 4;
     __shared__ R esh[NG][WL][NP + 1];
-    __shared__ double msh[NG][WL];
     __shared__ __align__(16) R vsh[NG][VS];
     using ET = typename EmitTraits<FAM, R>::T;
     const ET *ep = consts_ptr<FAM, R>(m);
@@ -215,29 +247,32 @@ __global__ __launch_bounds__(64) void k_wave_sweep(WaveGeom g, StagedModel<R> m,
         const int w0 = c * WL;
         const int wn = act ? min(WL, T - w0) : 0;
         __syncthreads();
+        double msum = 0.0;   // this lane's share of the window's log shifts
         for (int q = j; q < wn; q += NP) {
             R y, ly;
-            msh[grp][q] = tab_step<R, NP, FAM>(g, N, off + w0 + q, ep, &esh[grp][q][0], &y, &ly, &bad);
+            msum += tab_step<R, NP, FAM>(g, N, off + w0 + q, ep, &esh[grp][q][0], &y, &ly, &bad);
         }
+        const double wsum = grp_all<NP, false>(msum);
+        if (fwd) logS += wsum;
         __syncthreads();
+        // step s of the window is local step s (forward) or wn - 1 - s (backward);
+        // the next step's emission factor is read one step ahead
+        R e_cur = (wn > 0) ? esh[grp][fwd ? 0 : wn - 1][j] : (R)0;
         for (int s = 0; s < WL; ++s) {
             const bool on = s < wn;
-            const int sl = on ? (fwd ? s : wn - 1 - s) : 0;   // local step of the window
-            const int t = w0 + sl;
-            const R e = on ? esh[grp][sl][j] : (R)0;
-            vsh[grp][j] = fwd ? v : e * v;
-            __syncthreads();
+            const int t = w0 + (fwd ? s : wn - 1 - s);
+            vsh[grp][j] = fwd ? v : e_cur * v;
+            wave_lds_order();
             const R acc = lds_dot<R, NP>(&vsh[grp][0], coef);
-            __syncthreads();
-            const R nv = fwd ? ((t == 0) ? (live ? m.pi[j] * e : (R)0) : e * acc) : acc;
-            const int ex = fexp(grp_all<NP, true>(nv));
+            const R e_nxt = (s + 1 < wn) ? esh[grp][fwd ? s + 1 : wn - 2 - s][j] : (R)0;
+            wave_lds_order();
+            const R nv = fwd ? ((t == 0) ? (live ? m.pi[j] * e_cur : (R)0) : e_cur * acc) : acc;
+            const int ex = fexp(grp_max_nn<NP>(nv));
             if (on) {
                 v = fldexp(nv, -ex);
-                if (fwd) {
-                    E += ex;
-                    logS += msh[grp][sl];
-                }
+                if (fwd) E += ex;
             }
+            e_cur = e_nxt;
         }
         if (act) {
             if (fwd) F[(size_t)(cb + c) * NP + j] = v;
@@ -352,15 +387,17 @@ __global__ __launch_bounds__(64) void k_wave_stats(WaveGeom g, StagedModel<R> m,
         // forward steps of the chunk
         const R ap = (!valid || first || !live) ? (R)0 : F[(size_t)(c - 1) * NP + j];
         R a = ap;
+        R e_cur = (len > 0) ? esh[grp][0][j] : (R)0;
         for (int s = 0; s < lmax; ++s) {
             const bool on = s < len;
-            const R e = on ? esh[grp][s][j] : (R)0;
+            const R e = e_cur;
             vsh[grp][j] = a;
-            __syncthreads();
+            wave_lds_order();
             const R acc = lds_dot<R, NP>(&vsh[grp][0], coefC);
-            __syncthreads();
+            e_cur = (s + 1 < len) ? esh[grp][s + 1][j] : (R)0;
+            wave_lds_order();
             const R nv = (first && s == 0) ? (live ? pi_j * e : (R)0) : e * acc;
-            const int ex = fexp(grp_all<NP, true>(nv));
+            const int ex = fexp(grp_max_nn<NP>(nv));
             if (on) {
                 a = fldexp(nv, -ex);
                 ash[grp][s][j] = a;
@@ -389,13 +426,15 @@ __global__ __launch_bounds__(64) void k_wave_stats(WaveGeom g, StagedModel<R> m,
             }
         }
         const int s_stop = first ? 1 : 0;
+        e_cur = (len - 1 >= s_stop) ? esh[grp][len > 0 ? len - 1 : 0][j] : (R)0;
         for (int s = lmax - 1; s >= 0; --s) {
             const bool on = s < len && s >= s_stop;
-            const R e = on ? esh[grp][s][j] : (R)0;
+            const R e = on ? e_cur : (R)0;
             vsh[grp][j] = e * be;
-            __syncthreads();
+            wave_lds_order();
             const R bp = lds_dot<R, NP>(&vsh[grp][0], coefR);
-            const int ex = fexp(grp_all<NP, true>(bp));
+            if (on) e_cur = (s - 1 >= s_stop) ? esh[grp][s > 0 ? s - 1 : 0][j] : (R)0;
+            const int ex = fexp(grp_max_nn<NP>(bp));
             const R bn = fldexp(bp, -ex);
             const R xp = (s > 0) ? ash[grp][s > 0 ? s - 1 : 0][j] : ap;
             const R h = on ? xp * bn : (R)0;
@@ -407,7 +446,7 @@ __global__ __launch_bounds__(64) void k_wave_stats(WaveGeom g, StagedModel<R> m,
 #pragma unroll
                 for (int k = 0; k < UN; ++k) U[k] = fma(xr, vsh[grp][k], U[k]);
             }
-            __syncthreads();
+            wave_lds_order();
             if (on) {
                 if (s > 0 && own) {
                     const R gmv = h * rz;
