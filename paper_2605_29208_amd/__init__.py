@@ -33,7 +33,11 @@ EXPORTED = [
     "hmm_mstep_gaussian", "hmm_mstep_gamma", "hmm_mstep_student_t", "hmm_mstep_poisson",
     "hmm_mstep_diag_gaussian", "hmm_mstep_full_gaussian", "hmm_set_chunk_len",
     "hmm_profile_enable", "hmm_profile_count", "hmm_profile_get", "hmm_profile_reset",
+    # include/hmm_serve.h
+    "hmm_server_default_opts", "hmm_server_now", "hmm_server_create", "hmm_server_destroy",
+    "hmm_server_add_model", "hmm_server_submit", "hmm_server_poll", "hmm_server_get_info",
 ]
+REQ = {"viterbi": 0, "posterior_decode": 1}
 
 
 class HmmError(RuntimeError):
@@ -62,9 +66,30 @@ class HmmMstepOptsC(ctypes.Structure):
                 ("max_iter", ctypes.c_int32), ("t_nu_printed", ctypes.c_int32)]
 
 
+class HmmServerOptsC(ctypes.Structure):
+    _fields_ = [("hbm_budget", ctypes.c_size_t), ("host_staging", ctypes.c_size_t),
+                ("max_batch", ctypes.c_int32), ("n_streams", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("device", ctypes.c_int32)]
+
+
+class HmmCompletionC(ctypes.Structure):
+    _fields_ = [("id", ctypes.c_uint64), ("model", ctypes.c_int32), ("kind", ctypes.c_int32),
+                ("status", ctypes.c_int32), ("batch_size", ctypes.c_int32),
+                ("T", ctypes.c_int64), ("logp", ctypes.c_double),
+                ("t_submit", ctypes.c_double), ("t_launch", ctypes.c_double),
+                ("t_done", ctypes.c_double)]
+
+
+class HmmServerInfoC(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64),
+                ("launches", ctypes.c_int64), ("pending", ctypes.c_int64),
+                ("in_flight", ctypes.c_int64), ("pool_bytes", ctypes.c_size_t),
+                ("pool_used", ctypes.c_size_t), ("pool_peak", ctypes.c_size_t)]
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
-        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2605_29208_amd.build`")
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python paper_2605_29208_amd/build.py`")
     lib = ctypes.CDLL(LIB_PATH)
     P, i32, i64, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
     MP, BP = ctypes.POINTER(HmmModelC), ctypes.POINTER(HmmBatchC)
@@ -87,6 +112,16 @@ def _load():
         "hmm_profile_get": ([i32, ctypes.POINTER(ctypes.c_char_p), ctypes.POINTER(ctypes.c_float)],
                             ctypes.c_int),
         "hmm_profile_reset": ([], ctypes.c_int),
+        "hmm_server_default_opts": ([ctypes.POINTER(HmmServerOptsC)], None),
+        "hmm_server_now": ([], ctypes.c_double),
+        "hmm_server_create": ([ctypes.POINTER(HmmServerOptsC), ctypes.POINTER(P)], ctypes.c_int),
+        "hmm_server_destroy": ([P], ctypes.c_int),
+        "hmm_server_add_model": ([P, MP, ctypes.POINTER(i32)], ctypes.c_int),
+        "hmm_server_submit": ([P, i32, i32, P, i32, i64, P, ctypes.POINTER(ctypes.c_uint64)],
+                              ctypes.c_int),
+        "hmm_server_poll": ([P, ctypes.POINTER(HmmCompletionC), i32, i32, ctypes.POINTER(i32)],
+                            ctypes.c_int),
+        "hmm_server_get_info": ([P, ctypes.POINTER(HmmServerInfoC)], ctypes.c_int),
     }
     for fam in ("gaussian", "gamma", "student_t", "poisson", "diag_gaussian", "full_gaussian"):
         sig[f"hmm_mstep_{fam}"] = ([MP, P, OPP, P, P, P, P], ctypes.c_int)
@@ -346,3 +381,93 @@ def posterior_decode(model, batch, prec="f32", ws=None, stream=None):
         ws = _ws(hmm_workspace_size("posterior_decode", model, batch, prec))
     hmm_posterior_decode(model, batch, prec, path, loglik, ws, stream)
     return path[:batch.total], loglik[:batch.n_seq]
+
+
+# --------------------------------------------------------------------------
+# serving runtime (include/hmm_serve.h)
+# --------------------------------------------------------------------------
+
+def hmm_server_default_opts() -> HmmServerOptsC:
+    o = HmmServerOptsC()
+    _lib.hmm_server_default_opts(ctypes.byref(o))
+    return o
+
+
+def hmm_server_now() -> float:
+    return _lib.hmm_server_now()
+
+
+class Server:
+    """Owns one hmm_server.  Models are registered from DeviceModel objects;
+    submit() takes host observations and a host int32 path buffer that the
+    server fills before the request's completion is returned by poll()."""
+
+    def __init__(self, hbm_budget=None, host_staging=None, max_batch=None, n_streams=None,
+                 prec="f32", device=0):
+        o = hmm_server_default_opts()
+        if hbm_budget is not None:
+            o.hbm_budget = int(hbm_budget)
+        if host_staging is not None:
+            o.host_staging = int(host_staging)
+        if max_batch is not None:
+            o.max_batch = int(max_batch)
+        if n_streams is not None:
+            o.n_streams = int(n_streams)
+        o.precision = PREC[prec]
+        o.device = int(device)
+        h = ctypes.c_void_p()
+        _check(_lib.hmm_server_create(ctypes.byref(o), ctypes.byref(h)))
+        self._h = h
+        self._bufs = {}      # id -> (path buffer, obs copy kept for the caller's convenience)
+        self.opts = o
+
+    def add_model(self, model: "DeviceModel") -> int:
+        mid = ctypes.c_int32()
+        _check(_lib.hmm_server_add_model(self._h, ctypes.byref(model.c), ctypes.byref(mid)))
+        return mid.value
+
+    def submit(self, model_id: int, kind: str, obs, path_out: Optional[np.ndarray] = None):
+        obs = np.ascontiguousarray(obs)
+        f64 = obs.dtype == np.float64
+        if not f64:
+            obs = np.ascontiguousarray(obs, dtype=np.float32)
+        T = int(obs.shape[0])
+        if path_out is None:
+            path_out = np.empty(T, dtype=np.int32)
+        assert path_out.dtype == np.int32 and path_out.flags.c_contiguous and path_out.size >= T
+        rid = ctypes.c_uint64()
+        _check(_lib.hmm_server_submit(self._h, int(model_id), REQ[kind],
+                                      obs.ctypes.data_as(ctypes.c_void_p), 1 if f64 else 0, T,
+                                      path_out.ctypes.data_as(ctypes.c_void_p),
+                                      ctypes.byref(rid)))
+        self._bufs[rid.value] = path_out
+        return rid.value
+
+    def poll(self, max_n=256, timeout_us=0):
+        arr = (HmmCompletionC * max_n)()
+        n = ctypes.c_int32()
+        _check(_lib.hmm_server_poll(self._h, arr, int(max_n), int(timeout_us), ctypes.byref(n)))
+        out = []
+        for i in range(n.value):
+            c = arr[i]
+            out.append({"id": c.id, "model": c.model, "kind": c.kind, "status": c.status,
+                        "batch_size": c.batch_size, "T": c.T, "logp": c.logp,
+                        "t_submit": c.t_submit, "t_launch": c.t_launch, "t_done": c.t_done,
+                        "path": self._bufs.pop(c.id, None)})
+        return out
+
+    def info(self):
+        i = HmmServerInfoC()
+        _check(_lib.hmm_server_get_info(self._h, ctypes.byref(i)))
+        return {k: getattr(i, k) for k, _ in HmmServerInfoC._fields_}
+
+    def close(self):
+        if self._h:
+            _check(_lib.hmm_server_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

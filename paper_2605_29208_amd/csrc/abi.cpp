@@ -361,6 +361,38 @@ void launch_argmax_rows(const void *gamma, bool f64, int64_t rows, int N, int32_
                         hipStream_t s);
 }
 
+static size_t theta_len(const hmm_model *m) {
+    const size_t N = (size_t)m->n_states, D = (size_t)m->dim;
+    switch (m->family) {
+    case HMM_GAUSSIAN:
+    case HMM_GAMMA: return 2 * N;
+    case HMM_STUDENT_T: return 3 * N;
+    case HMM_POISSON: return N;
+    case HMM_DIAG_GAUSSIAN: return 2 * N * D;
+    case HMM_FULL_GAUSSIAN: return N * D + N * D * D;
+    default: return 0;
+    }
+}
+
+namespace hmmk {
+hmm_status fail_status(hmm_status st, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+hmm_status model_theta_len(const hmm_model *m, size_t *len) {
+    hmm_status st = check_model(m);
+    if (st != HMM_OK) return st;
+    *len = theta_len(m);
+    return HMM_OK;
+}
+}  // namespace hmmk
+
 extern "C" {
 
 const char *hmm_version(void) { return "hmmgpu 0.1.0 (gfx950)"; }
@@ -509,19 +541,6 @@ void hmm_mstep_default_opts(hmm_mstep_opts *o) {
     o->nu_max = 1e4;
     o->max_iter = 100;
     o->t_nu_printed = 0;
-}
-
-static size_t theta_len(const hmm_model *m) {
-    const size_t N = (size_t)m->n_states, D = (size_t)m->dim;
-    switch (m->family) {
-    case HMM_GAUSSIAN:
-    case HMM_GAMMA: return 2 * N;
-    case HMM_STUDENT_T: return 3 * N;
-    case HMM_POISSON: return N;
-    case HMM_DIAG_GAUSSIAN: return 2 * N * D;
-    case HMM_FULL_GAUSSIAN: return N * D + N * D * D;
-    default: return 0;
-    }
 }
 
 static hmm_status mstep_family(int family, const char *name, const hmm_model *model,

@@ -164,6 +164,11 @@ void launch_mstep_emission(int family, int N, int D, const double *theta_in,
                            const double *stats, const hmm_mstep_opts &o, double *theta_out,
                            int32_t *collapsed, int32_t *iters, hipStream_t s);
 
+// error reporting (message for hmm_last_error of this thread) and model
+// validation shared with the serving runtime
+hmm_status fail_status(hmm_status st, const char *fmt, ...);
+hmm_status model_theta_len(const hmm_model *m, size_t *len);
+
 // fixed-order reduction of per-block partial statistics + log-likelihood sum;
 // red is scratch of reduce_scratch_len(nparts, S) doubles
 int64_t reduce_scratch_len(int64_t nparts, int64_t S);

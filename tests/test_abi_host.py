@@ -13,9 +13,13 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def header_functions():
-    txt = open(os.path.join(ROOT, "include", "hmm_gpu.h")).read()
-    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
-    return sorted(set(re.findall(r"\b(hmm_[a-z0-9_]+)\s*\(", txt)))
+    names = set()
+    for hdr in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if hdr.endswith(".h"):
+            txt = open(os.path.join(ROOT, "include", hdr)).read()
+            txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+            names |= set(re.findall(r"\b(hmm_[a-z0-9_]+)\s*\(", txt))
+    return sorted(names)
 
 
 @pytest.fixture(scope="module")
@@ -106,3 +110,28 @@ def test_default_opts_and_chunk_len(h):
     assert h._lib.hmm_set_chunk_len(7) == h.HMM_ERR_ARG
     assert h._lib.hmm_set_chunk_len(16) == h.HMM_OK
     assert h._lib.hmm_set_chunk_len(0) == h.HMM_OK
+
+
+def test_server_host_validation(h):
+    """Serving calls reject bad arguments before touching the device."""
+    lib = h._lib
+    o = h.hmm_server_default_opts()
+    assert o.max_batch >= 1 and 1 <= o.n_streams <= 8 and o.precision == h.PREC["f32"]
+    out = ctypes.c_void_p()
+    assert lib.hmm_server_create(None, ctypes.byref(out)) == h.HMM_ERR_ARG
+    bad = h.hmm_server_default_opts()
+    bad.n_streams = 9
+    assert lib.hmm_server_create(ctypes.byref(bad), ctypes.byref(out)) == h.HMM_ERR_ARG
+    bad = h.hmm_server_default_opts()
+    bad.precision = h.PREC["plain_f32"]
+    assert lib.hmm_server_create(ctypes.byref(bad), ctypes.byref(out)) == h.HMM_ERR_ARG
+    bad = h.hmm_server_default_opts()
+    bad.max_batch = 0
+    assert lib.hmm_server_create(ctypes.byref(bad), ctypes.byref(out)) == h.HMM_ERR_ARG
+    assert lib.hmm_server_destroy(None) == h.HMM_ERR_ARG
+    n = ctypes.c_int32()
+    assert lib.hmm_server_poll(None, None, 0, 0, ctypes.byref(n)) == h.HMM_ERR_ARG
+    rid = ctypes.c_uint64()
+    assert lib.hmm_server_submit(None, 0, 0, None, 0, 1, None, ctypes.byref(rid)) == h.HMM_ERR_ARG
+    t0 = h.hmm_server_now()
+    assert h.hmm_server_now() >= t0

@@ -1,0 +1,170 @@
+"""Serving runtime (include/hmm_serve.h) on the GPU.
+
+Requests of uneven length against several resident models are submitted
+from the host; the server batches them per model and kind and overlaps the
+launches.  Each result must equal the direct library call on the same
+sequence alone, bit for bit (sequences never interact inside a launch), and
+therefore be the same alone and in the mix; FP64 Viterbi paths must match
+the oracle except at near-ties, posterior decodes the oracle's argmax except
+at near-ties; a small device budget must queue requests, never exceed the
+budget, and refuse a request that can never fit.
+"""
+import time
+
+import numpy as np
+import pytest
+import torch  # noqa: F401
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+MODEL_SPECS = [("gaussian", 4), ("poisson", 16), ("gaussian", 64), ("poisson", 4),
+               ("gaussian", 9)]
+
+
+@pytest.fixture(scope="module")
+def h():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_2605_29208_amd as h
+    return h
+
+
+@pytest.fixture(scope="module")
+def models():
+    rng = np.random.default_rng(700)
+    return [workloads.make_model(f, n, 1, rng, sticky=0.9) for f, n in MODEL_SPECS]
+
+
+def make_requests(models, count, seed, lo=1, hi=3000):
+    rng = np.random.default_rng(seed)
+    reqs = []
+    for i in range(count):
+        k = int(rng.integers(len(models)))
+        T = int(np.clip(np.exp(rng.normal(np.log(300), 1.0)), lo, hi))
+        w = workloads.simulate("req", models[k], [T], rng)
+        kind = "viterbi" if rng.random() < 0.5 else "posterior_decode"
+        reqs.append((k, kind, w.obs.copy()))
+    return reqs
+
+
+def collect(server, n, timeout_s=120.0):
+    got = {}
+    t_end = time.time() + timeout_s
+    while len(got) < n:
+        assert time.time() < t_end, f"only {len(got)} of {n} requests completed"
+        for c in server.poll(256, 20000):
+            got[c["id"]] = c
+    return got
+
+
+def direct(h, dm, kind, obs, prec):
+    import torch
+    dt = np.float64 if prec == "f64" else np.float32
+    db = h.DeviceBatch(obs, np.array([0, len(obs)], dtype=np.int64), dtype=dt)
+    if kind == "viterbi":
+        p, lp = h.viterbi(dm, db, prec)
+    else:
+        p, lp = h.posterior_decode(dm, db, prec)
+    torch.cuda.synchronize()
+    return p.cpu().numpy(), float(lp.cpu().numpy()[0])
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_server_matches_direct_calls(h, models, prec):
+    dms = [h.DeviceModel.from_model(m) for m in models]
+    srv = h.Server(hbm_budget=256 << 20, host_staging=64 << 20, max_batch=8, n_streams=3,
+                   prec=prec)
+    try:
+        ids = [srv.add_model(dm) for dm in dms]
+        reqs = make_requests(models, 48, 710)
+        rid = [srv.submit(ids[k], kind, obs) for k, kind, obs in reqs]
+        got = collect(srv, len(reqs))
+        assert max(c["batch_size"] for c in got.values()) > 1
+        for (k, kind, obs), r in zip(reqs, rid):
+            c = got[r]
+            assert c["status"] == 0 and c["T"] == len(obs)
+            p, lp = direct(h, dms[k], kind, obs, prec)
+            np.testing.assert_array_equal(c["path"], p)
+            assert c["logp"] == lp
+    finally:
+        srv.close()
+
+
+def test_server_invariance_alone_vs_mix(h, models):
+    dms = [h.DeviceModel.from_model(m) for m in models]
+    srv = h.Server(hbm_budget=256 << 20, host_staging=64 << 20, max_batch=16, n_streams=4)
+    try:
+        ids = [srv.add_model(dm) for dm in dms]
+        reqs = make_requests(models, 40, 720)
+        alone = []
+        for k, kind, obs in reqs:
+            r = srv.submit(ids[k], kind, obs)
+            c = collect(srv, 1)[r]
+            assert c["batch_size"] == 1
+            alone.append(c)
+        rid = [srv.submit(ids[k], kind, obs) for k, kind, obs in reqs]
+        mix = collect(srv, len(reqs))
+        for a, r in zip(alone, rid):
+            m = mix[r]
+            np.testing.assert_array_equal(a["path"], m["path"])
+            assert a["logp"] == m["logp"] and a["status"] == m["status"]
+        assert max(c["batch_size"] for c in mix.values()) > 1
+        info = srv.info()
+        assert info["completed"] == 2 * len(reqs) and info["pending"] == 0
+    finally:
+        srv.close()
+
+
+def test_server_f64_against_oracle(h, models):
+    dms = [h.DeviceModel.from_model(m) for m in models]
+    srv = h.Server(hbm_budget=128 << 20, host_staging=32 << 20, max_batch=4, n_streams=2,
+                   prec="f64")
+    try:
+        ids = [srv.add_model(dm) for dm in dms]
+        reqs = make_requests(models, 16, 730, hi=800)
+        rid = [srv.submit(ids[k], kind, obs) for k, kind, obs in reqs]
+        got = collect(srv, len(reqs))
+        for (k, kind, obs), r in zip(reqs, rid):
+            m = models[k]
+            c = got[r]
+            logB = oracle.emission(m.family, m.n_states, 1, m.theta, obs)
+            if kind == "viterbi":
+                rp, rlp, nties = oracle.viterbi(m.log_pi, m.log_A, logB)
+                if nties == 0:
+                    np.testing.assert_array_equal(c["path"], rp)
+                assert abs(c["logp"] - rlp) <= 1e-9 * max(1.0, abs(rlp))
+            else:
+                offs = np.array([0, len(obs)], dtype=np.int64)
+                ref = oracle.estep(m, offs, obs, want_gamma=True)
+                rp = oracle.posterior_decode(ref["gamma"])
+                srt = np.sort(ref["gamma"], axis=1)
+                gap = srt[:, -1] - srt[:, -2]
+                assert np.all((c["path"] == rp) | (gap < 1e-9))
+                assert abs(c["logp"] - ref["loglik"][0]) <= 1e-9 * abs(ref["loglik"][0])
+    finally:
+        srv.close()
+
+
+def test_server_admission_under_small_budget(h, models):
+    dms = [h.DeviceModel.from_model(m) for m in models]
+    budget = 3 << 20
+    srv = h.Server(hbm_budget=budget, host_staging=8 << 20, max_batch=32, n_streams=4)
+    try:
+        ids = [srv.add_model(dm) for dm in dms]
+        reqs = make_requests(models, 30, 740, lo=500, hi=4000)
+        rid = [srv.submit(ids[k], kind, obs) for k, kind, obs in reqs]
+        got = collect(srv, len(reqs))
+        info = srv.info()
+        assert info["pool_peak"] <= budget
+        assert info["launches"] > 1
+        for (k, kind, obs), r in zip(reqs, rid):
+            p, lp = direct(h, dms[k], kind, obs, "f32")
+            np.testing.assert_array_equal(got[r]["path"], p)
+        with pytest.raises(h.HmmError) as e:
+            srv.submit(ids[2], "posterior_decode", np.zeros(200000, dtype=np.float32))
+        assert e.value.status == h.HMM_ERR_WORKSPACE
+    finally:
+        srv.close()
