@@ -17,12 +17,19 @@ import argparse
 import json
 import os
 import sys
+import threading
 import time
 
 import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
+
+# the serving run keeps up to SERVING_STREAMS latency-bound launches in
+# flight; HIP gives each stream its own hardware queue only up to this count
+# (read once, when the HIP runtime starts)
+SERVING_STREAMS = 16
+os.environ.setdefault("GPU_MAX_HW_QUEUES", str(SERVING_STREAMS))
 
 PEAK_FP32_VALU_TFLOPS = 157.3   # MI355X FP32 vector, spec sheet
 METRIC = "E-step state-transitions/s (B*T*N^2) vs plain GPU; p50/p99 decode latency"
@@ -88,6 +95,83 @@ def cpu_baseline(w, reps=2):
                       f"FP64 oracle, 1 thread on {cpu_model()}, {dt:.1f} s"}
 
 
+def serving_bench(h, workloads, qps_list, seconds, pool_size=256, streams=SERVING_STREAMS):
+    """Decode requests (half Viterbi, half posterior decoding) arriving as a
+    Poisson process at each rate in qps_list against 16 resident models
+    (N in {4, 16, 64}, Gaussian and Poisson emissions), lengths log-normal
+    (median 2000, sigma 1.0, 16..100,000).  Latency = scheduled arrival ->
+    path in host memory; throughput in sequence steps per second."""
+    models = workloads.serving_models()
+    rng = np.random.default_rng(5007)
+    srv = h.Server(hbm_budget=16 << 30, host_staging=1 << 30, max_batch=64, n_streams=streams)
+    try:
+        ids = [srv.add_model(h.DeviceModel.from_model(m)) for m in models]
+        lengths = workloads.serving_request_lengths(rng, pool_size)
+        pool = []
+        for i in range(pool_size):
+            k = int(rng.integers(len(models)))
+            w = workloads.simulate("serve", models[k], [int(lengths[i])], rng)
+            kind = "viterbi" if rng.random() < 0.5 else "posterior_decode"
+            pool.append((k, kind, np.ascontiguousarray(w.obs, dtype=np.float32)))
+        # warm-up: every (model, kind) once
+        warm = 0
+        for k in range(len(models)):
+            for kind in ("viterbi", "posterior_decode"):
+                srv.submit(ids[k], kind, pool[0][2][:64])
+                warm += 1
+        while warm > 0:
+            warm -= len(srv.poll(256, 100000))
+        points = []
+        for qps in qps_list:
+            n_req = max(1, int(qps * seconds))
+            arrivals = np.cumsum(rng.exponential(1.0 / qps, n_req))
+            t0 = h.hmm_server_now() + 0.02
+            sent = []
+
+            def submitter():
+                for i in range(n_req):
+                    ta = t0 + arrivals[i]
+                    while True:
+                        d = ta - h.hmm_server_now()
+                        if d <= 0:
+                            break
+                        if d > 2e-3:
+                            time.sleep(d - 1e-3)
+                    k, kind, obs = pool[i % pool_size]
+                    sent.append((srv.submit(ids[k], kind, obs), ta, len(obs)))
+
+            th = threading.Thread(target=submitter)
+            th.start()
+            done = {}
+            while len(done) < n_req:
+                for c in srv.poll(1024, 2000):
+                    done[c["id"]] = c
+            th.join()
+            lat = np.array([done[r]["t_done"] - ta for r, ta, _ in sent])
+            wait = np.array([done[r]["t_launch"] - ta for r, ta, _ in sent])
+            serv = np.array([done[r]["t_done"] - done[r]["t_launch"] for r, _, _ in sent])
+            bs = np.array([done[r]["batch_size"] for r, _, _ in sent])
+            steps = sum(T for _, _, T in sent)
+            span = max(done[r]["t_done"] for r, _, _ in sent) - t0
+            bad = sum(1 for r, _, _ in sent if done[r]["status"] != 0)
+            points.append({"qps_offered": qps, "requests": n_req,
+                           "qps_served": n_req / span, "p50_ms": 1e3 * float(np.percentile(lat, 50)),
+                           "p99_ms": 1e3 * float(np.percentile(lat, 99)),
+                           "max_ms": 1e3 * float(lat.max()),
+                           "queue_p50_ms": 1e3 * float(np.percentile(wait, 50)),
+                           "service_p50_ms": 1e3 * float(np.percentile(serv, 50)),
+                           "service_p99_ms": 1e3 * float(np.percentile(serv, 99)),
+                           "seq_steps_per_s": steps / span, "mean_batch": float(bs.mean()),
+                           "failed": bad})
+        info = srv.info()
+    finally:
+        srv.close()
+    return {"models": "16 resident: 6 x N=4, 5 x N=16, 5 x N=64, Gaussian/Poisson alternating",
+            "lengths": "log-normal median 2000, sigma 1.0, clipped 16..100000",
+            "mix": "50% Viterbi, 50% posterior decode, FP32", "seconds_per_point": seconds,
+            "points": points, "launches": info["launches"], "pool_peak_bytes": info["pool_peak"]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -100,6 +184,12 @@ def main():
     ap.add_argument("--chunk", type=int, default=0, help="chunk length (0 = library default)")
     ap.add_argument("--em-iters", type=int, default=20,
                     help="EM iterations captured in one HIP graph (0 = skip)")
+    ap.add_argument("--serving-seconds", type=float, default=3.0,
+                    help="seconds of Poisson arrivals per serving rate (0 = skip)")
+    ap.add_argument("--serving-qps", default="100,1000,3000",
+                    help="comma-separated request rates of the serving run")
+    ap.add_argument("--serving-streams", type=int, default=SERVING_STREAMS,
+                    help="launches the server keeps in flight")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; multi-GPU sharding of the "
@@ -253,6 +343,10 @@ def main():
         "em_graph": em,
         "kernels": kt,
     }
+    if args.serving_seconds > 0:
+        qps = [float(x) for x in args.serving_qps.split(",") if x]
+        out["serving"] = serving_bench(h, workloads, qps, args.serving_seconds,
+                                       streams=args.serving_streams)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(out))

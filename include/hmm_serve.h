@@ -2,8 +2,10 @@
  *
  * Decoding requests (Viterbi, section 3.3; posterior decoding, section 3.4)
  * of uneven length arrive at any time against models that stay resident on
- * the device.  A worker thread batches pending requests of the same model
- * and kind into one launch as soon as a launch slot is free (continuous
+ * the device.  A worker thread batches pending requests of the same model,
+ * kind and length class (under 2048 steps, under 16384, longer) into one
+ * launch as soon as a launch slot is free; launches with requests of the
+ * longest class hold at most half of the slots (continuous
  * batching: requests that arrive while others run are admitted as slots and
  * memory free up, and their launches overlap on the device on separate
  * streams).  Admission is by a device-memory budget: the server allocates
@@ -41,7 +43,10 @@ typedef struct {
                                creation; a request needing more is refused at submit */
     size_t host_staging;    /* pinned host bytes for uploads and downloads, allocated at creation */
     int32_t max_batch;      /* most requests in one launch, >= 1 */
-    int32_t n_streams;      /* launches in flight at once, 1 .. 8 */
+    int32_t n_streams;      /* launches in flight at once, 1 .. 16.  Streams share the
+                               process's hardware queues (HIP's GPU_MAX_HW_QUEUES, 4 by
+                               default), so more than that many overlap only if the
+                               process raises it */
     int32_t precision;      /* HMM_PREC_F32 or HMM_PREC_F64 */
     int32_t device;         /* HIP device ordinal */
 } hmm_server_opts;

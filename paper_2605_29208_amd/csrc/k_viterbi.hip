@@ -22,7 +22,13 @@
 
 namespace hmmk {
 
-constexpr int VK = 64;   // steps per backtrace chunk
+constexpr int VK = 64;   // steps per backtrace chunk and per emission window
+
+// LDS accesses of one wave are performed in program order: a wavefront-scope
+// fence (no wait) orders the lanes' store of a vector before their reads.
+__device__ __forceinline__ void wave_lds_order() {
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+}
 
 __device__ __forceinline__ double wave_max_d(double v) {
     for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
@@ -33,14 +39,60 @@ __device__ __forceinline__ float wave_max_d(float v) {
     return v;
 }
 
-// one wave per sequence; NMAX = 8 or 64 bounds the (unrolled) predecessor loop
-template <typename R, int NMAX>
+// log b_j(y) of the NMAX states of one step, computed by one lane into its
+// LDS row (without the state-independent part, which is returned in FP64).
+// FAM < 0 evaluates any family through emission_any.
+template <typename R, int NMAX, int FAM>
+__device__ __forceinline__ double vit_tab_step(const StagedModel<R> &m, const ObsRef &o, int64_t row,
+                                               R *lrow, bool *bad) {
+    const int N = m.N;
+    double common = 0.0;
+    if constexpr (FAM < 0) {
+#pragma unroll 2
+        for (int j = 0; j < NMAX; ++j) {
+            if (j < N) {
+                bool bd = false;
+                lrow[j] = (R)emission_any<R>(m, o, row, j, &common, &bd);
+                *bad |= bd;
+            }
+        }
+    } else if constexpr (FAM == HMM_TABLE) {
+#pragma unroll 4
+        for (int j = 0; j < NMAX; ++j) {
+            if (j < N) {
+                const R v = load_obs<R>(o, row * N + j);
+                *bad |= isnan(v) || (v > (R)0 && isinf(v));
+                lrow[j] = v;
+            }
+        }
+    } else {
+        using ET = typename EmitTraits<FAM, R>::T;
+        const ET *ep = consts_ptr<FAM, R>(m);
+        const ET y = load_obs<ET>(o, row);
+#pragma unroll 4
+        for (int j = 0; j < NMAX; ++j) {
+            if (j < N) {
+                const Emit<ET> e = emit_scalar<FAM, ET>(y, load_consts(ep, j, true), true);
+                lrow[j] = (R)e.ell;
+                common = e.common;
+                *bad |= e.bad;
+            }
+        }
+    }
+    return common;
+}
+
+// one wave per sequence; NMAX bounds the (unrolled) predecessor loop.  The
+// emissions of a window of VK steps are tabulated first, one lane per step.
+template <typename R, int NMAX, int FAM>
 __global__ __launch_bounds__(64) void k_vit_forward(StagedModel<R> m, ObsRef o, int64_t nseq,
                                                     const int64_t *__restrict__ offsets,
                                                     uint8_t *__restrict__ psi,
                                                     double *__restrict__ logp,
                                                     uint8_t *__restrict__ qlast) {
-    __shared__ R dsh[64];
+    __shared__ R lsh[VK][NMAX + 1];
+    __shared__ double csh[VK];
+    __shared__ __align__(16) R dsh[64];
     const int64_t b = blockIdx.x;
     const int j = threadIdx.x;
     const int N = m.N;
@@ -50,40 +102,44 @@ __global__ __launch_bounds__(64) void k_vit_forward(StagedModel<R> m, ObsRef o, 
 #pragma unroll
     for (int i = 0; i < NMAX; ++i) col[i] = (live && i < N) ? m.lA[i * N + j] : neg_inf<R>();
     const R ninf = neg_inf<R>();
-    double common = 0.0;
-    bool bad = false;
-    double lb = live ? emission_any<R>(m, o, off, j, &common, &bad) : -__builtin_inf();
-    R d = live ? (R)(m.lpi[j] + (R)lb) : ninf;
-    R mx = wave_max_d(d);
-    bool dead = (mx == ninf);
-    double offset = (double)mx + common;
-    d = dead ? ninf : d - mx;
-    for (int64_t t = 1; t < T; ++t) {
-        dsh[j] = d;
+    bool bad = false, dead = false;
+    double offset = 0.0;
+    R d = ninf;
+    for (int64_t w0 = 0; w0 < T; w0 += VK) {
+        const int wn = (int)((T - w0) < VK ? (T - w0) : VK);
         __syncthreads();
-        R best = ninf;
-        int arg = 0;
+        if (j < wn) csh[j] = vit_tab_step<R, NMAX, FAM>(m, o, off + w0 + j, &lsh[j][0], &bad);
+        __syncthreads();
+        for (int s = 0; s < wn; ++s) {
+            const int64_t t = w0 + s;
+            const R lt = live ? lsh[s][j] : ninf;
+            R nd;
+            if (t == 0) {
+                nd = live ? (R)(m.lpi[j] + lt) : ninf;
+            } else {
+                dsh[j] = d;
+                wave_lds_order();
+                R best = ninf;
+                int arg = 0;
 #pragma unroll
-        for (int i = 0; i < NMAX; ++i) {
-            if (i < N) {
-                R v = dsh[i] + col[i];
-                if (v > best) {
-                    best = v;
-                    arg = i;
+                for (int i = 0; i < NMAX; ++i) {
+                    if (i < N) {
+                        const R v = dsh[i] + col[i];
+                        if (v > best) {
+                            best = v;
+                            arg = i;
+                        }
+                    }
                 }
+                wave_lds_order();
+                nd = live ? (R)(best + lt) : ninf;
+                if (live) psi[(off + t) * N + j] = (uint8_t)arg;
             }
+            const R mt = wave_max_d(nd);
+            if (mt == ninf) dead = true;
+            offset += (double)mt + csh[s];
+            d = (mt == ninf) ? ninf : nd - mt;
         }
-        __syncthreads();
-        bool bd = false;
-        double cm = 0.0;
-        double lt = live ? emission_any<R>(m, o, off + t, j, &cm, &bd) : -__builtin_inf();
-        bad |= bd;
-        R nd = live ? (R)(best + (R)lt) : ninf;
-        if (live) psi[(off + t) * N + j] = (uint8_t)arg;
-        R mt = wave_max_d(nd);
-        if (mt == ninf) dead = true;
-        offset += (double)mt + cm;
-        d = (mt == ninf) ? ninf : nd - mt;
     }
     // final state: lowest argmax
     R best = ninf;
@@ -99,8 +155,8 @@ __global__ __launch_bounds__(64) void k_vit_forward(StagedModel<R> m, ObsRef o, 
         logp[b] = dead ? -__builtin_inf() : offset + (double)best;
         qlast[b] = (uint8_t)(dead ? 255 : q);
     }
-    // a non-finite observation in any lane makes the whole sequence undecodable
-    int badw = __any(bad);
+    // a non-finite observation anywhere makes the whole sequence undecodable
+    const int badw = __any(bad);
     if (j == 0 && badw) {
         logp[b] = __builtin_nan("");
         qlast[b] = 255;
@@ -194,6 +250,35 @@ __global__ __launch_bounds__(64) void k_vit_fill(const ChunkDesc *__restrict__ c
     if (tid < d.len) path[d.off + d.t0 + tid] = out[tid];
 }
 
+template <typename R, int NMAX, int FAM>
+static void launch_vit_forward_f(const StagedModel<R> &m, const ObsDesc &o, uint8_t *psi,
+                                 double *logp, uint8_t *qlast, hipStream_t s) {
+    hipLaunchKernelGGL((k_vit_forward<R, NMAX, FAM>), dim3((unsigned)o.nseq), dim3(64), 0, s, m,
+                       ObsRef{o.obs, o.obs_f64}, o.nseq, o.offsets, psi, logp, qlast);
+}
+
+template <typename R, int NMAX>
+static void launch_vit_forward_n(const StagedModel<R> &m, const ObsDesc &o, uint8_t *psi,
+                                 double *logp, uint8_t *qlast, hipStream_t s) {
+    switch (m.family) {
+    case HMM_GAUSSIAN: return launch_vit_forward_f<R, NMAX, HMM_GAUSSIAN>(m, o, psi, logp, qlast, s);
+    case HMM_GAMMA: return launch_vit_forward_f<R, NMAX, HMM_GAMMA>(m, o, psi, logp, qlast, s);
+    case HMM_STUDENT_T: return launch_vit_forward_f<R, NMAX, HMM_STUDENT_T>(m, o, psi, logp, qlast, s);
+    case HMM_POISSON: return launch_vit_forward_f<R, NMAX, HMM_POISSON>(m, o, psi, logp, qlast, s);
+    case HMM_TABLE: return launch_vit_forward_f<R, NMAX, HMM_TABLE>(m, o, psi, logp, qlast, s);
+    default: return launch_vit_forward_f<R, NMAX, -1>(m, o, psi, logp, qlast, s);
+    }
+}
+
+template <typename R>
+static void launch_vit_forward(const StagedModel<R> &m, const ObsDesc &o, uint8_t *psi,
+                               double *logp, uint8_t *qlast, hipStream_t s) {
+    if (m.N <= 8) launch_vit_forward_n<R, 8>(m, o, psi, logp, qlast, s);
+    else if (m.N <= 16) launch_vit_forward_n<R, 16>(m, o, psi, logp, qlast, s);
+    else if (m.N <= 32) launch_vit_forward_n<R, 32>(m, o, psi, logp, qlast, s);
+    else launch_vit_forward_n<R, 64>(m, o, psi, logp, qlast, s);
+}
+
 template <typename R>
 hmm_status run_viterbi(const StagedModel<R> &m, const ObsDesc &o, const int *cbase,
                        const ChunkDesc *cdesc, int C, uint8_t *psi, uint8_t *J, uint8_t *qlast,
@@ -201,12 +286,7 @@ hmm_status run_viterbi(const StagedModel<R> &m, const ObsDesc &o, const int *cba
     if (o.nseq == 0) return HMM_OK;
     {
         ProfScope ps("vit_forward", s);
-        if (m.N <= 8)
-            hipLaunchKernelGGL((k_vit_forward<R, 8>), dim3((unsigned)o.nseq), dim3(64), 0, s, m,
-                               ObsRef{o.obs, o.obs_f64}, o.nseq, o.offsets, psi, logp, qlast);
-        else
-            hipLaunchKernelGGL((k_vit_forward<R, 64>), dim3((unsigned)o.nseq), dim3(64), 0, s, m,
-                               ObsRef{o.obs, o.obs_f64}, o.nseq, o.offsets, psi, logp, qlast);
+        launch_vit_forward<R>(m, o, psi, logp, qlast, s);
     }
     {
         ProfScope ps("vit_jump", s);

@@ -1,15 +1,17 @@
 // serve.cpp -- the request-serving runtime of hmm_serve.h.
 //
 // One worker thread per server.  Each pass of its loop
-//   1. retires launches whose completion event has fired: copies every
+//   1. retires launches whose host callback has run (it is enqueued on the
+//      launch's stream after the download and only sets a flag): copies every
 //      request's path out of the pinned staging area into the caller's
 //      buffer, records the completion and returns the launch's device and
 //      host blocks to their pools;
 //   2. while a launch slot (stream) is free, forms a batch from the oldest
-//      pending request and the pending requests of the same model and kind
-//      behind it (up to max_batch, as long as the batch's bytes fit the free
-//      device budget and staging area), uploads it, enqueues the decode and
-//      the download on the slot's stream and records the slot's event;
+//      pending request allowed to start and the pending requests of the same
+//      model, kind and length class behind it (up to max_batch, as long as
+//      the batch's bytes fit the free device budget and staging area),
+//      uploads it, enqueues the decode and the download on the slot's stream
+//      and records the slot's event;
 //   3. sleeps until a submission arrives or, with launches in flight, for a
 //      few microseconds.
 // Device and pinned memory come from two areas allocated at creation and
@@ -20,9 +22,11 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <atomic>
 #include <condition_variable>
 #include <cstring>
 #include <deque>
+#include <list>
 #include <map>
 #include <mutex>
 #include <thread>
@@ -123,7 +127,9 @@ struct Layout {
 };
 
 struct Flight {
-    int slot;
+    int slot = 0, cls = 0;
+    Model md;                         // the resident model (copied: the list may grow)
+    std::atomic<bool> ready{false};   // set by the stream's host callback after the download
     std::vector<Req> reqs;
     std::vector<int64_t> h_off;
     Layout lay;
@@ -134,32 +140,62 @@ struct Flight {
 
 struct Slot {
     hipStream_t stream = nullptr;
-    hipEvent_t done = nullptr;
     bool busy = false;
+    bool long_launch = false;   // holds requests of the longest length class
 };
+
+// Length class of a request: a launch lasts as long as its longest
+// sequence, so requests are batched only with others of their class, and
+// launches holding long requests may occupy at most half of the slots (a
+// short request then always finds a slot within one short launch's time).
+int len_class(int64_t T) { return T < 2048 ? 0 : (T < 16384 ? 1 : 2); }
 
 }  // namespace
 
+// Locking: `mu` guards the request queue, the completion queue, the
+// counters and the wake-up state shared with submitters, pollers and the
+// stream callbacks.  The pools, slots and launches in flight belong to the
+// worker alone, and the worker never holds `mu` across a HIP call, so a
+// callback (which takes `mu` briefly) can never wait on a HIP call.
 struct hmm_server {
     hmm_server_opts opts;
     char *dev = nullptr;     // device budget area
     char *host = nullptr;    // pinned staging area
+    size_t es = 4;           // bytes per observation value
+    // worker-owned
     Pool dpool, hpool;
     std::vector<Slot> slots;
-    std::vector<Model> models;
-    std::deque<Req> pending;
-    std::deque<Flight> flights;
-    std::deque<hmm_completion> done;
+    std::list<Flight> flights;   // stable addresses: host callbacks point at them
+    // shared, under mu
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
+    std::vector<Model> models;
+    std::deque<Req> pending;
+    std::deque<hmm_completion> done;
     std::thread worker;
-    bool stop = false;
-    uint64_t next_id = 1;
-    int64_t n_submitted = 0, n_completed = 0, n_launches = 0;
-    size_t es = 4;           // bytes per observation value
+    bool stop = false, wake = false;
+    uint64_t next_id = 1, submits = 0;
+    int64_t n_submitted = 0, n_completed = 0, n_launches = 0, n_in_flight = 0;
+    size_t pool_used = 0, pool_peak = 0;
 
-    hmm_status plan(int model, int kind, const std::vector<int64_t> &h_off, Layout *lay);
-    bool launch_one();
+    struct CbArg {
+        hmm_server *s;
+        Flight *f;
+    };
+    static void on_done(void *p) {
+        CbArg *a = (CbArg *)p;
+        a->f->ready.store(true, std::memory_order_release);
+        {
+            std::lock_guard<std::mutex> lk(a->s->mu);
+            a->s->wake = true;
+        }
+        a->s->cv_work.notify_one();
+        delete a;
+    }
+
+    hmm_status plan(const Model &md, int kind, const std::vector<int64_t> &h_off, Layout *lay);
+    bool select(Flight *f);
+    void issue(Flight *f);
     void retire(Flight &f);
     void run();
 };
@@ -170,8 +206,8 @@ hmm_status server_fail(hmm_status st, const char *msg) { return fail_status(st, 
 
 }  // namespace
 
-hmm_status hmm_server::plan(int model, int kind, const std::vector<int64_t> &h_off, Layout *lay) {
-    const Model &md = models[(size_t)model];
+hmm_status hmm_server::plan(const Model &md, int kind, const std::vector<int64_t> &h_off,
+                            Layout *lay) {
     const int64_t B = (int64_t)h_off.size() - 1, total = h_off.back();
     // sizing only: the planner reads the host offsets; device pointers are
     // placeholders that are never dereferenced
@@ -189,12 +225,125 @@ hmm_status hmm_server::plan(int model, int kind, const std::vector<int64_t> &h_o
     return HMM_OK;
 }
 
+// Worker: pick the next batch (called with mu held).  Returns false when no
+// slot is free or nothing can start now.  A request that no launch can serve
+// comes back as a one-request flight with launch_status set.
+bool hmm_server::select(Flight *f) {
+    int slot = -1, long_busy = 0;
+    for (size_t i = 0; i < slots.size(); ++i) {
+        if (!slots[i].busy && slot < 0) slot = (int)i;
+        if (slots[i].busy && slots[i].long_launch) ++long_busy;
+    }
+    if (slot < 0 || pending.empty()) return false;
+    const int long_cap = std::max(1, (int)slots.size() / 2);
+    // the oldest request whose class may start now sets the batch key
+    const size_t window = std::min<size_t>(pending.size(), 1024);
+    size_t head = window;
+    for (size_t i = 0; i < window; ++i)
+        if (len_class(pending[i].T) < 2 || long_busy < long_cap) {
+            head = i;
+            break;
+        }
+    if (head == window) return false;
+    const int model = pending[head].model, kind = pending[head].kind;
+    const int cls = len_class(pending[head].T);
+    const Model &md = models[(size_t)model];
+    std::vector<size_t> pick;
+    std::vector<int64_t> h_off{0};
+    Layout lay;
+    const size_t dfree = dpool.largest(), hfree = hpool.largest();
+    for (size_t i = head; i < window && (int)pick.size() < opts.max_batch; ++i) {
+        const Req &r = pending[i];
+        if (r.model != model || r.kind != kind || len_class(r.T) != cls) continue;
+        std::vector<int64_t> trial = h_off;
+        trial.push_back(trial.back() + r.T);
+        Layout l;
+        const hmm_status st = plan(md, kind, trial, &l);
+        if (st != HMM_OK) {
+            if (!pick.empty()) break;
+            f->reqs.push_back(std::move(pending[i]));
+            pending.erase(pending.begin() + (std::ptrdiff_t)i);
+            f->h_off = {0, f->reqs[0].T};
+            f->launch_status = st;
+            f->slot = -1;
+            return true;
+        }
+        if (l.dev_total > dfree || l.host_total > hfree) break;
+        pick.push_back(i);
+        h_off.swap(trial);
+        lay = l;
+    }
+    if (pick.empty()) return false;   // wait for memory to free up
+    f->slot = slot;
+    f->cls = cls;
+    f->md = md;
+    f->h_off = h_off;
+    f->lay = lay;
+    f->reqs.resize(pick.size());
+    for (size_t k = pick.size(); k-- > 0;) {   // back to front keeps indices valid
+        f->reqs[k] = std::move(pending[pick[k]]);
+        pending.erase(pending.begin() + (std::ptrdiff_t)pick[k]);
+    }
+    dpool.alloc(lay.dev_total, &f->dev_off);
+    hpool.alloc(lay.host_total, &f->host_off);
+    slots[(size_t)slot].busy = true;
+    slots[(size_t)slot].long_launch = cls == 2;
+    pool_used = dpool.used;
+    pool_peak = dpool.peak;
+    ++n_launches;
+    ++n_in_flight;
+    return true;
+}
+
+// Worker, without mu: upload, decode, download, then the completion callback.
+void hmm_server::issue(Flight *f) {
+    const Layout &lay = f->lay;
+    const Model &md = f->md;
+    const int kind = f->reqs[0].kind;
+    char *hb = host + f->host_off;
+    char *db = dev + f->dev_off;
+    std::memcpy(hb, f->h_off.data(), lay.off_b);
+    for (size_t k = 0; k < f->reqs.size(); ++k)
+        std::memcpy(hb + lay.o_obs + (size_t)f->h_off[k] * md.D * es, f->reqs[k].obs.data(),
+                    f->reqs[k].obs.size());
+    hipStream_t s = slots[(size_t)f->slot].stream;
+    hmm_status st = HMM_OK;
+    if (hipMemcpyAsync(db, hb, lay.o_path, hipMemcpyHostToDevice, s) != hipSuccess)
+        st = HMM_ERR_DEVICE;
+    const int64_t B = (int64_t)f->reqs.size();
+    hmm_batch b{B, (const int64_t *)db, f->h_off.data(), db + lay.o_obs,
+                opts.precision == HMM_PREC_F64, 0};
+    int32_t *path = (int32_t *)(db + lay.o_path);
+    double *logp = (double *)(db + lay.o_logp);
+    if (st == HMM_OK) {
+        if (kind == HMM_REQ_VITERBI)
+            st = hmm_viterbi(&md.m, &b, (hmm_precision)opts.precision, path, logp, db + lay.o_ws,
+                             lay.ws_b, s);
+        else
+            st = hmm_posterior_decode(&md.m, &b, (hmm_precision)opts.precision, path, logp,
+                                      db + lay.o_ws, lay.ws_b, s);
+    }
+    if (st == HMM_OK &&
+        hipMemcpyAsync(hb + lay.o_path, db + lay.o_path, lay.host_total - lay.o_path,
+                       hipMemcpyDeviceToHost, s) != hipSuccess)
+        st = HMM_ERR_DEVICE;
+    f->launch_status = st;
+    f->t_launch = now_s();
+    if (hipLaunchHostFunc(s, &hmm_server::on_done, new CbArg{this, f}) != hipSuccess) {
+        hipStreamSynchronize(s);   // no callback: finish the launch here
+        f->ready.store(true, std::memory_order_release);
+    }
+}
+
+// Worker, without mu: paths into the callers' buffers, then the records.
 void hmm_server::retire(Flight &f) {
     const char *hb = host + f.host_off;
     const double *lp = (const double *)(hb + f.lay.o_logp);
+    std::vector<hmm_completion> out(f.reqs.size());
     for (size_t k = 0; k < f.reqs.size(); ++k) {
         Req &r = f.reqs[k];
-        hmm_completion c{};
+        hmm_completion &c = out[k];
+        c = hmm_completion{};
         c.id = r.id;
         c.model = r.model;
         c.kind = r.kind;
@@ -211,129 +360,67 @@ void hmm_server::retire(Flight &f) {
             c.status = std::isnan(c.logp) ? 2 : (std::isinf(c.logp) && c.logp < 0 ? 1 : 0);
         }
         c.t_done = now_s();
-        done.push_back(c);
-        ++n_completed;
     }
-    if (f.lay.dev_total) dpool.release(f.dev_off, f.lay.dev_total);
-    if (f.lay.host_total) hpool.release(f.host_off, f.lay.host_total);
-    slots[(size_t)f.slot].busy = false;
+    if (f.slot >= 0) {
+        dpool.release(f.dev_off, f.lay.dev_total);
+        hpool.release(f.host_off, f.lay.host_total);
+        slots[(size_t)f.slot].busy = false;
+        slots[(size_t)f.slot].long_launch = false;
+    }
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        for (auto &c : out) done.push_back(c);
+        n_completed += (int64_t)out.size();
+        if (f.slot >= 0) --n_in_flight;
+        pool_used = dpool.used;
+    }
     cv_done.notify_all();
-}
-
-bool hmm_server::launch_one() {
-    int slot = -1;
-    for (size_t i = 0; i < slots.size(); ++i)
-        if (!slots[i].busy) {
-            slot = (int)i;
-            break;
-        }
-    if (slot < 0 || pending.empty()) return false;
-    const int model = pending.front().model, kind = pending.front().kind;
-    // gather same-key requests in arrival order while the batch fits
-    std::vector<size_t> pick;
-    std::vector<int64_t> h_off{0};
-    Layout lay;
-    const size_t dfree = dpool.largest(), hfree = hpool.largest();
-    const size_t window = std::min<size_t>(pending.size(), 1024);
-    for (size_t i = 0; i < window && (int)pick.size() < opts.max_batch; ++i) {
-        const Req &r = pending[i];
-        if (r.model != model || r.kind != kind) continue;
-        std::vector<int64_t> trial = h_off;
-        trial.push_back(trial.back() + r.T);
-        Layout l;
-        if (plan(model, kind, trial, &l) != HMM_OK) {
-            if (pick.empty()) {
-                // the head request cannot be served at all: report it
-                Flight f;
-                f.slot = slot;
-                f.reqs.push_back(std::move(pending.front()));
-                pending.pop_front();
-                f.h_off = {0, f.reqs[0].T};
-                f.launch_status = HMM_ERR_UNSUPPORTED;
-                f.t_launch = now_s();
-                slots[(size_t)slot].busy = true;
-                retire(f);
-                return true;
-            }
-            break;
-        }
-        if (l.dev_total > dfree || l.host_total > hfree) break;
-        pick.push_back(i);
-        h_off.swap(trial);
-        lay = l;
-    }
-    if (pick.empty()) return false;   // wait for memory to free up
-    Flight f;
-    f.slot = slot;
-    f.h_off = h_off;
-    f.lay = lay;
-    dpool.alloc(lay.dev_total, &f.dev_off);
-    hpool.alloc(lay.host_total, &f.host_off);
-    // move the picked requests out of the queue (back to front keeps indices valid)
-    f.reqs.resize(pick.size());
-    for (size_t k = pick.size(); k-- > 0;) {
-        f.reqs[k] = std::move(pending[pick[k]]);
-        pending.erase(pending.begin() + (std::ptrdiff_t)pick[k]);
-    }
-    char *hb = host + f.host_off;
-    char *db = dev + f.dev_off;
-    std::memcpy(hb, h_off.data(), lay.off_b);
-    for (size_t k = 0; k < f.reqs.size(); ++k)
-        std::memcpy(hb + lay.o_obs + (size_t)h_off[k] * models[(size_t)model].D * es,
-                    f.reqs[k].obs.data(), f.reqs[k].obs.size());
-    Slot &sl = slots[(size_t)slot];
-    hipStream_t s = sl.stream;
-    hmm_status st = HMM_OK;
-    if (hipMemcpyAsync(db, hb, lay.o_path, hipMemcpyHostToDevice, s) != hipSuccess)
-        st = HMM_ERR_DEVICE;
-    const Model &md = models[(size_t)model];
-    const int64_t B = (int64_t)f.reqs.size();
-    hmm_batch b{B, (const int64_t *)db, h_off.data(), db + lay.o_obs,
-                opts.precision == HMM_PREC_F64, 0};
-    int32_t *path = (int32_t *)(db + lay.o_path);
-    double *logp = (double *)(db + lay.o_logp);
-    if (st == HMM_OK) {
-        if (kind == HMM_REQ_VITERBI)
-            st = hmm_viterbi(&md.m, &b, (hmm_precision)opts.precision, path, logp, db + lay.o_ws,
-                             lay.ws_b, s);
-        else
-            st = hmm_posterior_decode(&md.m, &b, (hmm_precision)opts.precision, path, logp,
-                                      db + lay.o_ws, lay.ws_b, s);
-    }
-    if (st == HMM_OK &&
-        hipMemcpyAsync(hb + lay.o_path, db + lay.o_path, lay.host_total - lay.o_path,
-                       hipMemcpyDeviceToHost, s) != hipSuccess)
-        st = HMM_ERR_DEVICE;
-    f.launch_status = st;
-    f.t_launch = now_s();
-    hipEventRecord(sl.done, s);
-    sl.busy = true;
-    ++n_launches;
-    flights.push_back(std::move(f));
-    return true;
 }
 
 void hmm_server::run() {
     hipSetDevice(opts.device);
-    std::unique_lock<std::mutex> lk(mu);
+    uint64_t seen = 0;
     for (;;) {
-        bool progressed = false;
         for (auto it = flights.begin(); it != flights.end();) {
-            if (hipEventQuery(slots[(size_t)it->slot].done) != hipErrorNotReady) {
+            if (it->ready.load(std::memory_order_acquire)) {
                 retire(*it);
                 it = flights.erase(it);
-                progressed = true;
             } else {
                 ++it;
             }
         }
-        if (stop && flights.empty()) break;
-        while (!stop && launch_one()) progressed = true;
-        if (progressed) continue;
-        if (flights.empty())
-            cv_work.wait(lk, [&] { return stop || !pending.empty(); });
-        else
-            cv_work.wait_for(lk, std::chrono::microseconds(20));
+        bool quit = false;
+        for (;;) {
+            flights.emplace_back();
+            Flight *f = &flights.back();
+            bool got;
+            {
+                std::lock_guard<std::mutex> lk(mu);
+                quit = stop;
+                seen = submits;
+                got = !stop && select(f);
+            }
+            if (!got) {
+                flights.pop_back();
+                break;
+            }
+            if (f->slot < 0) {   // refused request: report at once
+                retire(*f);
+                flights.pop_back();
+                continue;
+            }
+            issue(f);
+        }
+        bool any_ready = false;
+        for (auto &f : flights) any_ready |= f.ready.load(std::memory_order_acquire);
+        if (any_ready) continue;
+        std::unique_lock<std::mutex> lk(mu);
+        if ((quit || stop) && flights.empty()) break;
+        // woken by a finished launch, a submission, or destroy
+        cv_work.wait(lk, [&] {
+            return wake || (stop ? flights.empty() : submits != seen);
+        });
+        wake = false;
     }
 }
 
@@ -354,8 +441,8 @@ double hmm_server_now(void) { return now_s(); }
 hmm_status hmm_server_create(const hmm_server_opts *opts, hmm_server **out) {
     if (!opts || !out) return server_fail(HMM_ERR_ARG, "opts / out is NULL");
     if (opts->max_batch < 1) return server_fail(HMM_ERR_ARG, "max_batch must be >= 1");
-    if (opts->n_streams < 1 || opts->n_streams > 8)
-        return server_fail(HMM_ERR_ARG, "n_streams must be in 1 .. 8");
+    if (opts->n_streams < 1 || opts->n_streams > 16)
+        return server_fail(HMM_ERR_ARG, "n_streams must be in 1 .. 16");
     if (opts->precision != HMM_PREC_F32 && opts->precision != HMM_PREC_F64)
         return server_fail(HMM_ERR_ARG, "precision must be HMM_PREC_F32 or HMM_PREC_F64");
     if (opts->hbm_budget < 4096 || opts->host_staging < 4096)
@@ -379,10 +466,9 @@ hmm_status hmm_server_create(const hmm_server_opts *opts, hmm_server **out) {
     s->hpool.init(opts->host_staging);
     s->slots.resize((size_t)opts->n_streams);
     for (auto &sl : s->slots) {
-        if (hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) != hipSuccess ||
-            hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) != hipSuccess) {
+        if (hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) != hipSuccess) {
             hmm_server_destroy(s);
-            return server_fail(HMM_ERR_DEVICE, "stream / event creation failed");
+            return server_fail(HMM_ERR_DEVICE, "stream creation failed");
         }
     }
     s->worker = std::thread([s] { s->run(); });
@@ -400,7 +486,6 @@ hmm_status hmm_server_destroy(hmm_server *s) {
     if (s->worker.joinable()) s->worker.join();
     for (auto &sl : s->slots) {
         if (sl.stream) hipStreamSynchronize(sl.stream);
-        if (sl.done) hipEventDestroy(sl.done);
         if (sl.stream) hipStreamDestroy(sl.stream);
     }
     for (auto &m : s->models) hipFree(m.buf);
@@ -454,7 +539,7 @@ hmm_status hmm_server_submit(hmm_server *s, int32_t model_id, int32_t kind, cons
             return server_fail(HMM_ERR_ARG, "unknown model id");
         D = s->models[(size_t)model_id].D;
         Layout l;
-        hmm_status st = s->plan(model_id, kind, {0, T}, &l);
+        hmm_status st = s->plan(s->models[(size_t)model_id], kind, {0, T}, &l);
         if (st != HMM_OK) return st;
         if (l.dev_total > s->dpool.cap || l.host_total > s->hpool.cap)
             return server_fail(HMM_ERR_WORKSPACE, "request needs more than the server's budget");
@@ -482,6 +567,7 @@ hmm_status hmm_server_submit(hmm_server *s, int32_t model_id, int32_t kind, cons
         r.t_submit = now_s();
         s->pending.push_back(std::move(r));
         ++s->n_submitted;
+        ++s->submits;
     }
     s->cv_work.notify_one();
     return HMM_OK;
@@ -510,10 +596,10 @@ hmm_status hmm_server_get_info(hmm_server *s, hmm_server_info *info) {
     info->completed = s->n_completed;
     info->launches = s->n_launches;
     info->pending = (int64_t)s->pending.size();
-    info->in_flight = (int64_t)s->flights.size();
-    info->pool_bytes = s->dpool.cap;
-    info->pool_used = s->dpool.used;
-    info->pool_peak = s->dpool.peak;
+    info->in_flight = s->n_in_flight;
+    info->pool_bytes = s->opts.hbm_budget & ~(size_t)255;
+    info->pool_used = s->pool_used;
+    info->pool_peak = s->pool_peak;
     return HMM_OK;
 }
 

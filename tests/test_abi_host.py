@@ -116,11 +116,11 @@ def test_server_host_validation(h):
     """Serving calls reject bad arguments before touching the device."""
     lib = h._lib
     o = h.hmm_server_default_opts()
-    assert o.max_batch >= 1 and 1 <= o.n_streams <= 8 and o.precision == h.PREC["f32"]
+    assert o.max_batch >= 1 and 1 <= o.n_streams <= 16 and o.precision == h.PREC["f32"]
     out = ctypes.c_void_p()
     assert lib.hmm_server_create(None, ctypes.byref(out)) == h.HMM_ERR_ARG
     bad = h.hmm_server_default_opts()
-    bad.n_streams = 9
+    bad.n_streams = 17
     assert lib.hmm_server_create(ctypes.byref(bad), ctypes.byref(out)) == h.HMM_ERR_ARG
     bad = h.hmm_server_default_opts()
     bad.precision = h.PREC["plain_f32"]
