@@ -108,7 +108,7 @@ hmm_status check_batch(const hmm_batch *b, const hmm_model *m, Checked *c) {
 
 // ---------------------------------------------------------------- planning
 struct Plan {
-    bool f64 = false, plain = false, chunked = false, wave = false;
+    bool f64 = false, plain = false, chunked = false, wave = false, block = false;
     int G = 0, L = 0, C = 0, nblk = 0;
     int64_t S = 0;
     size_t staged = 0, cbase = 0, frec = 0, brec = 0, F = 0, Gb = 0, partial = 0;
@@ -118,6 +118,7 @@ struct Plan {
     size_t ll = 0, st = 0, gam = 0;
     size_t logB = 0, alpha = 0, beta = 0, ps = 0;
     size_t red = 0;
+    size_t etab = 0, mt = 0, balpha = 0, aexp = 0, bgam = 0, xi = 0, g1 = 0, compact = 0;
     size_t total = 0;
 };
 
@@ -179,11 +180,34 @@ hmm_status make_plan(hmm_op op, const Checked &c, hmm_precision prec, Plan *p) {
         p->red = take((size_t)reduce_scratch_len(c.B, p->S) * 8);
     } else {
         const bool scalar = c.fam <= HMM_POISSON || c.fam == HMM_TABLE;
-        if (!(N <= 64 && scalar))
-            return fail(HMM_ERR_UNSUPPORTED,
-                        "batched path: this build covers N <= 64 with scalar or table emissions "
-                        "(N = %d, family %d); use a PLAIN precision",
-                        N, c.fam);
+        if (!scalar || N > 64) {
+            // one workgroup per sequence, emission table, xi by GEMM
+            if (N > 256)
+                return fail(HMM_ERR_UNSUPPORTED,
+                            "batched path: this build covers N <= 256 (N = %d); use a PLAIN "
+                            "precision", N);
+            if (op == HMM_OP_ESTEP && c.fam == HMM_FULL_GAUSSIAN)
+                return fail(HMM_ERR_UNSUPPORTED,
+                            "batched E-step statistics of the full-covariance family are not "
+                            "built; use a PLAIN precision");
+            p->block = true;
+            const size_t T = (size_t)c.total;
+            p->etab = take(T * N * r);
+            p->mt = take(T * 8);
+            p->balpha = take(T * N * r);
+            p->aexp = take(T * 4);
+            if (op == HMM_OP_ESTEP || op == HMM_OP_FORWARD_BACKWARD) p->bgam = take(T * N * r);
+            const int nch = blk_xi_chunks(p->f64, c.total);
+            p->xi = take((size_t)nch * N * N * r + 256);
+            p->g1 = take((size_t)N * 8);
+            const int64_t S2 = 1 + N + (int64_t)N * family_k(c.fam, c.D);
+            const int ntile = blk_gstats_tiles(c.total);
+            p->compact = take((size_t)S2 * 8);
+            p->partial = take((size_t)ntile * S2 * 8);
+            p->red = take((size_t)reduce_scratch_len(ntile, S2) * 8);
+            p->total = off;
+            return HMM_OK;
+        }
         if (N > 8) {
             // per-sequence sweeps + one wave per chunk of WAVE_L steps
             p->wave = true;
@@ -277,6 +301,20 @@ hmm_status run_posterior_path(const hmm_model *m, const hmm_batch *b, const Chec
         PlainBuffers pb{ws + p.logB, ws + p.alpha, ws + p.beta, (double *)(ws + p.ps),
                         (double *)(ws + p.red)};
         r = run_plain<R>(sm, od, pb, ll, st, gamma_out, stats, p.S, s);
+    } else if (p.block) {
+        BlockBuffers bb;
+        bb.total = c.total;
+        bb.etab = ws + p.etab;
+        bb.mt = (double *)(ws + p.mt);
+        bb.alpha = ws + p.balpha;
+        bb.aexp = (int32_t *)(ws + p.aexp);
+        bb.gamma = p.bgam ? (void *)(ws + p.bgam) : nullptr;
+        bb.xi = ws + p.xi;
+        bb.g1 = (double *)(ws + p.g1);
+        bb.partial = (double *)(ws + p.partial);
+        bb.compact = (double *)(ws + p.compact);
+        bb.red = (double *)(ws + p.red);
+        r = run_block<R>(sm, od, bb, ll, st, gamma_out, stats, p.S, s);
     } else if (p.wave) {
         WaveBuffers wb;
         wb.C = p.C;

@@ -22,6 +22,7 @@ struct StagedModel {
     int N, D, family;
     const R *pi;        // [N]      exp(log pi)
     const R *A;         // [N*N]    exp(log A), row i = from state i
+    const R *AT;        // [N*N]    its transpose, row j = into state j
     const R *lpi;       // [N]      log pi in R
     const R *lA;        // [N*N]    log A in R
     const R *ep;        // [N*EP_STRIDE] emission constants
@@ -134,6 +135,43 @@ template <typename R>
 hmm_status run_wave(const StagedModel<R> &m, const ObsDesc &o, const WaveBuffers &wb,
                     double *loglik, int32_t *status, void *gamma_out, double *stats,
                     int64_t stats_len, hipStream_t s);
+
+// batched path for large N (<= 256) and the multivariate families: one
+// workgroup per sequence, emission table, stored alpha, xi by a GEMM
+constexpr int BLK_KC = 16384;   // steps per FP32 xi GEMM chunk (FP32 partial sums)
+constexpr int BLK_TS = 1024;    // steps per tile of the family-sum kernel
+struct BlockBuffers {
+    int64_t total;       // sum of T
+    void *etab;          // [total * N] R  emission factors, then w' (in place)
+    double *mt;          // [total]   per-step log shift
+    void *alpha;         // [total * N] R  normalised alpha
+    int32_t *aexp;       // [total]   binary exponent removed at each forward step
+    void *gamma;         // [total * N] R  posteriors (when the caller gives none)
+    void *xi;            // [chunks * N * N] R  GEMM partial sums (column-major)
+    double *g1;          // [N]
+    double *partial;     // [tiles * (1 + N + N*K)]
+    double *compact;     // [1 + N + N*K]
+    double *red;         // reduction scratch
+};
+int blk_xi_chunks(bool f64, int64_t total);
+int blk_gstats_tiles(int64_t total);
+template <typename R>
+hmm_status run_block(const StagedModel<R> &m, const ObsDesc &o, const BlockBuffers &bb,
+                     double *loglik, int32_t *status, void *gamma_out, double *stats,
+                     int64_t stats_len, hipStream_t s);
+
+// number of family-statistic slots per state (runtime family)
+__host__ __device__ inline int family_k_hd(int family, int D) {
+    switch (family) {
+    case HMM_GAUSSIAN: return 2;
+    case HMM_GAMMA: return 3;
+    case HMM_STUDENT_T: return 4;
+    case HMM_POISSON: return 1;
+    case HMM_DIAG_GAUSSIAN: return 2 * D;
+    case HMM_FULL_GAUSSIAN: return D + D * (D + 1) / 2;
+    default: return 0;
+    }
+}
 
 // plain path (one thread per sequence, literal log-sum-exp)
 struct PlainBuffers {

@@ -18,7 +18,7 @@ static size_t mv_count(int N, int D, int family) {
 size_t staged_bytes(int N, int D, int family, bool f64) {
     size_t r = f64 ? 8 : 4;
     size_t n = (size_t)N, nn = n * n;
-    return align256(n * r) * 2 + align256(nn * r) * 2 + align256(n * EP_STRIDE * r) +
+    return align256(n * r) * 2 + align256(nn * r) * 3 + align256(n * EP_STRIDE * r) +
            align256(n * EP_STRIDE * 8) + align256(mv_count(N, D, family) * r + r) + 256 +
            align256(64 * r) + 256;
 }
@@ -27,8 +27,9 @@ size_t staged_bytes(int N, int D, int family, bool f64) {
 // emission constants (see dev_common.hpp for their meaning) and, for the
 // multivariate families, the location vectors and -1/(2 var) or L^{-1}.
 template <typename R>
-__global__ __launch_bounds__(BLOCK) void k_stage(RawModel m, R *pi, R *A, R *lpi, R *lA, R *ep,
-                                                 double *ep64, R *mv, int *perr, R *A8, int *nrm) {
+__global__ __launch_bounds__(BLOCK) void k_stage(RawModel m, R *pi, R *A, R *AT, R *lpi, R *lA,
+                                                 R *ep, double *ep64, R *mv, int *perr, R *A8,
+                                                 int *nrm) {
     const int N = m.N, D = m.D;
     int bad = 0;
     __shared__ double amin_sh[BLOCK];
@@ -48,6 +49,8 @@ __global__ __launch_bounds__(BLOCK) void k_stage(RawModel m, R *pi, R *A, R *lpi
         double l = m.log_A[k];
         A[k] = (R)exp(l);
         lA[k] = (R)l;
+        const int i = k / N, j = k % N;
+        AT[j * N + i] = (R)exp(l);
     }
     const double *th = m.theta;
     const double kLog2Pi = 1.8378770664093454835606594728112;
@@ -153,6 +156,7 @@ void launch_stage(const RawModel &m, void *region, StagedModel<R> *out, hipStrea
     R *pi = (R *)p; p += align256(n * r);
     R *lpi = (R *)p; p += align256(n * r);
     R *A = (R *)p; p += align256(nn * r);
+    R *AT = (R *)p; p += align256(nn * r);
     R *lA = (R *)p; p += align256(nn * r);
     R *ep = (R *)p; p += align256(n * EP_STRIDE * r);
     double *ep64 = (double *)p; p += align256(n * EP_STRIDE * 8);
@@ -162,14 +166,15 @@ void launch_stage(const RawModel &m, void *region, StagedModel<R> *out, hipStrea
     int *nrm = (int *)p;
     {
         ProfScope ps("stage", s);
-        hipLaunchKernelGGL(k_stage<R>, dim3(1), dim3(BLOCK), 0, s, m, pi, A, lpi, lA, ep, ep64, mv,
-                           perr, A8, nrm);
+        hipLaunchKernelGGL(k_stage<R>, dim3(1), dim3(BLOCK), 0, s, m, pi, A, AT, lpi, lA, ep, ep64,
+                           mv, perr, A8, nrm);
     }
     out->N = m.N;
     out->D = m.D;
     out->family = m.family;
     out->pi = pi;
     out->A = A;
+    out->AT = AT;
     out->lpi = lpi;
     out->lA = lA;
     out->ep = ep;

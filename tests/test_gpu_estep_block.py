@@ -1,0 +1,158 @@
+"""GPU parity of the batched E-step for large state counts and for the
+multivariate families (one workgroup per sequence, emission table, xi as a
+GEMM over stored alpha and w') against the FP64 oracle, through the C ABI.
+
+The large-state workload (256 sequences of 2048 steps, N = 256 diagonal
+Gaussian states in D = 16) runs at full size in the benchmark's launch
+configuration and is checked on a sampled sequence plus exact identities.
+"""
+import numpy as np
+import pytest
+import torch  # noqa: F401  (imported at collection, outside the per-test time limit)
+
+import oracle
+import workloads
+from tests.parity import TOL, assert_loglik_close, assert_stats_close
+
+pytestmark = pytest.mark.gpu
+
+LENGTHS = [1, 2, 31, 64, 65, 200]
+
+
+@pytest.fixture(scope="module")
+def h():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_2605_29208_amd as h
+    return h
+
+
+def run_estep(h, w, prec, model=None, obs=None):
+    import torch
+    m = model if model is not None else w.model
+    dm = h.DeviceModel.from_model(m)
+    dt = np.float64 if prec in ("f64", "plain_f64") else np.float32
+    db = h.DeviceBatch(w.obs if obs is None else obs, w.offsets, dtype=dt)
+    stats, ll, st = h.estep_stats(dm, db, prec)
+    torch.cuda.synchronize()
+    return stats.cpu().numpy(), ll.cpu().numpy(), st.cpu().numpy()
+
+
+@pytest.mark.parametrize("fam", ["gaussian", "gamma", "student_t", "poisson"])
+@pytest.mark.parametrize("n", [65, 128, 150, 200, 256])
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_block_scalar_families(h, fam, n, prec):
+    w = workloads.random_workload(fam, n, 1, LENGTHS, 800 + n)
+    ref = oracle.estep(w.model, w.offsets, w.obs)
+    stats, ll, st = run_estep(h, w, prec)
+    assert np.array_equal(st, ref["status"])
+    assert_loglik_close(ll, ref["loglik"], TOL[prec], f"{fam} N={n} {prec}")
+    assert_stats_close(stats, ref["stats"], n, fam, TOL[prec], f"{fam} N={n} {prec}")
+
+
+@pytest.mark.parametrize("n,d", [(3, 2), (20, 5), (70, 16), (256, 16)])
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_block_diag_family(h, n, d, prec):
+    w = workloads.random_workload("diag", n, d, [1, 40, 130], 820 + n + d)
+    ref = oracle.estep(w.model, w.offsets, w.obs)
+    stats, ll, st = run_estep(h, w, prec)
+    assert np.array_equal(st, ref["status"])
+    assert_loglik_close(ll, ref["loglik"], TOL[prec], f"diag N={n} D={d} {prec}")
+    assert_stats_close(stats, ref["stats"], n, "diag", TOL[prec], f"diag N={n} D={d} {prec}", d=d)
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_block_table_family(h, prec):
+    import torch
+    n = 100
+    rng = np.random.default_rng(840)
+    lengths = [1, 40, 97]
+    T = sum(lengths)
+    logB = np.log(rng.dirichlet(np.ones(12), size=n).T[rng.integers(0, 12, T)])
+    offs = np.concatenate([[0], np.cumsum(lengths)])
+    base = workloads.make_model("gaussian", n, 1, rng)
+    m = workloads.Model("table", n, n, base.log_pi, base.log_A, np.zeros(0))
+    ref = oracle.estep(m, offs, None, logB=logB)
+    dm = h.DeviceModel("table", n, n, m.log_pi, m.log_A, None)
+    db = h.DeviceBatch(logB, offs, dtype=np.float64 if prec == "f64" else np.float32)
+    stats, ll, st = h.estep_stats(dm, db, prec)
+    torch.cuda.synchronize()
+    assert_loglik_close(ll.cpu().numpy(), ref["loglik"], TOL[prec], "table")
+    assert_stats_close(stats.cpu().numpy(), ref["stats"], n, 0, TOL[prec], "table")
+
+
+@pytest.mark.parametrize("fam,n,d", [("full", 5, 3), ("diag", 7, 4), ("gaussian", 100, 1)])
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_block_posteriors_and_decode(h, fam, n, d, prec):
+    import torch
+    w = workloads.random_workload(fam, n, d, [1, 45, 160], 850 + n)
+    ref = oracle.estep(w.model, w.offsets, w.obs, want_gamma=True)
+    dm = h.DeviceModel.from_model(w.model)
+    db = h.DeviceBatch(w.obs, w.offsets, dtype=np.float64 if prec == "f64" else np.float32)
+    ll, gam, st = h.forward_backward(dm, db, prec)
+    path, _ = h.posterior_decode(dm, db, prec)
+    torch.cuda.synchronize()
+    assert_loglik_close(ll.cpu().numpy(), ref["loglik"], TOL[prec], f"{fam} fb loglik")
+    g = gam.cpu().numpy().astype(np.float64)
+    atol = 1e-11 if prec == "f64" else 5e-5
+    assert np.abs(g - ref["gamma"]).max() <= atol
+    rp = oracle.posterior_decode(ref["gamma"])
+    srt = np.sort(ref["gamma"], axis=1)
+    gap = srt[:, -1] - srt[:, -2]
+    assert np.all((path.cpu().numpy() == rp) | (gap < 1e-4))
+
+
+def test_block_status_codes_and_exclusion(h):
+    w = workloads.random_workload("gamma", 80, 1, [50, 60, 70, 33], 860)
+    obs = w.obs.copy()
+    obs[w.offsets[1] + 5] = np.nan          # non-finite observation -> status 2
+    obs[w.offsets[2] + 40] = -1.0           # outside the Gamma support -> status 1
+    ref = oracle.estep(w.model, w.offsets, obs)
+    for prec in ("f32", "f64"):
+        stats, ll, st = run_estep(h, w, prec, obs=obs)
+        assert list(st) == list(ref["status"]) == [0, 2, 1, 0], (prec, st)
+        assert ll[2] == -np.inf and np.isnan(ll[1])
+        assert_stats_close(stats, ref["stats"], 80, "gamma", TOL[prec], f"status {prec}")
+
+
+def test_block_determinism(h):
+    w = workloads.random_workload("gaussian", 150, 1, [300, 1000, 77, 1], 870)
+    a = run_estep(h, w, "f32")
+    b = run_estep(h, w, "f32")
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_config3_subset(h, prec):
+    w = workloads.config3(n_seq=3, T=300)
+    ref = oracle.estep(w.model, w.offsets, w.obs)
+    stats, ll, st = run_estep(h, w, prec)
+    assert (st == 0).all()
+    assert_loglik_close(ll, ref["loglik"], TOL[prec], f"config3 subset {prec}")
+    assert_stats_close(stats, ref["stats"], 256, "diag", TOL[prec], f"config3 subset {prec}", d=16)
+
+
+def test_config3_full_size(h):
+    """256 sequences of 2048 steps, N = 256, D = 16, as the benchmark launches
+    them: a sampled sequence against the oracle, identities that hold at any
+    size, and FP32 against FP64 on every pooled statistic."""
+    w = workloads.config3()
+    stats, ll, st = run_estep(h, w, "f32")
+    assert (st == 0).all()
+    B = len(w.offsets) - 1
+    pick = np.array([37])
+    sub = w.subset(pick)
+    ref = oracle.estep(sub.model, sub.offsets, sub.obs)
+    assert_loglik_close(ll[pick], ref["loglik"], TOL["f32"], "config3 sampled")
+    N = 256
+    g1 = stats[1:1 + N]
+    xi = stats[1 + N:1 + N + N * N]
+    gs = stats[1 + N + N * N:1 + 2 * N + N * N]
+    total = int(w.offsets[-1])
+    assert abs(g1.sum() - B) < 1e-4 * B
+    assert abs(gs.sum() - total) < 1e-4 * total
+    assert abs(xi.sum() - (total - B)) < 1e-4 * total
+    assert abs(stats[0] - ll.sum()) < 1e-9 * abs(stats[0])
+    s64, ll64, _ = run_estep(h, w, "f64")
+    assert_loglik_close(ll, ll64, TOL["f32"], "config3 f32 vs f64")
+    assert_stats_close(stats, s64, N, "diag", TOL["f32"], "config3 f32 vs f64", d=16)
