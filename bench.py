@@ -35,6 +35,11 @@ PEAK_FP32_VALU_TFLOPS = 157.3   # MI355X FP32 vector, spec sheet
 METRIC = "E-step state-transitions/s (B*T*N^2) vs plain GPU; p50/p99 decode latency"
 
 
+def log(msg):
+    """Progress of the run on stderr (the JSON line alone goes to stdout)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def kernel_table(records, steps):
     agg = {}
     for name, ms in records:
@@ -61,6 +66,11 @@ def algorithmic_flops(name, w):
     if name == "wave_sweep":
         # forward alpha*A and backward A*w over every sequence
         return 4.0 * steps * n * n
+    if name in ("block_fwd", "block_bwd"):
+        # one vector-matrix product per step
+        return 2.0 * steps * n * n
+    if name == "block_xi_gemm":
+        return 2.0 * (steps - 1) * n * n
     return None
 
 
@@ -69,6 +79,8 @@ WORKLOADS = {
                 lambda workloads: workloads.config2()),
     "heavy": ("heavy-tailed E-step: B=512, T~lognormal(median 3000, sigma 0.6, <=20000), "
               "N=32 Student-t, FP32 obs", lambda workloads: workloads.config4b()),
+    "large": ("large-state E-step: B=256, T=2048, N=256 diagonal Gaussian D=16, FP32 obs",
+              lambda workloads: workloads.config3()),
 }
 
 
@@ -154,6 +166,7 @@ def serving_bench(h, workloads, qps_list, seconds, pool_size=256, streams=SERVIN
             steps = sum(T for _, _, T in sent)
             span = max(done[r]["t_done"] for r, _, _ in sent) - t0
             bad = sum(1 for r, _, _ in sent if done[r]["status"] != 0)
+            log(f"serving {qps:g} QPS done")
             points.append({"qps_offered": qps, "requests": n_req,
                            "qps_served": n_req / span, "p50_ms": 1e3 * float(np.percentile(lat, 50)),
                            "p99_ms": 1e3 * float(np.percentile(lat, 99)),
@@ -215,9 +228,11 @@ def main():
     def step(p=prec, wsp=ws):
         h.hmm_estep_stats(dm, db, p, stats, loglik, status, wsp)
 
+    log(f"workload {args.workload}: {w.n_seq} sequences, {w.total_steps} steps, N={w.model.n_states}")
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
+    log("warm-up done")
     # (1) eager calls with per-kernel hipEvents (the kernel table and roofline)
     h.hmm_profile_enable(True)
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -232,6 +247,7 @@ def main():
     h.hmm_profile_enable(False)
     kt = kernel_table(recs, args.steps)
     assert (status.cpu().numpy() == 0).all()
+    log(f"eager: {eager_ms:.3f} ms per E-step")
     # (2) the same E-steps captured once in a HIP graph and replayed (the way an
     # EM loop issues them): the timed value
     side = torch.cuda.Stream()
@@ -253,22 +269,46 @@ def main():
     ms = ev0.elapsed_time(ev1) / args.steps
     del g_est
     assert (status.cpu().numpy() == 0).all()
+    log(f"graph replay: {ms:.3f} ms per E-step")
 
-    # plain GPU method (one thread per sequence, literal log-sum-exp) on the same data
-    plain_ms = None
+    # plain GPU method (one thread per sequence, literal log-sum-exp) on the same
+    # data.  Its sequences run side by side (one thread each), so its time is
+    # linear in the longest sequence; for large N it is timed on the same
+    # batch cut to its first plain_t steps and scaled by T / plain_t.
+    plain_ms, plain_note = None, None
     if args.plain_steps > 0:
         pprec = "plain_" + prec
-        pws = h._ws(h.hmm_workspace_size("estep", dm, db, pprec))
-        step(pprec, pws)
+        scale = 1.0
+        T_max = int(np.max(w.lengths))
+        plain_t = max(16, int(2e8 // (w.model.n_states ** 2 * 64)))
+        if T_max > plain_t:
+            cut = np.minimum(w.lengths, plain_t)
+            offs = np.concatenate([[0], np.cumsum(cut)]).astype(np.int64)
+            rows = np.concatenate([np.arange(w.offsets[b], w.offsets[b] + cut[b])
+                                   for b in range(w.n_seq)])
+            pdb = h.DeviceBatch(w.obs[rows], offs, dtype=np.float32 if prec == "f32" else np.float64)
+            scale = T_max / plain_t
+            plain_note = (f"timed on the batch cut to its first {plain_t} steps per sequence, "
+                          f"scaled by {scale:.1f} (linear in the longest sequence)")
+        else:
+            pdb = db
+        pws = h._ws(h.hmm_workspace_size("estep", dm, pdb, pprec))
+
+        def pstep():
+            h.hmm_estep_stats(dm, pdb, pprec, stats, loglik, status, pws)
+
+        pstep()
         torch.cuda.synchronize()
+        log("plain warm-up done")
         t0 = torch.cuda.Event(enable_timing=True)
         t1 = torch.cuda.Event(enable_timing=True)
         t0.record()
         for _ in range(args.plain_steps):
-            step(pprec, pws)
+            pstep()
         t1.record()
         torch.cuda.synchronize()
-        plain_ms = t0.elapsed_time(t1) / args.plain_steps
+        plain_ms = t0.elapsed_time(t1) / args.plain_steps * scale
+        log(f"plain: {plain_ms:.3f} ms per E-step")
         del pws
 
     # Baum-Welch: E-step + FP64 M-step of the family (Gamma Newton, Student-t ECM),
@@ -305,6 +345,7 @@ def main():
         torch.cuda.synchronize()
         em_ms = e0.elapsed_time(e1)
         traj = em_stats[:, 0].cpu().numpy()
+        log(f"EM graph: {em_ms / K:.3f} ms per iteration")
         em = {"iterations": K, "ms_total": em_ms, "ms_per_iteration": em_ms / K,
               "transitions_per_s": K * w.transitions / (em_ms / 1e3),
               "loglik_first": float(traj[0]), "loglik_last": float(traj[-1]),
@@ -338,7 +379,7 @@ def main():
                    "transitions_per_step": w.transitions, "precision": prec},
         "plain_gpu": None if plain_ms is None else {
             "value": w.transitions / (plain_ms / 1e3), "ms_per_step": plain_ms,
-            "speedup": plain_ms / ms},
+            "speedup": plain_ms / ms, "note": plain_note},
         "roofline": roof,
         "em_graph": em,
         "kernels": kt,
@@ -347,6 +388,7 @@ def main():
         qps = [float(x) for x in args.serving_qps.split(",") if x]
         out["serving"] = serving_bench(h, workloads, qps, args.serving_seconds,
                                        streams=args.serving_streams)
+        log("serving done")
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(out))

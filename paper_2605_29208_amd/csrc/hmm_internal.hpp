@@ -139,7 +139,8 @@ hmm_status run_wave(const StagedModel<R> &m, const ObsDesc &o, const WaveBuffers
 // batched path for large N (<= 256) and the multivariate families: one
 // workgroup per sequence, emission table, stored alpha, xi by a GEMM
 constexpr int BLK_KC = 16384;   // steps per FP32 xi GEMM chunk (FP32 partial sums)
-constexpr int BLK_TS = 1024;    // steps per tile of the family-sum kernel
+constexpr int BLK_TS = 1024;    // steps per tile of the family-sum kernels
+constexpr int BLK_GS_BLOCKS = 1024;   // blocks (partial rows) of the per-state family-sum kernel
 struct BlockBuffers {
     int64_t total;       // sum of T
     void *etab;          // [total * N] R  emission factors, then w' (in place)

@@ -32,20 +32,49 @@
 namespace hmmk {
 
 constexpr int BT = 256;   // threads of the sweep and emission blocks
+constexpr int PF = 8;     // steps of sweep inputs loaded ahead
 
-__device__ __forceinline__ double wave_max_dbl(double v) {
-    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+enum : int { DPP_ROW_MIRROR_B = 0x140 };   // lane p <-> 15 - p inside each row of 16
+
+// wave-wide all-reductions through DPP row operations and the permlane
+// swaps (every lane receives the result, identical in all lanes)
+template <typename V, typename Op>
+__device__ __forceinline__ V wave_all(V v, Op op) {
+    v = op(v, dpp_v<DPP_QP_X1>(v));
+    v = op(v, dpp_v<DPP_QP_X2>(v));
+    v = op(v, dpp_v<DPP_HALF_MIRROR>(v));
+    v = op(v, dpp_v<DPP_ROW_MIRROR_B>(v));
+    if constexpr (sizeof(V) == 4) {
+        const uint32_t u = __builtin_bit_cast(uint32_t, v);
+        auto r16 = __builtin_amdgcn_permlane16_swap(u, u, false, false);
+        v = op(__builtin_bit_cast(V, (uint32_t)r16[0]), __builtin_bit_cast(V, (uint32_t)r16[1]));
+        const uint32_t w = __builtin_bit_cast(uint32_t, v);
+        auto r32 = __builtin_amdgcn_permlane32_swap(w, w, false, false);
+        v = op(__builtin_bit_cast(V, (uint32_t)r32[0]), __builtin_bit_cast(V, (uint32_t)r32[1]));
+    } else {
+        uint64_t u = __builtin_bit_cast(uint64_t, v);
+        auto lo = __builtin_amdgcn_permlane16_swap((uint32_t)u, (uint32_t)u, false, false);
+        auto hi = __builtin_amdgcn_permlane16_swap((uint32_t)(u >> 32), (uint32_t)(u >> 32), false, false);
+        v = op(__builtin_bit_cast(V, ((uint64_t)(uint32_t)hi[0] << 32) | (uint32_t)lo[0]),
+               __builtin_bit_cast(V, ((uint64_t)(uint32_t)hi[1] << 32) | (uint32_t)lo[1]));
+        u = __builtin_bit_cast(uint64_t, v);
+        auto lo2 = __builtin_amdgcn_permlane32_swap((uint32_t)u, (uint32_t)u, false, false);
+        auto hi2 = __builtin_amdgcn_permlane32_swap((uint32_t)(u >> 32), (uint32_t)(u >> 32), false, false);
+        v = op(__builtin_bit_cast(V, ((uint64_t)(uint32_t)hi2[0] << 32) | (uint32_t)lo2[0]),
+               __builtin_bit_cast(V, ((uint64_t)(uint32_t)hi2[1] << 32) | (uint32_t)lo2[1]));
+    }
     return v;
+}
+__device__ __forceinline__ double wave_max_dbl(double v) {
+    return wave_all(v, [](double a, double b) { return fmax(a, b); });
 }
 template <typename R>
 __device__ __forceinline__ R wave_sum_r(R v) {
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
+    return wave_all(v, [](R a, R b) { return a + b; });
 }
 template <typename R>
 __device__ __forceinline__ R wave_max_r(R v) {
-    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-    return v;
+    return wave_all(v, [](R a, R b) { return fmax(a, b); });
 }
 
 __host__ __device__ inline int blk_nc(int N) { return ((N + 63) / 64) * 64; }
@@ -86,6 +115,73 @@ __global__ __launch_bounds__(BT) void k_blk_emit(StagedModel<R> m, ObsRef o, int
     }
 }
 
+// Diagonal-Gaussian emissions: a tile of ES steps has its observations
+// staged in LDS; thread j (state j, constants in registers) evaluates
+// log b_j for every step of the tile into LDS; then each wave takes steps,
+// forms the per-step maximum and writes the factors (coalesced rows).
+constexpr int ES = 32;
+template <typename R, int DM>
+__global__ __launch_bounds__(BT) void k_blk_emit_diag(StagedModel<R> m, ObsRef o, int64_t total,
+                                                      R *__restrict__ etab, double *__restrict__ mt) {
+    __shared__ R ysh[ES][DM];
+    __shared__ R lsh[ES][BT + 1];
+    __shared__ int bsh[ES];
+    const int N = m.N, D = m.D, j = threadIdx.x, lane = j & 63, wv = j >> 6;
+    const bool live = j < N;
+    R mu[DM], wq[DM];
+#pragma unroll
+    for (int d = 0; d < DM; ++d) {
+        mu[d] = (live && d < D) ? m.mv[(size_t)j * D + d] : (R)0;
+        wq[d] = (live && d < D) ? m.mv[(size_t)N * D + (size_t)j * D + d] : (R)0;
+    }
+    const R c0 = live ? m.ep[j * EP_STRIDE] : (R)0;
+    for (int64_t base = (int64_t)blockIdx.x * ES; base < total; base += (int64_t)gridDim.x * ES) {
+        const int ns = (int)((total - base) < ES ? (total - base) : ES);
+        __syncthreads();
+        if (j < ES) bsh[j] = 0;
+        __syncthreads();
+        for (int k = j; k < ns * D; k += BT) {
+            const int sidx = k / D, d = k % D;
+            const R y = load_obs<R>(o, (base + sidx) * D + d);
+            ysh[sidx][d] = y;
+            if (!isfinite(y)) bsh[sidx] = 1;
+        }
+        __syncthreads();
+        if (live) {
+            for (int sidx = 0; sidx < ns; ++sidx) {
+                R acc = c0;
+#pragma unroll
+                for (int d = 0; d < DM; ++d) {
+                    if (d < D) {
+                        const R dv = ysh[sidx][d] - mu[d];
+                        acc = fma(wq[d], dv * dv, acc);
+                    }
+                }
+                lsh[sidx][j] = acc;
+            }
+        }
+        __syncthreads();
+        for (int sidx = wv; sidx < ns; sidx += BT / 64) {
+            R l[4];
+            R mx = neg_inf<R>();
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const int jj = lane + 64 * k;
+                l[k] = jj < N ? lsh[sidx][jj] : neg_inf<R>();
+                mx = fmax(mx, l[k]);
+            }
+            mx = wave_max_r(mx);
+            const int64_t row = base + sidx;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const int jj = lane + 64 * k;
+                if (jj < N) etab[row * N + jj] = (l[k] == neg_inf<R>()) ? (R)0 : fexp_e(l[k] - mx);
+            }
+            if (lane == 0) mt[row] = bsh[sidx] ? __builtin_nan("") : (double)mx;
+        }
+    }
+}
+
 // largest entry of a non-negative vector spread over the block (every part
 // holds the same values; the waves of part 0 publish their maxima)
 template <typename R>
@@ -98,21 +194,88 @@ __device__ __forceinline__ R blk_max(R v, R *wred, int NC) {
     return mx;
 }
 
+// Thread (col, p) of a sweep: its share sum_{i in row block p} x_i M[i][col]
+// of a vector-matrix product (M = A for the forward, A^T for the backward,
+// both row-major N x N).  AREG keeps the thread's RP entries of M in
+// registers for the whole sequence (single precision); otherwise they are
+// read from global memory (L2) at every step.
+template <typename R, int RPM, bool AREG>
+struct PartDot {
+    R a[AREG ? RPM : 1];
+    int i0, RP, N, col;
+    bool live;
+    __device__ __forceinline__ void init(const R *M, int n, int c, int p, int rp, bool lv) {
+        N = n;
+        col = c;
+        RP = rp;
+        i0 = p * rp;
+        live = lv;
+        if constexpr (AREG) {
+            // unconditional loads at clamped indices (straight-line code),
+            // entries outside the matrix set to zero
+            const int cc = min(col, N - 1);
+#pragma unroll
+            for (int k = 0; k < RPM; ++k) {
+                const int i = i0 + k;
+                const R v = M[min(i, N - 1) * N + cc];
+                a[k] = (live && k < RP && i < N) ? v : (R)0;
+            }
+        }
+    }
+    __device__ __forceinline__ R dot(const R *x, const R *M) const {
+        R acc0 = (R)0, acc1 = (R)0;
+        if constexpr (AREG) {
+            // RP == RPM (a multiple of 4) and i0 a multiple of RP: the shared
+            // vector is read four entries per broadcast load
+            const float4 *xv = reinterpret_cast<const float4 *>(x + i0);
+#pragma unroll
+            for (int k = 0; k < RPM; k += 4) {
+                // at most 16 broadcast values in flight: the thread's RPM
+                // matrix entries already hold most of its registers
+                if (k % 16 == 0) __builtin_amdgcn_sched_barrier(0);
+                const float4 q = xv[k / 4];
+                acc0 = fma(q.x, a[k], acc0);
+                acc1 = fma(q.y, a[k + 1], acc1);
+                acc0 = fma(q.z, a[k + 2], acc0);
+                acc1 = fma(q.w, a[k + 3], acc1);
+            }
+        } else {
+            for (int k = 0; k + 1 < RP; k += 2) {
+                const int i = i0 + k;
+                if (i + 1 < N) {
+                    acc0 = fma(x[i], live ? M[i * N + col] : (R)0, acc0);
+                    acc1 = fma(x[i + 1], live ? M[(i + 1) * N + col] : (R)0, acc1);
+                } else if (i < N) {
+                    acc0 = fma(x[i], live ? M[i * N + col] : (R)0, acc0);
+                }
+            }
+        }
+        return acc0 + acc1;
+    }
+};
+
 // ---------------------------------------------------------------- 2. forward
-template <typename R>
-__global__ __launch_bounds__(BT) void k_blk_fwd(StagedModel<R> m, const int64_t *__restrict__ offsets,
+// NT threads: NC = N rounded up to 64 columns, P = NT / NC row blocks of
+// RP = NC / P rows (threads beyond P * NC only take part in the barriers).
+template <typename R, int NT, int RPM, bool AREG, int NCT>
+__global__ __launch_bounds__(NT) void k_blk_fwd(StagedModel<R> m, const int64_t *__restrict__ offsets,
                                                 const R *__restrict__ etab,
                                                 const double *__restrict__ mt, R *__restrict__ alpha,
                                                 int32_t *__restrict__ aexp,
                                                 double *__restrict__ loglik,
                                                 int32_t *__restrict__ status) {
-    __shared__ R x[BT];
-    __shared__ R psum[4][BT];
+    __shared__ __align__(16) R x[NT + 8];
+    __shared__ R psum[8][256];
     __shared__ R wred[4];
     __shared__ R wsum[4];
-    const int N = m.N, NC = blk_nc(N), P = BT / NC, RP = NC / P;
+    __shared__ R etile[2][PF][256];
+    __shared__ double mtile[2][PF];
+    // NCT > 0: the column count is a compile-time constant
+    const int N = m.N, NC = NCT > 0 ? NCT : blk_nc(N), P = NT / NC, RP = NC / P;
     const int tid = threadIdx.x, c = tid % NC, p = tid / NC;
     const bool live = c < N;
+    PartDot<R, RPM, AREG> pd;
+    pd.init(m.A, N, c, p, RP, live);
     const int64_t b = blockIdx.x;
     const int64_t off = offsets[b];
     const int T = (int)(offsets[b + 1] - off);
@@ -126,33 +289,61 @@ __global__ __launch_bounds__(BT) void k_blk_fwd(StagedModel<R> m, const int64_t 
     if (p == 0 && live) alpha[off * N + c] = v;
     if (tid == 0) aexp[off] = ex;
     __syncthreads();
-    for (int t = 1; t < T; ++t) {
-        const int64_t row = off + t;
-        const R e = live ? etab[row * N + c] : (R)0;
-        R acc0 = (R)0, acc1 = (R)0;
-        const int i0 = p * RP;
-        int k = 0;
-        for (; k + 1 < RP; k += 2) {
-            const int i = i0 + k;
-            if (i + 1 < N) {
-                acc0 = fma(x[i], live ? m.A[i * N + c] : (R)0, acc0);
-                acc1 = fma(x[i + 1], live ? m.A[(i + 1) * N + c] : (R)0, acc1);
-            } else if (i < N) {
-                acc0 = fma(x[i], live ? m.A[i * N + c] : (R)0, acc0);
+    // Inputs of the next window of PF steps (emission rows, log shifts) are
+    // loaded into a few registers while the current window runs from an LDS
+    // tile, then parked in the other tile (indices clamped to the sequence).
+    constexpr int EPTM = (PF * 256 + NT - 1) / NT;   // tile entries per thread, at most
+    const int EPT = (PF * NC + NT - 1) / NT;         // tile entries per thread
+    auto fetch = [&](int w0, R *ev, double *mv) {
+        for (int k = 0; k < EPTM; ++k) {
+            const int idx = tid + k * NT;
+            if (k < EPT && idx < PF * NC) {
+                const int sl = idx / NC, col = idx % NC;
+                const int64_t rr = off + min(w0 + sl, T - 1);
+                ev[k] = col < N ? etab[rr * N + col] : (R)0;
             }
         }
-        psum[p][c] = acc0 + acc1;
-        __syncthreads();
-        R s = psum[0][c];
-        for (int q = 1; q < P; ++q) s += psum[q][c];
-        v = s * e;
-        ex = fexp(blk_max(v, wred, NC));
-        v = fldexp(v, -ex);
-        if (p == 0) x[c] = v;
-        if (p == 0 && live) alpha[row * N + c] = v;
-        if (tid == 0) aexp[row] = ex;
-        E += ex;
-        logS += mt[row];
+        if (tid < PF) *mv = mt[off + min(w0 + tid, T - 1)];
+    };
+    auto park = [&](int buf, const R *ev, double mv) {
+        for (int k = 0; k < EPTM; ++k) {
+            const int idx = tid + k * NT;
+            if (k < EPT && idx < PF * NC) etile[buf][idx / NC][idx % NC] = ev[k];
+        }
+        if (tid < PF) mtile[buf][tid] = mv;
+    };
+    R ev[EPTM];
+#pragma unroll
+    for (int k = 0; k < EPTM; ++k) ev[k] = (R)0;
+    double mv = 0.0;
+    fetch(1, ev, &mv);
+    park(0, ev, mv);
+    __syncthreads();
+    int buf = 0;
+    for (int w0 = 1; w0 < T; w0 += PF) {
+        fetch(w0 + PF, ev, &mv);
+        for (int sl = 0; sl < PF; ++sl) {
+            const int t = w0 + sl;
+            if (t >= T) break;
+            const int64_t row = off + t;
+            const R e = etile[buf][sl][c];
+            const R acc = pd.dot(x, m.A);
+            if (p < 8) psum[p][c] = acc;
+            __syncthreads();
+            R s = psum[0][c];
+            for (int q = 1; q < P; ++q) s += psum[q][c];
+            v = s * e;
+            ex = fexp(blk_max(v, wred, NC));
+            v = fldexp(v, -ex);
+            if (p == 0) x[c] = v;
+            if (p == 0 && live) alpha[row * N + c] = v;
+            if (tid == 0) aexp[row] = ex;
+            E += ex;
+            logS += mtile[buf][sl];
+            __syncthreads();
+        }
+        buf ^= 1;
+        park(buf, ev, mv);
         __syncthreads();
     }
     // log P(y): sum of the last normalised alpha (part 0 waves)
@@ -183,60 +374,104 @@ __global__ __launch_bounds__(BT) void k_blk_fwd(StagedModel<R> m, const int64_t 
 }
 
 // ---------------------------------------------------------------- 3. backward
-template <typename R>
-__global__ __launch_bounds__(BT) void k_blk_bwd(StagedModel<R> m, const int64_t *__restrict__ offsets,
+template <typename R, int NT, int RPM, bool AREG, int NCT>
+__global__ __launch_bounds__(NT) void k_blk_bwd(StagedModel<R> m, const int64_t *__restrict__ offsets,
                                                 R *__restrict__ etab, const R *__restrict__ alpha,
                                                 const int32_t *__restrict__ aexp,
                                                 const int32_t *__restrict__ status,
                                                 R *__restrict__ gamma) {
-    __shared__ R xw[BT];
-    __shared__ R psum[4][BT];
+    __shared__ __align__(16) R xw[NT + 8];
+    __shared__ R psum[8][256];
     __shared__ R wred[4];
     __shared__ R wsum[4];
-    const int N = m.N, NC = blk_nc(N), P = BT / NC, RP = NC / P;
+    __shared__ R atile[2][PF][256];
+    __shared__ R etile[2][PF][256];
+    __shared__ int xtile[2][PF];
+    const int N = m.N, NC = NCT > 0 ? NCT : blk_nc(N), P = NT / NC, RP = NC / P;
     const int tid = threadIdx.x, r = tid % NC, p = tid / NC;
     const bool live = r < N;
+    PartDot<R, RPM, AREG> pd;
+    pd.init(m.AT, N, r, p, RP, live);
     const int64_t b = blockIdx.x;
     const int64_t off = offsets[b];
     const int T = (int)(offsets[b + 1] - off);
     const bool use = status[b] == 0;
     R bt = live ? (R)1 : (R)0;   // beta^_t of state r (identical in every part)
-    for (int t = T - 1; t >= 0; --t) {
-        const int64_t row = off + t;
-        const R a = live ? alpha[row * N + r] : (R)0;
-        const R e = live ? etab[row * N + r] : (R)0;
-        const R h = a * bt;
-        const R w = e * bt;
-        if (p == 0) xw[r] = w;
-        const R hs = wave_sum_r((p == 0) ? h : (R)0);
-        if (tid < NC && (tid & 63) == 0) wsum[tid / 64] = hs;
-        __syncthreads();
-        R Z = wsum[0];
-        for (int q = 1; q < NC / 64; ++q) Z += wsum[q];
-        const R rz = (R)1 / Z;
-        if (p == 0 && live) {
-            gamma[row * N + r] = use ? h * rz : (R)0;
-            etab[row * N + r] = (use && t > 0) ? fldexp(w * rz, -aexp[row]) : (R)0;
-        }
-        if (t == 0) break;
-        R acc0 = (R)0, acc1 = (R)0;
-        const int k0 = p * RP;
-        int k = 0;
-        for (; k + 1 < RP; k += 2) {
-            const int kk = k0 + k;
-            if (kk + 1 < N) {
-                acc0 = fma(xw[kk], live ? m.AT[kk * N + r] : (R)0, acc0);
-                acc1 = fma(xw[kk + 1], live ? m.AT[(kk + 1) * N + r] : (R)0, acc1);
-            } else if (kk < N) {
-                acc0 = fma(xw[kk], live ? m.AT[kk * N + r] : (R)0, acc0);
+    // alpha and emission rows and exponents of the next window of PF steps
+    // are loaded into registers while the current window runs from LDS
+    // tiles (indices clamped to the sequence)
+    constexpr int EPTM = (PF * 256 + NT - 1) / NT;
+    const int EPT = (PF * NC + NT - 1) / NT;
+    auto fetch = [&](int w0, R *av, R *ev, int *xv) {
+        for (int k = 0; k < EPTM; ++k) {
+            const int idx = tid + k * NT;
+            if (k < EPT && idx < PF * NC) {
+                const int sl = idx / NC, col = idx % NC;
+                const int64_t rr = off + max(w0 - sl, 0);
+                av[k] = col < N ? alpha[rr * N + col] : (R)0;
+                ev[k] = col < N ? etab[rr * N + col] : (R)0;
             }
         }
-        psum[p][r] = acc0 + acc1;
+        if (tid < PF) *xv = aexp[off + max(w0 - tid, 0)];
+    };
+    auto park = [&](int bf, const R *av, const R *ev, int xv) {
+        for (int k = 0; k < EPTM; ++k) {
+            const int idx = tid + k * NT;
+            if (k < EPT && idx < PF * NC) {
+                atile[bf][idx / NC][idx % NC] = av[k];
+                etile[bf][idx / NC][idx % NC] = ev[k];
+            }
+        }
+        if (tid < PF) xtile[bf][tid] = xv;
+    };
+    R av[EPTM], ev[EPTM];
+#pragma unroll
+    for (int k = 0; k < EPTM; ++k) av[k] = ev[k] = (R)0;
+    int xv = 0;
+    fetch(T - 1, av, ev, &xv);
+    park(0, av, ev, xv);
+    __syncthreads();
+    int buf = 0;
+    for (int w0 = T - 1; w0 >= 0; w0 -= PF) {
+        fetch(w0 - PF, av, ev, &xv);
+        bool done = false;
+        for (int sl = 0; sl < PF; ++sl) {
+            const int t = w0 - sl;
+            if (t < 0) break;
+            const int64_t row = off + t;
+            const R a = atile[buf][sl][r];
+            const R e = etile[buf][sl][r];
+            const int xt = xtile[buf][sl];
+            const R h = a * bt;
+            const R w = e * bt;
+            if (p == 0) xw[r] = w;
+            const R hs = wave_sum_r((p == 0) ? h : (R)0);
+            if (tid < NC && (tid & 63) == 0) wsum[tid / 64] = hs;
+            __syncthreads();
+            R Z = wsum[0];
+            for (int q = 1; q < NC / 64; ++q) Z += wsum[q];
+            const R rz = (R)1 / Z;
+            if (p == 0 && live) {
+                gamma[row * N + r] = use ? h * rz : (R)0;
+                etab[row * N + r] = (use && t > 0) ? fldexp(w * rz, -xt) : (R)0;
+            }
+            if (t == 0) {
+                done = true;
+                break;
+            }
+            const R acc = pd.dot(xw, m.AT);
+            if (p < 8) psum[p][r] = acc;
+            __syncthreads();
+            R s = psum[0][r];
+            for (int q = 1; q < P; ++q) s += psum[q][r];
+            const int ex = fexp(blk_max(s, wred, NC));
+            bt = fldexp(s, -ex);
+        }
+        if (done) break;
+        buf ^= 1;
+        __syncthreads();   // every lane is done with the tiles of this window
+        park(buf, av, ev, xv);
         __syncthreads();
-        R s = psum[0][r];
-        for (int q = 1; q < P; ++q) s += psum[q][r];
-        const int ex = fexp(blk_max(s, wred, NC));
-        bt = fldexp(s, -ex);
     }
 }
 
@@ -276,9 +511,11 @@ __global__ __launch_bounds__(BT) void k_blk_gstats(StagedModel<R> m, ObsRef o, i
     const double mu = fam == HMM_DIAG_GAUSSIAN ? (double)m.mv[(size_t)c * D + d] : (double)k.c0;
 #pragma unroll 8
     for (int64_t t = t0; t < t1; ++t) {
-        const double gm = (double)gamma[t * N + c];
-        const double y = (double)load_obs<R>(o, fam == HMM_DIAG_GAUSSIAN ? t * D + d : t);
-        if (!(gm > 0.0)) continue;
+        const double g0 = (double)gamma[t * N + c];
+        const double gm = g0 > 0.0 ? g0 : 0.0;
+        const double yr = (double)load_obs<R>(o, fam == HMM_DIAG_GAUSSIAN ? t * D + d : t);
+        // a zero weight adds nothing; keep y inside every family's domain there
+        const double y = gm > 0.0 ? yr : 1.0;
         g += gm;
         if (fam == HMM_GAUSSIAN || fam == HMM_DIAG_GAUSSIAN) {
             const double dv = y - mu;
@@ -310,6 +547,84 @@ __global__ __launch_bounds__(BT) void k_blk_gstats(StagedModel<R> m, ObsRef o, i
     case HMM_POISSON: f[0] = a0; break;
     case HMM_DIAG_GAUSSIAN: f[d] = a0; f[D + d] = a1; break;
     default: break;
+    }
+}
+
+// Same sums with one thread per state (N <= 256) and all DM dimensions of a
+// diagonal state in its registers: gamma rows are read whole (coalesced) and
+// the observation row is the same for every thread (uniform loads).  Blocks
+// take tiles of BLK_TS steps in turn and write one partial row each.
+template <typename R, int FAM, int DM>
+__global__ __launch_bounds__(BT) void k_blk_gstats_row(StagedModel<R> m, ObsRef o, int64_t total,
+                                                       const R *__restrict__ gamma,
+                                                       double *__restrict__ partial, int64_t S2) {
+    const int N = m.N, D = m.D, c = threadIdx.x;
+    const bool live = c < N;
+    constexpr int NA = FAM == HMM_DIAG_GAUSSIAN ? 2 * DM : 4;
+    double acc[NA], g = 0.0;
+#pragma unroll
+    for (int k = 0; k < NA; ++k) acc[k] = 0.0;
+    const StateConsts<R> kc = load_consts(m.ep, live ? c : 0, true);
+    R mu[DM];
+#pragma unroll
+    for (int d = 0; d < DM; ++d)
+        mu[d] = (FAM == HMM_DIAG_GAUSSIAN && live && d < D) ? m.mv[(size_t)c * D + d] : (R)0;
+    const int ntile = (int)((total + BLK_TS - 1) / BLK_TS);
+    for (int tile = blockIdx.x; tile < ntile; tile += gridDim.x) {
+        const int64_t t0 = (int64_t)tile * BLK_TS;
+        const int64_t t1 = t0 + BLK_TS < total ? t0 + BLK_TS : total;
+#pragma unroll 4
+        for (int64_t t = t0; t < t1; ++t) {
+            const double g0 = live ? (double)gamma[t * N + c] : 0.0;
+            const double gm = g0 > 0.0 ? g0 : 0.0;
+            g += gm;
+            if constexpr (FAM == HMM_DIAG_GAUSSIAN) {
+#pragma unroll
+                for (int d = 0; d < DM; ++d) {
+                    if (d < D) {
+                        const double dv = (double)load_obs<R>(o, t * D + d) - (double)mu[d];
+                        acc[d] += gm * dv;
+                        acc[DM + d] += gm * dv * dv;
+                    }
+                }
+            } else {
+                const double yr = (double)load_obs<R>(o, t);
+                const double y = gm > 0.0 ? yr : 1.0;   // a zero weight adds nothing
+                if constexpr (FAM == HMM_GAUSSIAN) {
+                    const double dv = y - (double)kc.c0;
+                    acc[0] += gm * dv;
+                    acc[1] += gm * dv * dv;
+                } else if constexpr (FAM == HMM_GAMMA) {
+                    acc[0] += gm * y;
+                    acc[1] += gm * log(y);
+                    acc[2] += gm * y * y;
+                } else if constexpr (FAM == HMM_STUDENT_T) {
+                    const double dv = y - (double)kc.c0;
+                    const double u = (double)kc.c4 / (1.0 + (double)kc.c1 * dv * dv);
+                    acc[0] += gm * u;
+                    acc[1] += gm * u * dv;
+                    acc[2] += gm * u * dv * dv;
+                    acc[3] += gm * (log(u) - u);
+                } else if constexpr (FAM == HMM_POISSON) {
+                    acc[0] += gm * y;
+                }
+            }
+        }
+    }
+    if (!live) return;
+    double *row = partial + (int64_t)blockIdx.x * S2;
+    row[1 + c] = g;
+    const int K = family_k_hd(FAM, D);
+    double *f = row + 1 + N + (int64_t)c * K;
+    if constexpr (FAM == HMM_DIAG_GAUSSIAN) {
+#pragma unroll
+        for (int d = 0; d < DM; ++d)
+            if (d < D) {
+                f[d] = acc[d];
+                f[D + d] = acc[DM + d];
+            }
+    } else {
+        for (int k = 0; k < K; ++k) f[k] = acc[k];
     }
 }
 
@@ -393,6 +708,43 @@ int blk_xi_chunks(bool f64, int64_t total) {
 
 int blk_gstats_tiles(int64_t total) { return (int)((total + BLK_TS - 1) / BLK_TS); }
 
+// single precision keeps A in registers (512 threads, up to 128 entries each);
+// double precision reads it from L2 at every step
+template <typename R, int NT, int RPM, bool AREG, int NCT>
+static void launch_blk_sweep_t(bool fwd, const StagedModel<R> &m, const ObsDesc &o, R *etab,
+                               const BlockBuffers &bb, R *alpha, double *loglik, int32_t *status,
+                               R *gamma, hipStream_t s) {
+    if (fwd)
+        hipLaunchKernelGGL((k_blk_fwd<R, NT, RPM, AREG, NCT>), dim3((unsigned)o.nseq), dim3(NT), 0, s, m,
+                           o.offsets, (const R *)etab, (const double *)bb.mt, alpha, bb.aexp, loglik,
+                           status);
+    else
+        hipLaunchKernelGGL((k_blk_bwd<R, NT, RPM, AREG, NCT>), dim3((unsigned)o.nseq), dim3(NT), 0, s, m,
+                           o.offsets, etab, (const R *)alpha, (const int32_t *)bb.aexp,
+                           (const int32_t *)status, gamma);
+}
+
+template <typename R>
+static void launch_blk_sweep(bool fwd, const StagedModel<R> &m, const ObsDesc &o, R *etab,
+                             const BlockBuffers &bb, R *alpha, double *loglik, int32_t *status,
+                             R *gamma, hipStream_t s) {
+    if constexpr (sizeof(R) == 4) {
+        // rows per thread RP = NC / (512 / NC): 8, 32, 96, 128
+        switch (blk_nc(m.N)) {
+        case 64:
+            return launch_blk_sweep_t<R, 512, 8, true, 64>(fwd, m, o, etab, bb, alpha, loglik, status, gamma, s);
+        case 128:
+            return launch_blk_sweep_t<R, 512, 32, true, 128>(fwd, m, o, etab, bb, alpha, loglik, status, gamma, s);
+        case 192:
+            return launch_blk_sweep_t<R, 512, 96, true, 192>(fwd, m, o, etab, bb, alpha, loglik, status, gamma, s);
+        default:
+            return launch_blk_sweep_t<R, 512, 128, true, 256>(fwd, m, o, etab, bb, alpha, loglik, status, gamma, s);
+        }
+    } else {
+        launch_blk_sweep_t<R, 256, 1, false, 0>(fwd, m, o, etab, bb, alpha, loglik, status, gamma, s);
+    }
+}
+
 template <typename R>
 hmm_status run_block(const StagedModel<R> &m, const ObsDesc &o, const BlockBuffers &bb,
                      double *loglik, int32_t *status, void *gamma_out, double *stats, int64_t S,
@@ -406,45 +758,72 @@ hmm_status run_block(const StagedModel<R> &m, const ObsDesc &o, const BlockBuffe
     const int64_t total = bb.total;
     {
         ProfScope ps("block_emit", s);
-        const int spb = BT / blk_nc(N);
-        const int64_t nb = (total + spb - 1) / spb;
-        hipLaunchKernelGGL(k_blk_emit<R>, dim3((unsigned)(nb < 8192 ? nb : 8192)), dim3(BT), 0, s, m,
-                           obs, total, etab, bb.mt);
+        if (m.family == HMM_DIAG_GAUSSIAN && m.D <= 64) {
+            const int64_t nb = (total + ES - 1) / ES;
+            const dim3 g((unsigned)(nb < 16384 ? nb : 16384));
+            if (m.D <= 16)
+                hipLaunchKernelGGL((k_blk_emit_diag<R, 16>), g, dim3(BT), 0, s, m, obs, total, etab, bb.mt);
+            else
+                hipLaunchKernelGGL((k_blk_emit_diag<R, 64>), g, dim3(BT), 0, s, m, obs, total, etab, bb.mt);
+        } else {
+            const int spb = BT / blk_nc(N);
+            const int64_t nb = (total + spb - 1) / spb;
+            hipLaunchKernelGGL(k_blk_emit<R>, dim3((unsigned)(nb < 8192 ? nb : 8192)), dim3(BT), 0, s, m,
+                               obs, total, etab, bb.mt);
+        }
     }
     {
         ProfScope ps("block_fwd", s);
-        hipLaunchKernelGGL(k_blk_fwd<R>, dim3((unsigned)o.nseq), dim3(BT), 0, s, m, o.offsets,
-                           (const R *)etab, (const double *)bb.mt, alpha, bb.aexp, loglik, status);
+        launch_blk_sweep<R>(true, m, o, etab, bb, alpha, loglik, status, nullptr, s);
     }
     if (!gamma_out && !stats) return HMM_OK;
     {
         ProfScope ps("block_bwd", s);
-        hipLaunchKernelGGL(k_blk_bwd<R>, dim3((unsigned)o.nseq), dim3(BT), 0, s, m, o.offsets, etab,
-                           (const R *)alpha, (const int32_t *)bb.aexp, (const int32_t *)status,
-                           gamma);
+        launch_blk_sweep<R>(false, m, o, etab, bb, alpha, loglik, status, gamma, s);
     }
     if (!stats) return HMM_OK;
     if (m.family == HMM_FULL_GAUSSIAN) return HMM_ERR_UNSUPPORTED;
     const int K = family_k_hd(m.family, m.D);
     const int64_t S2 = 1 + N + (int64_t)N * K;
-    const int ntile = blk_gstats_tiles(total);
-    const int DD = m.family == HMM_DIAG_GAUSSIAN ? m.D : 1;
-    const int spb = BT / DD;
-    const int ncb = (N + spb - 1) / spb;
+    int nparts = blk_gstats_tiles(total);
     {
         ProfScope ps("block_gstats", s);
-        if (m.family == HMM_TABLE) {
-            const int64_t nz = (int64_t)ntile * S2;
-            hipLaunchKernelGGL(k_blk_zero,
-                               dim3((unsigned)((nz + BT - 1) / BT < 4096 ? (nz + BT - 1) / BT : 4096)),
-                               dim3(BT), 0, s, bb.partial, nz);
+        const bool rowk = !(m.family == HMM_DIAG_GAUSSIAN && m.D > 16);
+        if (rowk) {
+            // one thread per state; blocks take tiles in turn
+            nparts = nparts < BLK_GS_BLOCKS ? nparts : BLK_GS_BLOCKS;
+            const dim3 g((unsigned)nparts);
+            const R *gp = (const R *)gamma;
+            switch (m.family) {
+            case HMM_GAUSSIAN:
+                hipLaunchKernelGGL((k_blk_gstats_row<R, HMM_GAUSSIAN, 1>), g, dim3(BT), 0, s, m, obs, total, gp, bb.partial, S2);
+                break;
+            case HMM_GAMMA:
+                hipLaunchKernelGGL((k_blk_gstats_row<R, HMM_GAMMA, 1>), g, dim3(BT), 0, s, m, obs, total, gp, bb.partial, S2);
+                break;
+            case HMM_STUDENT_T:
+                hipLaunchKernelGGL((k_blk_gstats_row<R, HMM_STUDENT_T, 1>), g, dim3(BT), 0, s, m, obs, total, gp, bb.partial, S2);
+                break;
+            case HMM_POISSON:
+                hipLaunchKernelGGL((k_blk_gstats_row<R, HMM_POISSON, 1>), g, dim3(BT), 0, s, m, obs, total, gp, bb.partial, S2);
+                break;
+            case HMM_DIAG_GAUSSIAN:
+                hipLaunchKernelGGL((k_blk_gstats_row<R, HMM_DIAG_GAUSSIAN, 16>), g, dim3(BT), 0, s, m, obs, total, gp, bb.partial, S2);
+                break;
+            default:   // table: sum gamma only
+                hipLaunchKernelGGL((k_blk_gstats_row<R, HMM_TABLE, 1>), g, dim3(BT), 0, s, m, obs, total, gp, bb.partial, S2);
+                break;
+            }
+        } else {
+            const int DD = m.D;
+            const int spb = BT / DD;
+            const int ncb = (N + spb - 1) / spb;
+            hipLaunchKernelGGL(k_blk_gstats<R>, dim3((unsigned)ncb, (unsigned)nparts), dim3(BT), 0, s, m,
+                               obs, total, (const R *)gamma, bb.partial, S2);
         }
-        hipLaunchKernelGGL(k_blk_gstats<R>, dim3((unsigned)ncb, (unsigned)ntile), dim3(BT), 0, s, m,
-                           obs, total, (const R *)gamma, bb.partial, S2);
         hipLaunchKernelGGL(k_blk_gamma1<R>, dim3((unsigned)((N + BT - 1) / BT)), dim3(BT), 0, s, N,
                            o.nseq, o.offsets, (const int32_t *)status, (const R *)gamma, bb.g1);
     }
-    const int nparts = ntile;
     // sum gamma and family sums into the compact vector (entry 0: sum logL)
     launch_reduce_stats(bb.partial, nparts, S2, loglik, status, o.nseq, bb.compact, bb.red, s);
     const int nch = blk_xi_chunks(sizeof(R) == 8, total);
