@@ -191,7 +191,7 @@ def main():
     ap.add_argument("--workload", default="batched", choices=sorted(WORKLOADS))
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--prec", default="f32", choices=["f32", "f64"])
+    ap.add_argument("--prec", default="f32", choices=["f32", "f64", "bf16_scaled", "f16_scaled"])
     ap.add_argument("--plain-steps", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--chunk", type=int, default=0, help="chunk length (0 = library default)")
@@ -217,7 +217,7 @@ def main():
     wl_name, wl_make = WORKLOADS[args.workload]
     w = wl_make(workloads)
     dm = h.DeviceModel.from_model(w.model)
-    db = h.DeviceBatch(w.obs, w.offsets, dtype=np.float32 if args.prec == "f32" else np.float64)
+    db = h.DeviceBatch(w.obs, w.offsets, dtype=np.float64 if args.prec == "f64" else np.float32)
     prec = args.prec
     ws = h._ws(h.hmm_workspace_size("estep", dm, db, prec))
     S = h.hmm_stats_len(dm)
@@ -277,7 +277,7 @@ def main():
     # batch cut to its first plain_t steps and scaled by T / plain_t.
     plain_ms, plain_note = None, None
     if args.plain_steps > 0:
-        pprec = "plain_" + prec
+        pprec = "plain_f64" if prec == "f64" else "plain_f32"
         scale = 1.0
         T_max = int(np.max(w.lengths))
         plain_t = max(16, int(2e8 // (w.model.n_states ** 2 * 64)))
@@ -286,7 +286,7 @@ def main():
             offs = np.concatenate([[0], np.cumsum(cut)]).astype(np.int64)
             rows = np.concatenate([np.arange(w.offsets[b], w.offsets[b] + cut[b])
                                    for b in range(w.n_seq)])
-            pdb = h.DeviceBatch(w.obs[rows], offs, dtype=np.float32 if prec == "f32" else np.float64)
+            pdb = h.DeviceBatch(w.obs[rows], offs, dtype=np.float64 if prec == "f64" else np.float32)
             scale = T_max / plain_t
             plain_note = (f"timed on the batch cut to its first {plain_t} steps per sequence, "
                           f"scaled by {scale:.1f} (linear in the longest sequence)")
@@ -373,7 +373,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if prec == "f32" else "f64",
+        "dtype": {"f32": "f32", "f64": "f64", "bf16_scaled": "bf16", "f16_scaled": "f16"}[prec],
         "data": "synthetic",
         "config": {"workload": wl_name, "global_batch": w.n_seq, "total_steps": w.total_steps,
                    "transitions_per_step": w.transitions, "precision": prec},

@@ -109,6 +109,7 @@ hmm_status check_batch(const hmm_batch *b, const hmm_model *m, Checked *c) {
 // ---------------------------------------------------------------- planning
 struct Plan {
     bool f64 = false, plain = false, chunked = false, wave = false, block = false;
+    int mfma = 0;   // scaled low-precision sweeps: 1 bf16, 2 fp16
     int G = 0, L = 0, C = 0, nblk = 0;
     int64_t S = 0;
     size_t staged = 0, cbase = 0, frec = 0, brec = 0, F = 0, Gb = 0, partial = 0;
@@ -130,8 +131,6 @@ int default_chunk_len(bool f64) {
 }
 
 hmm_status make_plan(hmm_op op, const Checked &c, hmm_precision prec, Plan *p) {
-    if (prec == HMM_PREC_BF16_SCALED || prec == HMM_PREC_F16_SCALED)
-        return fail(HMM_ERR_UNSUPPORTED, "scaled low-precision recursions are not built");
     if (prec < HMM_PREC_F64 || prec > HMM_PREC_PLAIN_F64)
         return fail(HMM_ERR_ARG, "unknown precision %d", (int)prec);
     p->f64 = is_f64(prec);
@@ -151,7 +150,8 @@ hmm_status make_plan(hmm_op op, const Checked &c, hmm_precision prec, Plan *p) {
         return HMM_OK;
     }
     if (op == HMM_OP_VITERBI) {
-        if (p->plain) return fail(HMM_ERR_UNSUPPORTED, "Viterbi runs in HMM_PREC_F64 or HMM_PREC_F32");
+        if (p->plain || prec == HMM_PREC_BF16_SCALED || prec == HMM_PREC_F16_SCALED)
+            return fail(HMM_ERR_UNSUPPORTED, "Viterbi runs in HMM_PREC_F64 or HMM_PREC_F32");
         if (N > 64) return fail(HMM_ERR_UNSUPPORTED, "Viterbi: this build covers N <= 64 (N = %d)", N);
         int64_t C = 0;
         for (int64_t b = 0; b < c.B; ++b) C += (c.h_off[b + 1] - c.h_off[b] + 63) / 64;
@@ -180,7 +180,8 @@ hmm_status make_plan(hmm_op op, const Checked &c, hmm_precision prec, Plan *p) {
         p->red = take((size_t)reduce_scratch_len(c.B, p->S) * 8);
     } else {
         const bool scalar = c.fam <= HMM_POISSON || c.fam == HMM_TABLE;
-        if (!scalar || N > 64) {
+        p->mfma = prec == HMM_PREC_BF16_SCALED ? 1 : (prec == HMM_PREC_F16_SCALED ? 2 : 0);
+        if (!scalar || N > 64 || p->mfma) {
             // one workgroup per sequence, emission table, xi by GEMM
             if (N > 256)
                 return fail(HMM_ERR_UNSUPPORTED,
@@ -304,6 +305,7 @@ hmm_status run_posterior_path(const hmm_model *m, const hmm_batch *b, const Chec
     } else if (p.block) {
         BlockBuffers bb;
         bb.total = c.total;
+        bb.mfma = p.mfma;
         bb.etab = ws + p.etab;
         bb.mt = (double *)(ws + p.mt);
         bb.alpha = ws + p.balpha;

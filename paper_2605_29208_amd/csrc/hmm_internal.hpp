@@ -143,6 +143,7 @@ constexpr int BLK_TS = 1024;    // steps per tile of the family-sum kernels
 constexpr int BLK_GS_BLOCKS = 1024;   // blocks (partial rows) of the per-state family-sum kernel
 struct BlockBuffers {
     int64_t total;       // sum of T
+    int mfma = 0;        // sweeps: 0 FP32/FP64 vector ALU, 1 bf16 MFMA, 2 fp16 MFMA
     void *etab;          // [total * N] R  emission factors, then w' (in place)
     double *mt;          // [total]   per-step log shift
     void *alpha;         // [total * N] R  normalised alpha

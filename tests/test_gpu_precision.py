@@ -1,0 +1,93 @@
+"""Scaled low-precision recursions (bf16 / fp16 matrix-core products with
+FP32 accumulation and per-step rescaling) against the FP64 oracle.
+
+These paths are approximations by construction: the test states their
+error per output (log-likelihood, posteriors, pooled statistics) and checks
+it against bounds set from the unit roundoff of the operand format (bf16
+2^-9, fp16 2^-12) with a margin, plus the identities that per-step
+normalisation keeps whatever the rounding (posteriors sum to one, so the
+gamma totals count the steps).  The xi normaliser is the forward product,
+which the low-precision path rounds, so the xi total (T - B exactly in
+FP32/FP64) is only held to the format's statistics bound.  The printed
+figures are the precision study's numbers.
+"""
+import numpy as np
+import pytest
+import torch  # noqa: F401
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+# bounds per format: (log-likelihood relative, gamma absolute, statistics
+# relative to their natural scale)
+BOUNDS = {"bf16_scaled": (2e-3, 0.08, 0.05), "f16_scaled": (3e-4, 0.02, 0.01),
+          "f32": (1e-4, 1e-4, 1e-4)}
+
+
+@pytest.fixture(scope="module")
+def h():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_2605_29208_amd as h
+    return h
+
+
+def errors(h, w, prec):
+    import torch
+    dm = h.DeviceModel.from_model(w.model)
+    db = h.DeviceBatch(w.obs, w.offsets, dtype=np.float32)
+    stats, ll, st = h.estep_stats(dm, db, prec)
+    llg, gam, _ = h.forward_backward(dm, db, prec)
+    torch.cuda.synchronize()
+    ref = oracle.estep(w.model, w.offsets, w.obs, want_gamma=True)
+    s = stats.cpu().numpy()
+    rs = ref["stats"]
+    ll = ll.cpu().numpy()
+    g = gam.cpu().numpy().astype(np.float64)
+    n = w.model.n_states
+    e_ll = float(np.max(np.abs(ll - ref["loglik"]) / np.abs(ref["loglik"])))
+    e_g = float(np.max(np.abs(g - ref["gamma"])))
+    # pooled statistics: each block relative to its own scale
+    blocks = {"gamma1": slice(1, 1 + n), "xi": slice(1 + n, 1 + n + n * n),
+              "gamma_sum": slice(1 + n + n * n, 1 + 2 * n + n * n),
+              "family": slice(1 + 2 * n + n * n, None)}
+    e_s = {k: float(np.max(np.abs(s[v] - rs[v])) / max(np.max(np.abs(rs[v])), 1e-300))
+           for k, v in blocks.items()}
+    return e_ll, e_g, e_s, g, s
+
+
+@pytest.mark.parametrize("prec", ["bf16_scaled", "f16_scaled", "f32"])
+@pytest.mark.parametrize("fam,n,d", [("gaussian", 20, 1), ("student_t", 64, 1),
+                                     ("diag", 256, 16), ("gamma", 130, 1)])
+def test_scaled_precision_error(h, prec, fam, n, d):
+    w = workloads.random_workload(fam, n, d, [1, 64, 300, 700], 900 + n)
+    e_ll, e_g, e_s, g, s = errors(h, w, prec)
+    print(f"\n[precision] {prec:12s} {fam:9s} N={n:3d} D={d:2d}: loglik rel {e_ll:.2e}, "
+          f"gamma abs {e_g:.2e}, stats rel " + ", ".join(f"{k} {v:.2e}" for k, v in e_s.items()))
+    b_ll, b_g, b_s = BOUNDS[prec]
+    assert e_ll <= b_ll and e_g <= b_g
+    assert max(e_s.values()) <= b_s
+    # identities that rounding does not break: sum_j gamma_t(j) = 1 per step
+    assert np.allclose(g.sum(axis=1), 1.0, atol=1e-5)
+    N = n
+    xi = s[1 + N:1 + N + N * N].reshape(N, N)
+    gs = s[1 + N + N * N:1 + 2 * N + N * N]
+    T = int(w.offsets[-1])
+    assert abs(gs.sum() - T) < 1e-4 * T
+    assert abs(xi.sum() - (T - (len(w.offsets) - 1))) < b_s * T
+
+
+def test_config3_precision_study(h):
+    """Large-state workload (N = 256, D = 16), three sequences of 2048 steps:
+    every precision's error against the oracle, printed side by side."""
+    w = workloads.config3(n_seq=3)
+    for prec in ("f64", "f32", "bf16_scaled", "f16_scaled"):
+        e_ll, e_g, e_s, _, _ = errors(h, w, prec) if prec != "f64" else (None,) * 5
+        if prec == "f64":
+            continue
+        print(f"\n[precision] config3 {prec:12s}: loglik rel {e_ll:.2e}, gamma abs {e_g:.2e}, "
+              "stats rel " + ", ".join(f"{k} {v:.2e}" for k, v in e_s.items()))
+        b_ll, b_g, b_s = BOUNDS[prec]
+        assert e_ll <= b_ll and e_g <= b_g and max(e_s.values()) <= b_s
