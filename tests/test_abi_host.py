@@ -86,8 +86,13 @@ def test_workspace_size_and_validation(h):
                 fake_model(h, 3, "gaussian", dim=2), fake_model(h, 3, "table", dim=2)):
         st, _ = ws_size(h, "estep", bad, b, "f32")
         assert st == h.HMM_ERR_ARG
-    # scaled precisions are reserved
-    st, _ = ws_size(h, "estep", m, b, "bf16_scaled")
+    # scaled precisions run the E-step (large-state path) but not Viterbi;
+    # state counts above 256 have no batched path
+    st, n3 = ws_size(h, "estep", m, b, "bf16_scaled")
+    assert st == h.HMM_OK and n3 > 0
+    st, _ = ws_size(h, "viterbi", m, b, "f16_scaled")
+    assert st == h.HMM_ERR_UNSUPPORTED
+    st, _ = ws_size(h, "estep", fake_model(h, 300, "gaussian"), b, "f32")
     assert st == h.HMM_ERR_UNSUPPORTED
 
 
