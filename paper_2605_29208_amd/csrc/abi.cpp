@@ -187,10 +187,6 @@ hmm_status make_plan(hmm_op op, const Checked &c, hmm_precision prec, Plan *p) {
                 return fail(HMM_ERR_UNSUPPORTED,
                             "batched path: this build covers N <= 256 (N = %d); use a PLAIN "
                             "precision", N);
-            if (op == HMM_OP_ESTEP && c.fam == HMM_FULL_GAUSSIAN)
-                return fail(HMM_ERR_UNSUPPORTED,
-                            "batched E-step statistics of the full-covariance family are not "
-                            "built; use a PLAIN precision");
             p->block = true;
             const size_t T = (size_t)c.total;
             p->etab = take(T * N * r);
@@ -202,7 +198,7 @@ hmm_status make_plan(hmm_op op, const Checked &c, hmm_precision prec, Plan *p) {
             p->xi = take((size_t)nch * N * N * r + 256);
             p->g1 = take((size_t)N * 8);
             const int64_t S2 = 1 + N + (int64_t)N * family_k(c.fam, c.D);
-            const int ntile = blk_gstats_tiles(c.total);
+            const int ntile = blk_gstats_tiles(c.total, c.fam);
             p->compact = take((size_t)S2 * 8);
             p->partial = take((size_t)ntile * S2 * 8);
             p->red = take((size_t)reduce_scratch_len(ntile, S2) * 8);

@@ -140,6 +140,7 @@ hmm_status run_wave(const StagedModel<R> &m, const ObsDesc &o, const WaveBuffers
 // workgroup per sequence, emission table, stored alpha, xi by a GEMM
 constexpr int BLK_KC = 16384;   // steps per FP32 xi GEMM chunk (FP32 partial sums)
 constexpr int BLK_TS = 1024;    // steps per tile of the family-sum kernels
+constexpr int FULL_TS = 8192;   // steps per tile of the full-covariance family sums
 constexpr int BLK_GS_BLOCKS = 1024;   // blocks (partial rows) of the per-state family-sum kernel
 struct BlockBuffers {
     int64_t total;       // sum of T
@@ -156,7 +157,7 @@ struct BlockBuffers {
     double *red;         // reduction scratch
 };
 int blk_xi_chunks(bool f64, int64_t total);
-int blk_gstats_tiles(int64_t total);
+int blk_gstats_tiles(int64_t total, int family);
 template <typename R>
 hmm_status run_block(const StagedModel<R> &m, const ObsDesc &o, const BlockBuffers &bb,
                      double *loglik, int32_t *status, void *gamma_out, double *stats,

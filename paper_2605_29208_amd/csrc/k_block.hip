@@ -959,6 +959,48 @@ __global__ __launch_bounds__(BT) void k_blk_gstats_row(StagedModel<R> m, ObsRef 
     }
 }
 
+// Full-covariance family sums: thread (state c, slot q) with q < D the
+// shifted first moment sum gamma d_q and q >= D the packed lower entry
+// (r, k), r >= k, of sum gamma d d^T (d = y - mu_c).  Grid (slot blocks,
+// tiles of FULL_TS steps); each tile fills one partial row.
+template <typename R>
+__global__ __launch_bounds__(BT) void k_blk_gstats_full(StagedModel<R> m, ObsRef o, int64_t total,
+                                                        const R *__restrict__ gamma,
+                                                        double *__restrict__ partial, int64_t S2) {
+    const int N = m.N, D = m.D, K = D + D * (D + 1) / 2;
+    const int64_t gid = (int64_t)blockIdx.x * BT + threadIdx.x;
+    if (gid >= (int64_t)N * K) return;
+    const int c = (int)(gid / K), q = (int)(gid % K);
+    int r, k;
+    if (q < D) {
+        r = q;
+        k = -1;
+    } else {
+        // packed lower triangle row by row: slot p = r (r + 1) / 2 + k
+        const int p = q - D;
+        r = (int)((sqrt(8.0 * p + 1.0) - 1.0) * 0.5);
+        while ((r + 1) * (r + 2) / 2 <= p) ++r;
+        while (r * (r + 1) / 2 > p) --r;
+        k = p - r * (r + 1) / 2;
+    }
+    const double mr = (double)m.mv[(size_t)c * D + r];
+    const double mk = k >= 0 ? (double)m.mv[(size_t)c * D + k] : 0.0;
+    const int64_t t0 = (int64_t)blockIdx.y * FULL_TS;
+    const int64_t t1 = t0 + FULL_TS < total ? t0 + FULL_TS : total;
+    double acc = 0.0, g = 0.0;
+#pragma unroll 4
+    for (int64_t t = t0; t < t1; ++t) {
+        const double gm = (double)gamma[t * N + c];
+        const double dr = (double)load_obs<R>(o, t * D + r) - mr;
+        const double dk = k >= 0 ? (double)load_obs<R>(o, t * D + k) - mk : 1.0;
+        acc += gm * dr * dk;
+        g += gm;
+    }
+    double *row = partial + (int64_t)blockIdx.y * S2;
+    if (q == 0) row[1 + c] = g;
+    row[1 + N + (int64_t)c * K + q] = acc;
+}
+
 __global__ __launch_bounds__(BT) void k_blk_zero(double *p, int64_t n) {
     for (int64_t i = (int64_t)blockIdx.x * BT + threadIdx.x; i < n; i += (int64_t)gridDim.x * BT)
         p[i] = 0.0;
@@ -1037,7 +1079,10 @@ int blk_xi_chunks(bool f64, int64_t total) {
     return (int)((K + BLK_KC - 1) / BLK_KC);
 }
 
-int blk_gstats_tiles(int64_t total) { return (int)((total + BLK_TS - 1) / BLK_TS); }
+int blk_gstats_tiles(int64_t total, int family) {
+    const int64_t ts = family == HMM_FULL_GAUSSIAN ? FULL_TS : BLK_TS;
+    return (int)((total + ts - 1) / ts);
+}
 
 // single precision keeps A in registers (512 threads, up to 128 entries each);
 // double precision reads it from L2 at every step
@@ -1143,14 +1188,17 @@ hmm_status run_block(const StagedModel<R> &m, const ObsDesc &o, const BlockBuffe
         launch_blk_sweep<R>(false, m, o, etab, bb, alpha, loglik, status, gamma, s);
     }
     if (!stats) return HMM_OK;
-    if (m.family == HMM_FULL_GAUSSIAN) return HMM_ERR_UNSUPPORTED;
     const int K = family_k_hd(m.family, m.D);
     const int64_t S2 = 1 + N + (int64_t)N * K;
-    int nparts = blk_gstats_tiles(total);
+    int nparts = blk_gstats_tiles(total, m.family);
     {
         ProfScope ps("block_gstats", s);
         const bool rowk = !(m.family == HMM_DIAG_GAUSSIAN && m.D > 16);
-        if (rowk) {
+        if (m.family == HMM_FULL_GAUSSIAN) {
+            const int64_t nt = (int64_t)N * K;
+            hipLaunchKernelGGL(k_blk_gstats_full<R>, dim3((unsigned)((nt + BT - 1) / BT), (unsigned)nparts),
+                               dim3(BT), 0, s, m, obs, total, (const R *)gamma, bb.partial, S2);
+        } else if (rowk) {
             // one thread per state; blocks take tiles in turn
             nparts = nparts < BLK_GS_BLOCKS ? nparts : BLK_GS_BLOCKS;
             const dim3 g((unsigned)nparts);

@@ -61,6 +61,42 @@ def test_block_diag_family(h, n, d, prec):
     assert_stats_close(stats, ref["stats"], n, "diag", TOL[prec], f"diag N={n} D={d} {prec}", d=d)
 
 
+@pytest.mark.parametrize("n,d", [(3, 2), (8, 5), (32, 32)])
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_block_full_family(h, n, d, prec):
+    w = workloads.random_workload("full", n, d, [1, 40, 130], 830 + n + d)
+    ref = oracle.estep(w.model, w.offsets, w.obs)
+    stats, ll, st = run_estep(h, w, prec)
+    assert np.array_equal(st, ref["status"])
+    assert_loglik_close(ll, ref["loglik"], TOL[prec], f"full N={n} D={d} {prec}")
+    assert_stats_close(stats, ref["stats"], n, "full", TOL[prec], f"full N={n} D={d} {prec}", d=d)
+
+
+def truncate(w, tmax):
+    """The same sequences cut to their first tmax steps."""
+    lens = np.minimum(w.lengths, tmax)
+    rows = np.concatenate([np.arange(w.offsets[b], w.offsets[b] + lens[b]) for b in range(len(lens))])
+    offs = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+    return workloads.Workload(w.name, w.model, lens, offs, w.obs[rows], w.states[rows])
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_config4a_subset(h, prec):
+    """Full covariance, D = 32, condition numbers up to 1e3.  log P(y) reaches
+    ~1e5 here, and the oracle's unnormalised log-space recursion carries about
+    u * sqrt(T) * |log P| of absolute rounding (u = 2^-53): ~1e-9 at T = 4000,
+    the FP64 tolerance itself.  FP64 is therefore compared on the sequences cut
+    to 600 steps; FP32 on the whole sequences."""
+    w = workloads.config4a(n_seq=3)
+    if prec == "f64":
+        w = truncate(w, 600)
+    ref = oracle.estep(w.model, w.offsets, w.obs)
+    stats, ll, st = run_estep(h, w, prec)
+    assert (st == 0).all()
+    assert_loglik_close(ll, ref["loglik"], TOL[prec], f"config4a subset {prec}")
+    assert_stats_close(stats, ref["stats"], 32, "full", TOL[prec], f"config4a subset {prec}", d=32)
+
+
 @pytest.mark.parametrize("prec", ["f32", "f64"])
 def test_block_table_family(h, prec):
     import torch
