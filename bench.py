@@ -84,6 +84,39 @@ WORKLOADS = {
 }
 
 
+# kernel -> source file; the committed counter summary records the source's
+# SHA-256 next to the measured bytes, and the figure is used only while the
+# source is unchanged
+KERNEL_SOURCE = {"chunk_stats": "k_chunk.hip", "chunk_product": "k_chunk.hip",
+                 "wave_stats": "k_wave.hip", "wave_sweep": "k_wave.hip",
+                 "block_fwd": "k_block.hip", "block_bwd": "k_block.hip"}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_counters.md")
+
+
+def source_sha(kernel):
+    import hashlib
+    f = KERNEL_SOURCE.get(kernel)
+    if f is None:
+        return None
+    with open(os.path.join(ROOT, "paper_2605_29208_amd", "csrc", f), "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()
+
+
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch (fetch + write) from the committed summary, or None."""
+    try:
+        lines = open(TRAFFIC_FILE).read().splitlines()
+    except OSError:
+        return None
+    sha = source_sha(kernel)
+    for ln in lines:
+        if ln.startswith("traffic:"):
+            f = dict(kv.split("=", 1) for kv in ln[len("traffic:"):].split())
+            if f.get("kernel") == kernel and f.get("workload") == workload and f.get("sha") == sha:
+                return float(f["fetch_bytes"]) + float(f["write_bytes"])
+    return None
+
+
 def cpu_model():
     try:
         for line in open("/proc/cpuinfo"):
@@ -105,6 +138,56 @@ def cpu_baseline(w, reps=2):
             "kind": "oracle",
             "sample": f"full workload ({w.n_seq} sequences, {w.total_steps} steps) x{reps}, "
                       f"FP64 oracle, 1 thread on {cpu_model()}, {dt:.1f} s"}
+
+
+def estep_time(h, w, prec, steps):
+    """Mean milliseconds of one E-step (events around `steps` calls) and the
+    per-kernel table."""
+    import torch
+    dm = h.DeviceModel.from_model(w.model)
+    db = h.DeviceBatch(w.obs, w.offsets, dtype=np.float64 if prec == "f64" else np.float32)
+    ws = h._ws(h.hmm_workspace_size("estep", dm, db, prec))
+    S = h.hmm_stats_len(dm)
+    stats = torch.empty(S, dtype=torch.float64, device="cuda")
+    ll = torch.empty(w.n_seq, dtype=torch.float64, device="cuda")
+    st = torch.empty(w.n_seq, dtype=torch.int32, device="cuda")
+    h.hmm_estep_stats(dm, db, prec, stats, ll, st, ws)
+    torch.cuda.synchronize()
+    h.hmm_profile_reset()
+    h.hmm_profile_enable(True)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        h.hmm_estep_stats(dm, db, prec, stats, ll, st, ws)
+    e1.record()
+    torch.cuda.synchronize()
+    recs = h.hmm_profile_records()
+    h.hmm_profile_enable(False)
+    h.hmm_profile_reset()
+    ok = bool((st.cpu().numpy() == 0).all())
+    return e0.elapsed_time(e1) / steps, kernel_table(recs, steps), ok
+
+
+def other_workloads(h, workloads, steps):
+    """The other configurations' E-steps at full size (context for the
+    headline line): heavy-tailed N = 32 Student-t, large-state N = 256
+    diagonal Gaussian in FP32 and in the scaled bf16 / fp16 forms, and
+    full-covariance N = 32, D = 32."""
+    res = {}
+    for key, make, precs in (("heavy_student_t_n32", workloads.config4b, ("f32",)),
+                             ("large_diag_n256", workloads.config3, ("f32", "bf16_scaled", "f16_scaled")),
+                             ("full_cov_n32_d32", workloads.config4a, ("f32",))):
+        w = make()
+        for prec in precs:
+            ms, kt, ok = estep_time(h, w, prec, steps)
+            res[f"{key}_{prec}"] = {
+                "sequences": w.n_seq, "total_steps": w.total_steps, "n_states": w.model.n_states,
+                "ms_per_estep": ms, "transitions_per_s": w.transitions / (ms / 1e3),
+                "all_status_ok": ok,
+                "kernels_ms": {k: round(v["ms_avg"], 4) for k, v in kt.items()}}
+            log(f"{key} {prec}: {ms:.3f} ms per E-step")
+        del w
+    return res
 
 
 def serving_bench(h, workloads, qps_list, seconds, pool_size=256, streams=SERVING_STREAMS):
@@ -203,6 +286,12 @@ def main():
                     help="comma-separated request rates of the serving run")
     ap.add_argument("--serving-streams", type=int, default=SERVING_STREAMS,
                     help="launches the server keeps in flight")
+    ap.add_argument("--eager-only", action="store_true",
+                    help="time eager calls only (no HIP graph capture), e.g. under counters")
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="also run one 256 MiB device copy (reference for traffic counters)")
+    ap.add_argument("--others", type=int, default=3,
+                    help="E-steps timed on each secondary workload (0 = skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; multi-GPU sharding of the "
@@ -250,25 +339,28 @@ def main():
     log(f"eager: {eager_ms:.3f} ms per E-step")
     # (2) the same E-steps captured once in a HIP graph and replayed (the way an
     # EM loop issues them): the timed value
-    side = torch.cuda.Stream()
-    side.wait_stream(torch.cuda.current_stream())
-    with torch.cuda.stream(side):
-        step()
-    torch.cuda.current_stream().wait_stream(side)
-    torch.cuda.synchronize()
-    g_est = torch.cuda.CUDAGraph()
-    with torch.cuda.graph(g_est):
-        for _ in range(args.steps):
+    if args.eager_only:
+        ms = eager_ms
+    else:
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
             step()
-    g_est.replay()
-    torch.cuda.synchronize()
-    ev0.record()
-    g_est.replay()
-    ev1.record()
-    torch.cuda.synchronize()
-    ms = ev0.elapsed_time(ev1) / args.steps
-    del g_est
-    assert (status.cpu().numpy() == 0).all()
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        g_est = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g_est):
+            for _ in range(args.steps):
+                step()
+        g_est.replay()
+        torch.cuda.synchronize()
+        ev0.record()
+        g_est.replay()
+        ev1.record()
+        torch.cuda.synchronize()
+        ms = ev0.elapsed_time(ev1) / args.steps
+        del g_est
+        assert (status.cpu().numpy() == 0).all()
     log(f"graph replay: {ms:.3f} ms per E-step")
 
     # plain GPU method (one thread per sequence, literal log-sum-exp) on the same
@@ -358,7 +450,8 @@ def main():
     if fl is not None:
         ach = fl / (kt[dom]["ms_avg"] / 1e3) / 1e12
         roof = {"bound": "alu", "kernel": dom, "achieved": ach, "peak": PEAK_FP32_VALU_TFLOPS,
-                "unit": "TFLOP/s", "frac": ach / PEAK_FP32_VALU_TFLOPS, "traffic": None,
+                "unit": "TFLOP/s", "frac": ach / PEAK_FP32_VALU_TFLOPS,
+                "traffic": measured_traffic(dom, args.workload),
                 "kernel_ms_avg": kt[dom]["ms_avg"]}
     out = {
         "metric": METRIC,
@@ -369,7 +462,8 @@ def main():
         "warmup": args.warmup,
         "ms_per_step": ms,
         "eager_ms_per_step": eager_ms,
-        "timing": "E-steps replayed from one captured HIP graph; eager figure beside it",
+        "timing": ("eager calls (no graph)" if args.eager_only else
+                   "E-steps replayed from one captured HIP graph; eager figure beside it"),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -384,6 +478,14 @@ def main():
         "em_graph": em,
         "kernels": kt,
     }
+    if args.copy_calib:
+        src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copy calibration: 256 MiB copied")
+    if args.others > 0 and args.workload == "batched":
+        out["other_workloads"] = other_workloads(h, workloads, args.others)
     if args.serving_seconds > 0:
         qps = [float(x) for x in args.serving_qps.split(",") if x]
         out["serving"] = serving_bench(h, workloads, qps, args.serving_seconds,

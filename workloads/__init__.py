@@ -232,7 +232,11 @@ def simulate_obs(rng, model: Model, states: np.ndarray) -> np.ndarray:
         mu = th[:n * d].reshape(n, d)
         L = th[n * d:].reshape(n, d, d)
         z = rng.standard_normal((m, d))
-        return mu[s] + np.einsum("tij,tj->ti", L[s], z)
+        y = np.empty((m, d))
+        for j in range(n):          # y_t = mu_j + L_j z_t for the steps in state j
+            idx = np.nonzero(s == j)[0]
+            y[idx] = mu[j] + z[idx] @ L[j].T
+        return y
     raise ValueError(model.family)
 
 
