@@ -33,9 +33,9 @@ __global__ __launch_bounds__(BLOCK) void k_stage(RawModel m, R *pi, R *A, R *AT,
     const int N = m.N, D = m.D;
     int bad = 0;
     __shared__ double amin_sh[BLOCK];
-    double amin = 1.0;
-    for (int k = threadIdx.x; k < N * N; k += blockDim.x) amin = fmin(amin, exp(m.log_A[k]));
-    amin_sh[threadIdx.x] = amin;
+    double lmin = 0.0;   // min log a_ij (exp is monotone: min a_ij = exp(min log a_ij))
+    for (int k = threadIdx.x; k < N * N; k += blockDim.x) lmin = fmin(lmin, m.log_A[k]);
+    amin_sh[threadIdx.x] = lmin;
     for (int k = threadIdx.x; k < 64; k += blockDim.x) {
         int i = k / 8, j = k % 8;
         A8[k] = (i < N && j < N) ? (R)exp(m.log_A[i * N + j]) : (R)0;
@@ -45,13 +45,7 @@ __global__ __launch_bounds__(BLOCK) void k_stage(RawModel m, R *pi, R *A, R *AT,
         pi[j] = (R)exp(l);
         lpi[j] = (R)l;
     }
-    for (int k = threadIdx.x; k < N * N; k += blockDim.x) {
-        double l = m.log_A[k];
-        A[k] = (R)exp(l);
-        lA[k] = (R)l;
-        const int i = k / N, j = k % N;
-        AT[j * N + i] = (R)exp(l);
-    }
+
     const double *th = m.theta;
     const double kLog2Pi = 1.8378770664093454835606594728112;
     for (int j = threadIdx.x; j < N; j += blockDim.x) {
@@ -136,8 +130,9 @@ __global__ __launch_bounds__(BLOCK) void k_stage(RawModel m, R *pi, R *A, R *AT,
     int any = __syncthreads_or(bad);
     if (threadIdx.x == 0) {
         *perr = any;
-        double a = 1.0;
-        for (int t = 0; t < BLOCK; ++t) a = fmin(a, amin_sh[t]);
+        double lm = 0.0;
+        for (int t = 0; t < BLOCK; ++t) lm = fmin(lm, amin_sh[t]);
+        const double a = exp(lm);
         // The largest entry of a product of forward-type steps (row vector times
         // A diag(e), max e = 1) grows by at most N <= 1024 = 2^10 and shrinks by
         // at most min a_ij per step, so rescaling every 4 steps keeps single
@@ -145,6 +140,20 @@ __global__ __launch_bounds__(BLOCK) void k_stage(RawModel m, R *pi, R *A, R *AT,
         const double lim4 = sizeof(R) == 4 ? 0x1p-25 : 0x1p-200;
         const double lim2 = sizeof(R) == 4 ? 0x1p-50 : 0x1p-400;
         *nrm = a >= lim4 ? 4 : (a >= lim2 ? 2 : 1);
+    }
+}
+
+// A, A^T and log A in R, all entries in parallel
+template <typename R>
+__global__ __launch_bounds__(BLOCK) void k_stage_mat(const double *log_A, int N, R *A, R *AT, R *lA) {
+    const int64_t NN = (int64_t)N * N;
+    for (int64_t k = (int64_t)blockIdx.x * BLOCK + threadIdx.x; k < NN; k += (int64_t)gridDim.x * BLOCK) {
+        const double l = log_A[k];
+        const R a = (R)exp(l);
+        A[k] = a;
+        lA[k] = (R)l;
+        const int64_t i = k / N, j = k % N;
+        AT[j * N + i] = a;
     }
 }
 
@@ -166,6 +175,9 @@ void launch_stage(const RawModel &m, void *region, StagedModel<R> *out, hipStrea
     int *nrm = (int *)p;
     {
         ProfScope ps("stage", s);
+        const int64_t nn2 = (int64_t)m.N * m.N;
+        const unsigned g = (unsigned)((nn2 + BLOCK - 1) / BLOCK < 512 ? (nn2 + BLOCK - 1) / BLOCK : 512);
+        hipLaunchKernelGGL(k_stage_mat<R>, dim3(g), dim3(BLOCK), 0, s, m.log_A, m.N, A, AT, lA);
         hipLaunchKernelGGL(k_stage<R>, dim3(1), dim3(BLOCK), 0, s, m, pi, A, AT, lpi, lA, ep, ep64,
                            mv, perr, A8, nrm);
     }
