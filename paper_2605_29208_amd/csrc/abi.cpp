@@ -112,9 +112,9 @@ struct Plan {
     int mfma = 0;   // scaled low-precision sweeps: 1 bf16, 2 fp16
     int G = 0, L = 0, C = 0, nblk = 0;
     int64_t S = 0;
-    size_t staged = 0, cbase = 0, frec = 0, brec = 0, F = 0, Gb = 0, partial = 0;
+    size_t staged = 0, cbase = 0, rec = 0, F = 0, Gb = 0, partial = 0;
     int SS = 16, SC = 0;   // chunks per superchunk, number of superchunks
-    size_t sbase = 0, sfrec = 0, sbrec = 0, Fs = 0, Gs = 0, cdesc = 0, sdesc = 0;
+    size_t sbase = 0, srec = 0, Fs = 0, Gs = 0, cdesc = 0, sdesc = 0;
     size_t vpsi = 0, vJ = 0, vqlast = 0, vqend = 0;
     size_t ll = 0, st = 0, gam = 0;
     size_t logB = 0, alpha = 0, beta = 0, ps = 0;
@@ -242,8 +242,7 @@ hmm_status make_plan(hmm_op op, const Checked &c, hmm_precision prec, Plan *p) {
         int64_t nb = (C + gpb - 1) / gpb;
         p->nblk = (int)(nb < 1 ? 1 : (nb > 2048 ? 2048 : nb));
         p->cbase = take((size_t)(c.B + 1) * 4);
-        p->frec = take((size_t)C * p->G * chunk_rec_bytes(p->f64, p->G));
-        p->brec = take((size_t)C * p->G * chunk_rec_bytes(p->f64, p->G));
+        p->rec = take((size_t)C * p->G * chunk_rec_bytes(p->f64, p->G));   // one record per lane
         p->F = take((size_t)(C + 1) * p->G * r);    // + one sink slot
         p->Gb = take((size_t)(C + 1) * p->G * r);
         p->partial = take((size_t)p->nblk * p->S * 8);
@@ -252,8 +251,7 @@ hmm_status make_plan(hmm_op op, const Checked &c, hmm_precision prec, Plan *p) {
         p->sbase = take((size_t)(c.B + 1) * 4);
         p->cdesc = take((size_t)C * sizeof(ChunkDesc));
         p->sdesc = take((size_t)SC * sizeof(SuperDesc));
-        p->sfrec = take((size_t)SC * p->G * rb);
-        p->sbrec = take((size_t)SC * p->G * rb);
+        p->srec = take((size_t)SC * p->G * rb);
         p->Fs = take((size_t)(SC + 1) * p->G * r);
         p->Gs = take((size_t)(SC + 1) * p->G * r);
     }
@@ -334,8 +332,7 @@ hmm_status run_posterior_path(const hmm_model *m, const hmm_batch *b, const Chec
         cb.G = p.G;
         cb.nblk_stats = p.nblk;
         cb.cbase = (int *)(ws + p.cbase);
-        cb.fwdrec = ws + p.frec;
-        cb.bwdrec = ws + p.brec;
+        cb.rec = ws + p.rec;
         cb.F = ws + p.F;
         cb.Gb = ws + p.Gb;
         cb.partial = (double *)(ws + p.partial);
@@ -343,8 +340,7 @@ hmm_status run_posterior_path(const hmm_model *m, const hmm_batch *b, const Chec
         cb.S = p.SS;
         cb.SC = p.SC;
         cb.sbase = (int *)(ws + p.sbase);
-        cb.sfwdrec = ws + p.sfrec;
-        cb.sbwdrec = ws + p.sbrec;
+        cb.srec = ws + p.srec;
         cb.Fs = ws + p.Fs;
         cb.Gs = ws + p.Gs;
         cb.cdesc = (ChunkDesc *)(ws + p.cdesc);

@@ -81,6 +81,28 @@ __device__ __forceinline__ R grp_dot(R x, const R (&c)[G]) {
     return s;
 }
 
+// Transposed counterpart of grp_dot: lane i receives sum_k u_k(src(i, k)),
+// where u_k = x * c[k] on every lane.  Each source map src(., k) is an
+// involution, so if lane q holds c[k] = M[src(q, k)][q] (its column of M in
+// grp_dot order) this is sum_j M[i][j] x_j, the matrix-vector product from
+// the same coefficients.  The quad permutations commute with the mirror, so
+// the upper four terms share one mirror move.
+template <int G, typename R>
+__device__ __forceinline__ R grp_tdot(R x, const R (&c)[G]) {
+    R s = x * c[0];
+    s += dpp_v<DPP_QP_X1>(x * c[1]);
+    s += dpp_v<DPP_QP_X2>(x * c[2]);
+    s += dpp_v<DPP_QP_X3>(x * c[3]);
+    if constexpr (G == 8) {
+        R h = x * c[4];
+        h += dpp_v<DPP_QP_X1>(x * c[5]);
+        h += dpp_v<DPP_QP_X2>(x * c[6]);
+        h += dpp_v<DPP_QP_X3>(x * c[7]);
+        s += dpp_v<DPP_HALF_MIRROR>(h);
+    }
+    return s;
+}
+
 // U[k] += x[src_k] * w
 template <int G, typename R>
 __device__ __forceinline__ void grp_outer_acc(R x, R w, R (&U)[G]) {

@@ -99,18 +99,16 @@ struct ChunkBuffers {
     int *sbase;          // [B+1]
     ChunkDesc *cdesc;    // [C]
     SuperDesc *sdesc;    // [SC]
-    void *sfwdrec;       // [SC*G] superchunk records
-    void *sbwdrec;       // [SC*G]
+    void *srec;          // [SC*G] superchunk transfer-matrix records (one per lane)
     void *Fs;            // [SC*G] R  alpha at each superchunk end
     void *Gs;            // [SC*G] R  beta at each superchunk end
-    void *fwdrec;        // [C*G] records: column of P_c, row exponent, chunk log shift
-    void *bwdrec;        // [C*G] records: row of P_c, row exponent
+    void *rec;           // [C*G] chunk records (one per lane): column of P_c, row exponent, log shift
     void *F;             // [C*G] R  alpha at each chunk end (normalised)
     void *Gb;            // [C*G] R  beta at each chunk end (normalised)
     double *partial;     // [nblk_stats * S]
     double *red;         // reduction scratch (reduce_scratch_len doubles)
 };
-// bytes of one transfer-matrix record (see k_chunk.hip)
+// bytes of one chunk (or superchunk) transfer-matrix record
 size_t chunk_rec_bytes(bool f64, int G);
 template <typename R>
 hmm_status run_chunked(const StagedModel<R> &m, const ObsDesc &o, const ChunkBuffers &cb,

@@ -8,9 +8,11 @@
 // is rescaled by a power of two (exact) and the exponents and the m_t are
 // summed on the side.  Writing M_t = A diag(e_t), a sequence is cut into
 // chunks of L steps and each chunk's transfer matrix P_c = prod_{t in c} M_t
-// is formed independently (phase 1).  Then, per sequence, the chunk-boundary
+// is formed independently (phase 1), together with the product of each
+// superchunk of 16 consecutive chunks.  Then, per sequence, the boundary
 // vectors alpha_{end(c)} = alpha_{end(c-1)} P_c and beta_{end(c-1)} = P_c
-// beta_{end(c)} follow from a short serial scan over chunks (phase 2).
+// beta_{end(c)} follow from a short serial scan over superchunks, and within
+// each superchunk from a serial scan over its chunks (phase 2).
 // Finally every chunk re-runs its own L forward steps from its boundary and
 // the backward recursion beta_{t-1} = M_t beta_t down to its start, forming
 // gamma_t and xi_t (definitions of section 3.1) and accumulating the
@@ -18,9 +20,8 @@
 // sequential recursion up to rounding; phase 1 costs N^3 per step instead of
 // N^2 but has no serial dependency between chunks.
 //
-// Lanes: a chunk's N x N transfer matrix occupies G*G lanes in phase 1
-// (lane = (row i, column j)); in phases 2 and 3 a sequence or chunk occupies
-// G lanes (lane = state).  G = 4 (N <= 4) or 8 (N <= 8); the lane exchanges
+// Lanes: a chunk occupies G lanes in every phase (phase 1: lane = row of its
+// transfer matrix; phases 2 and 3: lane = state).  G = 4 (N <= 4) or 8 (N <= 8); the lane exchanges
 // inside a group of G lanes are DPP quad permutations and the half-row mirror.
 #include <climits>
 
@@ -64,20 +65,16 @@ __device__ __forceinline__ Emit<R> emit_step(R v, const StateConsts<R> &k, bool 
     }
 }
 
-// Transfer-matrix records read by the boundary scan.  Lane p of a sequence
-// reads one record per chunk with a few 16-byte loads:
-//   FwdRec (forward scan, lane = column p): coef[k] = P_c[src(p,k)][p],
-//          r = binary exponent of row p, clog = the chunk's summed log shifts;
-//   BwdRec (backward scan, lane = row p):   coef[k] = P_c[p][src(p,k)], r as above.
+// Transfer-matrix records of a chunk (or of a superchunk of 16 chunks), one
+// per lane of a G-lane group, stored once and read by both boundary scans:
+// with P = diag(2^r) P~ (each nonzero row of P~ with its largest entry in
+// [1/2, 1)), lane p's record holds column p of P~ in grp_dot order,
+// coef[k] = P~[src(p, k)][p], the exponent r[p] of row p and the summed log
+// shift m_t of the steps covered (NaN after a non-finite observation).  The
+// forward scan forms f P with grp_dot, the backward scan P g with grp_tdot
+// from the same coefficients.
 template <typename R, int G>
-struct __align__(16) FwdRec {
-    R coef[G];
-    int r;
-    int pad;
-    double clog;
-};
-template <typename R, int G>
-struct __align__(16) BwdRec {
+struct __align__(16) ColRec {
     R coef[G];
     int r;
     int pad;
@@ -85,11 +82,21 @@ struct __align__(16) BwdRec {
 };
 
 size_t chunk_rec_bytes(bool f64, int G) {
-    size_t a = f64 ? (G == 8 ? sizeof(FwdRec<double, 8>) : sizeof(FwdRec<double, 4>))
-                   : (G == 8 ? sizeof(FwdRec<float, 8>) : sizeof(FwdRec<float, 4>));
-    size_t b = f64 ? (G == 8 ? sizeof(BwdRec<double, 8>) : sizeof(BwdRec<double, 4>))
-                   : (G == 8 ? sizeof(BwdRec<float, 8>) : sizeof(BwdRec<float, 4>));
-    return a > b ? a : b;
+    return f64 ? (G == 8 ? sizeof(ColRec<double, 8>) : sizeof(ColRec<double, 4>))
+               : (G == 8 ? sizeof(ColRec<float, 8>) : sizeof(ColRec<float, 4>));
+}
+
+// lane li writes its record from the natural-order matrix rows in LDS
+template <typename R, int G, int RS>
+__device__ __forceinline__ void store_colrec(ColRec<R, G> *dst, const R (*rows)[RS], int li,
+                                             int r, double clog) {
+    ColRec<R, G> f;
+#pragma unroll
+    for (int k = 0; k < G; ++k) f.coef[k] = rows[grp_src(li, k)][li];
+    f.r = r;
+    f.pad = 0;
+    f.clog = clog;
+    *dst = f;
 }
 
 // ---------------------------------------------------------------- phase 1
@@ -98,21 +105,42 @@ size_t chunk_rec_bytes(bool f64, int G) {
 // uniform across the block, so the product needs no lane exchange at all.
 // The chunk's emissions e_t(j) are first tabulated in LDS, lane i taking the
 // steps i, i + G, ... (all states of a step in one lane, so the per-step
-// maximum is a local reduction).
+// maximum is a local reduction).  A block holds whole superchunks (SPC = 16
+// consecutive chunks of one sequence, slot i of a superchunk = its chunk i):
+// after writing the chunk records it multiplies the superchunk's chunk
+// matrices in a pairwise tree through LDS (slot i takes slot i + h at stride
+// h = 1, 2, 4, 8) and writes the superchunk record, so the boundary scan over
+// superchunks needs no separate pass over the chunk records.
+constexpr int SPC = 16;
+
 template <typename R, int G, int L, int FAM>
-__global__ __launch_bounds__(BLOCK) void k_chunk_product(ChunkGeom g, StagedModel<R> m,
+__global__ __launch_bounds__(BLOCK) void k_chunk_product(ChunkGeom g, const SuperDesc *__restrict__ sdesc,
+                                                         int SC, StagedModel<R> m,
                                                          const R *__restrict__ A8,
-                                                         FwdRec<R, G> *__restrict__ frec,
-                                                         BwdRec<R, G> *__restrict__ brec) {
+                                                         ColRec<R, G> *__restrict__ rec,
+                                                         ColRec<R, G> *__restrict__ srec) {
     constexpr int CPB = BLOCK / G;   // chunks per block
+    constexpr int SPB = CPB / SPC;   // superchunks per block
+    static_assert(SPB * SPC == CPB, "a block holds whole superchunks");
     __shared__ R esh[CPB][L][G];
     __shared__ double msh[CPB][G];
-    __shared__ R psh[CPB][G][G + 1];
+    // rows padded to G + 4 entries: 16-byte aligned for vector reads in the tree
+    constexpr int RS = G + 4;
+    __shared__ __align__(16) R psh[CPB][G][RS];
+    __shared__ __align__(16) int rsh[CPB][G];
+    __shared__ double csh[CPB];
 
     const int li = threadIdx.x % G;
     const int slot = threadIdx.x / G;
-    const int c = blockIdx.x * CPB + slot;
-    const bool valid = c < g.C;
+    const int si = slot % SPC;                        // chunk index inside its superchunk
+    const int sc = blockIdx.x * SPB + slot / SPC;     // superchunk
+    int nsc = 0, c = 0;
+    if (sc < SC) {
+        const SuperDesc sd = sdesc[sc];
+        nsc = sd.n;
+        c = sd.lo + si;
+    }
+    const bool valid = si < nsc;
     const int N = m.N;
     int64_t off = 0;
     int ts = 0, nsteps = 0;
@@ -133,10 +161,12 @@ __global__ __launch_bounds__(BLOCK) void k_chunk_product(ChunkGeom g, StagedMode
         ET ell[G];
         ET mx = neg_inf<ET>();
         double common = 0.0;
+        // scalar families: one observation per step, loaded once for all states
+        const R y = (FAM != HMM_TABLE) ? load_obs<R>(g.obs, row) : (R)0;
 #pragma unroll
         for (int j = 0; j < G; ++j) {
             const bool live = j < N;
-            R v = load_step<FAM, R>(g.obs, row, j, N, live);
+            R v = (FAM != HMM_TABLE) ? y : load_step<FAM, R>(g.obs, row, j, N, live);
             StateConsts<ET> k = load_consts(ep, j, live);
             Emit<ET> em = emit_step<FAM, ET>((ET)v, k, live);
             ell[j] = em.ell;
@@ -186,135 +216,60 @@ __global__ __launch_bounds__(BLOCK) void k_chunk_product(ChunkGeom g, StagedMode
         for (int j = 0; j < G; ++j) rowv[j] = rescale ? fldexp(nv[j], -ex) : nv[j];
         r += ex;
     }
-    // transpose through LDS into the two record layouts
+    double cl = 0.0;
+#pragma unroll
+    for (int q = 0; q < G; ++q) cl += msh[slot][q];
 #pragma unroll
     for (int j = 0; j < G; ++j) psh[slot][li][j] = rowv[j];
-    __syncthreads();
-    if (valid) {
-        double cl = 0.0;
-        for (int q = 0; q < G; ++q) cl += msh[slot][q];
-        FwdRec<R, G> f;
-        BwdRec<R, G> bw;
-#pragma unroll
-        for (int k = 0; k < G; ++k) {
-            f.coef[k] = psh[slot][grp_src(li, k)][li];
-            bw.coef[k] = psh[slot][li][grp_src(li, k)];
-        }
-        f.r = r;
-        f.pad = 0;
-        f.clog = cl;
-        bw.r = r;
-        bw.pad = 0;
-        bw.clog = cl;
-        frec[(size_t)c * G + li] = f;
-        brec[(size_t)c * G + li] = bw;
-    }
-}
-
-// ---------------------------------------------------------------- phase 1b
-// Products of S consecutive chunk matrices ("superchunks"), one G-lane group
-// per superchunk, lane = row.  Each chunk matrix is scattered into LDS in
-// natural order; the lane then multiplies its row by it, combining the
-// per-row binary exponents exactly.  Output records have the same layout as
-// the chunk records, so the boundary scan below runs on either level.
-template <typename R, int G>
-__global__ __launch_bounds__(BLOCK) void k_super_product(const SuperDesc *__restrict__ sdesc, int SC,
-                                                         int S, const FwdRec<R, G> *__restrict__ frec,
-                                                         const BwdRec<R, G> *__restrict__ brec,
-                                                         FwdRec<R, G> *__restrict__ sfrec,
-                                                         BwdRec<R, G> *__restrict__ sbrec) {
-    constexpr int GPB = BLOCK / G;
-    __shared__ R psh[GPB][G][G + 1];
-    __shared__ int rsh[GPB][G];
-    __shared__ double csh[GPB];
-    const int li = threadIdx.x % G;
-    const int slot = threadIdx.x / G;
-    const int k = blockIdx.x * GPB + slot;
-    const bool valid = k < SC;
-    int c0 = 0, nc = 0;
-    if (valid) {
-        const SuperDesc d = sdesc[k];
-        c0 = d.lo;
-        nc = d.n;
-    }
-    R rv[G];
-#pragma unroll
-    for (int j = 0; j < G; ++j) rv[j] = (R)0;
-    int E = 0;
-    double cl = 0.0;
-    // records are loaded one chunk ahead; indices are clamped into the
-    // superchunk so every load is in bounds and unconditional
-    constexpr int PFS = 4;
-    const int last = valid ? c0 + nc - 1 : 0;
-    BwdRec<R, G> ring[PFS];
-#pragma unroll
-    for (int q = 0; q < PFS; ++q) ring[q] = brec[(size_t)min(c0 + q, last) * G + li];
-    for (int it = 0; it < S; ++it) {
-        const bool act = valid && it < nc;
-        BwdRec<R, G> rec = ring[0];
-#pragma unroll
-        for (int q = 0; q + 1 < PFS; ++q) ring[q] = ring[q + 1];
-        ring[PFS - 1] = brec[(size_t)min(c0 + it + PFS, last) * G + li];
-        if (act) {
-#pragma unroll
-            for (int q = 0; q < G; ++q) psh[slot][li][grp_src(li, q)] = rec.coef[q];
-            rsh[slot][li] = rec.r;
-            cl += rec.clog;
-        }
-        __syncthreads();
-        if (act) {
-            if (it == 0) {
-#pragma unroll
-                for (int j = 0; j < G; ++j) rv[j] = psh[slot][li][j];
-                E = rsh[slot][li];
-            } else {
-                int Rm = NEG_EXP;
-#pragma unroll
-                for (int q = 0; q < G; ++q)
-                    if (rv[q] > (R)0) Rm = max(Rm, fexp(rv[q]) + rsh[slot][q]);
-                if (Rm != NEG_EXP) {
-                    R nv[G];
-#pragma unroll
-                    for (int j = 0; j < G; ++j) nv[j] = (R)0;
-#pragma unroll
-                    for (int q = 0; q < G; ++q) {
-                        R wq = (rv[q] > (R)0) ? fldexp(rv[q], rsh[slot][q] - Rm) : (R)0;
-#pragma unroll
-                        for (int j = 0; j < G; ++j) nv[j] = fma(wq, psh[slot][q][j], nv[j]);
-                    }
-                    R mx = nv[0];
-#pragma unroll
-                    for (int j = 1; j < G; ++j) mx = fmax(mx, nv[j]);
-                    const int ex = fexp(mx);
-#pragma unroll
-                    for (int j = 0; j < G; ++j) rv[j] = fldexp(nv[j], -ex);
-                    E += Rm + ex;
-                }
-            }
-        }
-        __syncthreads();
-    }
-#pragma unroll
-    for (int j = 0; j < G; ++j) psh[slot][li][j] = rv[j];
+    rsh[slot][li] = r;
     if (li == 0) csh[slot] = cl;
     __syncthreads();
-    if (valid) {
-        FwdRec<R, G> f;
-        BwdRec<R, G> bw;
+    if (valid) store_colrec<R, G, RS>(rec + (size_t)c * G + li, psh[slot], li, r, cl);
+
+    // pairwise tree over the superchunk's chunks (the records above only read
+    // the group's own slot, which no level writes before its next barrier)
 #pragma unroll
-        for (int q = 0; q < G; ++q) {
-            f.coef[q] = psh[slot][grp_src(li, q)][li];
-            bw.coef[q] = psh[slot][li][grp_src(li, q)];
+    for (int h = 1; h < SPC; h *= 2) {
+        if (h > 1) __syncthreads();
+        const bool act = (si % (2 * h)) == 0 && si + h < nsc;
+        if (act) {
+            // row li of (2^r P~)(2^r' P~') with the row exponents combined exactly
+            const int o = slot + h;
+            int Rm = NEG_EXP;
+#pragma unroll
+            for (int k = 0; k < G; ++k)
+                if (rowv[k] > (R)0) Rm = max(Rm, fexp(rowv[k]) + rsh[o][k]);
+            if (Rm != NEG_EXP) {
+                R nv[G];
+#pragma unroll
+                for (int j = 0; j < G; ++j) nv[j] = (R)0;
+#pragma unroll
+                for (int k = 0; k < G; ++k) {
+                    const R wk = (rowv[k] > (R)0) ? fldexp(rowv[k], rsh[o][k] - Rm) : (R)0;
+#pragma unroll
+                    for (int j = 0; j < G; ++j) nv[j] = fma(wk, psh[o][k][j], nv[j]);
+                }
+                R mx = nv[0];
+#pragma unroll
+                for (int j = 1; j < G; ++j) mx = fmax(mx, nv[j]);
+                const int ex = fexp(mx);
+#pragma unroll
+                for (int j = 0; j < G; ++j) rowv[j] = fldexp(nv[j], -ex);
+                r += Rm + ex;
+            }
+            cl += csh[o];
         }
-        f.r = E;
-        f.pad = 0;
-        f.clog = csh[slot];
-        bw.r = E;
-        bw.pad = 0;
-        bw.clog = csh[slot];
-        sfrec[(size_t)k * G + li] = f;
-        sbrec[(size_t)k * G + li] = bw;
+        // a level reads only slots with si % 2h == h and writes only slots
+        // with si % 2h == 0, so the next level's barrier orders these stores
+        if (act) {
+#pragma unroll
+            for (int j = 0; j < G; ++j) psh[slot][li][j] = rowv[j];
+            rsh[slot][li] = r;
+            if (li == 0) csh[slot] = cl;
+        }
     }
+    __syncthreads();
+    if (si == 0 && nsc > 0) store_colrec<R, G, RS>(srec + (size_t)sc * G + li, psh[slot], li, r, cl);
 }
 
 // ---------------------------------------------------------------- phase 2
@@ -358,8 +313,7 @@ __device__ __forceinline__ R alpha0(const StagedModel<R> &m, const ObsRef &obs, 
 
 template <typename R, int G, int FAM, int PF, bool EXPAND>
 __global__ __launch_bounds__(BLOCK) void k_chunk_scan(ScanGeom g, StagedModel<R> m,
-                                                      const FwdRec<R, G> *__restrict__ frec,
-                                                      const BwdRec<R, G> *__restrict__ brec,
+                                                      const ColRec<R, G> *__restrict__ rec,
                                                       const R *__restrict__ Fs,
                                                       const R *__restrict__ Gs,
                                                       R *__restrict__ Fo, R *__restrict__ Go,
@@ -368,7 +322,11 @@ __global__ __launch_bounds__(BLOCK) void k_chunk_scan(ScanGeom g, StagedModel<R>
     constexpr int SPW = 64 / G;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int sub = lane / G, p = lane % G;
-    const int64_t seg = ((int64_t)blockIdx.x * (BLOCK / 64) + wave) * SPW + sub;
+    // odd waves run the backward scan over the segments of the even wave
+    // before them, so both directions read a record at about the same time on
+    // the same compute unit (one fetch from memory serves both)
+    const bool fwd = (wave & 1) == 0;
+    const int64_t seg = ((int64_t)blockIdx.x * (BLOCK / 128) + (wave >> 1)) * SPW + sub;
     const bool valid = seg < (EXPAND ? (int64_t)g.SC : g.nseq);
     const bool live = p < m.N;
     int lo = 0, n = 0;
@@ -392,7 +350,7 @@ __global__ __launch_bounds__(BLOCK) void k_chunk_scan(ScanGeom g, StagedModel<R>
     }
     const int nmax = wave_max_i(n);
 
-    if (blockIdx.y == 0) {
+    if (fwd) {
         // forward: f <- f P_c over the segment's records
         double logS = 0.0;
         int E0 = 0;
@@ -410,16 +368,16 @@ __global__ __launch_bounds__(BLOCK) void k_chunk_scan(ScanGeom g, StagedModel<R>
         // (always in bounds, so they need no branch and their waits stay exact)
         const int lastf = lo + max(n - 1, 0);
         const int64_t fsl = valid ? -1 : (int64_t)sink;   // store slot override
-        FwdRec<R, G> ring[PF];
+        ColRec<R, G> ring[PF];
 #pragma unroll
-        for (int q = 0; q < PF; ++q) ring[q] = frec[(size_t)min(lo + q, lastf) * G + p];
+        for (int q = 0; q < PF; ++q) ring[q] = rec[(size_t)min(lo + q, lastf) * G + p];
         for (int s0 = 0; s0 < nmax; s0 += PF) {
 #pragma unroll
             for (int q = 0; q < PF; ++q) {
                 const int s = s0 + q;
                 const bool act = s < n;
-                const FwdRec<R, G> cur = ring[q];
-                ring[q] = frec[(size_t)min(lo + s + PF, lastf) * G + p];
+                const ColRec<R, G> cur = ring[q];
+                ring[q] = rec[(size_t)min(lo + s + PF, lastf) * G + p];
                 const int rr = act ? cur.r : 0;
                 const int ce = (f > (R)0) ? fexp(f) + rr : NEG_EXP;
                 const int Rm = grp_max_i<G>(ce);
@@ -469,21 +427,21 @@ __global__ __launch_bounds__(BLOCK) void k_chunk_scan(ScanGeom g, StagedModel<R>
         Go[(size_t)(gsl >= 0 ? gsl : (int64_t)(lo + n - 1)) * G + p] = gv;
         const int nb = n - 1;
         const int top = lo + max(n - 1, 0);
-        BwdRec<R, G> ring[PF];
+        ColRec<R, G> ring[PF];
 #pragma unroll
-        for (int q = 0; q < PF; ++q) ring[q] = brec[(size_t)max(top - q, lo) * G + p];
+        for (int q = 0; q < PF; ++q) ring[q] = rec[(size_t)max(top - q, lo) * G + p];
         for (int s0 = 0; s0 + 1 < nmax; s0 += PF) {
 #pragma unroll
             for (int q = 0; q < PF; ++q) {
                 const int s = s0 + q;
                 const bool act = s < nb;
-                const BwdRec<R, G> cur = ring[q];
-                ring[q] = brec[(size_t)max(top - (s + PF), lo) * G + p];
+                const ColRec<R, G> cur = ring[q];
+                ring[q] = rec[(size_t)max(top - (s + PF), lo) * G + p];
                 R coef[G];
 #pragma unroll
                 for (int kk = 0; kk < G; ++kk) coef[kk] = act ? cur.coef[kk] : (R)0;
                 const int rr = act ? cur.r : 0;
-                R v = grp_dot<G, R>(gv, coef);
+                R v = grp_tdot<G, R>(gv, coef);
                 const int ce = (v > (R)0) ? fexp(v) + rr : NEG_EXP;
                 const int Rm = grp_max_i<G>(ce);
                 v = (v > (R)0) ? fldexp(v, rr - Rm) : (R)0;
@@ -583,10 +541,11 @@ __global__ __launch_bounds__(BLOCK) void k_chunk_stats(ChunkGeom g, StagedModel<
             ET ell[G];
             ET mx = neg_inf<ET>();
             R y1 = (R)1;
+            const R y = (FAM != HMM_TABLE && act) ? load_obs<R>(g.obs, row) : (R)1;
 #pragma unroll
             for (int j = 0; j < G; ++j) {
                 const bool lj = j < N;
-                R v = act ? load_step<FAM, R>(g.obs, row, j, N, lj) : (R)1;
+                R v = (FAM != HMM_TABLE) ? y : (act ? load_step<FAM, R>(g.obs, row, j, N, lj) : (R)1);
                 if (j == 0) y1 = v;
                 Emit<ET> em = emit_step<FAM, ET>((ET)v, load_consts(ep, j, lj), lj);
                 ell[j] = em.ell;
@@ -734,11 +693,12 @@ static void launch_phase3(int nblk, const ChunkGeom &geom, const StagedModel<R> 
 }
 
 template <typename R, int G, int FAM, int L>
-static void launch_product(int C, const ChunkGeom &geom, const StagedModel<R> &m,
-                           FwdRec<R, G> *fr, BwdRec<R, G> *br, hipStream_t s) {
-    constexpr int CPB = BLOCK / G;
-    hipLaunchKernelGGL((k_chunk_product<R, G, L, FAM>), dim3((C + CPB - 1) / CPB), dim3(BLOCK), 0,
-                       s, geom, m, m.A8, fr, br);
+static void launch_product(int SC, const SuperDesc *sdesc, const ChunkGeom &geom,
+                           const StagedModel<R> &m, ColRec<R, G> *rec, ColRec<R, G> *srec,
+                           hipStream_t s) {
+    constexpr int SPB = BLOCK / G / SPC;
+    hipLaunchKernelGGL((k_chunk_product<R, G, L, FAM>), dim3((SC + SPB - 1) / SPB), dim3(BLOCK),
+                       0, s, geom, sdesc, SC, m, m.A8, rec, srec);
 }
 
 template <typename R, int G, int FAM>
@@ -747,45 +707,38 @@ static hmm_status run_chunked_g(const StagedModel<R> &m, const ObsDesc &o, const
                                 int64_t S, hipStream_t s) {
     ChunkGeom geom{o.nseq, o.offsets, cb.cbase, cb.cdesc, cb.L, cb.C, ObsRef{o.obs, o.obs_f64}};
     constexpr int SPB = (BLOCK / 64) * (64 / G);
-    auto *fr = (FwdRec<R, G> *)cb.fwdrec;
-    auto *br = (BwdRec<R, G> *)cb.bwdrec;
+    if (cb.S != SPC) return HMM_ERR_UNSUPPORTED;
+    auto *rec = (ColRec<R, G> *)cb.rec;
+    auto *srec = (ColRec<R, G> *)cb.srec;
+    const SuperDesc *sdesc = (const SuperDesc *)cb.sdesc;
     R *F = (R *)cb.F;
     R *Gb = (R *)cb.Gb;
     {
         ProfScope ps("chunk_product", s);
         switch (cb.L) {
-        case 16: launch_product<R, G, FAM, 16>(cb.C, geom, m, fr, br, s); break;
-        case 32: launch_product<R, G, FAM, 32>(cb.C, geom, m, fr, br, s); break;
-        case 64: launch_product<R, G, FAM, 64>(cb.C, geom, m, fr, br, s); break;
+        case 16: launch_product<R, G, FAM, 16>(cb.SC, sdesc, geom, m, rec, srec, s); break;
+        case 32: launch_product<R, G, FAM, 32>(cb.SC, sdesc, geom, m, rec, srec, s); break;
+        case 64: launch_product<R, G, FAM, 64>(cb.SC, sdesc, geom, m, rec, srec, s); break;
         default: return HMM_ERR_UNSUPPORTED;
         }
     }
     ScanGeom sg{o.nseq,  o.offsets, cb.cbase, cb.sbase, cb.S,
                 cb.SC,   cb.C,      cb.sdesc, ObsRef{o.obs, o.obs_f64}};
-    auto *sfr = (FwdRec<R, G> *)cb.sfwdrec;
-    auto *sbr = (BwdRec<R, G> *)cb.sbwdrec;
     R *Fs = (R *)cb.Fs;
     R *Gs = (R *)cb.Gs;
     {
-        ProfScope ps("super_product", s);
-        constexpr int GPB = BLOCK / G;
-        hipLaunchKernelGGL((k_super_product<R, G>), dim3((cb.SC + GPB - 1) / GPB), dim3(BLOCK), 0, s,
-                           (const SuperDesc *)cb.sdesc, cb.SC, cb.S, (const FwdRec<R, G> *)fr,
-                           (const BwdRec<R, G> *)br, sfr, sbr);
-    }
-    {
         ProfScope ps("chunk_scan", s);
         hipLaunchKernelGGL((k_chunk_scan<R, G, FAM, 8, false>),
-                           dim3((unsigned)((o.nseq + SPB - 1) / SPB), 2), dim3(BLOCK), 0, s, sg, m,
-                           (const FwdRec<R, G> *)sfr, (const BwdRec<R, G> *)sbr, (const R *)nullptr,
-                           (const R *)nullptr, Fs, Gs, loglik, status);
+                           dim3((unsigned)((o.nseq + SPB / 2 - 1) / (SPB / 2))), dim3(BLOCK), 0, s, sg, m,
+                           (const ColRec<R, G> *)srec, (const R *)nullptr, (const R *)nullptr, Fs,
+                           Gs, loglik, status);
     }
     {
         ProfScope ps("chunk_expand", s);
         hipLaunchKernelGGL((k_chunk_scan<R, G, FAM, 8, true>),
-                           dim3((unsigned)((cb.SC + SPB - 1) / SPB), 2), dim3(BLOCK), 0, s, sg, m,
-                           (const FwdRec<R, G> *)fr, (const BwdRec<R, G> *)br, (const R *)Fs,
-                           (const R *)Gs, F, Gb, loglik, status);
+                           dim3((unsigned)((cb.SC + SPB / 2 - 1) / (SPB / 2))), dim3(BLOCK), 0, s, sg, m,
+                           (const ColRec<R, G> *)rec, (const R *)Fs, (const R *)Gs, F, Gb, loglik,
+                           status);
     }
     switch (cb.L) {
     case 16:

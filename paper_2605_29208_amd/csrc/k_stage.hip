@@ -23,24 +23,63 @@ size_t staged_bytes(int N, int D, int family, bool f64) {
            align256(64 * r) + 256;
 }
 
-// One block.  Computes linear and log probabilities in R, the per-state
-// emission constants (see dev_common.hpp for their meaning) and, for the
-// multivariate families, the location vectors and -1/(2 var) or L^{-1}.
+// Block 0 computes the initial probabilities, the per-state emission
+// constants (see dev_common.hpp for their meaning), the diagonal-Gaussian
+// location and -1/(2 var) vectors, the full-Gaussian means, the parameter
+// check and the rescale interval.  Blocks 1 .. nmat fill A, A^T and log A in
+// R (block 0 does it when nmat = 0); for the full Gaussian, block
+// 1 + nmat + j forms L_j^{-1}, one thread per column.
 template <typename R>
-__global__ __launch_bounds__(BLOCK) void k_stage(RawModel m, R *pi, R *A, R *AT, R *lpi, R *lA,
-                                                 R *ep, double *ep64, R *mv, int *perr, R *A8,
-                                                 int *nrm) {
+__global__ __launch_bounds__(BLOCK) void k_stage(RawModel m, int nmat, R *pi, R *A, R *AT, R *lpi,
+                                                 R *lA, R *ep, double *ep64, R *mv, int *perr,
+                                                 R *A8, int *nrm) {
     const int N = m.N, D = m.D;
+    const int64_t NN = (int64_t)N * N;
+    const int bx = blockIdx.x;
+    if (bx > nmat) {
+        // L_j^{-1} column by column: L x = e_col by forward substitution (FP64),
+        // the column kept in LDS (thread col owns column col)
+        __shared__ double xs[64 * 64];
+        const int j = bx - 1 - nmat, col = threadIdx.x;
+        if (col >= D) return;
+        const double *L = m.theta + (size_t)N * D + (size_t)j * D * D;
+        R *Li = mv + (size_t)N * D + (size_t)j * D * D;
+        for (int r = 0; r < D; ++r) {
+            double x = 0.0;
+            if (r >= col) {
+                double acc = (r == col) ? 1.0 : 0.0;
+                for (int q = col; q < r; ++q) acc -= L[r * D + q] * xs[q * 64 + col];
+                x = acc / L[r * D + r];
+            }
+            xs[r * 64 + col] = x;
+            Li[r * D + col] = (R)x;
+        }
+        return;
+    }
+    if (bx > 0 || nmat == 0) {
+        const int64_t stride = (int64_t)(nmat > 0 ? nmat : 1) * BLOCK;
+        for (int64_t k = (int64_t)(bx > 0 ? bx - 1 : 0) * BLOCK + threadIdx.x; k < NN; k += stride) {
+            const double l = m.log_A[k];
+            const R av = (R)exp(l);
+            A[k] = av;
+            lA[k] = (R)l;
+            AT[(k % N) * N + k / N] = av;
+        }
+        if (bx > 0) return;
+    }
     int bad = 0;
     __shared__ double amin_sh[BLOCK];
-    double lmin = 0.0;   // min log a_ij (exp is monotone: min a_ij = exp(min log a_ij))
-    for (int k = threadIdx.x; k < N * N; k += blockDim.x) lmin = fmin(lmin, m.log_A[k]);
+    // min log a_ij (exp is monotone: min a_ij = exp(min log a_ij)).  Only the
+    // transfer-matrix path (N <= 8) uses the rescale interval; larger models
+    // get interval 1 without the scan.
+    double lmin = NN <= 4096 ? 0.0 : -__builtin_inf();
+    for (int64_t k = threadIdx.x; k < (NN <= 4096 ? NN : 0); k += BLOCK) lmin = fmin(lmin, m.log_A[k]);
     amin_sh[threadIdx.x] = lmin;
-    for (int k = threadIdx.x; k < 64; k += blockDim.x) {
+    for (int k = threadIdx.x; k < 64; k += BLOCK) {
         int i = k / 8, j = k % 8;
         A8[k] = (i < N && j < N) ? (R)exp(m.log_A[i * N + j]) : (R)0;
     }
-    for (int j = threadIdx.x; j < N; j += blockDim.x) {
+    for (int j = threadIdx.x; j < N; j += BLOCK) {
         double l = m.log_pi[j];
         pi[j] = (R)exp(l);
         lpi[j] = (R)l;
@@ -48,7 +87,7 @@ __global__ __launch_bounds__(BLOCK) void k_stage(RawModel m, R *pi, R *A, R *AT,
 
     const double *th = m.theta;
     const double kLog2Pi = 1.8378770664093454835606594728112;
-    for (int j = threadIdx.x; j < N; j += blockDim.x) {
+    for (int j = threadIdx.x; j < N; j += BLOCK) {
         double c[EP_STRIDE] = {0, 0, 0, 0, 0, 0, 0, 0};
         switch (m.family) {
         case HMM_GAUSSIAN: {
@@ -98,23 +137,11 @@ __global__ __launch_bounds__(BLOCK) void k_stage(RawModel m, R *pi, R *A, R *AT,
         }
         case HMM_FULL_GAUSSIAN: {
             const double *L = th + (size_t)N * D + (size_t)j * D * D;
-            R *Li = mv + (size_t)N * D + (size_t)j * D * D;
             double logdet = 0.0;
             for (int d = 0; d < D; ++d) {
                 mv[(size_t)j * D + d] = (R)th[(size_t)j * D + d];
                 bad |= !(L[d * D + d] > 0.0);
                 logdet += log(L[d * D + d]);
-            }
-            // L^{-1} column by column: solve L x = e_col by forward substitution (FP64)
-            for (int col = 0; col < D; ++col) {
-                double x[64];
-                for (int r = 0; r < D; ++r) {
-                    if (r < col) { x[r] = 0.0; continue; }
-                    double acc = (r == col) ? 1.0 : 0.0;
-                    for (int q = col; q < r; ++q) acc -= L[r * D + q] * x[q];
-                    x[r] = acc / L[r * D + r];
-                }
-                for (int r = 0; r < D; ++r) Li[r * D + col] = (R)x[r];
             }
             c[0] = -logdet - 0.5 * D * kLog2Pi;
             break;
@@ -128,11 +155,14 @@ __global__ __launch_bounds__(BLOCK) void k_stage(RawModel m, R *pi, R *A, R *AT,
         }
     }
     int any = __syncthreads_or(bad);
+    for (int o = BLOCK / 2; o > 0; o >>= 1) {
+        if (threadIdx.x < (unsigned)o)
+            amin_sh[threadIdx.x] = fmin(amin_sh[threadIdx.x], amin_sh[threadIdx.x + o]);
+        __syncthreads();
+    }
     if (threadIdx.x == 0) {
         *perr = any;
-        double lm = 0.0;
-        for (int t = 0; t < BLOCK; ++t) lm = fmin(lm, amin_sh[t]);
-        const double a = exp(lm);
+        const double a = exp(amin_sh[0]);
         // The largest entry of a product of forward-type steps (row vector times
         // A diag(e), max e = 1) grows by at most N <= 1024 = 2^10 and shrinks by
         // at most min a_ij per step, so rescaling every 4 steps keeps single
@@ -140,20 +170,6 @@ __global__ __launch_bounds__(BLOCK) void k_stage(RawModel m, R *pi, R *A, R *AT,
         const double lim4 = sizeof(R) == 4 ? 0x1p-25 : 0x1p-200;
         const double lim2 = sizeof(R) == 4 ? 0x1p-50 : 0x1p-400;
         *nrm = a >= lim4 ? 4 : (a >= lim2 ? 2 : 1);
-    }
-}
-
-// A, A^T and log A in R, all entries in parallel
-template <typename R>
-__global__ __launch_bounds__(BLOCK) void k_stage_mat(const double *log_A, int N, R *A, R *AT, R *lA) {
-    const int64_t NN = (int64_t)N * N;
-    for (int64_t k = (int64_t)blockIdx.x * BLOCK + threadIdx.x; k < NN; k += (int64_t)gridDim.x * BLOCK) {
-        const double l = log_A[k];
-        const R a = (R)exp(l);
-        A[k] = a;
-        lA[k] = (R)l;
-        const int64_t i = k / N, j = k % N;
-        AT[j * N + i] = a;
     }
 }
 
@@ -175,11 +191,12 @@ void launch_stage(const RawModel &m, void *region, StagedModel<R> *out, hipStrea
     int *nrm = (int *)p;
     {
         ProfScope ps("stage", s);
+        // small matrices are filled by block 0 itself
         const int64_t nn2 = (int64_t)m.N * m.N;
-        const unsigned g = (unsigned)((nn2 + BLOCK - 1) / BLOCK < 512 ? (nn2 + BLOCK - 1) / BLOCK : 512);
-        hipLaunchKernelGGL(k_stage_mat<R>, dim3(g), dim3(BLOCK), 0, s, m.log_A, m.N, A, AT, lA);
-        hipLaunchKernelGGL(k_stage<R>, dim3(1), dim3(BLOCK), 0, s, m, pi, A, AT, lpi, lA, ep, ep64,
-                           mv, perr, A8, nrm);
+        const int nmat = nn2 <= 4 * BLOCK ? 0 : (int)((nn2 + BLOCK - 1) / BLOCK < 512 ? (nn2 + BLOCK - 1) / BLOCK : 512);
+        const int nfull = m.family == HMM_FULL_GAUSSIAN ? m.N : 0;
+        hipLaunchKernelGGL(k_stage<R>, dim3((unsigned)(1 + nmat + nfull)), dim3(BLOCK), 0, s, m,
+                           nmat, pi, A, AT, lpi, lA, ep, ep64, mv, perr, A8, nrm);
     }
     out->N = m.N;
     out->D = m.D;
@@ -292,26 +309,55 @@ void launch_chunk_desc(const int64_t *offsets, int64_t nseq, int L, int S, const
 }
 
 // Pooled statistics from per-part rows partial[p * S + s] (p < nparts), in a
-// fixed order so that repeated calls give identical bits.  Parts are summed in
-// groups of RED_G (pass 1, one thread per (entry, group), coalesced over
-// entries), then the groups in order (pass 2).  Entry 0 is the sum of the
-// log-likelihoods of the sequences with status 0 (a block tree of its own).
+// fixed order so that repeated calls give identical bits.  A block covers 64
+// consecutive entries (one per lane, so every load is a coalesced 512-byte
+// row segment) and its four waves take interleaved parts: wave w sums parts
+// w, w + 4, ... of its range, with RED_U independent loads in flight, and the
+// four wave sums are added in wave order.  More than RED_G parts are first
+// summed in groups of RED_G (pass 1), then the group rows (pass 2).  Entry 0
+// is the sum of the log-likelihoods of the sequences with status 0 (a block
+// tree of its own).
 constexpr int RED_G = 64;
+constexpr int RED_U = 4;
 
 int64_t reduce_scratch_len(int64_t nparts, int64_t S) {
     return nparts > RED_G ? ((nparts + RED_G - 1) / RED_G) * S : 0;
 }
 
+// sum of rows[r * S + s] over r in [r0, r1), fixed order, result valid in wave 0
+__device__ __forceinline__ double block_rows_sum(const double *__restrict__ rows, int r0, int r1,
+                                                 int64_t S, int64_t s, bool live) {
+    __shared__ double sh[BLOCK / 64][64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    double acc = 0.0;
+    if (live) {
+        for (int r = r0 + w; r < r1; r += (BLOCK / 64) * RED_U) {
+            double v[RED_U];
+#pragma unroll
+            for (int u = 0; u < RED_U; ++u) {
+                const int q = r + u * (BLOCK / 64);
+                v[u] = q < r1 ? rows[(int64_t)q * S + s] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < RED_U; ++u) acc += v[u];
+        }
+    }
+    sh[w][lane] = acc;
+    __syncthreads();
+    double t = sh[0][lane];
+#pragma unroll
+    for (int q = 1; q < BLOCK / 64; ++q) t += sh[q][lane];
+    return t;
+}
+
 __global__ __launch_bounds__(BLOCK) void k_reduce_parts(const double *__restrict__ partial,
                                                        int nparts, int64_t S,
                                                        double *__restrict__ red) {
-    const int64_t s = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    const int64_t s = (int64_t)blockIdx.x * 64 + (threadIdx.x & 63);
     const int g = blockIdx.y;
-    if (s >= S) return;
-    const int p1 = min(nparts, (g + 1) * RED_G);
-    double acc = 0.0;
-    for (int p = g * RED_G; p < p1; ++p) acc += partial[(int64_t)p * S + s];
-    red[(int64_t)g * S + s] = acc;
+    const int r1 = min(nparts, (g + 1) * RED_G);
+    const double t = block_rows_sum(partial, g * RED_G, r1, S, s, s < S);
+    if (threadIdx.x < 64 && s < S) red[(int64_t)g * S + s] = t;
 }
 
 __global__ __launch_bounds__(BLOCK) void k_reduce_final(const double *__restrict__ rows, int nrows,
@@ -332,18 +378,16 @@ __global__ __launch_bounds__(BLOCK) void k_reduce_final(const double *__restrict
         if (threadIdx.x == 0) stats[0] = sh[0];
         return;
     }
-    const int64_t s = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-    if (s < 1 || s >= S) return;
-    double acc = 0.0;
-    for (int r = 0; r < nrows; ++r) acc += rows[(int64_t)r * S + s];
-    stats[s] = acc;
+    const int64_t s = (int64_t)blockIdx.x * 64 + (threadIdx.x & 63);
+    const double t = block_rows_sum(rows, 0, nrows, S, s, s >= 1 && s < S);
+    if (threadIdx.x < 64 && s >= 1 && s < S) stats[s] = t;
 }
 
 void launch_reduce_stats(const double *partial, int nparts, int64_t S, const double *loglik,
                          const int32_t *status, int64_t nseq, double *stats, double *red,
                          hipStream_t s) {
     ProfScope ps("reduce_stats", s);
-    const unsigned sb = (unsigned)((S + BLOCK - 1) / BLOCK);
+    const unsigned sb = (unsigned)((S + 63) / 64);
     const double *rows = partial;
     int nrows = nparts;
     if (nparts > RED_G) {

@@ -96,6 +96,19 @@ def test_workspace_size_and_validation(h):
     assert st == h.HMM_ERR_UNSUPPORTED
 
 
+def test_chunk_path_workspace_covers_records(h):
+    # N <= 8 E-step: one 48-byte transfer-matrix record per lane (8 lanes per
+    # chunk of 16 steps, FP32) for every chunk and every superchunk of 16
+    # chunks, plus the two boundary vectors per chunk
+    m = fake_model(h, 8, "gamma")
+    b, offs = fake_batch(h, [4096] * 64)
+    st, n = ws_size(h, "estep", m, b, "f32")
+    assert st == h.HMM_OK
+    C = 64 * (4096 // 16)
+    SC = C // 16
+    assert n >= (C + SC) * 8 * 48 + 2 * (C + 1) * 8 * 4
+
+
 def test_calls_reject_small_workspace_on_host(h):
     m = fake_model(h, 3, "gaussian")
     b, offs = fake_batch(h, [10, 20])
