@@ -238,8 +238,9 @@ hmm_status make_plan(hmm_op op, const Checked &c, hmm_precision prec, Plan *p) {
         p->SC = (int)SC;
         if (C > INT32_MAX / 64) return fail(HMM_ERR_UNSUPPORTED, "too many chunks");
         p->C = (int)C;
-        const int gpb = (BLOCK / 64) * (64 / p->G);
-        int64_t nb = (C + gpb - 1) / gpb;
+        // statistics blocks take whole superchunks of SS chunks, one lane group per chunk
+        const int spb = (BLOCK / 64) * (64 / p->G) / p->SS;
+        int64_t nb = (SC + spb - 1) / spb;
         p->nblk = (int)(nb < 1 ? 1 : (nb > 2048 ? 2048 : nb));
         p->cbase = take((size_t)(c.B + 1) * 4);
         p->rec = take((size_t)C * p->G * chunk_rec_bytes(p->f64, p->G));   // one record per lane
@@ -249,7 +250,6 @@ hmm_status make_plan(hmm_op op, const Checked &c, hmm_precision prec, Plan *p) {
         p->red = take((size_t)reduce_scratch_len(p->nblk, p->S) * 8);
         const size_t rb = chunk_rec_bytes(p->f64, p->G);
         p->sbase = take((size_t)(c.B + 1) * 4);
-        p->cdesc = take((size_t)C * sizeof(ChunkDesc));
         p->sdesc = take((size_t)SC * sizeof(SuperDesc));
         p->srec = take((size_t)SC * p->G * rb);
         p->Fs = take((size_t)(SC + 1) * p->G * r);
@@ -343,10 +343,9 @@ hmm_status run_posterior_path(const hmm_model *m, const hmm_batch *b, const Chec
         cb.srec = ws + p.srec;
         cb.Fs = ws + p.Fs;
         cb.Gs = ws + p.Gs;
-        cb.cdesc = (ChunkDesc *)(ws + p.cdesc);
         cb.sdesc = (SuperDesc *)(ws + p.sdesc);
         launch_plan_chunks(b->offsets, c.B, p.L, p.SS, cb.cbase, cb.sbase, s);
-        launch_chunk_desc(b->offsets, c.B, p.L, p.SS, cb.cbase, cb.sbase, p.C, p.SC, cb.cdesc,
+        launch_chunk_desc(b->offsets, c.B, p.L, p.SS, cb.cbase, cb.sbase, 0, p.SC, nullptr,
                           cb.sdesc, s);
         r = run_chunked<R>(sm, od, cb, ll, st, gamma_out, stats, p.S, s);
     }

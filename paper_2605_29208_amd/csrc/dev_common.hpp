@@ -64,6 +64,15 @@ __device__ __forceinline__ void grp_gather(R x, R (&out)[G]) {
     }
 }
 
+// Orders this wave's LDS accesses around a lane exchange.  LDS instructions
+// of one wave are performed in program order, so a wavefront-scope fence
+// (which only stops the compiler from moving accesses across it) is enough
+// between the lanes' store of a vector and their broadcast reads of it, and
+// between those reads and the next store: no wait for completion.
+__device__ __forceinline__ void wave_lds_order() {
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+}
+
 // sum_k x[src_k] * c[k]
 template <int G, typename R>
 __device__ __forceinline__ R grp_dot(R x, const R (&c)[G]) {

@@ -80,7 +80,8 @@ struct __align__(16) SuperDesc {
     int lo;         // first chunk of the superchunk
     int n;          // chunks in the superchunk (<= S)
     int head;       // 1 if it is the sequence's first superchunk
-    int64_t pad;
+    int t0;         // first step of its first chunk inside the sequence
+    int T;          // steps of the owning sequence
 };
 void launch_chunk_desc(const int64_t *offsets, int64_t nseq, int L, int S, const int *cbase,
                        const int *sbase, int C, int SC, ChunkDesc *cdesc, SuperDesc *sdesc,
@@ -97,8 +98,7 @@ struct ChunkBuffers {
     int S, SC;           // chunks per superchunk, number of superchunks
     int *cbase;          // [B+1]
     int *sbase;          // [B+1]
-    ChunkDesc *cdesc;    // [C]
-    SuperDesc *sdesc;    // [SC]
+    SuperDesc *sdesc;    // [SC] (chunk c = sdesc.lo + i covers steps t0 + i L ...)
     void *srec;          // [SC*G] superchunk transfer-matrix records (one per lane)
     void *Fs;            // [SC*G] R  alpha at each superchunk end
     void *Gs;            // [SC*G] R  beta at each superchunk end

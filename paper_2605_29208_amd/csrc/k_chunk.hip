@@ -34,7 +34,8 @@ struct ChunkGeom {
     int64_t nseq;
     const int64_t *offsets;
     const int *cbase;
-    const ChunkDesc *cdesc;
+    const SuperDesc *sdesc;   // chunk i of superchunk k: index sdesc[k].lo + i
+    int SC;
     int L;
     int C;
     ObsRef obs;
@@ -134,26 +135,34 @@ __global__ __launch_bounds__(BLOCK) void k_chunk_product(ChunkGeom g, const Supe
     const int slot = threadIdx.x / G;
     const int si = slot % SPC;                        // chunk index inside its superchunk
     const int sc = blockIdx.x * SPB + slot / SPC;     // superchunk
-    int nsc = 0, c = 0;
+    int nsc = 0, c = 0, t0 = 0, len = 0;
+    int64_t off = 0;
     if (sc < SC) {
         const SuperDesc sd = sdesc[sc];
         nsc = sd.n;
         c = sd.lo + si;
+        off = sd.off;
+        t0 = sd.t0 + si * L;
+        len = min(L, sd.T - t0);
     }
     const bool valid = si < nsc;
     const int N = m.N;
-    int64_t off = 0;
     int ts = 0, nsteps = 0;
     if (valid) {
-        const ChunkDesc d = g.cdesc[c];
-        off = d.off;
-        ts = max(d.t0, 1);
-        nsteps = max(d.t0 + d.len - ts, 0);
+        ts = max(t0, 1);
+        nsteps = max(t0 + len - ts, 0);
     }
     using ET = typename EmitTraits<FAM, R>::T;
     const ET *ep = consts_ptr<FAM, R>(m);
 
     // emissions: e_t(j) = exp(log b_j(y_t) - max_j log b_j(y_t))
+    // per-state constants held across the step loop (Poisson's FP64 ones are
+    // re-read instead: held, they would raise the register count)
+    StateConsts<ET> kc[G];
+    if constexpr (FAM != HMM_POISSON) {
+#pragma unroll
+        for (int j = 0; j < G; ++j) kc[j] = load_consts(ep, j, j < N);
+    }
     double msum = 0.0;
     bool bad = false;
     for (int tt = li; tt < nsteps; tt += G) {
@@ -167,8 +176,10 @@ __global__ __launch_bounds__(BLOCK) void k_chunk_product(ChunkGeom g, const Supe
         for (int j = 0; j < G; ++j) {
             const bool live = j < N;
             R v = (FAM != HMM_TABLE) ? y : load_step<FAM, R>(g.obs, row, j, N, live);
-            StateConsts<ET> k = load_consts(ep, j, live);
-            Emit<ET> em = emit_step<FAM, ET>((ET)v, k, live);
+            StateConsts<ET> kj;
+            if constexpr (FAM == HMM_POISSON) kj = load_consts(ep, j, live);
+            else kj = kc[j];
+            Emit<ET> em = emit_step<FAM, ET>((ET)v, kj, live);
             ell[j] = em.ell;
             mx = fmax(mx, em.ell);
             bad |= em.bad;
@@ -473,8 +484,24 @@ struct StatsLds {
     static constexpr size_t tab = sizeof(R) * GPB * L * G;
     static constexpr size_t ysz = sizeof(R) * GPB * L * 2;
     static constexpr size_t red = sizeof(double) * GPB * G * NV;
-    static constexpr size_t bytes = (2 * tab + ysz) > red ? (2 * tab + ysz) : red;
+    // G = 8: each group exchanges its vector through LDS (one store, two
+    // broadcast reads) instead of seven DPP moves on the vector ALU
+    static constexpr bool XL = G == 8;
+    static constexpr size_t xsz = XL ? sizeof(R) * GPB * G : 0;
+    static constexpr size_t loop = 2 * tab + ysz + xsz;
+    static constexpr size_t bytes = loop > red ? loop : red;
 };
+
+// all G entries of the group's vector in state order (lane p stores x into
+// the group's slot xs)
+template <typename R, int G>
+__device__ __forceinline__ void lds_vec(R x, R *xs, int p, R (&out)[G]) {
+    xs[p] = x;
+    wave_lds_order();
+#pragma unroll
+    for (int j = 0; j < G; ++j) out[j] = xs[j];
+    wave_lds_order();
+}
 
 template <typename R, int G, int L, int FAM, bool WG>
 __global__ __launch_bounds__(BLOCK) void k_chunk_stats(ChunkGeom g, StagedModel<R> m,
@@ -492,6 +519,8 @@ __global__ __launch_bounds__(BLOCK) void k_chunk_stats(ChunkGeom g, StagedModel<
     R (*tab)[L][G] = reinterpret_cast<R (*)[L][G]>(lds_raw);             // e_t(j)
     R (*atab)[L][G] = reinterpret_cast<R (*)[L][G]>(lds_raw + LD::tab);  // alpha history
     R (*ysh)[L][2] = reinterpret_cast<R (*)[L][2]>(lds_raw + 2 * LD::tab);
+    constexpr bool XL = LD::XL;
+    R (*xsh)[G] = reinterpret_cast<R (*)[G]>(lds_raw + 2 * LD::tab + LD::ysz);
 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int sub = lane / G, p = lane % G, grp = wave * GPW + sub;
@@ -500,10 +529,16 @@ __global__ __launch_bounds__(BLOCK) void k_chunk_stats(ChunkGeom g, StagedModel<
     using ET = typename EmitTraits<FAM, R>::T;
     const ET *ep = consts_ptr<FAM, R>(m);
     const StateConsts<ET> k = load_consts(ep, p, live);
+    StateConsts<ET> kc[G];   // as in phase 1
+    if constexpr (FAM != HMM_POISSON) {
+#pragma unroll
+        for (int j = 0; j < G; ++j) kc[j] = load_consts(ep, j, j < N);
+    }
     R coefC[G], coefR[G];
 #pragma unroll
     for (int q = 0; q < G; ++q) {
-        int i = grp_src(p, q);
+        // state order for the LDS exchange, grp_dot order for DPP
+        int i = XL ? q : grp_src(p, q);
         coefC[q] = (live && i < N) ? m.A[i * N + p] : (R)0;
         coefR[q] = (live && i < N) ? m.A[p * N + i] : (R)0;
     }
@@ -516,20 +551,27 @@ __global__ __launch_bounds__(BLOCK) void k_chunk_stats(ChunkGeom g, StagedModel<
 #pragma unroll
     for (int q = 0; q < KK; ++q) facc[q] = 0.0;
 
-    const int per_round = gridDim.x * GPB;
-    const int nrounds = (g.C + per_round - 1) / per_round;
+    // a round takes whole superchunks, lane group si of a superchunk its
+    // chunk si (groups past a short superchunk's end idle)
+    constexpr int SPB = GPB / SPC;
+    static_assert(SPB * SPC == GPB, "a block holds whole superchunks");
+    const int si = grp % SPC;
+    const int per_round = gridDim.x * SPB;
+    const int nrounds = (g.SC + per_round - 1) / per_round;
     for (int rnd = 0; rnd < nrounds; ++rnd) {
-        const int c = (rnd * (int)gridDim.x + (int)blockIdx.x) * GPB + grp;
-        const bool valid = c < g.C;
-        int t0 = 0, len = 0;
+        const int sc = (rnd * (int)gridDim.x + (int)blockIdx.x) * SPB + grp / SPC;
+        bool valid = false;
+        int c = 0, t0 = 0, len = 0;
         int64_t off = 0;
         bool use = false;
-        if (valid) {
-            const ChunkDesc d = g.cdesc[c];
+        if (sc < g.SC) {
+            const SuperDesc d = g.sdesc[sc];
+            valid = si < d.n;
+            c = d.lo + si;
             off = d.off;
-            t0 = d.t0;
-            len = d.len;
-            use = status[d.b] == 0;
+            t0 = d.t0 + si * L;
+            len = valid ? min(L, d.T - t0) : 0;
+            use = valid && status[d.b] == 0;
         }
         const int tt0 = L - len;
         const bool first = (t0 == 0);
@@ -547,7 +589,10 @@ __global__ __launch_bounds__(BLOCK) void k_chunk_stats(ChunkGeom g, StagedModel<
                 const bool lj = j < N;
                 R v = (FAM != HMM_TABLE) ? y : (act ? load_step<FAM, R>(g.obs, row, j, N, lj) : (R)1);
                 if (j == 0) y1 = v;
-                Emit<ET> em = emit_step<FAM, ET>((ET)v, load_consts(ep, j, lj), lj);
+                StateConsts<ET> kj;
+                if constexpr (FAM == HMM_POISSON) kj = load_consts(ep, j, lj);
+                else kj = kc[j];
+                Emit<ET> em = emit_step<FAM, ET>((ET)v, kj, lj);
                 ell[j] = em.ell;
                 mx = fmax(mx, em.ell);
             }
@@ -564,14 +609,24 @@ __global__ __launch_bounds__(BLOCK) void k_chunk_stats(ChunkGeom g, StagedModel<
         const R ap = (valid && !first) ? Fi[(size_t)(c - 1) * G + p] : (R)0;
         R start;
         {
-            R v = pi_p * tab[grp][tt0][p];
+            R v = pi_p * tab[grp][tt0 < L ? tt0 : L - 1][p];   // tt0 = L: idle group
             start = fldexp(v, -fexp(grp_max_pos<G>(v)));
         }
         R acur = ap;
 #pragma unroll 4
         for (int tt = 0; tt < L; ++tt) {
             const R xin = (tt == tt0) ? ap : acur;
-            R v = tab[grp][tt][p] * grp_dot<G, R>(xin, coefC);
+            R d;
+            if constexpr (XL) {
+                R xa[G];
+                lds_vec<R, G>(xin, xsh[grp], p, xa);
+                d = xa[0] * coefC[0];
+#pragma unroll
+                for (int q = 1; q < G; ++q) d = fma(xa[q], coefC[q], d);
+            } else {
+                d = grp_dot<G, R>(xin, coefC);
+            }
+            R v = tab[grp][tt][p] * d;
             if (first && tt == tt0) v = start;
             if ((tt % nrm) == nrm - 1 || tt == L - 1) v = fldexp(v, -fexp(grp_max_pos<G>(v)));
             acur = v;
@@ -602,12 +657,13 @@ __global__ __launch_bounds__(BLOCK) void k_chunk_stats(ChunkGeom g, StagedModel<
         // w_j = e_t(j) beta_t(j) from its group once and uses it twice: for
         // beta_{t-1}(i) and for xi_t(i, j) = alpha_{t-1}(i) a_ij w_j / Z_t, where
         // Z_t = sum_i alpha_{t-1}(i) beta_{t-1}(i) also normalises gamma_{t-1}.
-#pragma unroll 4
+#pragma unroll 2
         for (int tt = L - 1; tt >= 0; --tt) {
             const bool trans = (tt > tt0) || (tt == tt0 && !first);
             R w = tab[grp][tt][p] * bcur;
-            R wg[G];
-            grp_gather<G, R>(w, wg);
+            R wg[G];   // w of the group: state order (LDS) or source order (DPP)
+            if constexpr (XL) lds_vec<R, G>(w, xsh[grp], p, wg);
+            else grp_gather<G, R>(w, wg);
             R bp = wg[0] * coefR[0];
 #pragma unroll
             for (int q = 1; q < G; ++q) bp = fma(wg[q], coefR[q], bp);
@@ -662,7 +718,7 @@ __global__ __launch_bounds__(BLOCK) void k_chunk_stats(ChunkGeom g, StagedModel<
             int q = (int)(s - 1 - N);
             int i = q / N, j = q % N;
             pp = i;
-            slot = grp_inv(i, j);
+            slot = XL ? j : grp_inv(i, j);
         } else if (s < 1 + 2 * N + (int64_t)N * N) {
             pp = (int)(s - 1 - N - (int64_t)N * N);
             slot = G + 1;
@@ -705,7 +761,8 @@ template <typename R, int G, int FAM>
 static hmm_status run_chunked_g(const StagedModel<R> &m, const ObsDesc &o, const ChunkBuffers &cb,
                                 double *loglik, int32_t *status, R *gamma_out, double *stats,
                                 int64_t S, hipStream_t s) {
-    ChunkGeom geom{o.nseq, o.offsets, cb.cbase, cb.cdesc, cb.L, cb.C, ObsRef{o.obs, o.obs_f64}};
+    ChunkGeom geom{o.nseq, o.offsets, cb.cbase, (const SuperDesc *)cb.sdesc, cb.SC, cb.L, cb.C,
+                   ObsRef{o.obs, o.obs_f64}};
     constexpr int SPB = (BLOCK / 64) * (64 / G);
     if (cb.S != SPC) return HMM_ERR_UNSUPPORTED;
     auto *rec = (ColRec<R, G> *)cb.rec;

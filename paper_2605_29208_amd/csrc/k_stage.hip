@@ -294,7 +294,8 @@ __global__ __launch_bounds__(BLOCK) void k_chunk_desc(const int64_t *offsets, in
         d.lo = cbase[b] + (i - sbase[b]) * S;
         d.n = min(S, cbase[b + 1] - d.lo);
         d.head = (i == sbase[b]) ? 1 : 0;
-        d.pad = 0;
+        d.t0 = (d.lo - cbase[b]) * L;
+        d.T = (int)(offsets[b + 1] - d.off);
         sdesc[i] = d;
     }
 }

@@ -24,12 +24,6 @@ namespace hmmk {
 
 constexpr int VK = 64;   // steps per backtrace chunk and per emission window
 
-// LDS accesses of one wave are performed in program order: a wavefront-scope
-// fence (no wait) orders the lanes' store of a vector before their reads.
-__device__ __forceinline__ void wave_lds_order() {
-    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-}
-
 __device__ __forceinline__ double wave_max_d(double v) {
     for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
     return v;

@@ -191,15 +191,6 @@ __device__ __forceinline__ R lds_dot(const R *v, const R (&c)[NP]) {
     return acc0 + acc1;
 }
 
-// Orders this wave's LDS accesses around a lane exchange.  LDS instructions of
-// one wave are performed in program order, so a wavefront-scope fence (which
-// only stops the compiler from moving accesses across it) is enough between
-// the lanes' store of a vector and their broadcast reads of it: no wait for
-// the store to complete.
-__device__ __forceinline__ void wave_lds_order() {
-    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-}
-
 // ---------------------------------------------------------------- sweeps
 // Task 2b is the forward sweep of sequence b (alpha at chunk ends, logL and
 // status), task 2b + 1 its backward sweep (beta at chunk ends).  Loops run to
