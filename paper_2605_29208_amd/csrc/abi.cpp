@@ -283,7 +283,9 @@ hmm_status run_posterior_path(const hmm_model *m, const hmm_batch *b, const Chec
                               const Plan &p, char *ws, double *loglik, int32_t *status,
                               void *gamma_out, double *stats, hipStream_t s) {
     StagedModel<R> sm;
-    launch_stage<R>(raw(m), ws + p.staged, &sm, s);
+    // the N <= 8 path counts its chunks in the staging launch
+    const PlanArgs plan{b->offsets, c.B, p.L, p.SS, (int *)(ws + p.cbase), (int *)(ws + p.sbase)};
+    launch_stage<R>(raw(m), ws + p.staged, &sm, s, (p.chunked && c.B > 0) ? &plan : nullptr);
     double *ll = loglik ? loglik : (double *)(ws + p.ll);
     int32_t *st = status ? status : (int32_t *)(ws + p.st);
     ObsDesc od{b->obs, b->obs_f64, c.B, b->offsets};
@@ -344,7 +346,6 @@ hmm_status run_posterior_path(const hmm_model *m, const hmm_batch *b, const Chec
         cb.Fs = ws + p.Fs;
         cb.Gs = ws + p.Gs;
         cb.sdesc = (SuperDesc *)(ws + p.sdesc);
-        launch_plan_chunks(b->offsets, c.B, p.L, p.SS, cb.cbase, cb.sbase, s);
         launch_chunk_desc(b->offsets, c.B, p.L, p.SS, cb.cbase, cb.sbase, 0, p.SC, nullptr,
                           cb.sdesc, s);
         r = run_chunked<R>(sm, od, cb, ll, st, gamma_out, stats, p.S, s);

@@ -61,8 +61,18 @@ struct ProfScope {
 size_t staged_bytes(int N, int D, int family, bool f64);
 
 // ----- launchers (each defined in the kernel translation unit) -----
+// Chunk counts of the N <= 8 path, formed in the staging launch: cbase and
+// sbase, [B+1] exclusive prefix counts of chunks (L steps) and superchunks
+// (S chunks)
+struct PlanArgs {
+    const int64_t *offsets;
+    int64_t nseq;
+    int L, S;
+    int *cbase, *sbase;
+};
 template <typename R>
-void launch_stage(const RawModel &m, void *region, StagedModel<R> *out, hipStream_t s);
+void launch_stage(const RawModel &m, void *region, StagedModel<R> *out, hipStream_t s,
+                  const PlanArgs *plan = nullptr);
 
 // Per-chunk and per-superchunk descriptors, written once per call so the
 // kernels find their sequence with a single load.

@@ -23,19 +23,63 @@ size_t staged_bytes(int N, int D, int family, bool f64) {
            align256(64 * r) + 256;
 }
 
+// Chunk plan in one block of BLOCK threads: cbase and sbase by inclusive
+// scans of the chunk and superchunk counts over tiles of BLOCK sequences.
+__device__ void plan_block(const PlanArgs &a) {
+    __shared__ int s_nc[BLOCK], s_ns[BLOCK];
+    const int t = threadIdx.x;
+    int carry_c = 0, carry_s = 0;
+    for (int64_t base = 0; base < a.nseq; base += BLOCK) {
+        const int64_t b = base + t;
+        int nc = 0, ns = 0;
+        if (b < a.nseq) {
+            const int64_t T = a.offsets[b + 1] - a.offsets[b];
+            nc = (int)((T + a.L - 1) / a.L);
+            ns = (nc + a.S - 1) / a.S;
+        }
+        s_nc[t] = nc;
+        s_ns[t] = ns;
+        __syncthreads();
+        for (int o = 1; o < BLOCK; o <<= 1) {   // Hillis-Steele inclusive scans
+            const int u = t >= o ? s_nc[t - o] : 0;
+            const int v = t >= o ? s_ns[t - o] : 0;
+            __syncthreads();
+            s_nc[t] += u;
+            s_ns[t] += v;
+            __syncthreads();
+        }
+        if (b < a.nseq) {
+            a.cbase[b] = carry_c + s_nc[t] - nc;
+            a.sbase[b] = carry_s + s_ns[t] - ns;
+        }
+        carry_c += s_nc[BLOCK - 1];
+        carry_s += s_ns[BLOCK - 1];
+        __syncthreads();
+    }
+    if (t == 0) {
+        a.cbase[a.nseq] = carry_c;
+        a.sbase[a.nseq] = carry_s;
+    }
+}
+
 // Block 0 computes the initial probabilities, the per-state emission
 // constants (see dev_common.hpp for their meaning), the diagonal-Gaussian
 // location and -1/(2 var) vectors, the full-Gaussian means, the parameter
 // check and the rescale interval.  Blocks 1 .. nmat fill A, A^T and log A in
 // R (block 0 does it when nmat = 0); for the full Gaussian, block
-// 1 + nmat + j forms L_j^{-1}, one thread per column.
+// 1 + nmat + j forms L_j^{-1}, one thread per column.  With a plan
+// (plan.nseq > 0) the last block forms the chunk plan.
 template <typename R>
-__global__ __launch_bounds__(BLOCK) void k_stage(RawModel m, int nmat, R *pi, R *A, R *AT, R *lpi,
-                                                 R *lA, R *ep, double *ep64, R *mv, int *perr,
-                                                 R *A8, int *nrm) {
+__global__ __launch_bounds__(BLOCK) void k_stage(RawModel m, int nmat, PlanArgs plan, R *pi, R *A,
+                                                 R *AT, R *lpi, R *lA, R *ep, double *ep64, R *mv,
+                                                 int *perr, R *A8, int *nrm) {
     const int N = m.N, D = m.D;
     const int64_t NN = (int64_t)N * N;
     const int bx = blockIdx.x;
+    if (plan.nseq > 0 && bx == (int)gridDim.x - 1) {
+        plan_block(plan);
+        return;
+    }
     if (bx > nmat) {
         // L_j^{-1} column by column: L x = e_col by forward substitution (FP64),
         // the column kept in LDS (thread col owns column col)
@@ -174,7 +218,8 @@ __global__ __launch_bounds__(BLOCK) void k_stage(RawModel m, int nmat, R *pi, R 
 }
 
 template <typename R>
-void launch_stage(const RawModel &m, void *region, StagedModel<R> *out, hipStream_t s) {
+void launch_stage(const RawModel &m, void *region, StagedModel<R> *out, hipStream_t s,
+                  const PlanArgs *plan) {
     size_t r = sizeof(R);
     size_t n = (size_t)m.N, nn = n * n;
     char *p = (char *)region;
@@ -195,8 +240,10 @@ void launch_stage(const RawModel &m, void *region, StagedModel<R> *out, hipStrea
         const int64_t nn2 = (int64_t)m.N * m.N;
         const int nmat = nn2 <= 4 * BLOCK ? 0 : (int)((nn2 + BLOCK - 1) / BLOCK < 512 ? (nn2 + BLOCK - 1) / BLOCK : 512);
         const int nfull = m.family == HMM_FULL_GAUSSIAN ? m.N : 0;
-        hipLaunchKernelGGL(k_stage<R>, dim3((unsigned)(1 + nmat + nfull)), dim3(BLOCK), 0, s, m,
-                           nmat, pi, A, AT, lpi, lA, ep, ep64, mv, perr, A8, nrm);
+        const PlanArgs pa = plan ? *plan : PlanArgs{nullptr, 0, 0, 0, nullptr, nullptr};
+        const int nplan = pa.nseq > 0 ? 1 : 0;
+        hipLaunchKernelGGL(k_stage<R>, dim3((unsigned)(1 + nmat + nfull + nplan)), dim3(BLOCK), 0,
+                           s, m, nmat, pa, pi, A, AT, lpi, lA, ep, ep64, mv, perr, A8, nrm);
     }
     out->N = m.N;
     out->D = m.D;
@@ -214,8 +261,10 @@ void launch_stage(const RawModel &m, void *region, StagedModel<R> *out, hipStrea
     out->nrm = nrm;
 }
 
-template void launch_stage<float>(const RawModel &, void *, StagedModel<float> *, hipStream_t);
-template void launch_stage<double>(const RawModel &, void *, StagedModel<double> *, hipStream_t);
+template void launch_stage<float>(const RawModel &, void *, StagedModel<float> *, hipStream_t,
+                                  const PlanArgs *);
+template void launch_stage<double>(const RawModel &, void *, StagedModel<double> *, hipStream_t,
+                                   const PlanArgs *);
 
 // cbase[b] = sum_{b' < b} ceil(T_b' / L) and sbase[b] = sum_{b' < b}
 // ceil(nchunks_b' / S); single block, exclusive scans in tiles of 1024.
