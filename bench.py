@@ -32,6 +32,8 @@ SERVING_STREAMS = 16
 os.environ.setdefault("GPU_MAX_HW_QUEUES", str(SERVING_STREAMS))
 
 PEAK_FP32_VALU_TFLOPS = 157.3   # MI355X FP32 vector, spec sheet
+PEAK_FP64_VALU_TFLOPS = 78.6    # MI355X FP64 vector
+PEAK_BF16_MFMA_TFLOPS = 2500.0  # MI355X dense bf16 / fp16 matrix
 METRIC = "E-step state-transitions/s (B*T*N^2) vs plain GPU; p50/p99 decode latency"
 
 
@@ -449,8 +451,12 @@ def main():
     roof = None
     if fl is not None:
         ach = fl / (kt[dom]["ms_avg"] / 1e3) / 1e12
-        roof = {"bound": "alu", "kernel": dom, "achieved": ach, "peak": PEAK_FP32_VALU_TFLOPS,
-                "unit": "TFLOP/s", "frac": ach / PEAK_FP32_VALU_TFLOPS,
+        # the scaled low-precision sweeps run their products on the matrix cores
+        mfma = prec in ("bf16_scaled", "f16_scaled") and dom in ("block_fwd", "block_bwd")
+        peak = (PEAK_BF16_MFMA_TFLOPS if mfma else
+                PEAK_FP64_VALU_TFLOPS if prec == "f64" else PEAK_FP32_VALU_TFLOPS)
+        roof = {"bound": "mfma" if mfma else "alu", "kernel": dom, "achieved": ach, "peak": peak,
+                "unit": "TFLOP/s", "frac": ach / peak,
                 "traffic": measured_traffic(dom, args.workload),
                 "kernel_ms_avg": kt[dom]["ms_avg"]}
     out = {

@@ -182,6 +182,60 @@ __global__ __launch_bounds__(BT) void k_blk_emit_diag(StagedModel<R> m, ObsRef o
     }
 }
 
+// Full-covariance Gaussian emissions, one lane per step: the lane keeps
+// its observation in registers and, for each state j in turn (uniform across
+// the wave), forms z = L_j^{-1} (y - mu_j) by the lower-triangular product
+// and log b_j(y) = c_j - |z|^2 / 2 (c_j = -log det L_j - D log(2 pi) / 2).
+// L_j^{-1}, mu_j and c_j are read through the scalar unit (uniform addresses,
+// no aliasing stores), so the D(D+1)/2 multiply-adds per state take their
+// matrix operand from scalar registers.  The log-densities go to the row
+// first; a second pass over the row, which stays in cache, subtracts the
+// row maximum and exponentiates.
+template <typename R, int DM>
+__global__ __launch_bounds__(64) void k_blk_emit_full(int N, int D, ObsRef o, int64_t total,
+                                                      const R *__restrict__ mu,
+                                                      const R *__restrict__ Linv,
+                                                      const R *__restrict__ ep,
+                                                      R *__restrict__ etab, double *__restrict__ mt) {
+    const int64_t row = (int64_t)blockIdx.x * 64 + threadIdx.x;
+    const bool ok = row < total;
+    R y[DM];
+    bool bad = false;
+#pragma unroll
+    for (int d = 0; d < DM; ++d) {
+        y[d] = (ok && d < D) ? load_obs<R>(o, row * D + d) : (R)0;
+        bad |= !isfinite(y[d]);
+    }
+    R *out = etab + (ok ? row : 0) * N;
+    R mx = neg_inf<R>();
+    for (int j = 0; j < N; ++j) {
+        const R *W = Linv + (size_t)j * D * D;
+        const R *mj = mu + (size_t)j * D;
+        R dv[DM];
+#pragma unroll
+        for (int d = 0; d < DM; ++d) dv[d] = d < D ? y[d] - mj[d] : (R)0;
+        R q = (R)0;
+#pragma unroll
+        for (int r = 0; r < DM; ++r) {
+            if (r < D) {
+                R acc = W[r * D] * dv[0];
+#pragma unroll
+                for (int c = 1; c <= r; ++c) acc = fma(W[r * D + c], dv[c], acc);
+                q = fma(acc, acc, q);
+            }
+        }
+        const R l = ep[j * EP_STRIDE] - (R)0.5 * q;
+        mx = fmax(mx, l);
+        if (ok) out[j] = l;
+    }
+    if (!ok) return;
+    for (int j = 0; j < N; ++j) {
+        const R l = out[j];
+        out[j] = (l == neg_inf<R>()) ? (R)0 : fexp_e(l - mx);
+    }
+    mt[row] = bad ? __builtin_nan("") : (double)mx;
+}
+
 // largest entry of a non-negative vector spread over the block (every part
 // holds the same values; the waves of part 0 publish their maxima)
 template <typename R>
@@ -959,46 +1013,92 @@ __global__ __launch_bounds__(BT) void k_blk_gstats_row(StagedModel<R> m, ObsRef 
     }
 }
 
-// Full-covariance family sums: thread (state c, slot q) with q < D the
-// shifted first moment sum gamma d_q and q >= D the packed lower entry
-// (r, k), r >= k, of sum gamma d d^T (d = y - mu_c).  Grid (slot blocks,
-// tiles of FULL_TS steps); each tile fills one partial row.
-template <typename R>
-__global__ __launch_bounds__(BT) void k_blk_gstats_full(StagedModel<R> m, ObsRef o, int64_t total,
-                                                        const R *__restrict__ gamma,
-                                                        double *__restrict__ partial, int64_t S2) {
-    const int N = m.N, D = m.D, K = D + D * (D + 1) / 2;
-    const int64_t gid = (int64_t)blockIdx.x * BT + threadIdx.x;
-    if (gid >= (int64_t)N * K) return;
-    const int c = (int)(gid / K), q = (int)(gid % K);
-    int r, k;
-    if (q < D) {
-        r = q;
-        k = -1;
-    } else {
-        // packed lower triangle row by row: slot p = r (r + 1) / 2 + k
-        const int p = q - D;
-        r = (int)((sqrt(8.0 * p + 1.0) - 1.0) * 0.5);
-        while ((r + 1) * (r + 2) / 2 <= p) ++r;
-        while (r * (r + 1) / 2 > p) --r;
-        k = p - r * (r + 1) / 2;
-    }
-    const double mr = (double)m.mv[(size_t)c * D + r];
-    const double mk = k >= 0 ? (double)m.mv[(size_t)c * D + k] : 0.0;
+// Full-covariance family sums of one state c over one tile of FULL_TS steps:
+// sum gamma, sum gamma (y - mu_c) and the lower triangle of
+// sum gamma (y - mu_c)(y - mu_c)^T.  Sub-tiles of 64 steps are staged in LDS
+// (centred observations and gamma); thread t owns 2 x 2 blocks of the lower
+// triangle (block index t, t + BT, ...), reading two rows and two columns per
+// step for four products.  Sums run in R over a sub-tile and in FP64 across
+// sub-tiles.
+template <typename R, int DM>
+__global__ __launch_bounds__(BT) void k_blk_gstats_full2(int N, int D, ObsRef o, int64_t total,
+                                                         const R *__restrict__ mu,
+                                                         const R *__restrict__ gamma,
+                                                         double *__restrict__ partial, int64_t S2) {
+    constexpr int SB = 64;                       // steps per sub-tile
+    constexpr int HB = DM / 2;                   // 2 x 2 blocks per row of blocks
+    constexpr int NB = HB * (HB + 1) / 2;        // lower-triangle blocks
+    constexpr int BPT = (NB + BT - 1) / BT;      // blocks per thread
+    __shared__ R vs[SB][DM + 1];
+    __shared__ R gs[SB];
+    const int c = blockIdx.x, tid = threadIdx.x;
+    const int K = D + D * (D + 1) / 2;
     const int64_t t0 = (int64_t)blockIdx.y * FULL_TS;
     const int64_t t1 = t0 + FULL_TS < total ? t0 + FULL_TS : total;
-    double acc = 0.0, g = 0.0;
-#pragma unroll 4
-    for (int64_t t = t0; t < t1; ++t) {
-        const double gm = (double)gamma[t * N + c];
-        const double dr = (double)load_obs<R>(o, t * D + r) - mr;
-        const double dk = k >= 0 ? (double)load_obs<R>(o, t * D + k) - mk : 1.0;
-        acc += gm * dr * dk;
-        g += gm;
+    int br[BPT], bc[BPT];
+#pragma unroll
+    for (int u = 0; u < BPT; ++u) {
+        int b = tid + u * BT, r = 0;
+        if (b >= NB) b = -1;
+        if (b >= 0) {   // block b = r (r + 1) / 2 + k of the block triangle
+            while ((r + 1) * (r + 2) / 2 <= b) ++r;
+        }
+        br[u] = b >= 0 ? r : -1;
+        bc[u] = b >= 0 ? b - r * (r + 1) / 2 : 0;
     }
-    double *row = partial + (int64_t)blockIdx.y * S2;
-    if (q == 0) row[1 + c] = g;
-    row[1 + N + (int64_t)c * K + q] = acc;
+    double S[BPT][4], F = 0.0, G = 0.0;
+#pragma unroll
+    for (int u = 0; u < BPT; ++u) S[u][0] = S[u][1] = S[u][2] = S[u][3] = 0.0;
+    for (int64_t sb = t0; sb < t1; sb += SB) {
+        const int ns = (int)(t1 - sb < SB ? t1 - sb : SB);
+        __syncthreads();
+        for (int k = tid; k < SB * DM; k += BT) {
+            const int st = k / DM, d = k % DM;
+            R v = (R)0;
+            if (st < ns && d < D) v = load_obs<R>(o, (sb + st) * D + d) - mu[(size_t)c * D + d];
+            vs[st][d] = v;
+        }
+        if (tid < SB) gs[tid] = tid < ns ? gamma[(sb + tid) * N + c] : (R)0;
+        __syncthreads();
+        R a[BPT][4], f = (R)0, g = (R)0;
+#pragma unroll
+        for (int u = 0; u < BPT; ++u) a[u][0] = a[u][1] = a[u][2] = a[u][3] = (R)0;
+        for (int st = 0; st < SB; ++st) {
+            const R gm = gs[st];
+#pragma unroll
+            for (int u = 0; u < BPT; ++u) {
+                if (br[u] >= 0) {
+                    const int r0 = 2 * br[u], c0 = 2 * bc[u];
+                    const R x0 = gm * vs[st][r0], x1 = gm * vs[st][r0 + 1];
+                    const R w0 = vs[st][c0], w1 = vs[st][c0 + 1];
+                    a[u][0] = fma(x0, w0, a[u][0]);
+                    a[u][1] = fma(x0, w1, a[u][1]);
+                    a[u][2] = fma(x1, w0, a[u][2]);
+                    a[u][3] = fma(x1, w1, a[u][3]);
+                }
+            }
+            if (tid < D) f = fma(gm, vs[st][tid], f);
+            g += gm;
+        }
+#pragma unroll
+        for (int u = 0; u < BPT; ++u)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) S[u][e] += (double)a[u][e];
+        F += (double)f;
+        G += (double)g;
+    }
+    double *row = partial + (int64_t)blockIdx.y * S2 + 1 + N + (int64_t)c * K;
+    if (tid == 0) partial[(int64_t)blockIdx.y * S2 + 1 + c] = G;
+    if (tid < D) row[tid] = F;
+#pragma unroll
+    for (int u = 0; u < BPT; ++u) {
+        if (br[u] < 0) continue;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int r = 2 * br[u] + (e >> 1), k = 2 * bc[u] + (e & 1);
+            if (r < D && k <= r) row[D + r * (r + 1) / 2 + k] = S[u][e];
+        }
+    }
 }
 
 __global__ __launch_bounds__(BT) void k_blk_zero(double *p, int64_t n) {
@@ -1171,6 +1271,18 @@ hmm_status run_block(const StagedModel<R> &m, const ObsDesc &o, const BlockBuffe
                 hipLaunchKernelGGL((k_blk_emit_diag<R, 16>), g, dim3(BT), 0, s, m, obs, total, etab, bb.mt);
             else
                 hipLaunchKernelGGL((k_blk_emit_diag<R, 64>), g, dim3(BT), 0, s, m, obs, total, etab, bb.mt);
+        } else if (m.family == HMM_FULL_GAUSSIAN && m.D <= 64) {
+            const dim3 g((unsigned)((total + 63) / 64));
+            const R *mu = m.mv, *Li = m.mv + (size_t)N * m.D;
+            if (m.D <= 16)
+                hipLaunchKernelGGL((k_blk_emit_full<R, 16>), g, dim3(64), 0, s, N, m.D, obs, total, mu,
+                                   Li, (const R *)m.ep, etab, bb.mt);
+            else if (m.D <= 32)
+                hipLaunchKernelGGL((k_blk_emit_full<R, 32>), g, dim3(64), 0, s, N, m.D, obs, total, mu,
+                                   Li, (const R *)m.ep, etab, bb.mt);
+            else
+                hipLaunchKernelGGL((k_blk_emit_full<R, 64>), g, dim3(64), 0, s, N, m.D, obs, total, mu,
+                                   Li, (const R *)m.ep, etab, bb.mt);
         } else {
             const int spb = BT / blk_nc(N);
             const int64_t nb = (total + spb - 1) / spb;
@@ -1195,9 +1307,16 @@ hmm_status run_block(const StagedModel<R> &m, const ObsDesc &o, const BlockBuffe
         ProfScope ps("block_gstats", s);
         const bool rowk = !(m.family == HMM_DIAG_GAUSSIAN && m.D > 16);
         if (m.family == HMM_FULL_GAUSSIAN) {
-            const int64_t nt = (int64_t)N * K;
-            hipLaunchKernelGGL(k_blk_gstats_full<R>, dim3((unsigned)((nt + BT - 1) / BT), (unsigned)nparts),
-                               dim3(BT), 0, s, m, obs, total, (const R *)gamma, bb.partial, S2);
+            const dim3 g((unsigned)N, (unsigned)nparts);
+            if (m.D <= 16)
+                hipLaunchKernelGGL((k_blk_gstats_full2<R, 16>), g, dim3(BT), 0, s, N, m.D, obs, total,
+                                   (const R *)m.mv, (const R *)gamma, bb.partial, S2);
+            else if (m.D <= 32)
+                hipLaunchKernelGGL((k_blk_gstats_full2<R, 32>), g, dim3(BT), 0, s, N, m.D, obs, total,
+                                   (const R *)m.mv, (const R *)gamma, bb.partial, S2);
+            else
+                hipLaunchKernelGGL((k_blk_gstats_full2<R, 64>), g, dim3(BT), 0, s, N, m.D, obs, total,
+                                   (const R *)m.mv, (const R *)gamma, bb.partial, S2);
         } else if (rowk) {
             // one thread per state; blocks take tiles in turn
             nparts = nparts < BLK_GS_BLOCKS ? nparts : BLK_GS_BLOCKS;
