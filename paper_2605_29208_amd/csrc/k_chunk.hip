@@ -215,7 +215,7 @@ __global__ __launch_bounds__(BLOCK) void k_chunk_product(ChunkGeom g, const Supe
             for (int k = 1; k < G; ++k) acc = fma(rowv[k], a[k][j], acc);
             nv[j] = acc * e[j];
         }
-        const bool rescale = ((s + 1) % nrm == 0) || (s + 1 == nsteps);
+        const bool rescale = ((s + 1) & (nrm - 1)) == 0 || (s + 1 == nsteps);   // nrm: 1, 2 or 4
         int ex = 0;
         if (rescale) {
             R mxv = nv[0];
@@ -628,7 +628,7 @@ __global__ __launch_bounds__(BLOCK) void k_chunk_stats(ChunkGeom g, StagedModel<
             }
             R v = tab[grp][tt][p] * d;
             if (first && tt == tt0) v = start;
-            if ((tt % nrm) == nrm - 1 || tt == L - 1) v = fldexp(v, -fexp(grp_max_pos<G>(v)));
+            if ((tt & (nrm - 1)) == nrm - 1 || tt == L - 1) v = fldexp(v, -fexp(grp_max_pos<G>(v)));
             acur = v;
             atab[grp][tt][p] = v;
         }
@@ -686,8 +686,12 @@ __global__ __launch_bounds__(BLOCK) void k_chunk_stats(ChunkGeom g, StagedModel<
                     if (ok) gamma_out[(off + t0 + (tt - 1 - tt0)) * N + p] = gm;
                 }
             }
-            int ex = fexp(grp_max_pos<G>(bp));
-            if (trans) bcur = fldexp(bp, -ex);
+            // rescaled every nrm steps like the forward: after a rescale, max
+            // (e o beta) >= min a_ij / 2 (the state with e = 1 holds at least
+            // min a_ij times the previous maximum), and each further step
+            // keeps at least a fraction min a_ij of it and never grows
+            if ((tt & (nrm - 1)) == 0) bp = fldexp(bp, -fexp(grp_max_pos<G>(bp)));
+            if (trans) bcur = bp;
         }
         if (use && live) {
 #pragma unroll

@@ -179,16 +179,17 @@ __device__ __forceinline__ double tab_step(const WaveGeom &g, int N, int64_t row
     return (double)mx + common;
 }
 
-// out = sum_i v_i c_i with v broadcast from LDS (two independent chains)
+// out = sum_i v_i c_i with v broadcast from LDS (four independent chains, so
+// the dependent depth of the sweep step is NP / 4 + 2)
 template <typename R, int NP>
 __device__ __forceinline__ R lds_dot(const R *v, const R (&c)[NP]) {
-    R acc0 = (R)0, acc1 = (R)0;
+    R acc[4] = {(R)0, (R)0, (R)0, (R)0};
 #pragma unroll
-    for (int i = 0; i < NP; i += 2) {
-        acc0 = fma(v[i], c[i], acc0);
-        acc1 = fma(v[i + 1], c[i + 1], acc1);
+    for (int i = 0; i < NP; i += 4) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) acc[u] = fma(v[i + u], c[i + u], acc[u]);
     }
-    return acc0 + acc1;
+    return (acc[0] + acc[1]) + (acc[2] + acc[3]);
 }
 
 // ---------------------------------------------------------------- sweeps
@@ -227,6 +228,7 @@ __global__ __launch_bounds__(64) void k_wave_sweep(WaveGeom g, StagedModel<R> m,
     for (int i = 0; i < NP; ++i)
         coef[i] = (live && i < N) ? (fwd ? m.A[i * N + j] : m.A[j * N + i]) : (R)0;
     bool bad = false;
+    const int nrm = *m.nrm;   // steps between rescalings (both directions)
     R v = (tv && live) ? (R)1 : (R)0;   // running alpha (forward) or beta (backward)
     double logS = 0.0;
     int64_t E = 0;
@@ -258,9 +260,12 @@ __global__ __launch_bounds__(64) void k_wave_sweep(WaveGeom g, StagedModel<R> m,
             const R e_nxt = (s + 1 < wn) ? esh[grp][fwd ? s + 1 : wn - 2 - s][j] : (R)0;
             wave_lds_order();
             const R nv = fwd ? ((t == 0) ? (live ? m.pi[j] * e_cur : (R)0) : e_cur * acc) : acc;
-            const int ex = fexp(grp_max_nn<NP>(nv));
+            // rescaled every nrm steps and at the window's end (the bound of the
+            // staging kernel holds for both directions)
+            const bool rs = (s & (nrm - 1)) == nrm - 1 || s == WL - 1;   // nrm: 1, 2 or 4
+            const int ex = rs ? fexp(grp_max_nn<NP>(nv)) : 0;
             if (on) {
-                v = fldexp(nv, -ex);
+                v = rs ? fldexp(nv, -ex) : nv;
                 if (fwd) E += ex;
             }
             e_cur = e_nxt;
@@ -340,6 +345,7 @@ __global__ __launch_bounds__(64) void k_wave_stats(WaveGeom g, StagedModel<R> m,
         coefR[i] = (live && i < N) ? m.A[j * N + i] : (R)0;
     }
     const R pi_j = live ? m.pi[j] : (R)0;
+    const int nrm = *m.nrm;
     double xacc[XN], gsacc = 0.0, g1acc = 0.0, facc[KK];
 #pragma unroll
     for (int k = 0; k < XN; ++k) xacc[k] = 0.0;
@@ -388,9 +394,10 @@ __global__ __launch_bounds__(64) void k_wave_stats(WaveGeom g, StagedModel<R> m,
             e_cur = (s + 1 < len) ? esh[grp][s + 1][j] : (R)0;
             wave_lds_order();
             const R nv = (first && s == 0) ? (live ? pi_j * e : (R)0) : e * acc;
-            const int ex = fexp(grp_max_nn<NP>(nv));
+            const bool rs = (s & (nrm - 1)) == nrm - 1;
+            const int ex = rs ? fexp(grp_max_nn<NP>(nv)) : 0;
             if (on) {
-                a = fldexp(nv, -ex);
+                a = rs ? fldexp(nv, -ex) : nv;
                 ash[grp][s][j] = a;
             }
         }
@@ -425,7 +432,7 @@ __global__ __launch_bounds__(64) void k_wave_stats(WaveGeom g, StagedModel<R> m,
             wave_lds_order();
             const R bp = lds_dot<R, NP>(&vsh[grp][0], coefR);
             if (on) e_cur = (s - 1 >= s_stop) ? esh[grp][s > 0 ? s - 1 : 0][j] : (R)0;
-            const int ex = fexp(grp_max_nn<NP>(bp));
+            const int ex = (s & (nrm - 1)) == 0 ? fexp(grp_max_nn<NP>(bp)) : 0;
             const R bn = fldexp(bp, -ex);
             const R xp = (s > 0) ? ash[grp][s > 0 ? s - 1 : 0][j] : ap;
             const R h = on ? xp * bn : (R)0;
