@@ -1240,11 +1240,11 @@ static void launch_blk_sweep(bool fwd, const StagedModel<R> &m, const ObsDesc &o
         case 64:
             return launch_blk_sweep_t<R, 512, 8, true, 64>(fwd, m, o, etab, bb, alpha, loglik, status, gamma, s);
         case 128:
-            return launch_blk_sweep_t<R, 512, 32, true, 128>(fwd, m, o, etab, bb, alpha, loglik, status, gamma, s);
+            return launch_blk_sweep_t<R, 1024, 16, true, 128>(fwd, m, o, etab, bb, alpha, loglik, status, gamma, s);
         case 192:
-            return launch_blk_sweep_t<R, 512, 96, true, 192>(fwd, m, o, etab, bb, alpha, loglik, status, gamma, s);
+            return launch_blk_sweep_t<R, 768, 48, true, 192>(fwd, m, o, etab, bb, alpha, loglik, status, gamma, s);
         default:
-            return launch_blk_sweep_t<R, 512, 128, true, 256>(fwd, m, o, etab, bb, alpha, loglik, status, gamma, s);
+            return launch_blk_sweep_t<R, 1024, 64, true, 256>(fwd, m, o, etab, bb, alpha, loglik, status, gamma, s);
         }
     } else {
         launch_blk_sweep_t<R, 256, 1, false, 0>(fwd, m, o, etab, bb, alpha, loglik, status, gamma, s);
