@@ -50,7 +50,7 @@ def test_block_scalar_families(h, fam, n, prec):
     assert_stats_close(stats, ref["stats"], n, fam, TOL[prec], f"{fam} N={n} {prec}")
 
 
-@pytest.mark.parametrize("n,d", [(3, 2), (20, 5), (70, 16), (256, 16)])
+@pytest.mark.parametrize("n,d", [(3, 2), (20, 5), (70, 16), (256, 16), (5, 40)])
 @pytest.mark.parametrize("prec", ["f32", "f64"])
 def test_block_diag_family(h, n, d, prec):
     w = workloads.random_workload("diag", n, d, [1, 40, 130], 820 + n + d)
@@ -61,7 +61,7 @@ def test_block_diag_family(h, n, d, prec):
     assert_stats_close(stats, ref["stats"], n, "diag", TOL[prec], f"diag N={n} D={d} {prec}", d=d)
 
 
-@pytest.mark.parametrize("n,d", [(3, 2), (8, 5), (32, 32)])
+@pytest.mark.parametrize("n,d", [(3, 2), (8, 5), (4, 17), (32, 32), (3, 40), (2, 64)])
 @pytest.mark.parametrize("prec", ["f32", "f64"])
 def test_block_full_family(h, n, d, prec):
     w = workloads.random_workload("full", n, d, [1, 40, 130], 830 + n + d)
