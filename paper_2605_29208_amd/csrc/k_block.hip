@@ -1013,6 +1013,72 @@ __global__ __launch_bounds__(BT) void k_blk_gstats_row(StagedModel<R> m, ObsRef 
     }
 }
 
+// Diagonal-Gaussian family sums (D <= DM = 16), one thread per state: blocks
+// take tiles of BLK_TS steps in turn; each sub-tile of 64 steps has its
+// observations staged in LDS (read back as broadcasts) and is summed in R,
+// the sub-tile sums are added in FP64.  One partial row per block.
+template <typename R, int DM>
+__global__ __launch_bounds__(BT) void k_blk_gstats_diag(StagedModel<R> m, ObsRef o, int64_t total,
+                                                        const R *__restrict__ gamma,
+                                                        double *__restrict__ partial, int64_t S2) {
+    constexpr int SB = 64;
+    __shared__ __align__(16) R ysh[SB][DM];
+    const int N = m.N, D = m.D, c = threadIdx.x;
+    const bool live = c < N;
+    R mu[DM];
+#pragma unroll
+    for (int d = 0; d < DM; ++d) mu[d] = (live && d < D) ? m.mv[(size_t)c * D + d] : (R)0;
+    double s1[DM], s2[DM], G = 0.0;
+#pragma unroll
+    for (int d = 0; d < DM; ++d) s1[d] = s2[d] = 0.0;
+    const int ntile = (int)((total + BLK_TS - 1) / BLK_TS);
+    for (int tile = blockIdx.x; tile < ntile; tile += gridDim.x) {
+        const int64_t t0 = (int64_t)tile * BLK_TS;
+        const int64_t t1 = t0 + BLK_TS < total ? t0 + BLK_TS : total;
+        for (int64_t sb = t0; sb < t1; sb += SB) {
+            const int ns = (int)(t1 - sb < SB ? t1 - sb : SB);
+            __syncthreads();
+            for (int k = c; k < SB * DM; k += BT) {
+                const int st = k / DM, d = k % DM;
+                ysh[st][d] = (st < ns && d < D) ? load_obs<R>(o, (sb + st) * D + d) : (R)0;
+            }
+            __syncthreads();
+            R a1[DM], a2[DM], g = (R)0;
+#pragma unroll
+            for (int d = 0; d < DM; ++d) a1[d] = a2[d] = (R)0;
+#pragma unroll 4
+            for (int st = 0; st < ns; ++st) {
+                const R g0 = live ? gamma[(sb + st) * N + c] : (R)0;
+                const R gm = g0 > (R)0 ? g0 : (R)0;
+                g += gm;
+#pragma unroll
+                for (int d = 0; d < DM; ++d) {
+                    const R dv = ysh[st][d] - mu[d];
+                    const R gd = gm * dv;
+                    a1[d] += gd;
+                    a2[d] = fma(gd, dv, a2[d]);
+                }
+            }
+#pragma unroll
+            for (int d = 0; d < DM; ++d) {
+                s1[d] += (double)a1[d];
+                s2[d] += (double)a2[d];
+            }
+            G += (double)g;
+        }
+    }
+    if (!live) return;
+    double *row = partial + (int64_t)blockIdx.x * S2;
+    row[1 + c] = G;
+    double *f = row + 1 + N + (int64_t)c * (2 * D);
+#pragma unroll
+    for (int d = 0; d < DM; ++d)
+        if (d < D) {
+            f[d] = s1[d];
+            f[D + d] = s2[d];
+        }
+}
+
 // Full-covariance family sums of one state c over one tile of FULL_TS steps:
 // sum gamma, sum gamma (y - mu_c) and the lower triangle of
 // sum gamma (y - mu_c)(y - mu_c)^T.  Sub-tiles of 64 steps are staged in LDS
@@ -1336,7 +1402,7 @@ hmm_status run_block(const StagedModel<R> &m, const ObsDesc &o, const BlockBuffe
                 hipLaunchKernelGGL((k_blk_gstats_row<R, HMM_POISSON, 1>), g, dim3(BT), 0, s, m, obs, total, gp, bb.partial, S2);
                 break;
             case HMM_DIAG_GAUSSIAN:
-                hipLaunchKernelGGL((k_blk_gstats_row<R, HMM_DIAG_GAUSSIAN, 16>), g, dim3(BT), 0, s, m, obs, total, gp, bb.partial, S2);
+                hipLaunchKernelGGL((k_blk_gstats_diag<R, 16>), g, dim3(BT), 0, s, m, obs, total, gp, bb.partial, S2);
                 break;
             default:   // table: sum gamma only
                 hipLaunchKernelGGL((k_blk_gstats_row<R, HMM_TABLE, 1>), g, dim3(BT), 0, s, m, obs, total, gp, bb.partial, S2);
