@@ -120,6 +120,8 @@ struct Plan {
     size_t logB = 0, alpha = 0, beta = 0, ps = 0;
     size_t red = 0;
     size_t etab = 0, mt = 0, balpha = 0, aexp = 0, bgam = 0, xi = 0, g1 = 0, compact = 0;
+    bool mvw = false;   // multivariate family on the wave path (log-density table)
+    size_t lt = 0, fpart = 0, red2 = 0;
     size_t total = 0;
 };
 
@@ -181,7 +183,9 @@ hmm_status make_plan(hmm_op op, const Checked &c, hmm_precision prec, Plan *p) {
     } else {
         const bool scalar = c.fam <= HMM_POISSON || c.fam == HMM_TABLE;
         p->mfma = prec == HMM_PREC_BF16_SCALED ? 1 : (prec == HMM_PREC_F16_SCALED ? 2 : 0);
-        if (!scalar || N > 64 || p->mfma) {
+        const bool mvw = !scalar && N <= 64 && !p->mfma &&
+                         (c.fam == HMM_DIAG_GAUSSIAN || c.fam == HMM_FULL_GAUSSIAN);
+        if (!mvw && (!scalar || N > 64 || p->mfma)) {
             // one workgroup per sequence, emission table, xi by GEMM
             if (N > 256)
                 return fail(HMM_ERR_UNSUPPORTED,
@@ -205,7 +209,7 @@ hmm_status make_plan(hmm_op op, const Checked &c, hmm_precision prec, Plan *p) {
             p->total = off;
             return HMM_OK;
         }
-        if (N > 8) {
+        if (N > 8 || mvw) {
             // per-sequence sweeps + one wave per chunk of WAVE_L steps
             p->wave = true;
             p->L = WAVE_L;
@@ -222,6 +226,18 @@ hmm_status make_plan(hmm_op op, const Checked &c, hmm_precision prec, Plan *p) {
             p->Gb = take((size_t)C * np * r);
             p->partial = take((size_t)p->nblk * p->S * 8);
             p->red = take((size_t)reduce_scratch_len(p->nblk, p->S) * 8);
+            if (mvw) {
+                p->mvw = true;
+                p->lt = take((size_t)c.total * N * r);
+                if (op == HMM_OP_ESTEP) {
+                    const int64_t S2 = 1 + N + (int64_t)N * family_k(c.fam, c.D);
+                    const int ntile = blk_gstats_tiles(c.total, c.fam);
+                    p->bgam = take((size_t)c.total * N * r);
+                    p->fpart = take((size_t)ntile * S2 * 8);
+                    p->compact = take((size_t)S2 * 8);
+                    p->red2 = take((size_t)reduce_scratch_len(ntile, S2) * 8);
+                }
+            }
             p->total = off;
             return HMM_OK;
         }
@@ -326,7 +342,18 @@ hmm_status run_posterior_path(const hmm_model *m, const hmm_batch *b, const Chec
         int *sbase = (int *)(ws + p.sbase);
         launch_plan_chunks(b->offsets, c.B, p.L, 1, wb.cbase, sbase, s);
         launch_chunk_desc(b->offsets, c.B, p.L, 1, wb.cbase, sbase, p.C, 0, wb.cdesc, nullptr, s);
-        r = run_wave<R>(sm, od, wb, ll, st, gamma_out, stats, p.S, s);
+        if (p.mvw) {
+            MvBuffers mb;
+            mb.total = c.total;
+            mb.lt = ws + p.lt;
+            mb.gamma = p.bgam ? (void *)(ws + p.bgam) : nullptr;
+            mb.partial = (double *)(ws + p.fpart);
+            mb.compact = (double *)(ws + p.compact);
+            mb.red = (double *)(ws + p.red2);
+            r = run_wave_mv<R>(sm, od, wb, mb, ll, st, gamma_out, stats, s);
+        } else {
+            r = run_wave<R>(sm, od, wb, ll, st, gamma_out, stats, p.S, s);
+        }
     } else {
         ChunkBuffers cb;
         cb.L = p.L;

@@ -171,6 +171,22 @@ hmm_status run_block(const StagedModel<R> &m, const ObsDesc &o, const BlockBuffe
                      double *loglik, int32_t *status, void *gamma_out, double *stats,
                      int64_t stats_len, hipStream_t s);
 
+// Multivariate families with N <= 64 on the wave path: the log-density table
+// [total x N] feeds the table-family sweeps and statistics (which also give
+// gamma), then the family sums are formed from gamma.
+struct MvBuffers {
+    int64_t total;       // sum of T
+    void *lt;            // [total * N] R  log b_j(y_t)
+    void *gamma;         // [total * N] R  posteriors (when statistics are asked for and the caller gives none)
+    double *partial;     // [blk_gstats_tiles * (1 + N + N*K)]
+    double *compact;     // [1 + N + N*K]
+    double *red;         // reduction scratch
+};
+template <typename R>
+hmm_status run_wave_mv(const StagedModel<R> &m, const ObsDesc &o, const WaveBuffers &wb,
+                       const MvBuffers &mb, double *loglik, int32_t *status, void *gamma_out,
+                       double *stats, hipStream_t s);
+
 // number of family-statistic slots per state (runtime family)
 __host__ __device__ inline int family_k_hd(int family, int D) {
     switch (family) {

@@ -119,8 +119,10 @@ __global__ __launch_bounds__(BT) void k_blk_emit(StagedModel<R> m, ObsRef o, int
 // staged in LDS; thread j (state j, constants in registers) evaluates
 // log b_j for every step of the tile into LDS; then each wave takes steps,
 // forms the per-step maximum and writes the factors (coalesced rows).
+// RAW: the rows receive log b itself (NaN for a non-finite observation) and
+// mt is not written -- the log-emission table of the wave route.
 constexpr int ES = 32;
-template <typename R, int DM>
+template <typename R, int DM, bool RAW>
 __global__ __launch_bounds__(BT) void k_blk_emit_diag(StagedModel<R> m, ObsRef o, int64_t total,
                                                       R *__restrict__ etab, double *__restrict__ mt) {
     __shared__ R ysh[ES][DM];
@@ -175,9 +177,14 @@ __global__ __launch_bounds__(BT) void k_blk_emit_diag(StagedModel<R> m, ObsRef o
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
                 const int jj = lane + 64 * k;
-                if (jj < N) etab[row * N + jj] = (l[k] == neg_inf<R>()) ? (R)0 : fexp_e(l[k] - mx);
+                if constexpr (RAW) {
+                    if (jj < N) etab[row * N + jj] = bsh[sidx] ? (R)__builtin_nan("") : l[k];
+                } else {
+                    if (jj < N) etab[row * N + jj] = (l[k] == neg_inf<R>()) ? (R)0 : fexp_e(l[k] - mx);
+                }
             }
-            if (lane == 0) mt[row] = bsh[sidx] ? __builtin_nan("") : (double)mx;
+            if constexpr (!RAW)
+                if (lane == 0) mt[row] = bsh[sidx] ? __builtin_nan("") : (double)mx;
         }
     }
 }
@@ -190,8 +197,9 @@ __global__ __launch_bounds__(BT) void k_blk_emit_diag(StagedModel<R> m, ObsRef o
 // no aliasing stores), so the D(D+1)/2 multiply-adds per state take their
 // matrix operand from scalar registers.  The log-densities go to the row
 // first; a second pass over the row, which stays in cache, subtracts the
-// row maximum and exponentiates.
-template <typename R, int DM>
+// row maximum and exponentiates (RAW: the row keeps log b, NaN for a
+// non-finite observation, and mt is not written).
+template <typename R, int DM, bool RAW>
 __global__ __launch_bounds__(64) void k_blk_emit_full(int N, int D, ObsRef o, int64_t total,
                                                       const R *__restrict__ mu,
                                                       const R *__restrict__ Linv,
@@ -229,6 +237,11 @@ __global__ __launch_bounds__(64) void k_blk_emit_full(int N, int D, ObsRef o, in
         if (ok) out[j] = l;
     }
     if (!ok) return;
+    if constexpr (RAW) {
+        if (bad)
+            for (int j = 0; j < N; ++j) out[j] = (R)__builtin_nan("");
+        return;
+    }
     for (int j = 0; j < N; ++j) {
         const R l = out[j];
         out[j] = (l == neg_inf<R>()) ? (R)0 : fexp_e(l - mx);
@@ -1317,6 +1330,95 @@ static void launch_blk_sweep(bool fwd, const StagedModel<R> &m, const ObsDesc &o
     }
 }
 
+// gamma-weighted family sums from gamma rows [total x N] into partial rows
+// [- | sum gamma (N) | family (N x K)] of S2 doubles; returns the row count
+// (at most blk_gstats_tiles(total, family))
+template <typename R>
+static int launch_family_sums(const StagedModel<R> &m, const ObsRef &obs, int64_t total,
+                              const R *gamma, double *partial, int64_t S2, hipStream_t s) {
+    const int N = m.N;
+    int nparts = blk_gstats_tiles(total, m.family);
+    const bool rowk = !(m.family == HMM_DIAG_GAUSSIAN && m.D > 16);
+    if (m.family == HMM_FULL_GAUSSIAN) {
+        const dim3 g((unsigned)N, (unsigned)nparts);
+        if (m.D <= 16)
+            hipLaunchKernelGGL((k_blk_gstats_full2<R, 16>), g, dim3(BT), 0, s, N, m.D, obs, total,
+                               (const R *)m.mv, (const R *)gamma, partial, S2);
+        else if (m.D <= 32)
+            hipLaunchKernelGGL((k_blk_gstats_full2<R, 32>), g, dim3(BT), 0, s, N, m.D, obs, total,
+                               (const R *)m.mv, (const R *)gamma, partial, S2);
+        else
+            hipLaunchKernelGGL((k_blk_gstats_full2<R, 64>), g, dim3(BT), 0, s, N, m.D, obs, total,
+                               (const R *)m.mv, (const R *)gamma, partial, S2);
+    } else if (rowk) {
+        // one thread per state; blocks take tiles in turn
+        nparts = nparts < BLK_GS_BLOCKS ? nparts : BLK_GS_BLOCKS;
+        const dim3 g((unsigned)nparts);
+        const R *gp = (const R *)gamma;
+        switch (m.family) {
+        case HMM_GAUSSIAN:
+            hipLaunchKernelGGL((k_blk_gstats_row<R, HMM_GAUSSIAN, 1>), g, dim3(BT), 0, s, m, obs, total, gp, partial, S2);
+            break;
+        case HMM_GAMMA:
+            hipLaunchKernelGGL((k_blk_gstats_row<R, HMM_GAMMA, 1>), g, dim3(BT), 0, s, m, obs, total, gp, partial, S2);
+            break;
+        case HMM_STUDENT_T:
+            hipLaunchKernelGGL((k_blk_gstats_row<R, HMM_STUDENT_T, 1>), g, dim3(BT), 0, s, m, obs, total, gp, partial, S2);
+            break;
+        case HMM_POISSON:
+            hipLaunchKernelGGL((k_blk_gstats_row<R, HMM_POISSON, 1>), g, dim3(BT), 0, s, m, obs, total, gp, partial, S2);
+            break;
+        case HMM_DIAG_GAUSSIAN:
+            hipLaunchKernelGGL((k_blk_gstats_diag<R, 16>), g, dim3(BT), 0, s, m, obs, total, gp, partial, S2);
+            break;
+        default:   // table: sum gamma only
+            hipLaunchKernelGGL((k_blk_gstats_row<R, HMM_TABLE, 1>), g, dim3(BT), 0, s, m, obs, total, gp, partial, S2);
+            break;
+        }
+    } else {
+        const int DD = m.D;
+        const int spb = BT / DD;
+        const int ncb = (N + spb - 1) / spb;
+        hipLaunchKernelGGL(k_blk_gstats<R>, dim3((unsigned)ncb, (unsigned)nparts), dim3(BT), 0, s, m,
+                           obs, total, (const R *)gamma, partial, S2);
+    }
+    return nparts;
+}
+
+// Emission rows of the block path (RAW = false: e_t and m_t) or the raw
+// log-density table of the wave route for multivariate families (RAW = true)
+template <typename R, bool RAW>
+static void launch_blk_emission(const StagedModel<R> &m, const ObsRef &obs, int64_t total, R *etab,
+                                double *mt, hipStream_t s) {
+    const int N = m.N;
+    ProfScope ps("block_emit", s);
+    if (m.family == HMM_DIAG_GAUSSIAN && m.D <= 64) {
+        const int64_t nb = (total + ES - 1) / ES;
+        const dim3 g((unsigned)(nb < 16384 ? nb : 16384));
+        if (m.D <= 16)
+            hipLaunchKernelGGL((k_blk_emit_diag<R, 16, RAW>), g, dim3(BT), 0, s, m, obs, total, etab, mt);
+        else
+            hipLaunchKernelGGL((k_blk_emit_diag<R, 64, RAW>), g, dim3(BT), 0, s, m, obs, total, etab, mt);
+    } else if (m.family == HMM_FULL_GAUSSIAN && m.D <= 64) {
+        const dim3 g((unsigned)((total + 63) / 64));
+        const R *mu = m.mv, *Li = m.mv + (size_t)N * m.D;
+        if (m.D <= 16)
+            hipLaunchKernelGGL((k_blk_emit_full<R, 16, RAW>), g, dim3(64), 0, s, N, m.D, obs, total, mu,
+                               Li, (const R *)m.ep, etab, mt);
+        else if (m.D <= 32)
+            hipLaunchKernelGGL((k_blk_emit_full<R, 32, RAW>), g, dim3(64), 0, s, N, m.D, obs, total, mu,
+                               Li, (const R *)m.ep, etab, mt);
+        else
+            hipLaunchKernelGGL((k_blk_emit_full<R, 64, RAW>), g, dim3(64), 0, s, N, m.D, obs, total, mu,
+                               Li, (const R *)m.ep, etab, mt);
+    } else if constexpr (!RAW) {
+        const int spb = BT / blk_nc(N);
+        const int64_t nb = (total + spb - 1) / spb;
+        hipLaunchKernelGGL(k_blk_emit<R>, dim3((unsigned)(nb < 8192 ? nb : 8192)), dim3(BT), 0, s, m,
+                           obs, total, etab, mt);
+    }
+}
+
 template <typename R>
 hmm_status run_block(const StagedModel<R> &m, const ObsDesc &o, const BlockBuffers &bb,
                      double *loglik, int32_t *status, void *gamma_out, double *stats, int64_t S,
@@ -1328,34 +1430,7 @@ hmm_status run_block(const StagedModel<R> &m, const ObsDesc &o, const BlockBuffe
     R *gamma = gamma_out ? (R *)gamma_out : (R *)bb.gamma;
     const ObsRef obs{o.obs, o.obs_f64};
     const int64_t total = bb.total;
-    {
-        ProfScope ps("block_emit", s);
-        if (m.family == HMM_DIAG_GAUSSIAN && m.D <= 64) {
-            const int64_t nb = (total + ES - 1) / ES;
-            const dim3 g((unsigned)(nb < 16384 ? nb : 16384));
-            if (m.D <= 16)
-                hipLaunchKernelGGL((k_blk_emit_diag<R, 16>), g, dim3(BT), 0, s, m, obs, total, etab, bb.mt);
-            else
-                hipLaunchKernelGGL((k_blk_emit_diag<R, 64>), g, dim3(BT), 0, s, m, obs, total, etab, bb.mt);
-        } else if (m.family == HMM_FULL_GAUSSIAN && m.D <= 64) {
-            const dim3 g((unsigned)((total + 63) / 64));
-            const R *mu = m.mv, *Li = m.mv + (size_t)N * m.D;
-            if (m.D <= 16)
-                hipLaunchKernelGGL((k_blk_emit_full<R, 16>), g, dim3(64), 0, s, N, m.D, obs, total, mu,
-                                   Li, (const R *)m.ep, etab, bb.mt);
-            else if (m.D <= 32)
-                hipLaunchKernelGGL((k_blk_emit_full<R, 32>), g, dim3(64), 0, s, N, m.D, obs, total, mu,
-                                   Li, (const R *)m.ep, etab, bb.mt);
-            else
-                hipLaunchKernelGGL((k_blk_emit_full<R, 64>), g, dim3(64), 0, s, N, m.D, obs, total, mu,
-                                   Li, (const R *)m.ep, etab, bb.mt);
-        } else {
-            const int spb = BT / blk_nc(N);
-            const int64_t nb = (total + spb - 1) / spb;
-            hipLaunchKernelGGL(k_blk_emit<R>, dim3((unsigned)(nb < 8192 ? nb : 8192)), dim3(BT), 0, s, m,
-                               obs, total, etab, bb.mt);
-        }
-    }
+    launch_blk_emission<R, false>(m, obs, total, etab, bb.mt, s);
     {
         ProfScope ps("block_fwd", s);
         launch_blk_sweep<R>(true, m, o, etab, bb, alpha, loglik, status, nullptr, s);
@@ -1368,53 +1443,10 @@ hmm_status run_block(const StagedModel<R> &m, const ObsDesc &o, const BlockBuffe
     if (!stats) return HMM_OK;
     const int K = family_k_hd(m.family, m.D);
     const int64_t S2 = 1 + N + (int64_t)N * K;
-    int nparts = blk_gstats_tiles(total, m.family);
+    int nparts;
     {
         ProfScope ps("block_gstats", s);
-        const bool rowk = !(m.family == HMM_DIAG_GAUSSIAN && m.D > 16);
-        if (m.family == HMM_FULL_GAUSSIAN) {
-            const dim3 g((unsigned)N, (unsigned)nparts);
-            if (m.D <= 16)
-                hipLaunchKernelGGL((k_blk_gstats_full2<R, 16>), g, dim3(BT), 0, s, N, m.D, obs, total,
-                                   (const R *)m.mv, (const R *)gamma, bb.partial, S2);
-            else if (m.D <= 32)
-                hipLaunchKernelGGL((k_blk_gstats_full2<R, 32>), g, dim3(BT), 0, s, N, m.D, obs, total,
-                                   (const R *)m.mv, (const R *)gamma, bb.partial, S2);
-            else
-                hipLaunchKernelGGL((k_blk_gstats_full2<R, 64>), g, dim3(BT), 0, s, N, m.D, obs, total,
-                                   (const R *)m.mv, (const R *)gamma, bb.partial, S2);
-        } else if (rowk) {
-            // one thread per state; blocks take tiles in turn
-            nparts = nparts < BLK_GS_BLOCKS ? nparts : BLK_GS_BLOCKS;
-            const dim3 g((unsigned)nparts);
-            const R *gp = (const R *)gamma;
-            switch (m.family) {
-            case HMM_GAUSSIAN:
-                hipLaunchKernelGGL((k_blk_gstats_row<R, HMM_GAUSSIAN, 1>), g, dim3(BT), 0, s, m, obs, total, gp, bb.partial, S2);
-                break;
-            case HMM_GAMMA:
-                hipLaunchKernelGGL((k_blk_gstats_row<R, HMM_GAMMA, 1>), g, dim3(BT), 0, s, m, obs, total, gp, bb.partial, S2);
-                break;
-            case HMM_STUDENT_T:
-                hipLaunchKernelGGL((k_blk_gstats_row<R, HMM_STUDENT_T, 1>), g, dim3(BT), 0, s, m, obs, total, gp, bb.partial, S2);
-                break;
-            case HMM_POISSON:
-                hipLaunchKernelGGL((k_blk_gstats_row<R, HMM_POISSON, 1>), g, dim3(BT), 0, s, m, obs, total, gp, bb.partial, S2);
-                break;
-            case HMM_DIAG_GAUSSIAN:
-                hipLaunchKernelGGL((k_blk_gstats_diag<R, 16>), g, dim3(BT), 0, s, m, obs, total, gp, bb.partial, S2);
-                break;
-            default:   // table: sum gamma only
-                hipLaunchKernelGGL((k_blk_gstats_row<R, HMM_TABLE, 1>), g, dim3(BT), 0, s, m, obs, total, gp, bb.partial, S2);
-                break;
-            }
-        } else {
-            const int DD = m.D;
-            const int spb = BT / DD;
-            const int ncb = (N + spb - 1) / spb;
-            hipLaunchKernelGGL(k_blk_gstats<R>, dim3((unsigned)ncb, (unsigned)nparts), dim3(BT), 0, s, m,
-                               obs, total, (const R *)gamma, bb.partial, S2);
-        }
+        nparts = launch_family_sums<R>(m, obs, total, (const R *)gamma, bb.partial, S2, s);
         hipLaunchKernelGGL(k_blk_gamma1<R>, dim3((unsigned)((N + BT - 1) / BT)), dim3(BT), 0, s, N,
                            o.nseq, o.offsets, (const int32_t *)status, (const R *)gamma, bb.g1);
     }
@@ -1437,6 +1469,43 @@ hmm_status run_block(const StagedModel<R> &m, const ObsDesc &o, const BlockBuffe
     }
     return HMM_OK;
 }
+
+template <typename R>
+hmm_status run_wave_mv(const StagedModel<R> &m, const ObsDesc &o, const WaveBuffers &wb,
+                       const MvBuffers &mb, double *loglik, int32_t *status, void *gamma_out,
+                       double *stats, hipStream_t s) {
+    if (o.nseq == 0) return HMM_OK;
+    const int N = m.N;
+    const ObsRef obs{o.obs, o.obs_f64};
+    R *lt = (R *)mb.lt;
+    launch_blk_emission<R, true>(m, obs, mb.total, lt, nullptr, s);
+    StagedModel<R> mtab = m;
+    mtab.family = HMM_TABLE;
+    const ObsDesc otab{lt, sizeof(R) == 8 ? 1 : 0, o.nseq, o.offsets};
+    R *gam = gamma_out ? (R *)gamma_out : (stats ? (R *)mb.gamma : nullptr);
+    // the table family's statistics are the prefix [logL | gamma_1 | xi | sum gamma]
+    const int64_t Sw = 1 + 2 * (int64_t)N + (int64_t)N * N;
+    hmm_status r = run_wave<R>(mtab, otab, wb, loglik, status, gam, stats, Sw, s);
+    if (r != HMM_OK || !stats) return r;
+    const int K = family_k_hd(m.family, m.D);
+    const int64_t S2 = 1 + N + (int64_t)N * K;
+    int nparts;
+    {
+        ProfScope ps("block_gstats", s);
+        nparts = launch_family_sums<R>(m, obs, mb.total, gam, mb.partial, S2, s);
+    }
+    launch_reduce_stats(mb.partial, nparts, S2, loglik, status, o.nseq, mb.compact, mb.red, s);
+    hipMemcpyAsync(stats + Sw, mb.compact + 1 + N, (size_t)N * K * sizeof(double),
+                   hipMemcpyDeviceToDevice, s);
+    return HMM_OK;
+}
+
+template hmm_status run_wave_mv<float>(const StagedModel<float> &, const ObsDesc &,
+                                       const WaveBuffers &, const MvBuffers &, double *, int32_t *,
+                                       void *, double *, hipStream_t);
+template hmm_status run_wave_mv<double>(const StagedModel<double> &, const ObsDesc &,
+                                        const WaveBuffers &, const MvBuffers &, double *, int32_t *,
+                                        void *, double *, hipStream_t);
 
 template hmm_status run_block<float>(const StagedModel<float> &, const ObsDesc &,
                                      const BlockBuffers &, double *, int32_t *, void *, double *,

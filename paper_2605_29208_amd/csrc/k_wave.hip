@@ -412,16 +412,18 @@ __global__ __launch_bounds__(64) void k_wave_stats(WaveGeom g, StagedModel<R> m,
         {
             const R h = a * be;
             const R Z = grp_all<NP, false>(h);
+            const R gmv = h * frcp(Z);
             if (own) {
-                const R gmv = h * frcp(Z);
                 if constexpr (STATS) {
                     gs += gmv;
                     if constexpr (K > 0)
                         fam_accumulate<FAM, R, KK>(gmv, ysh[grp][len - 1][0], ysh[grp][len - 1][1], kj, fa);
                     if (first && len == 1) g1 += gmv;
                 }
-                if constexpr (GAMMA) gamma_out[(d.off + d.t0 + len - 1) * N + j] = gmv;
             }
+            // gamma rows of excluded sequences are written as zeros
+            if constexpr (GAMMA)
+                if (valid && live) gamma_out[(d.off + d.t0 + len - 1) * N + j] = own ? gmv : (R)0;
         }
         const int s_stop = first ? 1 : 0;
         e_cur = (len - 1 >= s_stop) ? esh[grp][len > 0 ? len - 1 : 0][j] : (R)0;
@@ -446,16 +448,17 @@ __global__ __launch_bounds__(64) void k_wave_stats(WaveGeom g, StagedModel<R> m,
             }
             wave_lds_order();
             if (on) {
+                const R gmv = h * rz;
                 if (s > 0 && own) {
-                    const R gmv = h * rz;
                     if constexpr (STATS) {
                         gs += gmv;
                         if constexpr (K > 0)
                             fam_accumulate<FAM, R, KK>(gmv, ysh[grp][s - 1][0], ysh[grp][s - 1][1], kj, fa);
                         if (first && s == 1) g1 += gmv;
                     }
-                    if constexpr (GAMMA) gamma_out[(d.off + d.t0 + s - 1) * N + j] = gmv;
                 }
+                if constexpr (GAMMA)
+                    if (s > 0 && live) gamma_out[(d.off + d.t0 + s - 1) * N + j] = own ? gmv : (R)0;
                 be = bn;
             }
         }
@@ -523,7 +526,11 @@ static hmm_status run_wave_np(const StagedModel<R> &m, const ObsDesc &o, const W
     if (!gamma_out && !stats) return HMM_OK;
     {
         ProfScope ps("wave_stats", s);
-        if (gamma_out)
+        if (gamma_out && stats)
+            hipLaunchKernelGGL((k_wave_stats<R, NP, FAM, true, true>), dim3(wb.nblk), dim3(64), 0,
+                               s, g, m, (const R *)F, (const R *)Gb, (const int32_t *)status,
+                               wb.partial, gamma_out, S);
+        else if (gamma_out)
             hipLaunchKernelGGL((k_wave_stats<R, NP, FAM, true, false>), dim3(wb.nblk), dim3(64), 0,
                                s, g, m, (const R *)F, (const R *)Gb, (const int32_t *)status,
                                wb.partial, gamma_out, S);
