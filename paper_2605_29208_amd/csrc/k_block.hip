@@ -1035,6 +1035,7 @@ __global__ __launch_bounds__(BT) void k_blk_gstats_diag(StagedModel<R> m, ObsRef
                                                         const R *__restrict__ gamma,
                                                         double *__restrict__ partial, int64_t S2) {
     constexpr int SB = 64;
+    static_assert((SB * DM) % BT == 0, "whole staging rounds");
     __shared__ __align__(16) R ysh[SB][DM];
     const int N = m.N, D = m.D, c = threadIdx.x;
     const bool live = c < N;
@@ -1051,25 +1052,46 @@ __global__ __launch_bounds__(BT) void k_blk_gstats_diag(StagedModel<R> m, ObsRef
         for (int64_t sb = t0; sb < t1; sb += SB) {
             const int ns = (int)(t1 - sb < SB ? t1 - sb : SB);
             __syncthreads();
-            for (int k = c; k < SB * DM; k += BT) {
-                const int st = k / DM, d = k % DM;
-                ysh[st][d] = (st < ns && d < D) ? load_obs<R>(o, (sb + st) * D + d) : (R)0;
+            // staging and gamma loads at clamped indices (in bounds, no
+            // branches), so each batch of loads is in flight together
+            {
+                R yv[SB * DM / BT];
+#pragma unroll
+                for (int u = 0; u < SB * DM / BT; ++u) {
+                    const int k = c + u * BT, st = k / DM, d = k % DM;
+                    const int64_t idx = (sb + (st < ns ? st : ns - 1)) * D + (d < D ? d : D - 1);
+                    yv[u] = load_obs<R>(o, idx);
+                }
+#pragma unroll
+                for (int u = 0; u < SB * DM / BT; ++u) {
+                    const int k = c + u * BT, st = k / DM, d = k % DM;
+                    ysh[st][d] = (st < ns && d < D) ? yv[u] : (R)0;
+                }
             }
             __syncthreads();
             R a1[DM], a2[DM], g = (R)0;
 #pragma unroll
             for (int d = 0; d < DM; ++d) a1[d] = a2[d] = (R)0;
-#pragma unroll 4
-            for (int st = 0; st < ns; ++st) {
-                const R g0 = live ? gamma[(sb + st) * N + c] : (R)0;
-                const R gm = g0 > (R)0 ? g0 : (R)0;
-                g += gm;
+            const int cc = live ? c : N - 1;
+            for (int s0 = 0; s0 < SB; s0 += 8) {
+                R gr[8];
 #pragma unroll
-                for (int d = 0; d < DM; ++d) {
-                    const R dv = ysh[st][d] - mu[d];
-                    const R gd = gm * dv;
-                    a1[d] += gd;
-                    a2[d] = fma(gd, dv, a2[d]);
+                for (int u = 0; u < 8; ++u) {
+                    const int st = s0 + u < ns ? s0 + u : ns - 1;
+                    gr[u] = gamma[(sb + st) * N + cc];
+                }
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const R g0 = (live && s0 + u < ns) ? gr[u] : (R)0;
+                    const R gm = g0 > (R)0 ? g0 : (R)0;
+                    g += gm;
+#pragma unroll
+                    for (int d = 0; d < DM; ++d) {
+                        const R dv = ysh[s0 + u][d] - mu[d];
+                        const R gd = gm * dv;
+                        a1[d] += gd;
+                        a2[d] = fma(gd, dv, a2[d]);
+                    }
                 }
             }
 #pragma unroll
@@ -1330,6 +1352,77 @@ static void launch_blk_sweep(bool fwd, const StagedModel<R> &m, const ObsDesc &o
     }
 }
 
+// Full-covariance family sums in single precision for D <= 32 on the matrix
+// cores: for state c the second moment sum_t gamma_t d_t d_t^T (d = y - mu_c)
+// is the product (diag(gamma) V)^T V over the tile's centred observations V,
+// taken two steps per v_mfma_f32_32x32x2_f32 (lane l holds dimension l % 32
+// of step 2q + l / 32 as both operands, the left one scaled by gamma).  One
+// wave per (state, tile of FULL_TS steps); the FP32 accumulators are added
+// into FP64 every 64 steps.  Result element (i, j) sits in lane
+// j + 32 ((i / 4) % 2), register 4 (i / 8) + i % 4.
+typedef float floatx16_t __attribute__((ext_vector_type(16)));
+template <typename Y>
+__global__ __launch_bounds__(64) void k_blk_gstats_full_mfma(int N, int D, const Y *__restrict__ obs,
+                                                            int64_t total,
+                                                            const float *__restrict__ mu,
+                                                            const float *__restrict__ gamma,
+                                                            double *__restrict__ partial,
+                                                            int64_t S2) {
+    const int c = blockIdx.x, l = threadIdx.x, i = l & 31, k = l >> 5;
+    const int ic = i < D ? i : D - 1;
+    const int K = D + D * (D + 1) / 2;
+    const int64_t t0 = (int64_t)blockIdx.y * FULL_TS;
+    const int64_t t1 = t0 + FULL_TS < total ? t0 + FULL_TS : total;
+    const float mui = mu[(size_t)c * D + ic];
+    double S[16], F = 0.0, G = 0.0;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) S[v] = 0.0;
+    for (int64_t base = t0; base < t1; base += 64) {
+        floatx16_t acc;
+#pragma unroll
+        for (int v = 0; v < 16; ++v) acc[v] = 0.0f;
+        float f = 0.0f, g = 0.0f;
+        // batches of 8 step pairs: all loads first, at clamped indices (always
+        // in bounds, no branches), so they are in flight together
+        for (int q0 = 0; q0 < 32; q0 += 8) {
+            float gr[8], yr[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int64_t t = base + 2 * (q0 + u) + k;
+                const int64_t tc = t < t1 ? t : t1 - 1;
+                gr[u] = gamma[tc * N + c];
+                yr[u] = (float)obs[tc * D + ic];
+            }
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const bool on = base + 2 * (q0 + u) + k < t1;
+                const float gm = on ? gr[u] : 0.0f;
+                const float dv = (on && i < D) ? yr[u] - mui : 0.0f;
+                const float a = gm * dv;
+                acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a, dv, acc, 0, 0, 0);
+                f += a;
+                g += gm;
+            }
+        }
+#pragma unroll
+        for (int v = 0; v < 16; ++v) S[v] += (double)acc[v];
+        F += (double)f;
+        G += (double)g;
+    }
+    // first moments and sum gamma: add the two step parities (lanes l and l ^ 32)
+    const double Fo = __shfl_xor(F, 32, 64), Go = __shfl_xor(G, 32, 64);
+    double *row = partial + (int64_t)blockIdx.y * S2;
+    if (l == 0) row[1 + c] = G + Go;
+    double *fr = row + 1 + N + (int64_t)c * K;
+    if (k == 0 && i < D) fr[i] = F + Fo;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+        const int ii = 8 * (v / 4) + 4 * k + (v % 4), jj = i;
+        if (ii < D && jj <= ii) fr[D + ii * (ii + 1) / 2 + jj] = S[v];
+    }
+}
+
 // gamma-weighted family sums from gamma rows [total x N] into partial rows
 // [- | sum gamma (N) | family (N x K)] of S2 doubles; returns the row count
 // (at most blk_gstats_tiles(total, family))
@@ -1341,6 +1434,19 @@ static int launch_family_sums(const StagedModel<R> &m, const ObsRef &obs, int64_
     const bool rowk = !(m.family == HMM_DIAG_GAUSSIAN && m.D > 16);
     if (m.family == HMM_FULL_GAUSSIAN) {
         const dim3 g((unsigned)N, (unsigned)nparts);
+        if constexpr (sizeof(R) == 4) {
+            if (m.D <= 32) {
+                if (obs.f64)
+                    hipLaunchKernelGGL(k_blk_gstats_full_mfma<double>, g, dim3(64), 0, s, N, m.D,
+                                       (const double *)obs.p, total, (const float *)m.mv,
+                                       (const float *)gamma, partial, S2);
+                else
+                    hipLaunchKernelGGL(k_blk_gstats_full_mfma<float>, g, dim3(64), 0, s, N, m.D,
+                                       (const float *)obs.p, total, (const float *)m.mv,
+                                       (const float *)gamma, partial, S2);
+                return nparts;
+            }
+        }
         if (m.D <= 16)
             hipLaunchKernelGGL((k_blk_gstats_full2<R, 16>), g, dim3(BT), 0, s, N, m.D, obs, total,
                                (const R *)m.mv, (const R *)gamma, partial, S2);
