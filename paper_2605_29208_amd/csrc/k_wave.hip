@@ -193,22 +193,40 @@ __device__ __forceinline__ R lds_dot(const R *v, const R (&c)[NP]) {
 }
 
 // ---------------------------------------------------------------- sweeps
+// sum of x over lanes l and l ^ 32, identical bits on both
+__device__ __forceinline__ float add_halves(float x) {
+    const uint32_t u = __builtin_bit_cast(uint32_t, x);
+    auto r = __builtin_amdgcn_permlane32_swap(u, u, false, false);
+    return __builtin_bit_cast(float, (uint32_t)r[0]) + __builtin_bit_cast(float, (uint32_t)r[1]);
+}
+__device__ __forceinline__ double add_halves(double x) {
+    double a, b;
+    swap_pair<32>(x, &a, &b);
+    return a + b;
+}
+
 // Task 2b is the forward sweep of sequence b (alpha at chunk ends, logL and
 // status), task 2b + 1 its backward sweep (beta at chunk ends).  Loops run to
 // the wave's largest trip count with per-group predicates, so every barrier
-// and cross-lane operation is reached by the whole wave.
-template <typename R, int NP, int FAM>
+// and cross-lane operation is reached by the whole wave.  SPL = 2 gives a
+// task two lanes per state (NP = 32, one task per wave): half h of the lanes
+// takes rows h NP/2 .. of the vector-matrix product and the halves are added
+// across the wave, which halves the dependent chain of the step.
+template <typename R, int NP, int FAM, int SPL>
 __global__ __launch_bounds__(64) void k_wave_sweep(WaveGeom g, StagedModel<R> m, R *__restrict__ F,
                                                    R *__restrict__ Gb, double *__restrict__ loglik,
                                                    int32_t *__restrict__ status) {
-    constexpr int NG = 64 / NP;
+    static_assert(SPL == 1 || (SPL == 2 && NP == 32), "two lanes per state for 32 states");
+    constexpr int LPT = NP * SPL;   // lanes per task
+    constexpr int NG = 64 / LPT;    // tasks per wave
+    constexpr int RPL = NP / SPL;   // rows of the product per lane
     constexpr int VS = NP + 4;
     __shared__ R esh[NG][WL][NP + 1];
     __shared__ __align__(16) R vsh[NG][VS];
     using ET = typename EmitTraits<FAM, R>::T;
     const ET *ep = consts_ptr<FAM, R>(m);
     const int lane = threadIdx.x;
-    const int grp = lane / NP, j = lane % NP;
+    const int grp = lane / LPT, sl = lane % LPT, j = sl % NP, h = sl / NP;
     const int64_t task = (int64_t)blockIdx.x * NG + grp;
     const bool tv = task < 2 * g.nseq;
     const int64_t b = tv ? (task >> 1) : 0;
@@ -223,16 +241,18 @@ __global__ __launch_bounds__(64) void k_wave_sweep(WaveGeom g, StagedModel<R> m,
     // the end of chunk c - 1)
     const int nk = fwd ? nc : (nc > 0 ? nc - 1 : 0);
     const int nkmax = wave_max_i(nk);
-    R coef[NP];
+    R coef[RPL];
 #pragma unroll
-    for (int i = 0; i < NP; ++i)
-        coef[i] = (live && i < N) ? (fwd ? m.A[i * N + j] : m.A[j * N + i]) : (R)0;
+    for (int r = 0; r < RPL; ++r) {
+        const int i = h * RPL + r;
+        coef[r] = (live && i < N) ? (fwd ? m.A[i * N + j] : m.A[j * N + i]) : (R)0;
+    }
     bool bad = false;
     const int nrm = *m.nrm;   // steps between rescalings (both directions)
     R v = (tv && live) ? (R)1 : (R)0;   // running alpha (forward) or beta (backward)
     double logS = 0.0;
     int64_t E = 0;
-    if (tv && !fwd) Gb[(size_t)(cb + nc - 1) * NP + j] = v;
+    if (tv && !fwd && h == 0) Gb[(size_t)(cb + nc - 1) * NP + j] = v;
 
     for (int k = 0; k < nkmax; ++k) {
         const bool act = k < nk;
@@ -241,11 +261,11 @@ __global__ __launch_bounds__(64) void k_wave_sweep(WaveGeom g, StagedModel<R> m,
         const int wn = act ? min(WL, T - w0) : 0;
         __syncthreads();
         double msum = 0.0;   // this lane's share of the window's log shifts
-        for (int q = j; q < wn; q += NP) {
+        for (int q = sl; q < wn; q += LPT) {
             R y, ly;
             msum += tab_step<R, NP, FAM>(g, N, off + w0 + q, ep, &esh[grp][q][0], &y, &ly, &bad);
         }
-        const double wsum = grp_all<NP, false>(msum);
+        const double wsum = grp_all<LPT, false>(msum);
         if (fwd) logS += wsum;
         __syncthreads();
         // step s of the window is local step s (forward) or wn - 1 - s (backward);
@@ -254,32 +274,33 @@ __global__ __launch_bounds__(64) void k_wave_sweep(WaveGeom g, StagedModel<R> m,
         for (int s = 0; s < WL; ++s) {
             const bool on = s < wn;
             const int t = w0 + (fwd ? s : wn - 1 - s);
-            vsh[grp][j] = fwd ? v : e_cur * v;
+            if (h == 0) vsh[grp][j] = fwd ? v : e_cur * v;
             wave_lds_order();
-            const R acc = lds_dot<R, NP>(&vsh[grp][0], coef);
+            R acc = lds_dot<R, RPL>(&vsh[grp][h * RPL], coef);
+            if constexpr (SPL == 2) acc = add_halves(acc);
             const R e_nxt = (s + 1 < wn) ? esh[grp][fwd ? s + 1 : wn - 2 - s][j] : (R)0;
             wave_lds_order();
             const R nv = fwd ? ((t == 0) ? (live ? m.pi[j] * e_cur : (R)0) : e_cur * acc) : acc;
             // rescaled every nrm steps and at the window's end (the bound of the
             // staging kernel holds for both directions)
             const bool rs = (s & (nrm - 1)) == nrm - 1 || s == WL - 1;   // nrm: 1, 2 or 4
-            const int ex = rs ? fexp(grp_max_nn<NP>(nv)) : 0;
+            const int ex = rs ? fexp(grp_max_nn<LPT>(nv)) : 0;
             if (on) {
                 v = rs ? fldexp(nv, -ex) : nv;
                 if (fwd) E += ex;
             }
             e_cur = e_nxt;
         }
-        if (act) {
+        if (act && h == 0) {
             if (fwd) F[(size_t)(cb + c) * NP + j] = v;
             else Gb[(size_t)(cb + c - 1) * NP + j] = v;
         }
     }
-    const R tot = grp_all<NP, false>(fwd ? v : (R)0);
+    const R tot = grp_all<LPT, false>((fwd && h == 0) ? v : (R)0);
     const uint64_t bal = __ballot(bad);
-    const uint64_t gmask = (NP == 64) ? ~0ull : (((1ull << (NP & 63)) - 1) << (grp * NP));
+    const uint64_t gmask = (LPT == 64) ? ~0ull : (((1ull << (LPT & 63)) - 1) << (grp * LPT));
     const bool anybad = (bal & gmask) != 0;
-    if (tv && fwd && j == 0) {
+    if (tv && fwd && sl == 0) {
         double ll;
         int st;
         if (*m.perr) {
@@ -514,14 +535,16 @@ template <typename R, int NP, int FAM>
 static hmm_status run_wave_np(const StagedModel<R> &m, const ObsDesc &o, const WaveBuffers &wb,
                               double *loglik, int32_t *status, R *gamma_out, double *stats,
                               int64_t S, hipStream_t s) {
-    constexpr int NG = 64 / NP;
+    // sweeps: two lanes per state for 32 states (one task per wave)
+    constexpr int SPL = NP == 32 ? 2 : 1;
+    constexpr int NG = 64 / (NP * SPL);
     WaveGeom g{o.nseq, o.offsets, wb.cbase, wb.cdesc, wb.C, ObsRef{o.obs, o.obs_f64}};
     R *F = (R *)wb.F, *Gb = (R *)wb.Gb;
     {
         ProfScope ps("wave_sweep", s);
         const unsigned nb = (unsigned)((2 * o.nseq + NG - 1) / NG);
-        hipLaunchKernelGGL((k_wave_sweep<R, NP, FAM>), dim3(nb), dim3(64), 0, s, g, m, F, Gb, loglik,
-                           status);
+        hipLaunchKernelGGL((k_wave_sweep<R, NP, FAM, SPL>), dim3(nb), dim3(64), 0, s, g, m, F, Gb,
+                           loglik, status);
     }
     if (!gamma_out && !stats) return HMM_OK;
     {
