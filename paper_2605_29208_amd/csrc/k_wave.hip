@@ -230,12 +230,18 @@ __global__ __launch_bounds__(64) void k_wave_sweep(WaveGeom g, StagedModel<R> m,
     const int64_t task = (int64_t)blockIdx.x * NG + grp;
     const bool tv = task < 2 * g.nseq;
     const int64_t b = tv ? (task >> 1) : 0;
-    const bool fwd = (task & 1) == 0;
+    // one task per wave: the direction is uniform, so its branches are scalar
+    const bool fwd = NG == 1 ? __builtin_amdgcn_readfirstlane((int)((task & 1) == 0)) != 0
+                             : (task & 1) == 0;
     const int N = m.N;
     const bool live = j < N;
     const int64_t off = g.offsets[b];
-    const int T = tv ? (int)(g.offsets[b + 1] - off) : 0;
-    const int cb = g.cbase[b];
+    int T = tv ? (int)(g.offsets[b + 1] - off) : 0;
+    int cb = g.cbase[b];
+    if constexpr (NG == 1) {   // uniform per wave: keep the loop control scalar
+        T = __builtin_amdgcn_readfirstlane(T);
+        cb = __builtin_amdgcn_readfirstlane(cb);
+    }
     const int nc = (T + WL - 1) / WL;
     // windows: forward 0 .. nc-1; backward nc-1 .. 1 (window c yields beta at
     // the end of chunk c - 1)
@@ -271,6 +277,37 @@ __global__ __launch_bounds__(64) void k_wave_sweep(WaveGeom g, StagedModel<R> m,
         // step s of the window is local step s (forward) or wn - 1 - s (backward);
         // the next step's emission factor is read one step ahead
         R e_cur = (wn > 0) ? esh[grp][fwd ? 0 : wn - 1][j] : (R)0;
+        if constexpr (NG == 1) {
+            // one task per wave: wn, the direction and the step are uniform, so
+            // the loop runs exactly the window's steps with scalar control
+            int s = 0;
+            if (fwd && w0 == 0 && wn > 0) {   // t = 0: alpha_0 = pi o e_0
+                const R nv = live ? m.pi[j] * e_cur : (R)0;
+                const int ex = fexp(grp_max_nn<LPT>(nv));
+                v = fldexp(nv, -ex);
+                E += ex;
+                e_cur = esh[grp][wn > 1 ? 1 : 0][j];
+                s = 1;
+            }
+            for (; s < wn; ++s) {
+                vsh[grp][j] = fwd ? v : e_cur * v;   // both halves store the same value
+                wave_lds_order();
+                R acc = lds_dot<R, RPL>(&vsh[grp][h * RPL], coef);
+                if constexpr (SPL == 2) acc = add_halves(acc);
+                const int sn = s + 1 < wn ? s + 1 : s;
+                const R e_nxt = esh[grp][fwd ? sn : wn - 1 - sn][j];
+                wave_lds_order();
+                const R nv = fwd ? e_cur * acc : acc;
+                if ((s & (nrm - 1)) == nrm - 1 || s == wn - 1) {
+                    const int ex = fexp(grp_max_nn<LPT>(nv));
+                    v = fldexp(nv, -ex);
+                    if (fwd) E += ex;
+                } else {
+                    v = nv;
+                }
+                e_cur = e_nxt;
+            }
+        } else
         for (int s = 0; s < WL; ++s) {
             const bool on = s < wn;
             const int t = w0 + (fwd ? s : wn - 1 - s);
