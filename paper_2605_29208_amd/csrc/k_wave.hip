@@ -204,6 +204,18 @@ __device__ __forceinline__ double add_halves(double x) {
     swap_pair<32>(x, &a, &b);
     return a + b;
 }
+// sum of x over lanes l, l ^ 16, l ^ 32, l ^ 48, identical bits on all four
+__device__ __forceinline__ float add_quarters(float x) {
+    const uint32_t u = __builtin_bit_cast(uint32_t, x);
+    auto r = __builtin_amdgcn_permlane16_swap(u, u, false, false);
+    return add_halves(__builtin_bit_cast(float, (uint32_t)r[0]) +
+                      __builtin_bit_cast(float, (uint32_t)r[1]));
+}
+__device__ __forceinline__ double add_quarters(double x) {
+    double a, b;
+    swap_pair<16>(x, &a, &b);
+    return add_halves(a + b);
+}
 
 // Task 2b is the forward sweep of sequence b (alpha at chunk ends, logL and
 // status), task 2b + 1 its backward sweep (beta at chunk ends).  Loops run to
@@ -211,12 +223,13 @@ __device__ __forceinline__ double add_halves(double x) {
 // and cross-lane operation is reached by the whole wave.  SPL = 2 gives a
 // task two lanes per state (NP = 32, one task per wave): half h of the lanes
 // takes rows h NP/2 .. of the vector-matrix product and the halves are added
-// across the wave, which halves the dependent chain of the step.
+// across the wave, which halves the dependent chain of the step; SPL = 4
+// does the same with four lanes per state for NP = 16.
 template <typename R, int NP, int FAM, int SPL>
 __global__ __launch_bounds__(64) void k_wave_sweep(WaveGeom g, StagedModel<R> m, R *__restrict__ F,
                                                    R *__restrict__ Gb, double *__restrict__ loglik,
                                                    int32_t *__restrict__ status) {
-    static_assert(SPL == 1 || (SPL == 2 && NP == 32), "two lanes per state for 32 states");
+    static_assert(SPL == 1 || NP * SPL == 64, "split tasks fill the wave");
     constexpr int LPT = NP * SPL;   // lanes per task
     constexpr int NG = 64 / LPT;    // tasks per wave
     constexpr int RPL = NP / SPL;   // rows of the product per lane
@@ -294,6 +307,7 @@ __global__ __launch_bounds__(64) void k_wave_sweep(WaveGeom g, StagedModel<R> m,
                 wave_lds_order();
                 R acc = lds_dot<R, RPL>(&vsh[grp][h * RPL], coef);
                 if constexpr (SPL == 2) acc = add_halves(acc);
+                if constexpr (SPL == 4) acc = add_quarters(acc);
                 const int sn = s + 1 < wn ? s + 1 : s;
                 const R e_nxt = esh[grp][fwd ? sn : wn - 1 - sn][j];
                 wave_lds_order();
@@ -315,6 +329,7 @@ __global__ __launch_bounds__(64) void k_wave_sweep(WaveGeom g, StagedModel<R> m,
             wave_lds_order();
             R acc = lds_dot<R, RPL>(&vsh[grp][h * RPL], coef);
             if constexpr (SPL == 2) acc = add_halves(acc);
+            if constexpr (SPL == 4) acc = add_quarters(acc);
             const R e_nxt = (s + 1 < wn) ? esh[grp][fwd ? s + 1 : wn - 2 - s][j] : (R)0;
             wave_lds_order();
             const R nv = fwd ? ((t == 0) ? (live ? m.pi[j] * e_cur : (R)0) : e_cur * acc) : acc;
@@ -572,8 +587,8 @@ template <typename R, int NP, int FAM>
 static hmm_status run_wave_np(const StagedModel<R> &m, const ObsDesc &o, const WaveBuffers &wb,
                               double *loglik, int32_t *status, R *gamma_out, double *stats,
                               int64_t S, hipStream_t s) {
-    // sweeps: two lanes per state for 32 states (one task per wave)
-    constexpr int SPL = NP == 32 ? 2 : 1;
+    // sweeps: one task per wave (two lanes per state for 32 states, four for 16)
+    constexpr int SPL = 64 / NP;
     constexpr int NG = 64 / (NP * SPL);
     WaveGeom g{o.nseq, o.offsets, wb.cbase, wb.cdesc, wb.C, ObsRef{o.obs, o.obs_f64}};
     R *F = (R *)wb.F, *Gb = (R *)wb.Gb;
