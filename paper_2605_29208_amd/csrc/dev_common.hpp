@@ -17,7 +17,8 @@ enum : int {
     DPP_QP_X1 = 0xB1,          // quad_perm [1,0,3,2]: lane ^ 1 inside each quad
     DPP_QP_X2 = 0x4E,          // quad_perm [2,3,0,1]: lane ^ 2
     DPP_QP_X3 = 0x1B,          // quad_perm [3,2,1,0]: lane ^ 3
-    DPP_HALF_MIRROR = 0x141    // row_half_mirror: lane p <-> 7 - p inside each 8 lanes
+    DPP_HALF_MIRROR = 0x141,   // row_half_mirror: lane p <-> 7 - p inside each 8 lanes
+    DPP_ROW_MIRROR = 0x140     // row_mirror: lane p <-> 15 - p inside each row of 16
 };
 
 template <int CTRL>
@@ -62,6 +63,44 @@ __device__ __forceinline__ void grp_gather(R x, R (&out)[G]) {
         out[6] = dpp_v<DPP_QP_X2>(m);
         out[7] = dpp_v<DPP_QP_X3>(m);
     }
+}
+
+// wave-wide all-reductions through DPP row operations and the permlane
+// swaps (every lane receives the result, identical in all lanes)
+template <typename V, typename Op>
+__device__ __forceinline__ V wave_all(V v, Op op) {
+    v = op(v, dpp_v<DPP_QP_X1>(v));
+    v = op(v, dpp_v<DPP_QP_X2>(v));
+    v = op(v, dpp_v<DPP_HALF_MIRROR>(v));
+    v = op(v, dpp_v<DPP_ROW_MIRROR>(v));
+    if constexpr (sizeof(V) == 4) {
+        const uint32_t u = __builtin_bit_cast(uint32_t, v);
+        auto r16 = __builtin_amdgcn_permlane16_swap(u, u, false, false);
+        v = op(__builtin_bit_cast(V, (uint32_t)r16[0]), __builtin_bit_cast(V, (uint32_t)r16[1]));
+        const uint32_t w = __builtin_bit_cast(uint32_t, v);
+        auto r32 = __builtin_amdgcn_permlane32_swap(w, w, false, false);
+        v = op(__builtin_bit_cast(V, (uint32_t)r32[0]), __builtin_bit_cast(V, (uint32_t)r32[1]));
+    } else {
+        uint64_t u = __builtin_bit_cast(uint64_t, v);
+        auto lo = __builtin_amdgcn_permlane16_swap((uint32_t)u, (uint32_t)u, false, false);
+        auto hi = __builtin_amdgcn_permlane16_swap((uint32_t)(u >> 32), (uint32_t)(u >> 32), false, false);
+        v = op(__builtin_bit_cast(V, ((uint64_t)(uint32_t)hi[0] << 32) | (uint32_t)lo[0]),
+               __builtin_bit_cast(V, ((uint64_t)(uint32_t)hi[1] << 32) | (uint32_t)lo[1]));
+        u = __builtin_bit_cast(uint64_t, v);
+        auto lo2 = __builtin_amdgcn_permlane32_swap((uint32_t)u, (uint32_t)u, false, false);
+        auto hi2 = __builtin_amdgcn_permlane32_swap((uint32_t)(u >> 32), (uint32_t)(u >> 32), false, false);
+        v = op(__builtin_bit_cast(V, ((uint64_t)(uint32_t)hi2[0] << 32) | (uint32_t)lo2[0]),
+               __builtin_bit_cast(V, ((uint64_t)(uint32_t)hi2[1] << 32) | (uint32_t)lo2[1]));
+    }
+    return v;
+}
+template <typename R>
+__device__ __forceinline__ R wave_sum_r(R v) {
+    return wave_all(v, [](R a, R b) { return a + b; });
+}
+template <typename R>
+__device__ __forceinline__ R wave_max_r(R v) {
+    return wave_all(v, [](R a, R b) { return fmax(a, b); });
 }
 
 // Orders this wave's LDS accesses around a lane exchange.  LDS instructions

@@ -34,47 +34,8 @@ namespace hmmk {
 constexpr int BT = 256;   // threads of the sweep and emission blocks
 constexpr int PF = 8;     // steps of sweep inputs loaded ahead
 
-enum : int { DPP_ROW_MIRROR_B = 0x140 };   // lane p <-> 15 - p inside each row of 16
-
-// wave-wide all-reductions through DPP row operations and the permlane
-// swaps (every lane receives the result, identical in all lanes)
-template <typename V, typename Op>
-__device__ __forceinline__ V wave_all(V v, Op op) {
-    v = op(v, dpp_v<DPP_QP_X1>(v));
-    v = op(v, dpp_v<DPP_QP_X2>(v));
-    v = op(v, dpp_v<DPP_HALF_MIRROR>(v));
-    v = op(v, dpp_v<DPP_ROW_MIRROR_B>(v));
-    if constexpr (sizeof(V) == 4) {
-        const uint32_t u = __builtin_bit_cast(uint32_t, v);
-        auto r16 = __builtin_amdgcn_permlane16_swap(u, u, false, false);
-        v = op(__builtin_bit_cast(V, (uint32_t)r16[0]), __builtin_bit_cast(V, (uint32_t)r16[1]));
-        const uint32_t w = __builtin_bit_cast(uint32_t, v);
-        auto r32 = __builtin_amdgcn_permlane32_swap(w, w, false, false);
-        v = op(__builtin_bit_cast(V, (uint32_t)r32[0]), __builtin_bit_cast(V, (uint32_t)r32[1]));
-    } else {
-        uint64_t u = __builtin_bit_cast(uint64_t, v);
-        auto lo = __builtin_amdgcn_permlane16_swap((uint32_t)u, (uint32_t)u, false, false);
-        auto hi = __builtin_amdgcn_permlane16_swap((uint32_t)(u >> 32), (uint32_t)(u >> 32), false, false);
-        v = op(__builtin_bit_cast(V, ((uint64_t)(uint32_t)hi[0] << 32) | (uint32_t)lo[0]),
-               __builtin_bit_cast(V, ((uint64_t)(uint32_t)hi[1] << 32) | (uint32_t)lo[1]));
-        u = __builtin_bit_cast(uint64_t, v);
-        auto lo2 = __builtin_amdgcn_permlane32_swap((uint32_t)u, (uint32_t)u, false, false);
-        auto hi2 = __builtin_amdgcn_permlane32_swap((uint32_t)(u >> 32), (uint32_t)(u >> 32), false, false);
-        v = op(__builtin_bit_cast(V, ((uint64_t)(uint32_t)hi2[0] << 32) | (uint32_t)lo2[0]),
-               __builtin_bit_cast(V, ((uint64_t)(uint32_t)hi2[1] << 32) | (uint32_t)lo2[1]));
-    }
-    return v;
-}
 __device__ __forceinline__ double wave_max_dbl(double v) {
-    return wave_all(v, [](double a, double b) { return fmax(a, b); });
-}
-template <typename R>
-__device__ __forceinline__ R wave_sum_r(R v) {
-    return wave_all(v, [](R a, R b) { return a + b; });
-}
-template <typename R>
-__device__ __forceinline__ R wave_max_r(R v) {
-    return wave_all(v, [](R a, R b) { return fmax(a, b); });
+    return wave_all(v, [](double x, double y) { return fmax(x, y); });
 }
 
 __host__ __device__ inline int blk_nc(int N) { return ((N + 63) / 64) * 64; }

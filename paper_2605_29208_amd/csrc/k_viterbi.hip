@@ -24,15 +24,6 @@ namespace hmmk {
 
 constexpr int VK = 64;   // steps per backtrace chunk and per emission window
 
-__device__ __forceinline__ double wave_max_d(double v) {
-    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-    return v;
-}
-__device__ __forceinline__ float wave_max_d(float v) {
-    for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
-    return v;
-}
-
 // log b_j(y) of the NMAX states of one step, computed by one lane into its
 // LDS row (without the state-independent part, which is returned in FP64).
 // FAM < 0 evaluates any family through emission_any.
@@ -129,7 +120,7 @@ __global__ __launch_bounds__(64) void k_vit_forward(StagedModel<R> m, ObsRef o, 
                 nd = live ? (R)(best + lt) : ninf;
                 if (live) psi[(off + t) * N + j] = (uint8_t)arg;
             }
-            const R mt = wave_max_d(nd);
+            const R mt = wave_max_r(nd);
             if (mt == ninf) dead = true;
             offset += (double)mt + csh[s];
             d = (mt == ninf) ? ninf : nd - mt;

@@ -24,7 +24,6 @@ namespace hmmk {
 
 constexpr int WL = WAVE_L;   // chunk length = tabulation window
 
-enum : int { DPP_ROW_MIRROR = 0x140 };   // lane p <-> 15 - p inside each row of 16
 
 // ---- group all-reductions (every lane of the group receives the result;
 // each level combines the same two values in every lane, so all lanes hold
