@@ -3,8 +3,11 @@
 Default workload (--workload batched): 1024 sequences with lengths uniform in
 {500..5000}, N = 8 Gamma states (shape U[1,10], scale U[0.5,3]), sticky A
 (a_ii = 0.95).  --workload heavy: 512 sequences with log-normal lengths
-(median 3000, sigma 0.6, at most 20,000), N = 32 Student-t states.  FP32
-observations resident in device memory.  One step = one full E-step
+(median 3000, sigma 0.6, at most 20,000), N = 32 Student-t states.
+--workload large: 256 sequences of 2048 steps, N = 256 diagonal Gaussian
+states in D = 16.  --workload full: the heavy workload's lengths with N = 32
+full-covariance Gaussian states in D = 32.  FP32 observations resident in
+device memory.  One step = one full E-step
 (parameter staging, emission log-densities, forward and backward
 recursions, posteriors and the pooled sufficient statistics).
 
@@ -83,6 +86,8 @@ WORKLOADS = {
               "N=32 Student-t, FP32 obs", lambda workloads: workloads.config4b()),
     "large": ("large-state E-step: B=256, T=2048, N=256 diagonal Gaussian D=16, FP32 obs",
               lambda workloads: workloads.config3()),
+    "full": ("full-covariance E-step: B=512, T~lognormal(median 3000, sigma 0.6, <=20000), "
+             "N=32 full-covariance Gaussian D=32, FP32 obs", lambda workloads: workloads.config4a()),
 }
 
 
