@@ -160,12 +160,14 @@ __global__ __launch_bounds__(BT) void k_blk_emit_diag(StagedModel<R> m, ObsRef o
 // first; a second pass over the row, which stays in cache, subtracts the
 // row maximum and exponentiates (RAW: the row keeps log b, NaN for a
 // non-finite observation, and mt is not written).
-template <typename R, int DM, bool RAW>
-__global__ __launch_bounds__(64) void k_blk_emit_full(int N, int D, ObsRef o, int64_t total,
+template <typename R, int DM, bool RAW, bool EXACT>
+__global__ __launch_bounds__(64) void k_blk_emit_full(int N, int D_, ObsRef o, int64_t total,
                                                       const R *__restrict__ mu,
                                                       const R *__restrict__ Linv,
                                                       const R *__restrict__ ep,
                                                       R *__restrict__ etab, double *__restrict__ mt) {
+    // EXACT: D == DM at compile time (contiguous, batched scalar loads)
+    const int D = EXACT ? DM : D_;
     const int64_t row = (int64_t)blockIdx.x * 64 + threadIdx.x;
     const bool ok = row < total;
     R y[DM];
@@ -180,18 +182,22 @@ __global__ __launch_bounds__(64) void k_blk_emit_full(int N, int D, ObsRef o, in
     for (int j = 0; j < N; ++j) {
         const R *W = Linv + (size_t)j * D * D;
         const R *mj = mu + (size_t)j * D;
+        // scalar loads at clamped indices (unconditional, so they are batched);
+        // entries past D meet dv = 0 or are left out of q
         R dv[DM];
 #pragma unroll
-        for (int d = 0; d < DM; ++d) dv[d] = d < D ? y[d] - mj[d] : (R)0;
+        for (int d = 0; d < DM; ++d) {
+            const R mjd = mj[EXACT ? d : (d < D ? d : D - 1)];
+            dv[d] = d < D ? y[d] - mjd : (R)0;
+        }
         R q = (R)0;
 #pragma unroll
         for (int r = 0; r < DM; ++r) {
-            if (r < D) {
-                R acc = W[r * D] * dv[0];
+            const R *Wr = W + (size_t)(EXACT ? r : (r < D ? r : D - 1)) * D;
+            R acc = Wr[0] * dv[0];
 #pragma unroll
-                for (int c = 1; c <= r; ++c) acc = fma(W[r * D + c], dv[c], acc);
-                q = fma(acc, acc, q);
-            }
+            for (int c = 1; c <= r; ++c) acc = fma(Wr[EXACT ? c : (c < D ? c : D - 1)], dv[c], acc);
+            q = r < D ? fma(acc, acc, q) : q;
         }
         const R l = ep[j * EP_STRIDE] - (R)0.5 * q;
         mx = fmax(mx, l);
@@ -1469,15 +1475,25 @@ static void launch_blk_emission(const StagedModel<R> &m, const ObsRef &obs, int6
     } else if (m.family == HMM_FULL_GAUSSIAN && m.D <= 64) {
         const dim3 g((unsigned)((total + 63) / 64));
         const R *mu = m.mv, *Li = m.mv + (size_t)N * m.D;
-        if (m.D <= 16)
-            hipLaunchKernelGGL((k_blk_emit_full<R, 16, RAW>), g, dim3(64), 0, s, N, m.D, obs, total, mu,
-                               Li, (const R *)m.ep, etab, mt);
-        else if (m.D <= 32)
-            hipLaunchKernelGGL((k_blk_emit_full<R, 32, RAW>), g, dim3(64), 0, s, N, m.D, obs, total, mu,
-                               Li, (const R *)m.ep, etab, mt);
+        const R *ep = (const R *)m.ep;
+        if (m.D == 16)
+            hipLaunchKernelGGL((k_blk_emit_full<R, 16, RAW, true>), g, dim3(64), 0, s, N, m.D, obs, total,
+                               mu, Li, ep, etab, mt);
+        else if (m.D == 32)
+            hipLaunchKernelGGL((k_blk_emit_full<R, 32, RAW, true>), g, dim3(64), 0, s, N, m.D, obs, total,
+                               mu, Li, ep, etab, mt);
+        else if (m.D == 64)
+            hipLaunchKernelGGL((k_blk_emit_full<R, 64, RAW, true>), g, dim3(64), 0, s, N, m.D, obs, total,
+                               mu, Li, ep, etab, mt);
+        else if (m.D < 16)
+            hipLaunchKernelGGL((k_blk_emit_full<R, 16, RAW, false>), g, dim3(64), 0, s, N, m.D, obs, total,
+                               mu, Li, ep, etab, mt);
+        else if (m.D < 32)
+            hipLaunchKernelGGL((k_blk_emit_full<R, 32, RAW, false>), g, dim3(64), 0, s, N, m.D, obs, total,
+                               mu, Li, ep, etab, mt);
         else
-            hipLaunchKernelGGL((k_blk_emit_full<R, 64, RAW>), g, dim3(64), 0, s, N, m.D, obs, total, mu,
-                               Li, (const R *)m.ep, etab, mt);
+            hipLaunchKernelGGL((k_blk_emit_full<R, 64, RAW, false>), g, dim3(64), 0, s, N, m.D, obs, total,
+                               mu, Li, ep, etab, mt);
     } else if constexpr (!RAW) {
         const int spb = BT / blk_nc(N);
         const int64_t nb = (total + spb - 1) / spb;
