@@ -104,18 +104,28 @@ __global__ __launch_bounds__(64) void k_vit_forward(StagedModel<R> m, ObsRef o, 
             } else {
                 dsh[j] = d;
                 wave_lds_order();
-                R best = ninf;
-                int arg = 0;
+                // max over predecessors by a pairwise tree over contiguous
+                // blocks (log2 NMAX dependent levels); the right block wins
+                // only if strictly larger, so ties keep the lowest index.
+                // Entries past N hold -inf (col and the dead lanes' d).
+                R vv[NMAX];
+                int aa[NMAX];
 #pragma unroll
                 for (int i = 0; i < NMAX; ++i) {
-                    if (i < N) {
-                        const R v = dsh[i] + col[i];
-                        if (v > best) {
-                            best = v;
-                            arg = i;
-                        }
+                    vv[i] = dsh[i] + col[i];
+                    aa[i] = i;
+                }
+#pragma unroll
+                for (int st = 1; st < NMAX; st *= 2) {
+#pragma unroll
+                    for (int k = 0; k + st < NMAX; k += 2 * st) {
+                        const bool right = vv[k + st] > vv[k];
+                        vv[k] = right ? vv[k + st] : vv[k];
+                        aa[k] = right ? aa[k + st] : aa[k];
                     }
                 }
+                const R best = vv[0];
+                const int arg = aa[0];
                 wave_lds_order();
                 nd = live ? (R)(best + lt) : ninf;
                 if (live) psi[(off + t) * N + j] = (uint8_t)arg;
