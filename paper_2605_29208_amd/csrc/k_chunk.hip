@@ -114,6 +114,51 @@ __device__ __forceinline__ void store_colrec(ColRec<R, G> *dst, const R (*rows)[
 // superchunks needs no separate pass over the chunk records.
 constexpr int SPC = 16;
 
+// row <- row A diag(e) for one step (e: the step's G emission factors)
+template <typename R, int G>
+__device__ __forceinline__ void product_step(const R (&a)[G][G], const R *e, R (&rowv)[G]) {
+    R nv[G];
+#pragma unroll
+    for (int j = 0; j < G; ++j) {
+        R acc = rowv[0] * a[0][j];
+#pragma unroll
+        for (int k = 1; k < G; ++k) acc = fma(rowv[k], a[k][j], acc);
+        nv[j] = acc * e[j];
+    }
+#pragma unroll
+    for (int j = 0; j < G; ++j) rowv[j] = nv[j];
+}
+
+// divide the row by 2^ex (ex = exponent of its largest entry), add ex to r
+template <typename R, int G>
+__device__ __forceinline__ void rescale_row(R (&rowv)[G], int &r) {
+    R mxv = rowv[0];
+#pragma unroll
+    for (int j = 1; j < G; ++j) mxv = fmax(mxv, rowv[j]);
+    const int ex = fexp(mxv);
+#pragma unroll
+    for (int j = 0; j < G; ++j) rowv[j] = fldexp(rowv[j], -ex);
+    r += ex;
+}
+
+// nsteps product steps over the emission table es ([step][G]), rescaled after
+// every NRM-th step and after the last
+template <typename R, int G, int NRM>
+__device__ __forceinline__ void product_steps(const R (&a)[G][G], const R *es, int nsteps,
+                                              R (&rowv)[G], int &r) {
+    int s = 0;
+    for (; s + NRM <= nsteps; s += NRM) {
+#pragma unroll
+        for (int u = 0; u < NRM; ++u) product_step<R, G>(a, es + (s + u) * G, rowv);
+        rescale_row<R, G>(rowv, r);
+    }
+    if (s < nsteps) {
+        for (; s < nsteps; ++s) product_step<R, G>(a, es + s * G, rowv);
+        rescale_row<R, G>(rowv, r);
+    }
+}
+
+
 template <typename R, int G, int L, int FAM>
 __global__ __launch_bounds__(BLOCK) void k_chunk_product(ChunkGeom g, const SuperDesc *__restrict__ sdesc,
                                                          int SC, StagedModel<R> m,
@@ -203,30 +248,12 @@ __global__ __launch_bounds__(BLOCK) void k_chunk_product(ChunkGeom g, const Supe
 #pragma unroll
     for (int j = 0; j < G; ++j) rowv[j] = (j == li && li < N) ? (R)1 : (R)0;
     int r = 0;
-    for (int s = 0; s < nsteps; ++s) {
-        R e[G];
-#pragma unroll
-        for (int j = 0; j < G; ++j) e[j] = esh[slot][s][j];
-        R nv[G];
-#pragma unroll
-        for (int j = 0; j < G; ++j) {
-            R acc = rowv[0] * a[0][j];
-#pragma unroll
-            for (int k = 1; k < G; ++k) acc = fma(rowv[k], a[k][j], acc);
-            nv[j] = acc * e[j];
-        }
-        const bool rescale = ((s + 1) & (nrm - 1)) == 0 || (s + 1 == nsteps);   // nrm: 1, 2 or 4
-        int ex = 0;
-        if (rescale) {
-            R mxv = nv[0];
-#pragma unroll
-            for (int j = 1; j < G; ++j) mxv = fmax(mxv, nv[j]);
-            ex = fexp(mxv);
-        }
-#pragma unroll
-        for (int j = 0; j < G; ++j) rowv[j] = rescale ? fldexp(nv[j], -ex) : nv[j];
-        r += ex;
-    }
+    // nrm (1, 2 or 4) is uniform: each variant runs nrm unrolled steps between
+    // rescales, and the row leaves rescaled whatever its step count
+    const R *es = &esh[slot][0][0];
+    if (nrm == 4) product_steps<R, G, 4>(a, es, nsteps, rowv, r);
+    else if (nrm == 2) product_steps<R, G, 2>(a, es, nsteps, rowv, r);
+    else product_steps<R, G, 1>(a, es, nsteps, rowv, r);
     double cl = 0.0;
 #pragma unroll
     for (int q = 0; q < G; ++q) cl += msh[slot][q];
