@@ -168,11 +168,16 @@ __global__ __launch_bounds__(BLOCK) void k_chunk_product(ChunkGeom g, const Supe
     constexpr int CPB = BLOCK / G;   // chunks per block
     constexpr int SPB = CPB / SPC;   // superchunks per block
     static_assert(SPB * SPC == CPB, "a block holds whole superchunks");
-    __shared__ R esh[CPB][L][G];
-    __shared__ double msh[CPB][G];
-    // rows padded to G + 4 entries: 16-byte aligned for vector reads in the tree
+    // A slot's emission table (L x G) is dead once its product loop ends, so
+    // its product rows (G rows padded to G + 4 entries, 16-byte aligned for
+    // vector reads in the tree) take the same space: every lane of a wave
+    // leaves the loop before any of them stores its row.
     constexpr int RS = G + 4;
-    __shared__ __align__(16) R psh[CPB][G][RS];
+    static_assert(G * RS <= L * G, "product rows fit in the emission table");
+    __shared__ __align__(16) R eps[CPB][L * G];
+    R (*esh)[L][G] = reinterpret_cast<R (*)[L][G]>(&eps[0][0]);
+    auto psh = [&](int q) { return reinterpret_cast<R (*)[RS]>(&eps[q][0]); };
+    __shared__ double msh[CPB][G];
     __shared__ __align__(16) int rsh[CPB][G];
     __shared__ double csh[CPB];
 
@@ -258,11 +263,11 @@ __global__ __launch_bounds__(BLOCK) void k_chunk_product(ChunkGeom g, const Supe
 #pragma unroll
     for (int q = 0; q < G; ++q) cl += msh[slot][q];
 #pragma unroll
-    for (int j = 0; j < G; ++j) psh[slot][li][j] = rowv[j];
+    for (int j = 0; j < G; ++j) psh(slot)[li][j] = rowv[j];
     rsh[slot][li] = r;
     if (li == 0) csh[slot] = cl;
     __syncthreads();
-    if (valid) store_colrec<R, G, RS>(rec + (size_t)c * G + li, psh[slot], li, r, cl);
+    if (valid) store_colrec<R, G, RS>(rec + (size_t)c * G + li, psh(slot), li, r, cl);
 
     // pairwise tree over the superchunk's chunks (the records above only read
     // the group's own slot, which no level writes before its next barrier)
@@ -273,19 +278,24 @@ __global__ __launch_bounds__(BLOCK) void k_chunk_product(ChunkGeom g, const Supe
         if (act) {
             // row li of (2^r P~)(2^r' P~') with the row exponents combined exactly
             const int o = slot + h;
+            // the right factor's row exponents are read unconditionally, so the
+            // tests below are selects, not branches around LDS reads
+            int ro[G];
+#pragma unroll
+            for (int k = 0; k < G; ++k) ro[k] = rsh[o][k];
             int Rm = NEG_EXP;
 #pragma unroll
             for (int k = 0; k < G; ++k)
-                if (rowv[k] > (R)0) Rm = max(Rm, fexp(rowv[k]) + rsh[o][k]);
+                Rm = max(Rm, (rowv[k] > (R)0) ? fexp(rowv[k]) + ro[k] : NEG_EXP);
             if (Rm != NEG_EXP) {
                 R nv[G];
 #pragma unroll
                 for (int j = 0; j < G; ++j) nv[j] = (R)0;
 #pragma unroll
                 for (int k = 0; k < G; ++k) {
-                    const R wk = (rowv[k] > (R)0) ? fldexp(rowv[k], rsh[o][k] - Rm) : (R)0;
+                    const R wk = (rowv[k] > (R)0) ? fldexp(rowv[k], ro[k] - Rm) : (R)0;
 #pragma unroll
-                    for (int j = 0; j < G; ++j) nv[j] = fma(wk, psh[o][k][j], nv[j]);
+                    for (int j = 0; j < G; ++j) nv[j] = fma(wk, psh(o)[k][j], nv[j]);
                 }
                 R mx = nv[0];
 #pragma unroll
@@ -301,13 +311,13 @@ __global__ __launch_bounds__(BLOCK) void k_chunk_product(ChunkGeom g, const Supe
         // with si % 2h == 0, so the next level's barrier orders these stores
         if (act) {
 #pragma unroll
-            for (int j = 0; j < G; ++j) psh[slot][li][j] = rowv[j];
+            for (int j = 0; j < G; ++j) psh(slot)[li][j] = rowv[j];
             rsh[slot][li] = r;
             if (li == 0) csh[slot] = cl;
         }
     }
     __syncthreads();
-    if (si == 0 && nsc > 0) store_colrec<R, G, RS>(srec + (size_t)sc * G + li, psh[slot], li, r, cl);
+    if (si == 0 && nsc > 0) store_colrec<R, G, RS>(srec + (size_t)sc * G + li, psh(slot), li, r, cl);
 }
 
 // ---------------------------------------------------------------- phase 2
