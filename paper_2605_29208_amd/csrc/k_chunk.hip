@@ -685,7 +685,6 @@ __global__ __launch_bounds__(BLOCK) void k_chunk_stats(ChunkGeom g, StagedModel<
             gs += gm;
             if constexpr (K > 0)
                 fam_accumulate<FAM, R, KK>(gm, ysh[grp][L - 1][0], ysh[grp][L - 1][1], k, fa);
-            g1 += (first && tt0 == L - 1) ? gm : (R)0;
             if constexpr (WG) {
                 if (own) gamma_out[(off + t0 + len - 1) * N + p] = gm;
             }
@@ -718,7 +717,6 @@ __global__ __launch_bounds__(BLOCK) void k_chunk_stats(ChunkGeom g, StagedModel<
                 if constexpr (K > 0)
                     fam_accumulate<FAM, R, KK>(gm, ysh[grp][tt - 1][0], ysh[grp][tt - 1][1], k,
                                                fa);
-                g1 += (first && tt - 1 == tt0) ? gm : (R)0;
                 if constexpr (WG) {
                     if (ok) gamma_out[(off + t0 + (tt - 1 - tt0)) * N + p] = gm;
                 }
@@ -729,6 +727,14 @@ __global__ __launch_bounds__(BLOCK) void k_chunk_stats(ChunkGeom g, StagedModel<
             // keeps at least a fraction min a_ij of it and never grows
             if ((tt & (nrm - 1)) == 0) bp = fldexp(bp, -fexp(grp_max_pos<G>(bp)));
             if (trans) bcur = bp;
+        }
+        // gamma at the sequence's first step, once per chunk: after the loop a
+        // first chunk's bcur is beta at tt0 (up to a power of two, which the
+        // normalisation removes), and alpha at tt0 is in the history
+        {
+            const R h0 = atab[grp][tt0 < L ? tt0 : L - 1][p] * bcur;
+            const R Z0 = grp_sum<G, R>(h0);
+            g1 = (first && own) ? h0 * frcp(Z0) : (R)0;
         }
         if (use && live) {
 #pragma unroll
