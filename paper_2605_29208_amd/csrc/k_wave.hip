@@ -134,27 +134,47 @@ struct WaveGeom {
     ObsRef obs;                 // observations, or the log-emission table (TABLE)
 };
 
+// One step's observation data (the observation, or the step's row of the
+// log-density table), loaded apart from its use so that a sweep can fetch the
+// next window's data while it runs the current one.  Indices are clamped, so
+// the loads are unconditional.
+template <typename R, int NP, int FAM>
+struct StepObs {
+    R v[FAM == HMM_TABLE ? NP : 1];
+};
+template <typename R, int NP, int FAM>
+__device__ __forceinline__ StepObs<R, NP, FAM> load_step_obs(const WaveGeom &g, int N, int64_t row) {
+    StepObs<R, NP, FAM> o;
+    if constexpr (FAM == HMM_TABLE) {
+#pragma unroll
+        for (int j = 0; j < NP; ++j) o.v[j] = load_obs<R>(g.obs, row * N + min(j, N - 1));
+    } else {
+        o.v[0] = load_obs<R>(g.obs, row);
+    }
+    return o;
+}
+
 // Emission factors of the NP states at one step, computed by one lane into its
 // LDS row: row[j] = exp(log b_j(y) - m) with m = max_j log b_j(y).  Returns m
 // plus the state-independent part in FP64 (-inf when no state can emit y);
 // sets *bad for a non-finite observation.  The first pass leaves log b in the
 // row (Poisson recomputes it instead: its values need FP64).
 template <typename R, int NP, int FAM>
-__device__ __forceinline__ double tab_step(const WaveGeom &g, int N, int64_t row,
-                                           const typename EmitTraits<FAM, R>::T *ep, R *erow,
-                                           R *y1, R *ly1, bool *bad) {
+__device__ __forceinline__ double tab_step_obs(const StepObs<R, NP, FAM> &o, int N,
+                                               const typename EmitTraits<FAM, R>::T *ep, R *erow,
+                                               R *y1, R *ly1, bool *bad) {
     using ET = typename EmitTraits<FAM, R>::T;
     constexpr bool RECOMP = FAM == HMM_POISSON;
     ET mx = neg_inf<ET>();
     double common = 0.0;
     R y = (R)0;
-    if constexpr (FAM != HMM_TABLE) y = load_obs<R>(g.obs, row);
+    if constexpr (FAM != HMM_TABLE) y = o.v[0];
 #pragma unroll 4
     for (int j = 0; j < NP; ++j) {
         const bool live = j < N;
         Emit<ET> em;
         if constexpr (FAM == HMM_TABLE) {
-            R v = live ? load_obs<R>(g.obs, row * N + j) : neg_inf<R>();
+            R v = live ? o.v[j] : neg_inf<R>();
             em.ell = v;
             em.common = 0.0;
             em.bad = live && (isnan(v) || (v > (R)0 && isinf(v)));
@@ -176,6 +196,14 @@ __device__ __forceinline__ double tab_step(const WaveGeom &g, int N, int64_t row
     *y1 = y;
     *ly1 = (FAM == HMM_GAMMA && y > (R)0) ? flog(y) : (R)0;
     return (double)mx + common;
+}
+
+template <typename R, int NP, int FAM>
+__device__ __forceinline__ double tab_step(const WaveGeom &g, int N, int64_t row,
+                                           const typename EmitTraits<FAM, R>::T *ep, R *erow,
+                                           R *y1, R *ly1, bool *bad) {
+    return tab_step_obs<R, NP, FAM>(load_step_obs<R, NP, FAM>(g, N, row), N, ep, erow, y1, ly1,
+                                    bad);
 }
 
 // out = sum_i v_i c_i with v broadcast from LDS (four independent chains, so
@@ -233,7 +261,8 @@ __global__ __launch_bounds__(64) void k_wave_sweep(WaveGeom g, StagedModel<R> m,
     constexpr int NG = 64 / LPT;    // tasks per wave
     constexpr int RPL = NP / SPL;   // rows of the product per lane
     constexpr int VS = NP + 4;
-    __shared__ R esh[NG][WL][NP + 1];
+    // one-task waves tabulate two chunks per window
+    __shared__ R esh[NG][NG == 1 ? 2 * WL : WL][NP + 1];
     __shared__ __align__(16) R vsh[NG][VS];
     using ET = typename EmitTraits<FAM, R>::T;
     const ET *ep = consts_ptr<FAM, R>(m);
@@ -272,6 +301,94 @@ __global__ __launch_bounds__(64) void k_wave_sweep(WaveGeom g, StagedModel<R> m,
     int64_t E = 0;
     if (tv && !fwd && h == 0) Gb[(size_t)(cb + nc - 1) * NP + j] = v;
 
+    if constexpr (NG == 1) {
+        // One task per wave: the direction, the length and the step are
+        // uniform, so the loops below have scalar control.  A window is two
+        // chunks (64 steps, one step per lane for the emission table), and the
+        // observations of the next window are loaded into registers while the
+        // current one runs, so the table of a window waits on no memory.
+        // Rescaling points and stored boundaries are those of one-chunk
+        // windows: forward after steps t = nrm - 1 (mod nrm), the last step and
+        // t = 0, boundary at every chunk end; backward after the steps whose
+        // distance to their chunk's end is nrm - 1 (mod nrm) and at the chunk's
+        // first step, boundary beta at the end of the previous chunk.
+        constexpr int WW = 2 * WL;
+        static_assert(WW == LPT, "one window step per lane");
+        const int nw = (T + WW - 1) / WW;
+        // window k covers steps [lo, hi); the backward skips chunk 0
+        auto wlo = [&](int k) { return fwd ? k * WW : max(k * WW, WL); };
+        auto whi = [&](int k) { return min(T, k * WW + WW); };
+        const int k0 = fwd ? 0 : nw - 1, kstep = fwd ? 1 : -1;
+        const int kend = fwd ? nw : -1;
+        StepObs<R, NP, FAM> pre;
+        if (k0 != kend && wlo(k0) < whi(k0))
+            pre = load_step_obs<R, NP, FAM>(g, N, off + min(wlo(k0) + sl, whi(k0) - 1));
+        for (int k = k0; k != kend; k += kstep) {
+            const int lo = wlo(k), hi = whi(k), wn = hi - lo;
+            if (wn <= 0) continue;
+            __syncthreads();
+            double msum = 0.0;
+            if (sl < wn) {
+                R y, ly;
+                msum = tab_step_obs<R, NP, FAM>(pre, N, ep, &esh[0][sl][0], &y, &ly, &bad);
+            }
+            const double wsum = grp_all<LPT, false>(msum);
+            if (fwd) logS += wsum;
+            __syncthreads();
+            // the next window's observations, in flight during this window
+            const int kn = k + kstep;
+            if (kn != kend && wlo(kn) < whi(kn))
+                pre = load_step_obs<R, NP, FAM>(g, N, off + min(wlo(kn) + sl, whi(kn) - 1));
+            if (fwd) {
+                R e_cur = esh[0][0][j];
+                for (int t = lo; t < hi; ++t) {
+                    const int q = t - lo;
+                    R nv;
+                    if (t == 0) {   // alpha_0 = pi o e_0
+                        nv = live ? m.pi[j] * e_cur : (R)0;
+                    } else {
+                        vsh[0][j] = v;   // both halves store the same value
+                        wave_lds_order();
+                        R acc = lds_dot<R, RPL>(&vsh[0][h * RPL], coef);
+                        if constexpr (SPL == 2) acc = add_halves(acc);
+                        if constexpr (SPL == 4) acc = add_quarters(acc);
+                        wave_lds_order();
+                        nv = e_cur * acc;
+                    }
+                    e_cur = esh[0][q + 1 < wn ? q + 1 : q][j];
+                    if (t == 0 || (t & (nrm - 1)) == nrm - 1 || t == T - 1) {
+                        const int ex = fexp(grp_max_nn<LPT>(nv));
+                        v = fldexp(nv, -ex);
+                        E += ex;
+                    } else {
+                        v = nv;
+                    }
+                    if ((t % WL == WL - 1 || t == T - 1) && h == 0) F[(size_t)(cb + t / WL) * NP + j] = v;
+                }
+            } else {
+                R e_cur = esh[0][wn - 1][j];
+                for (int t = hi - 1; t >= lo; --t) {
+                    const int q = t - lo;
+                    vsh[0][j] = e_cur * v;
+                    wave_lds_order();
+                    R acc = lds_dot<R, RPL>(&vsh[0][h * RPL], coef);
+                    if constexpr (SPL == 2) acc = add_halves(acc);
+                    if constexpr (SPL == 4) acc = add_quarters(acc);
+                    e_cur = esh[0][q > 0 ? q - 1 : q][j];
+                    wave_lds_order();
+                    const int c = t / WL;
+                    const int dist = min(T, c * WL + WL) - 1 - t;   // to the chunk's last step
+                    if ((dist & (nrm - 1)) == nrm - 1 || t == c * WL) {
+                        const int ex = fexp(grp_max_nn<LPT>(acc));
+                        v = fldexp(acc, -ex);
+                    } else {
+                        v = acc;
+                    }
+                    if (t == c * WL && h == 0) Gb[(size_t)(cb + c - 1) * NP + j] = v;
+                }
+            }
+        }
+    } else
     for (int k = 0; k < nkmax; ++k) {
         const bool act = k < nk;
         const int c = fwd ? k : nc - 1 - k;
@@ -289,38 +406,6 @@ __global__ __launch_bounds__(64) void k_wave_sweep(WaveGeom g, StagedModel<R> m,
         // step s of the window is local step s (forward) or wn - 1 - s (backward);
         // the next step's emission factor is read one step ahead
         R e_cur = (wn > 0) ? esh[grp][fwd ? 0 : wn - 1][j] : (R)0;
-        if constexpr (NG == 1) {
-            // one task per wave: wn, the direction and the step are uniform, so
-            // the loop runs exactly the window's steps with scalar control
-            int s = 0;
-            if (fwd && w0 == 0 && wn > 0) {   // t = 0: alpha_0 = pi o e_0
-                const R nv = live ? m.pi[j] * e_cur : (R)0;
-                const int ex = fexp(grp_max_nn<LPT>(nv));
-                v = fldexp(nv, -ex);
-                E += ex;
-                e_cur = esh[grp][wn > 1 ? 1 : 0][j];
-                s = 1;
-            }
-            for (; s < wn; ++s) {
-                vsh[grp][j] = fwd ? v : e_cur * v;   // both halves store the same value
-                wave_lds_order();
-                R acc = lds_dot<R, RPL>(&vsh[grp][h * RPL], coef);
-                if constexpr (SPL == 2) acc = add_halves(acc);
-                if constexpr (SPL == 4) acc = add_quarters(acc);
-                const int sn = s + 1 < wn ? s + 1 : s;
-                const R e_nxt = esh[grp][fwd ? sn : wn - 1 - sn][j];
-                wave_lds_order();
-                const R nv = fwd ? e_cur * acc : acc;
-                if ((s & (nrm - 1)) == nrm - 1 || s == wn - 1) {
-                    const int ex = fexp(grp_max_nn<LPT>(nv));
-                    v = fldexp(nv, -ex);
-                    if (fwd) E += ex;
-                } else {
-                    v = nv;
-                }
-                e_cur = e_nxt;
-            }
-        } else
         for (int s = 0; s < WL; ++s) {
             const bool on = s < wn;
             const int t = w0 + (fwd ? s : wn - 1 - s);
