@@ -220,8 +220,10 @@ __global__ __launch_bounds__(64) void k_blk_emit_full(int N, int D_, ObsRef o, i
 // holds the same values; the waves of part 0 publish their maxima)
 template <typename R>
 __device__ __forceinline__ R blk_max(R v, R *wred, int NC) {
-    const R w = wave_max_r(v);
-    if (threadIdx.x < (unsigned)NC && (threadIdx.x & 63) == 0) wred[threadIdx.x / 64] = w;
+    if (threadIdx.x < (unsigned)NC) {   // whole waves (NC is a multiple of 64)
+        const R w = wave_max_r(v);
+        if ((threadIdx.x & 63) == 0) wred[threadIdx.x / 64] = w;
+    }
     __syncthreads();
     R mx = wred[0];
     for (int k = 1; k < NC / 64; ++k) mx = fmax(mx, wred[k]);
@@ -313,6 +315,7 @@ __global__ __launch_bounds__(NT) void k_blk_fwd(StagedModel<R> m, const int64_t 
     const int64_t b = blockIdx.x;
     const int64_t off = offsets[b];
     const int T = (int)(offsets[b + 1] - off);
+    const int nrm = *m.nrm;   // steps between rescalings: 1, 2 or 4
     // t = 0
     R v = live ? m.pi[c] * etab[off * N + c] : (R)0;
     int ex = fexp(blk_max(v, wred, NC));
@@ -364,11 +367,19 @@ __global__ __launch_bounds__(NT) void k_blk_fwd(StagedModel<R> m, const int64_t 
             const R acc = pd.dot(x, m.A);
             if (p < 8) psum[p][c] = acc;
             __syncthreads();
-            R s = psum[0][c];
-            for (int q = 1; q < P; ++q) s += psum[q][c];
-            v = s * e;
-            ex = fexp(blk_max(v, wred, NC));
-            v = fldexp(v, -ex);
+            // only part 0 forms the new vector; the rescaling (every nrm steps
+            // and at the last step) is uniform, so its block maximum is skipped
+            // on the other steps
+            if (p == 0) {
+                R s = psum[0][c];
+                for (int q = 1; q < P; ++q) s += psum[q][c];
+                v = s * e;
+            }
+            ex = 0;
+            if ((t & (nrm - 1)) == nrm - 1 || t == T - 1) {
+                ex = fexp(blk_max(v, wred, NC));
+                v = fldexp(v, -ex);
+            }
             if (p == 0) x[c] = v;
             if (p == 0 && live) alpha[row * N + c] = v;
             if (tid == 0) aexp[row] = ex;
@@ -430,6 +441,7 @@ __global__ __launch_bounds__(NT) void k_blk_bwd(StagedModel<R> m, const int64_t 
     const int64_t off = offsets[b];
     const int T = (int)(offsets[b + 1] - off);
     const bool use = status[b] == 0;
+    const int nrm = *m.nrm;
     R bt = live ? (R)1 : (R)0;   // beta^_t of state r (identical in every part)
     // alpha and emission rows and exponents of the next window of PF steps
     // are loaded into registers while the current window runs from LDS
@@ -498,8 +510,14 @@ __global__ __launch_bounds__(NT) void k_blk_bwd(StagedModel<R> m, const int64_t 
             __syncthreads();
             R s = psum[0][r];
             for (int q = 1; q < P; ++q) s += psum[q][r];
-            const int ex = fexp(blk_max(s, wred, NC));
-            bt = fldexp(s, -ex);
+            // rescaled every nrm steps (beta never grows; the staging bound on
+            // its shrinking holds as for the forward)
+            if (((T - 1 - t) & (nrm - 1)) == nrm - 1) {
+                const int ex = fexp(blk_max(s, wred, NC));
+                bt = fldexp(s, -ex);
+            } else {
+                bt = s;
+            }
         }
         if (done) break;
         buf ^= 1;
