@@ -180,6 +180,7 @@ __global__ __launch_bounds__(BLOCK) void k_chunk_product(ChunkGeom g, const Supe
     __shared__ double msh[CPB][G];
     __shared__ __align__(16) int rsh[CPB][G];
     __shared__ double csh[CPB];
+    __shared__ int nscs[SPB];
 
     const int li = threadIdx.x % G;
     const int slot = threadIdx.x / G;
@@ -269,55 +270,64 @@ __global__ __launch_bounds__(BLOCK) void k_chunk_product(ChunkGeom g, const Supe
     __syncthreads();
     if (valid) store_colrec<R, G, RS>(rec + (size_t)c * G + li, psh(slot), li, r, cl);
 
-    // pairwise tree over the superchunk's chunks (the records above only read
-    // the group's own slot, which no level writes before its next barrier)
+    // pairwise tree over each superchunk's chunks, slot i taking slot i + h at
+    // h = 1, 2, 4, 8.  A level's products are spread over the block's first
+    // lanes, one lane per row of a product (128 / h lanes), rather than kept on
+    // the lanes of the left slot, so that a level issues its work on as few
+    // waves as it needs; rows and exponents stay in LDS.  A level reads only
+    // slots with i % 2h == h and writes only slots with i % 2h == 0, so one
+    // barrier per level orders it; the first also orders the chunk records'
+    // reads of the rows before the first level's writes.
+    if (li == 0 && si == 0) nscs[slot / SPC] = nsc;
 #pragma unroll
     for (int h = 1; h < SPC; h *= 2) {
-        if (h > 1) __syncthreads();
-        const bool act = (si % (2 * h)) == 0 && si + h < nsc;
-        if (act) {
-            // row li of (2^r P~)(2^r' P~') with the row exponents combined exactly
-            const int o = slot + h;
-            // the right factor's row exponents are read unconditionally, so the
-            // tests below are selects, not branches around LDS reads
-            int ro[G];
-#pragma unroll
-            for (int k = 0; k < G; ++k) ro[k] = rsh[o][k];
-            int Rm = NEG_EXP;
-#pragma unroll
-            for (int k = 0; k < G; ++k)
-                Rm = max(Rm, (rowv[k] > (R)0) ? fexp(rowv[k]) + ro[k] : NEG_EXP);
-            if (Rm != NEG_EXP) {
-                R nv[G];
-#pragma unroll
-                for (int j = 0; j < G; ++j) nv[j] = (R)0;
+        __syncthreads();
+        const int ppb = SPC / (2 * h);   // products per superchunk at this level
+        const int task = threadIdx.x;
+        if (task < SPB * ppb * G) {
+            const int tl = task % G, pidx = task / G;
+            const int sp = pidx / ppb, pi = pidx % ppb;
+            const int lft = sp * SPC + pi * 2 * h, o = lft + h;
+            if (pi * 2 * h + h < nscs[sp]) {
+                // row tl of (2^r P~)(2^r' P~') with the row exponents combined
+                // exactly; every operand is read unconditionally, so the tests
+                // below are selects
+                R rw[G];
+                int ro[G];
 #pragma unroll
                 for (int k = 0; k < G; ++k) {
-                    const R wk = (rowv[k] > (R)0) ? fldexp(rowv[k], ro[k] - Rm) : (R)0;
-#pragma unroll
-                    for (int j = 0; j < G; ++j) nv[j] = fma(wk, psh(o)[k][j], nv[j]);
+                    rw[k] = psh(lft)[tl][k];
+                    ro[k] = rsh[o][k];
                 }
-                R mx = nv[0];
+                int Rm = NEG_EXP;
 #pragma unroll
-                for (int j = 1; j < G; ++j) mx = fmax(mx, nv[j]);
-                const int ex = fexp(mx);
+                for (int k = 0; k < G; ++k)
+                    Rm = max(Rm, (rw[k] > (R)0) ? fexp(rw[k]) + ro[k] : NEG_EXP);
+                if (Rm != NEG_EXP) {
+                    R nv[G];
 #pragma unroll
-                for (int j = 0; j < G; ++j) rowv[j] = fldexp(nv[j], -ex);
-                r += Rm + ex;
+                    for (int j = 0; j < G; ++j) nv[j] = (R)0;
+#pragma unroll
+                    for (int k = 0; k < G; ++k) {
+                        const R wk = (rw[k] > (R)0) ? fldexp(rw[k], ro[k] - Rm) : (R)0;
+#pragma unroll
+                        for (int j = 0; j < G; ++j) nv[j] = fma(wk, psh(o)[k][j], nv[j]);
+                    }
+                    R mx = nv[0];
+#pragma unroll
+                    for (int j = 1; j < G; ++j) mx = fmax(mx, nv[j]);
+                    const int ex = fexp(mx);
+#pragma unroll
+                    for (int j = 0; j < G; ++j) psh(lft)[tl][j] = fldexp(nv[j], -ex);
+                    rsh[lft][tl] += Rm + ex;
+                }
+                if (tl == 0) csh[lft] += csh[o];
             }
-            cl += csh[o];
-        }
-        // a level reads only slots with si % 2h == h and writes only slots
-        // with si % 2h == 0, so the next level's barrier orders these stores
-        if (act) {
-#pragma unroll
-            for (int j = 0; j < G; ++j) psh(slot)[li][j] = rowv[j];
-            rsh[slot][li] = r;
-            if (li == 0) csh[slot] = cl;
         }
     }
     __syncthreads();
-    if (si == 0 && nsc > 0) store_colrec<R, G, RS>(srec + (size_t)sc * G + li, psh(slot), li, r, cl);
+    if (si == 0 && nsc > 0)
+        store_colrec<R, G, RS>(srec + (size_t)sc * G + li, psh(slot), li, rsh[slot][li], csh[slot]);
 }
 
 // ---------------------------------------------------------------- phase 2
