@@ -317,35 +317,84 @@ void launch_plan_chunks(const int64_t *offsets, int64_t nseq, int L, int S, int 
     hipLaunchKernelGGL(k_plan_chunks, dim3(1), dim3(1024), 0, s, offsets, nseq, L, S, cbase, sbase);
 }
 
+// Last sequence b < nseq with base[b] <= c0 (base non-decreasing, base[0] = 0
+// <= c0), found by the whole block: each round probes BLOCK evenly spaced
+// entries at once and keeps the bracket between the last probe that passes
+// and the next one, so B sequences take about log_BLOCK(B) dependent loads.
+__device__ __forceinline__ int block_find_seq(const int *base, int nseq, int c0) {
+    int lo = 0, hi = nseq - 1;
+    while (lo < hi) {   // uniform
+        const int64_t span = (int64_t)(hi - lo) + 1;
+        const int pk = lo + (int)(((int64_t)threadIdx.x * span) / BLOCK);
+        // the probes are non-decreasing in the thread index and probe 0 (= lo)
+        // passes, so the passing ones are threads 0 .. cnt - 1
+        const int cnt = __syncthreads_count(base[pk] <= c0);
+        const int k = cnt - 1;
+        const int plo = lo + (int)(((int64_t)k * span) / BLOCK);
+        const int phi = (k + 1 < BLOCK) ? lo + (int)(((int64_t)(k + 1) * span) / BLOCK) - 1 : hi;
+        lo = plo;
+        hi = phi;
+    }
+    return lo;
+}
+
+// Descriptors of the chunks (i < C) and superchunks (i < SC), thread i of the
+// grid for entry i.  A block's BLOCK consecutive entries belong to at most
+// BLOCK consecutive sequences (every sequence has one chunk and one superchunk
+// or more), so after the block finds the first one, the window of BLOCK + 1
+// prefix entries that follows is staged in LDS and each thread searches it.
+__device__ __forceinline__ int window_find_seq(const int *base, int nseq, int i0, int i, int *win,
+                                               int *b0) {
+    const int bl = block_find_seq(base, nseq, i0);
+    const int nw = min(BLOCK, nseq - bl);   // sequences in the window
+    for (int k = threadIdx.x; k <= nw; k += BLOCK) win[k] = base[bl + k];
+    __syncthreads();
+    int lo = 0, hi = nw - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (win[mid] <= i) lo = mid; else hi = mid - 1;
+    }
+    *b0 = bl;
+    return bl + lo;
+}
+
 __global__ __launch_bounds__(BLOCK) void k_chunk_desc(const int64_t *offsets, int64_t nseq, int L,
                                                       int S, const int *cbase, const int *sbase,
                                                       int C, int SC, ChunkDesc *cdesc,
                                                       SuperDesc *sdesc) {
-    const int i = blockIdx.x * BLOCK + threadIdx.x;
-    if (i < C) {
-        int b = find_seq(cbase, (int)nseq, i);
-        int64_t off = offsets[b];
-        int T = (int)(offsets[b + 1] - off);
-        ChunkDesc d;
-        d.off = off;
-        d.b = b;
-        d.t0 = (i - cbase[b]) * L;
-        d.len = min(L, T - d.t0);
-        d.pad0 = 0;
-        d.pad1 = 0;
-        cdesc[i] = d;
+    __shared__ int win[BLOCK + 1];
+    const int i0 = blockIdx.x * BLOCK;
+    const int i = i0 + threadIdx.x;
+    int bl;
+    if (i0 < C) {   // uniform
+        const int b = window_find_seq(cbase, (int)nseq, i0, min(i, C - 1), win, &bl);
+        if (i < C) {
+            int64_t off = offsets[b];
+            int T = (int)(offsets[b + 1] - off);
+            ChunkDesc d;
+            d.off = off;
+            d.b = b;
+            d.t0 = (i - cbase[b]) * L;
+            d.len = min(L, T - d.t0);
+            d.pad0 = 0;
+            d.pad1 = 0;
+            cdesc[i] = d;
+        }
+        __syncthreads();   // the window is reused below
     }
-    if (i < SC) {
-        int b = find_seq(sbase, (int)nseq, i);
-        SuperDesc d;
-        d.off = offsets[b];
-        d.b = b;
-        d.lo = cbase[b] + (i - sbase[b]) * S;
-        d.n = min(S, cbase[b + 1] - d.lo);
-        d.head = (i == sbase[b]) ? 1 : 0;
-        d.t0 = (d.lo - cbase[b]) * L;
-        d.T = (int)(offsets[b + 1] - d.off);
-        sdesc[i] = d;
+    if (i0 < SC) {   // uniform
+        const int b = window_find_seq(sbase, (int)nseq, i0, min(i, SC - 1), win, &bl);
+        if (i < SC) {
+            SuperDesc d;
+            d.off = offsets[b];
+            d.b = b;
+            d.lo = cbase[b] + (i - sbase[b]) * S;
+            d.n = min(S, cbase[b + 1] - d.lo);
+            d.head = (i == sbase[b]) ? 1 : 0;
+            d.t0 = (d.lo - cbase[b]) * L;
+            d.T = (int)(offsets[b + 1] - d.off);
+            sdesc[i] = d;
+        }
     }
 }
 
