@@ -23,43 +23,78 @@ size_t staged_bytes(int N, int D, int family, bool f64) {
            align256(64 * r) + 256;
 }
 
-// Chunk plan in one block of BLOCK threads: cbase and sbase by inclusive
-// scans of the chunk and superchunk counts over tiles of BLOCK sequences.
-__device__ void plan_block(const PlanArgs &a) {
-    __shared__ int s_nc[BLOCK], s_ns[BLOCK];
-    const int t = threadIdx.x;
+// Chunk plan in one block of NT threads: cbase and sbase are the exclusive
+// prefix sums of the per-sequence chunk and superchunk counts.  A tile of
+// NT * PER sequences takes one round of loads (each thread its PER
+// consecutive sequences), a scan inside each wave through lane shuffles and
+// one barrier for the wave totals, so B sequences cost about B / (NT * PER)
+// load latencies.
+template <int NT, int PER>
+__device__ void plan_scan(const int64_t *offsets, int64_t nseq, int L, int S, int *cbase,
+                          int *sbase) {
+    constexpr int NW = NT / 64, TILE = NT * PER;
+    __shared__ int w_nc[NW], w_ns[NW];
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
     int carry_c = 0, carry_s = 0;
-    for (int64_t base = 0; base < a.nseq; base += BLOCK) {
-        const int64_t b = base + t;
-        int nc = 0, ns = 0;
-        if (b < a.nseq) {
-            const int64_t T = a.offsets[b + 1] - a.offsets[b];
-            nc = (int)((T + a.L - 1) / a.L);
-            ns = (nc + a.S - 1) / a.S;
+    for (int64_t base = 0; base < nseq; base += TILE) {
+        const int64_t b0 = base + (int64_t)t * PER;
+        int64_t o[PER + 1];
+#pragma unroll
+        for (int k = 0; k <= PER; ++k) o[k] = offsets[min(b0 + k, nseq)];
+        int nc[PER], ns[PER], sc = 0, ss = 0;
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const bool in = b0 + k < nseq;
+            nc[k] = in ? (int)((o[k + 1] - o[k] + L - 1) / L) : 0;
+            ns[k] = (nc[k] + S - 1) / S;
+            sc += nc[k];
+            ss += ns[k];
         }
-        s_nc[t] = nc;
-        s_ns[t] = ns;
+        int ic = sc, is = ss;   // inclusive scans over the wave
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const int u = __shfl_up(ic, d), v = __shfl_up(is, d);
+            if (lane >= d) {
+                ic += u;
+                is += v;
+            }
+        }
+        if (lane == 63) {
+            w_nc[wv] = ic;
+            w_ns[wv] = is;
+        }
         __syncthreads();
-        for (int o = 1; o < BLOCK; o <<= 1) {   // Hillis-Steele inclusive scans
-            const int u = t >= o ? s_nc[t - o] : 0;
-            const int v = t >= o ? s_ns[t - o] : 0;
-            __syncthreads();
-            s_nc[t] += u;
-            s_ns[t] += v;
-            __syncthreads();
+        int cc = carry_c + ic - sc, cs = carry_s + is - ss, tc = 0, ts = 0;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+            if (w < wv) {
+                cc += w_nc[w];
+                cs += w_ns[w];
+            }
+            tc += w_nc[w];
+            ts += w_ns[w];
         }
-        if (b < a.nseq) {
-            a.cbase[b] = carry_c + s_nc[t] - nc;
-            a.sbase[b] = carry_s + s_ns[t] - ns;
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            if (b0 + k < nseq) {
+                cbase[b0 + k] = cc;
+                sbase[b0 + k] = cs;
+            }
+            cc += nc[k];
+            cs += ns[k];
         }
-        carry_c += s_nc[BLOCK - 1];
-        carry_s += s_ns[BLOCK - 1];
-        __syncthreads();
+        carry_c += tc;
+        carry_s += ts;
+        __syncthreads();   // the wave totals are rewritten by the next tile
     }
     if (t == 0) {
-        a.cbase[a.nseq] = carry_c;
-        a.sbase[a.nseq] = carry_s;
+        cbase[nseq] = carry_c;
+        sbase[nseq] = carry_s;
     }
+}
+
+__device__ void plan_block(const PlanArgs &a) {
+    plan_scan<BLOCK, 4>(a.offsets, a.nseq, a.L, a.S, a.cbase, a.sbase);
 }
 
 // Block 0 computes the initial probabilities, the per-state emission
@@ -267,48 +302,10 @@ template void launch_stage<double>(const RawModel &, void *, StagedModel<double>
                                    const PlanArgs *);
 
 // cbase[b] = sum_{b' < b} ceil(T_b' / L) and sbase[b] = sum_{b' < b}
-// ceil(nchunks_b' / S); single block, exclusive scans in tiles of 1024.
-__device__ __forceinline__ int block_incl_scan(int v, int *sh) {
-    sh[threadIdx.x] = v;
-    __syncthreads();
-    for (int o = 1; o < 1024; o <<= 1) {   // Hillis-Steele inclusive scan
-        int u = (threadIdx.x >= (unsigned)o) ? sh[threadIdx.x - o] : 0;
-        __syncthreads();
-        sh[threadIdx.x] += u;
-        __syncthreads();
-    }
-    return sh[threadIdx.x];
-}
-
+// ceil(nchunks_b' / S), one block of 1024 threads.
 __global__ __launch_bounds__(1024) void k_plan_chunks(const int64_t *offsets, int64_t nseq, int L,
                                                       int S, int *cbase, int *sbase) {
-    __shared__ int sh[1024];
-    int carry_c = 0, carry_s = 0;
-    for (int64_t base = 0; base < nseq; base += 1024) {
-        int64_t b = base + threadIdx.x;
-        int nc = 0, ns = 0;
-        if (b < nseq) {
-            int64_t T = offsets[b + 1] - offsets[b];
-            nc = (int)((T + L - 1) / L);
-            ns = (nc + S - 1) / S;
-        }
-        int ic = block_incl_scan(nc, sh);
-        int tc = sh[1023];
-        __syncthreads();
-        int is = block_incl_scan(ns, sh);
-        int ts = sh[1023];
-        __syncthreads();
-        if (b < nseq) {
-            cbase[b] = carry_c + ic - nc;
-            sbase[b] = carry_s + is - ns;
-        }
-        carry_c += tc;
-        carry_s += ts;
-    }
-    if (threadIdx.x == 0) {
-        cbase[nseq] = carry_c;
-        sbase[nseq] = carry_s;
-    }
+    plan_scan<1024, 4>(offsets, nseq, L, S, cbase, sbase);
 }
 
 void launch_plan_chunks(const int64_t *offsets, int64_t nseq, int L, int S, int *cbase,
