@@ -414,7 +414,7 @@ void launch_chunk_desc(const int64_t *offsets, int64_t nseq, int L, int S, const
 // is the sum of the log-likelihoods of the sequences with status 0 (a block
 // tree of its own).
 constexpr int RED_G = 64;
-constexpr int RED_U = 4;
+constexpr int RED_U = 16;   // loads in flight per lane (a group's rows in one round)
 
 int64_t reduce_scratch_len(int64_t nparts, int64_t S) {
     return nparts > RED_G ? ((nparts + RED_G - 1) / RED_G) * S : 0;
@@ -431,9 +431,12 @@ __device__ __forceinline__ double block_rows_sum(const double *__restrict__ rows
             double v[RED_U];
 #pragma unroll
             for (int u = 0; u < RED_U; ++u) {
+                // clamped unconditional loads (r < r1), so all are in flight
                 const int q = r + u * (BLOCK / 64);
-                v[u] = q < r1 ? rows[(int64_t)q * S + s] : 0.0;
+                const double x = rows[(int64_t)min(q, r1 - 1) * S + s];
+                v[u] = q < r1 ? x : 0.0;
             }
+            __builtin_amdgcn_sched_barrier(0);   // keep every load ahead of the sums
 #pragma unroll
             for (int u = 0; u < RED_U; ++u) acc += v[u];
         }
@@ -462,9 +465,24 @@ __global__ __launch_bounds__(BLOCK) void k_reduce_final(const double *__restrict
                                                        double *stats) {
     if (blockIdx.x == gridDim.x - 1) {
         __shared__ double sh[BLOCK];
+        // a lane's sequences b = lane, lane + BLOCK, ... in order, eight
+        // loads of each array in flight at a time
+        constexpr int U = 8;
         double acc = 0.0;
-        for (int64_t b = threadIdx.x; b < nseq; b += BLOCK)
-            if (status[b] == 0) acc += loglik[b];
+        for (int64_t b0 = threadIdx.x; b0 < nseq; b0 += (int64_t)BLOCK * U) {
+            double lv[U];
+            int32_t sv[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int64_t b = min(b0 + (int64_t)u * BLOCK, nseq - 1);
+                lv[u] = loglik[b];
+                sv[u] = status[b];
+            }
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (b0 + (int64_t)u * BLOCK < nseq && sv[u] == 0) acc += lv[u];
+        }
         sh[threadIdx.x] = acc;
         __syncthreads();
         for (int o = BLOCK / 2; o > 0; o >>= 1) {
