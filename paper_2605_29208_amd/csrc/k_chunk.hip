@@ -216,13 +216,25 @@ __global__ __launch_bounds__(BLOCK) void k_chunk_product(ChunkGeom g, const Supe
     }
     double msum = 0.0;
     bool bad = false;
-    for (int tt = li; tt < nsteps; tt += G) {
+    // scalar families: one observation per step, shared by all states; a
+    // lane's observations are all loaded up front (clamped rows, so the loads
+    // are unconditional and in flight together)
+    constexpr int NI = L / G;   // steps a lane tabulates, at most
+    R ypre[FAM != HMM_TABLE ? NI : 1];
+    if constexpr (FAM != HMM_TABLE) {
+        const int64_t rlast = off + ts + max(nsteps - 1, 0);
+#pragma unroll
+        for (int k = 0; k < NI; ++k) ypre[k] = load_obs<R>(g.obs, min(off + ts + li + k * G, rlast));
+    }
+#pragma unroll
+    for (int k = 0; k < NI; ++k) {
+        const int tt = li + k * G;
+        if (tt >= nsteps) break;
         const int64_t row = off + ts + tt;
         ET ell[G];
         ET mx = neg_inf<ET>();
         double common = 0.0;
-        // scalar families: one observation per step, loaded once for all states
-        const R y = (FAM != HMM_TABLE) ? load_obs<R>(g.obs, row) : (R)0;
+        const R y = (FAM != HMM_TABLE) ? ypre[FAM != HMM_TABLE ? k : 0] : (R)0;
 #pragma unroll
         for (int j = 0; j < G; ++j) {
             const bool live = j < N;
@@ -624,13 +636,26 @@ __global__ __launch_bounds__(BLOCK) void k_chunk_stats(ChunkGeom g, StagedModel<
         const bool first = (t0 == 0);
 
         // 1. emission table (lane p takes frame slots p, p + G, ...)
-        for (int tt = p; tt < L; tt += G) {
+        // a lane's observations loaded up front at clamped rows (unconditional
+        // loads, in flight together)
+        constexpr int NI = L / G;
+        R ypre[FAM != HMM_TABLE ? NI : 1];
+        if constexpr (FAM != HMM_TABLE) {
+#pragma unroll
+            for (int k = 0; k < NI; ++k) {
+                const int tt = p + k * G;
+                ypre[k] = load_obs<R>(g.obs, (valid && tt >= tt0) ? off + t0 + (tt - tt0) : off + t0);
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < NI; ++k) {
+            const int tt = p + k * G;
             const bool act = valid && tt >= tt0;
             const int64_t row = off + t0 + (tt - tt0);
             ET ell[G];
             ET mx = neg_inf<ET>();
             R y1 = (R)1;
-            const R y = (FAM != HMM_TABLE && act) ? load_obs<R>(g.obs, row) : (R)1;
+            const R y = (FAM != HMM_TABLE && act) ? ypre[FAM != HMM_TABLE ? k : 0] : (R)1;
 #pragma unroll
             for (int j = 0; j < G; ++j) {
                 const bool lj = j < N;
