@@ -272,6 +272,21 @@ struct StateConsts {
     R c0, c1, c2, c3, c4;
 };
 
+// State j's constants with no condition on the load (j must be a valid
+// state), for callers that mask dead states afterwards (emit_scalar does):
+// the loads of many states can then be in flight together.
+template <typename R>
+__device__ __forceinline__ StateConsts<R> load_consts_row(const R *ep, int j) {
+    const R *q = ep + j * EP_STRIDE;
+    StateConsts<R> s;
+    s.c0 = q[0];
+    s.c1 = q[1];
+    s.c2 = q[2];
+    s.c3 = q[3];
+    s.c4 = q[4];
+    return s;
+}
+
 template <typename R>
 __device__ __forceinline__ StateConsts<R> load_consts(const R *ep, int j, bool live) {
     StateConsts<R> s;

@@ -169,41 +169,93 @@ __device__ __forceinline__ double tab_step_obs(const StepObs<R, NP, FAM> &o, int
     double common = 0.0;
     R y = (R)0;
     if constexpr (FAM != HMM_TABLE) y = o.v[0];
-#pragma unroll 4
-    for (int j = 0; j < NP; ++j) {
-        const bool live = j < N;
-        Emit<ET> em;
-        if constexpr (FAM == HMM_TABLE) {
-            R v = live ? o.v[j] : neg_inf<R>();
-            em.ell = v;
-            em.common = 0.0;
-            em.bad = live && (isnan(v) || (v > (R)0 && isinf(v)));
-        } else {
-            em = emit_scalar<FAM, ET>((ET)y, load_consts(ep, j, live), live);
+    // states in groups of eight: the group's constants are all requested
+    // before any is used, so the group waits on one load latency, not eight
+    constexpr int GQ = 8;
+    static_assert(NP % GQ == 0, "whole groups of states");
+    for (int j0 = 0; j0 < NP; j0 += GQ) {
+        StateConsts<ET> kq[GQ];
+        if constexpr (FAM != HMM_TABLE) {
+#pragma unroll
+            for (int u = 0; u < GQ; ++u) kq[u] = load_consts_row(ep, j0 + u < N ? j0 + u : 0);
+            __builtin_amdgcn_sched_barrier(0);
         }
-        if constexpr (!RECOMP) erow[j] = em.ell;
-        mx = fmax(mx, em.ell);
-        common = em.common;
-        *bad |= em.bad;
+#pragma unroll
+        for (int u = 0; u < GQ; ++u) {
+            const int j = j0 + u;
+            const bool live = j < N;
+            Emit<ET> em;
+            if constexpr (FAM == HMM_TABLE) {
+                R v = live ? o.v[j] : neg_inf<R>();
+                em.ell = v;
+                em.common = 0.0;
+                em.bad = live && (isnan(v) || (v > (R)0 && isinf(v)));
+            } else {
+                em = emit_scalar<FAM, ET>((ET)y, kq[u], live);
+            }
+            if constexpr (!RECOMP) erow[j] = em.ell;
+            mx = fmax(mx, em.ell);
+            common = em.common;
+            *bad |= em.bad;
+        }
     }
-#pragma unroll 4
-    for (int j = 0; j < NP; ++j) {
-        ET ell;
-        if constexpr (RECOMP) ell = emit_scalar<FAM, ET>((ET)y, load_consts(ep, j, j < N), j < N).ell;
-        else ell = erow[j];
-        erow[j] = (ell == neg_inf<ET>()) ? (R)0 : fexp_e((R)(ell - mx));
+    for (int j0 = 0; j0 < NP; j0 += GQ) {
+        StateConsts<ET> kq[GQ];
+        if constexpr (RECOMP) {
+#pragma unroll
+            for (int u = 0; u < GQ; ++u) kq[u] = load_consts_row(ep, j0 + u < N ? j0 + u : 0);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+#pragma unroll
+        for (int u = 0; u < GQ; ++u) {
+            const int j = j0 + u;
+            ET ell;
+            if constexpr (RECOMP) ell = emit_scalar<FAM, ET>((ET)y, kq[u], j < N).ell;
+            else ell = erow[j];
+            erow[j] = (ell == neg_inf<ET>()) ? (R)0 : fexp_e((R)(ell - mx));
+        }
     }
     *y1 = y;
     *ly1 = (FAM == HMM_GAMMA && y > (R)0) ? flog(y) : (R)0;
     return (double)mx + common;
 }
 
+// The same with the loads in place.  The table family reads its row eight
+// states at a time here (rather than the whole row into registers first), so
+// that kernels running many lane groups keep their register count down.
 template <typename R, int NP, int FAM>
 __device__ __forceinline__ double tab_step(const WaveGeom &g, int N, int64_t row,
                                            const typename EmitTraits<FAM, R>::T *ep, R *erow,
                                            R *y1, R *ly1, bool *bad) {
-    return tab_step_obs<R, NP, FAM>(load_step_obs<R, NP, FAM>(g, N, row), N, ep, erow, y1, ly1,
-                                    bad);
+    if constexpr (FAM == HMM_TABLE) {
+        constexpr int GQ = 8;
+        R mx = neg_inf<R>();
+        for (int j0 = 0; j0 < NP; j0 += GQ) {
+            R v[GQ];
+#pragma unroll
+            for (int u = 0; u < GQ; ++u) v[u] = load_obs<R>(g.obs, row * N + min(j0 + u, N - 1));
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int u = 0; u < GQ; ++u) {
+                const bool live = j0 + u < N;
+                const R x = live ? v[u] : neg_inf<R>();
+                *bad |= live && (isnan(x) || (x > (R)0 && isinf(x)));
+                erow[j0 + u] = x;
+                mx = fmax(mx, x);
+            }
+        }
+#pragma unroll 8
+        for (int j = 0; j < NP; ++j) {
+            const R ell = erow[j];
+            erow[j] = (ell == neg_inf<R>()) ? (R)0 : fexp_e((R)(ell - mx));
+        }
+        *y1 = (R)0;
+        *ly1 = (R)0;
+        return (double)mx;
+    } else {
+        return tab_step_obs<R, NP, FAM>(load_step_obs<R, NP, FAM>(g, N, row), N, ep, erow, y1,
+                                        ly1, bad);
+    }
 }
 
 // out = sum_i v_i c_i with v broadcast from LDS (four independent chains, so
@@ -288,12 +340,17 @@ __global__ __launch_bounds__(64) void k_wave_sweep(WaveGeom g, StagedModel<R> m,
     // the end of chunk c - 1)
     const int nk = fwd ? nc : (nc > 0 ? nc - 1 : 0);
     const int nkmax = wave_max_i(nk);
+    // the lane's column (forward) or row (backward) of A: clamped loads, all
+    // in flight before the masking
     R coef[RPL];
 #pragma unroll
     for (int r = 0; r < RPL; ++r) {
-        const int i = h * RPL + r;
-        coef[r] = (live && i < N) ? (fwd ? m.A[i * N + j] : m.A[j * N + i]) : (R)0;
+        const int i = min(h * RPL + r, N - 1), jj = min(j, N - 1);
+        coef[r] = fwd ? m.A[i * N + jj] : m.A[jj * N + i];
     }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) coef[r] = (live && h * RPL + r < N) ? coef[r] : (R)0;
     bool bad = false;
     const int nrm = *m.nrm;   // steps between rescalings (both directions)
     R v = (tv && live) ? (R)1 : (R)0;   // running alpha (forward) or beta (backward)
