@@ -212,7 +212,7 @@ __global__ __launch_bounds__(BLOCK) void k_chunk_product(ChunkGeom g, const Supe
     StateConsts<ET> kc[G];
     if constexpr (FAM != HMM_POISSON) {
 #pragma unroll
-        for (int j = 0; j < G; ++j) kc[j] = load_consts(ep, j, j < N);
+        for (int j = 0; j < G; ++j) kc[j] = load_consts_row(ep, j < N ? j : 0);   // dead states masked by emit_step
     }
     double msum = 0.0;
     bool bad = false;
@@ -591,15 +591,25 @@ __global__ __launch_bounds__(BLOCK) void k_chunk_stats(ChunkGeom g, StagedModel<
     StateConsts<ET> kc[G];   // as in phase 1
     if constexpr (FAM != HMM_POISSON) {
 #pragma unroll
-        for (int j = 0; j < G; ++j) kc[j] = load_consts(ep, j, j < N);
+        for (int j = 0; j < G; ++j) kc[j] = load_consts_row(ep, j < N ? j : 0);   // dead states masked by emit_step
     }
     R coefC[G], coefR[G];
 #pragma unroll
     for (int q = 0; q < G; ++q) {
         // state order for the LDS exchange, grp_dot order for DPP
         int i = XL ? q : grp_src(p, q);
-        coefC[q] = (live && i < N) ? m.A[i * N + p] : (R)0;
-        coefR[q] = (live && i < N) ? m.A[p * N + i] : (R)0;
+        // clamped unconditional loads, masked once all are in flight
+        const int ic = min(i, N - 1), pc = min(p, N - 1);
+        coefC[q] = m.A[ic * N + pc];
+        coefR[q] = m.A[pc * N + ic];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int q = 0; q < G; ++q) {
+        const int i = XL ? q : grp_src(p, q);
+        const bool in = live && i < N;
+        coefC[q] = in ? coefC[q] : (R)0;
+        coefR[q] = in ? coefR[q] : (R)0;
     }
     const R pi_p = live ? m.pi[p] : (R)0;
     const int nrm = *m.nrm;
@@ -647,6 +657,12 @@ __global__ __launch_bounds__(BLOCK) void k_chunk_stats(ChunkGeom g, StagedModel<
                 ypre[k] = load_obs<R>(g.obs, (valid && tt >= tt0) ? off + t0 + (tt - tt0) : off + t0);
             }
         }
+        // the chunk's boundary vectors, requested after the observations (the
+        // load counter drains in order) so that their latency overlaps the
+        // emission table (clamped rows: unconditional loads)
+        const int cc = min(c, g.C - 1);
+        const R ap_in = Fi[(size_t)max(cc - 1, 0) * G + p];
+        const R gi_in = Gi[(size_t)cc * G + p];
 #pragma unroll
         for (int k = 0; k < NI; ++k) {
             const int tt = p + k * G;
@@ -678,7 +694,7 @@ __global__ __launch_bounds__(BLOCK) void k_chunk_stats(ChunkGeom g, StagedModel<
         __syncthreads();
 
         // 3. forward from the chunk's boundary; alpha history into LDS
-        const R ap = (valid && !first) ? Fi[(size_t)(c - 1) * G + p] : (R)0;
+        const R ap = (valid && !first) ? ap_in : (R)0;
         R start;
         {
             R v = pi_p * tab[grp][tt0 < L ? tt0 : L - 1][p];   // tt0 = L: idle group
@@ -711,7 +727,7 @@ __global__ __launch_bounds__(BLOCK) void k_chunk_stats(ChunkGeom g, StagedModel<
         for (int q = 0; q < G; ++q) U[q] = (R)0;
 #pragma unroll
         for (int q = 0; q < KK; ++q) fa[q] = (R)0;
-        R bcur = valid ? Gi[(size_t)c * G + p] : (R)0;
+        R bcur = valid ? gi_in : (R)0;
         const bool own = use && live;
         {   // gamma at the chunk's last step
             R h = acur * bcur;
