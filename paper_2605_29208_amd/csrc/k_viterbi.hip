@@ -42,25 +42,41 @@ __device__ __forceinline__ double vit_tab_step(const StagedModel<R> &m, const Ob
             }
         }
     } else if constexpr (FAM == HMM_TABLE) {
-#pragma unroll 4
-        for (int j = 0; j < NMAX; ++j) {
-            if (j < N) {
-                const R v = load_obs<R>(o, row * N + j);
-                *bad |= isnan(v) || (v > (R)0 && isinf(v));
-                lrow[j] = v;
+        // eight states at a time: clamped loads, all in flight before use
+        constexpr int GQ = NMAX < 8 ? NMAX : 8;
+        static_assert(NMAX % GQ == 0, "whole groups of states");
+        for (int j0 = 0; j0 < NMAX; j0 += GQ) {
+            R v[GQ];
+#pragma unroll
+            for (int u = 0; u < GQ; ++u) v[u] = load_obs<R>(o, row * N + min(j0 + u, N - 1));
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int u = 0; u < GQ; ++u) {
+                if (j0 + u < N) {
+                    *bad |= isnan(v[u]) || (v[u] > (R)0 && isinf(v[u]));
+                    lrow[j0 + u] = v[u];
+                }
             }
         }
     } else {
         using ET = typename EmitTraits<FAM, R>::T;
         const ET *ep = consts_ptr<FAM, R>(m);
         const ET y = load_obs<ET>(o, row);
-#pragma unroll 4
-        for (int j = 0; j < NMAX; ++j) {
-            if (j < N) {
-                const Emit<ET> e = emit_scalar<FAM, ET>(y, load_consts(ep, j, true), true);
-                lrow[j] = (R)e.ell;
-                common = e.common;
-                *bad |= e.bad;
+        constexpr int GQ = NMAX < 8 ? NMAX : 8;
+        static_assert(NMAX % GQ == 0, "whole groups of states");
+        for (int j0 = 0; j0 < NMAX; j0 += GQ) {
+            StateConsts<ET> kq[GQ];
+#pragma unroll
+            for (int u = 0; u < GQ; ++u) kq[u] = load_consts_row(ep, min(j0 + u, N - 1));
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int u = 0; u < GQ; ++u) {
+                if (j0 + u < N) {
+                    const Emit<ET> e = emit_scalar<FAM, ET>(y, kq[u], true);
+                    lrow[j0 + u] = (R)e.ell;
+                    common = e.common;
+                    *bad |= e.bad;
+                }
             }
         }
     }
