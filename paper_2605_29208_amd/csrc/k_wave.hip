@@ -297,24 +297,22 @@ __device__ __forceinline__ double add_quarters(double x) {
 }
 
 // Task 2b is the forward sweep of sequence b (alpha at chunk ends, logL and
-// status), task 2b + 1 its backward sweep (beta at chunk ends).  Loops run to
-// the wave's largest trip count with per-group predicates, so every barrier
-// and cross-lane operation is reached by the whole wave.  SPL = 2 gives a
-// task two lanes per state (NP = 32, one task per wave): half h of the lanes
-// takes rows h NP/2 .. of the vector-matrix product and the halves are added
-// across the wave, which halves the dependent chain of the step; SPL = 4
-// does the same with four lanes per state for NP = 16.
+// status), task 2b + 1 its backward sweep (beta at chunk ends), one task per
+// wave.  SPL = 64 / NP lanes per state: for NP = 32 half h of the lanes takes
+// rows h NP/2 .. of the vector-matrix product and the halves are added across
+// the wave, which halves the dependent chain of the step; SPL = 4 does the
+// same with four lanes per state for NP = 16.
 template <typename R, int NP, int FAM, int SPL>
 __global__ __launch_bounds__(64) void k_wave_sweep(WaveGeom g, StagedModel<R> m, R *__restrict__ F,
                                                    R *__restrict__ Gb, double *__restrict__ loglik,
                                                    int32_t *__restrict__ status) {
-    static_assert(SPL == 1 || NP * SPL == 64, "split tasks fill the wave");
+    static_assert(NP * SPL == 64, "one task per wave");
     constexpr int LPT = NP * SPL;   // lanes per task
-    constexpr int NG = 64 / LPT;    // tasks per wave
+    constexpr int NG = 64 / LPT;    // tasks per wave (one)
     constexpr int RPL = NP / SPL;   // rows of the product per lane
     constexpr int VS = NP + 4;
-    // one-task waves tabulate two chunks per window
-    __shared__ R esh[NG][NG == 1 ? 2 * WL : WL][NP + 1];
+    // a window of the emission table holds two chunks
+    __shared__ R esh[NG][2 * WL][NP + 1];
     __shared__ __align__(16) R vsh[NG][VS];
     using ET = typename EmitTraits<FAM, R>::T;
     const ET *ep = consts_ptr<FAM, R>(m);
@@ -324,22 +322,16 @@ __global__ __launch_bounds__(64) void k_wave_sweep(WaveGeom g, StagedModel<R> m,
     const bool tv = task < 2 * g.nseq;
     const int64_t b = tv ? (task >> 1) : 0;
     // one task per wave: the direction is uniform, so its branches are scalar
-    const bool fwd = NG == 1 ? __builtin_amdgcn_readfirstlane((int)((task & 1) == 0)) != 0
-                             : (task & 1) == 0;
+    const bool fwd = __builtin_amdgcn_readfirstlane((int)((task & 1) == 0)) != 0;
     const int N = m.N;
     const bool live = j < N;
     const int64_t off = g.offsets[b];
     int T = tv ? (int)(g.offsets[b + 1] - off) : 0;
     int cb = g.cbase[b];
-    if constexpr (NG == 1) {   // uniform per wave: keep the loop control scalar
-        T = __builtin_amdgcn_readfirstlane(T);
-        cb = __builtin_amdgcn_readfirstlane(cb);
-    }
+    // uniform per wave: keep the loop control scalar
+    T = __builtin_amdgcn_readfirstlane(T);
+    cb = __builtin_amdgcn_readfirstlane(cb);
     const int nc = (T + WL - 1) / WL;
-    // windows: forward 0 .. nc-1; backward nc-1 .. 1 (window c yields beta at
-    // the end of chunk c - 1)
-    const int nk = fwd ? nc : (nc > 0 ? nc - 1 : 0);
-    const int nkmax = wave_max_i(nk);
     // the lane's column (forward) or row (backward) of A: clamped loads, all
     // in flight before the masking
     R coef[RPL];
@@ -358,135 +350,90 @@ __global__ __launch_bounds__(64) void k_wave_sweep(WaveGeom g, StagedModel<R> m,
     int64_t E = 0;
     if (tv && !fwd && h == 0) Gb[(size_t)(cb + nc - 1) * NP + j] = v;
 
-    if constexpr (NG == 1) {
-        // One task per wave: the direction, the length and the step are
-        // uniform, so the loops below have scalar control.  A window is two
-        // chunks (64 steps, one step per lane for the emission table), and the
-        // observations of the next window are loaded into registers while the
-        // current one runs, so the table of a window waits on no memory.
-        // Rescaling points and stored boundaries are those of one-chunk
-        // windows: forward after steps t = nrm - 1 (mod nrm), the last step and
-        // t = 0, boundary at every chunk end; backward after the steps whose
-        // distance to their chunk's end is nrm - 1 (mod nrm) and at the chunk's
-        // first step, boundary beta at the end of the previous chunk.
-        constexpr int WW = 2 * WL;
-        static_assert(WW == LPT, "one window step per lane");
-        const int nw = (T + WW - 1) / WW;
-        // window k covers steps [lo, hi); the backward skips chunk 0
-        auto wlo = [&](int k) { return fwd ? k * WW : max(k * WW, WL); };
-        auto whi = [&](int k) { return min(T, k * WW + WW); };
-        const int k0 = fwd ? 0 : nw - 1, kstep = fwd ? 1 : -1;
-        const int kend = fwd ? nw : -1;
-        StepObs<R, NP, FAM> pre;
-        if (k0 != kend && wlo(k0) < whi(k0))
-            pre = load_step_obs<R, NP, FAM>(g, N, off + min(wlo(k0) + sl, whi(k0) - 1));
-        for (int k = k0; k != kend; k += kstep) {
-            const int lo = wlo(k), hi = whi(k), wn = hi - lo;
-            if (wn <= 0) continue;
-            __syncthreads();
-            double msum = 0.0;
-            if (sl < wn) {
-                R y, ly;
-                msum = tab_step_obs<R, NP, FAM>(pre, N, ep, &esh[0][sl][0], &y, &ly, &bad);
-            }
-            const double wsum = grp_all<LPT, false>(msum);
-            if (fwd) logS += wsum;
-            __syncthreads();
-            // the next window's observations, in flight during this window
-            const int kn = k + kstep;
-            if (kn != kend && wlo(kn) < whi(kn))
-                pre = load_step_obs<R, NP, FAM>(g, N, off + min(wlo(kn) + sl, whi(kn) - 1));
-            if (fwd) {
-                R e_cur = esh[0][0][j];
-                for (int t = lo; t < hi; ++t) {
-                    const int q = t - lo;
-                    R nv;
-                    if (t == 0) {   // alpha_0 = pi o e_0
-                        nv = live ? m.pi[j] * e_cur : (R)0;
-                    } else {
-                        vsh[0][j] = v;   // both halves store the same value
-                        wave_lds_order();
-                        R acc = lds_dot<R, RPL>(&vsh[0][h * RPL], coef);
-                        if constexpr (SPL == 2) acc = add_halves(acc);
-                        if constexpr (SPL == 4) acc = add_quarters(acc);
-                        wave_lds_order();
-                        nv = e_cur * acc;
-                    }
-                    e_cur = esh[0][q + 1 < wn ? q + 1 : q][j];
-                    if (t == 0 || (t & (nrm - 1)) == nrm - 1 || t == T - 1) {
-                        const int ex = fexp(grp_max_nn<LPT>(nv));
-                        v = fldexp(nv, -ex);
-                        E += ex;
-                    } else {
-                        v = nv;
-                    }
-                    if ((t % WL == WL - 1 || t == T - 1) && h == 0) F[(size_t)(cb + t / WL) * NP + j] = v;
-                }
-            } else {
-                R e_cur = esh[0][wn - 1][j];
-                for (int t = hi - 1; t >= lo; --t) {
-                    const int q = t - lo;
-                    vsh[0][j] = e_cur * v;
-                    wave_lds_order();
-                    R acc = lds_dot<R, RPL>(&vsh[0][h * RPL], coef);
-                    if constexpr (SPL == 2) acc = add_halves(acc);
-                    if constexpr (SPL == 4) acc = add_quarters(acc);
-                    e_cur = esh[0][q > 0 ? q - 1 : q][j];
-                    wave_lds_order();
-                    const int c = t / WL;
-                    const int dist = min(T, c * WL + WL) - 1 - t;   // to the chunk's last step
-                    if ((dist & (nrm - 1)) == nrm - 1 || t == c * WL) {
-                        const int ex = fexp(grp_max_nn<LPT>(acc));
-                        v = fldexp(acc, -ex);
-                    } else {
-                        v = acc;
-                    }
-                    if (t == c * WL && h == 0) Gb[(size_t)(cb + c - 1) * NP + j] = v;
-                }
-            }
-        }
-    } else
-    for (int k = 0; k < nkmax; ++k) {
-        const bool act = k < nk;
-        const int c = fwd ? k : nc - 1 - k;
-        const int w0 = c * WL;
-        const int wn = act ? min(WL, T - w0) : 0;
+    // One task per wave: the direction, the length and the step are
+    // uniform, so the loops below have scalar control.  A window is two
+    // chunks (64 steps, one step per lane for the emission table), and the
+    // observations of the next window are loaded into registers while the
+    // current one runs, so the table of a window waits on no memory.
+    // Rescaling points and stored boundaries are those of one-chunk
+    // windows: forward after steps t = nrm - 1 (mod nrm), the last step and
+    // t = 0, boundary at every chunk end; backward after the steps whose
+    // distance to their chunk's end is nrm - 1 (mod nrm) and at the chunk's
+    // first step, boundary beta at the end of the previous chunk.
+    constexpr int WW = 2 * WL;
+    static_assert(WW == LPT, "one window step per lane");
+    const int nw = (T + WW - 1) / WW;
+    // window k covers steps [lo, hi); the backward skips chunk 0
+    auto wlo = [&](int k) { return fwd ? k * WW : max(k * WW, WL); };
+    auto whi = [&](int k) { return min(T, k * WW + WW); };
+    const int k0 = fwd ? 0 : nw - 1, kstep = fwd ? 1 : -1;
+    const int kend = fwd ? nw : -1;
+    StepObs<R, NP, FAM> pre;
+    if (k0 != kend && wlo(k0) < whi(k0))
+        pre = load_step_obs<R, NP, FAM>(g, N, off + min(wlo(k0) + sl, whi(k0) - 1));
+    for (int k = k0; k != kend; k += kstep) {
+        const int lo = wlo(k), hi = whi(k), wn = hi - lo;
+        if (wn <= 0) continue;
         __syncthreads();
-        double msum = 0.0;   // this lane's share of the window's log shifts
-        for (int q = sl; q < wn; q += LPT) {
+        double msum = 0.0;
+        if (sl < wn) {
             R y, ly;
-            msum += tab_step<R, NP, FAM>(g, N, off + w0 + q, ep, &esh[grp][q][0], &y, &ly, &bad);
+            msum = tab_step_obs<R, NP, FAM>(pre, N, ep, &esh[0][sl][0], &y, &ly, &bad);
         }
         const double wsum = grp_all<LPT, false>(msum);
         if (fwd) logS += wsum;
         __syncthreads();
-        // step s of the window is local step s (forward) or wn - 1 - s (backward);
-        // the next step's emission factor is read one step ahead
-        R e_cur = (wn > 0) ? esh[grp][fwd ? 0 : wn - 1][j] : (R)0;
-        for (int s = 0; s < WL; ++s) {
-            const bool on = s < wn;
-            const int t = w0 + (fwd ? s : wn - 1 - s);
-            if (h == 0) vsh[grp][j] = fwd ? v : e_cur * v;
-            wave_lds_order();
-            R acc = lds_dot<R, RPL>(&vsh[grp][h * RPL], coef);
-            if constexpr (SPL == 2) acc = add_halves(acc);
-            if constexpr (SPL == 4) acc = add_quarters(acc);
-            const R e_nxt = (s + 1 < wn) ? esh[grp][fwd ? s + 1 : wn - 2 - s][j] : (R)0;
-            wave_lds_order();
-            const R nv = fwd ? ((t == 0) ? (live ? m.pi[j] * e_cur : (R)0) : e_cur * acc) : acc;
-            // rescaled every nrm steps and at the window's end (the bound of the
-            // staging kernel holds for both directions)
-            const bool rs = (s & (nrm - 1)) == nrm - 1 || s == WL - 1;   // nrm: 1, 2 or 4
-            const int ex = rs ? fexp(grp_max_nn<LPT>(nv)) : 0;
-            if (on) {
-                v = rs ? fldexp(nv, -ex) : nv;
-                if (fwd) E += ex;
+        // the next window's observations, in flight during this window
+        const int kn = k + kstep;
+        if (kn != kend && wlo(kn) < whi(kn))
+            pre = load_step_obs<R, NP, FAM>(g, N, off + min(wlo(kn) + sl, whi(kn) - 1));
+        if (fwd) {
+            R e_cur = esh[0][0][j];
+            for (int t = lo; t < hi; ++t) {
+                const int q = t - lo;
+                R nv;
+                if (t == 0) {   // alpha_0 = pi o e_0
+                    nv = live ? m.pi[j] * e_cur : (R)0;
+                } else {
+                    vsh[0][j] = v;   // both halves store the same value
+                    wave_lds_order();
+                    R acc = lds_dot<R, RPL>(&vsh[0][h * RPL], coef);
+                    if constexpr (SPL == 2) acc = add_halves(acc);
+                    if constexpr (SPL == 4) acc = add_quarters(acc);
+                    wave_lds_order();
+                    nv = e_cur * acc;
+                }
+                e_cur = esh[0][q + 1 < wn ? q + 1 : q][j];
+                if (t == 0 || (t & (nrm - 1)) == nrm - 1 || t == T - 1) {
+                    const int ex = fexp(grp_max_nn<LPT>(nv));
+                    v = fldexp(nv, -ex);
+                    E += ex;
+                } else {
+                    v = nv;
+                }
+                if ((t % WL == WL - 1 || t == T - 1) && h == 0) F[(size_t)(cb + t / WL) * NP + j] = v;
             }
-            e_cur = e_nxt;
-        }
-        if (act && h == 0) {
-            if (fwd) F[(size_t)(cb + c) * NP + j] = v;
-            else Gb[(size_t)(cb + c - 1) * NP + j] = v;
+        } else {
+            R e_cur = esh[0][wn - 1][j];
+            for (int t = hi - 1; t >= lo; --t) {
+                const int q = t - lo;
+                vsh[0][j] = e_cur * v;
+                wave_lds_order();
+                R acc = lds_dot<R, RPL>(&vsh[0][h * RPL], coef);
+                if constexpr (SPL == 2) acc = add_halves(acc);
+                if constexpr (SPL == 4) acc = add_quarters(acc);
+                e_cur = esh[0][q > 0 ? q - 1 : q][j];
+                wave_lds_order();
+                const int c = t / WL;
+                const int dist = min(T, c * WL + WL) - 1 - t;   // to the chunk's last step
+                if ((dist & (nrm - 1)) == nrm - 1 || t == c * WL) {
+                    const int ex = fexp(grp_max_nn<LPT>(acc));
+                    v = fldexp(acc, -ex);
+                } else {
+                    v = acc;
+                }
+                if (t == c * WL && h == 0) Gb[(size_t)(cb + c - 1) * NP + j] = v;
+            }
         }
     }
     const R tot = grp_all<LPT, false>((fwd && h == 0) ? v : (R)0);
