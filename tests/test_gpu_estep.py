@@ -234,3 +234,28 @@ def test_gamma_posteriors_and_posterior_decode(h, prec):
     srt = np.sort(ref["gamma"], axis=1)
     gap = srt[:, -1] - srt[:, -2]
     assert np.all((p == rp) | (gap < 1e-5))
+
+
+@pytest.mark.parametrize("fam,n", [("gamma", 8), ("gaussian", 16)])
+def test_many_short_sequences(h, fam, n):
+    """70,000 sequences of 1..40 steps: more sequences than one tile of the
+    chunk plan and than two rounds of the descriptors' block search, most
+    superchunks holding one or two chunks.  Sampled sequences against the
+    oracle, plus the pooled identities that hold at any size."""
+    rng = np.random.default_rng(77)
+    B = 70_000
+    lengths = rng.integers(1, 41, B)
+    w = workloads.random_workload(fam, n, 1, lengths, 78)
+    stats, ll, st = run_estep(h, w, "f32")
+    assert (st == 0).all()
+    pick = np.sort(rng.choice(B, 40, replace=False))
+    ref = oracle_ref(w.subset(pick))
+    assert_loglik_close(ll[pick], ref["loglik"], TOL["f32"], f"{fam} many short sampled")
+    g1 = stats[1:1 + n]
+    xi = stats[1 + n:1 + n + n * n]
+    gs = stats[1 + n + n * n:1 + 2 * n + n * n]
+    total = int(lengths.sum())
+    assert abs(g1.sum() - B) < 1e-4 * B
+    assert abs(gs.sum() - total) < 1e-4 * total
+    assert abs(xi.sum() - (total - B)) < 1e-4 * total
+    assert abs(stats[0] - ll.sum()) < 1e-9 * abs(stats[0])
