@@ -340,8 +340,7 @@ __device__ __forceinline__ int block_find_seq(const int *base, int nseq, int c0)
 // BLOCK consecutive sequences (every sequence has one chunk and one superchunk
 // or more), so after the block finds the first one, the window of BLOCK + 1
 // prefix entries that follows is staged in LDS and each thread searches it.
-__device__ __forceinline__ int window_find_seq(const int *base, int nseq, int i0, int i, int *win,
-                                               int *b0) {
+__device__ __forceinline__ int window_find_seq(const int *base, int nseq, int i0, int i, int *win) {
     const int bl = block_find_seq(base, nseq, i0);
     const int nw = min(BLOCK, nseq - bl);   // sequences in the window
     for (int k = threadIdx.x; k <= nw; k += BLOCK) win[k] = base[bl + k];
@@ -351,7 +350,6 @@ __device__ __forceinline__ int window_find_seq(const int *base, int nseq, int i0
         const int mid = (lo + hi + 1) >> 1;
         if (win[mid] <= i) lo = mid; else hi = mid - 1;
     }
-    *b0 = bl;
     return bl + lo;
 }
 
@@ -362,9 +360,8 @@ __global__ __launch_bounds__(BLOCK) void k_chunk_desc(const int64_t *offsets, in
     __shared__ int win[BLOCK + 1];
     const int i0 = blockIdx.x * BLOCK;
     const int i = i0 + threadIdx.x;
-    int bl;
     if (i0 < C) {   // uniform
-        const int b = window_find_seq(cbase, (int)nseq, i0, min(i, C - 1), win, &bl);
+        const int b = window_find_seq(cbase, (int)nseq, i0, min(i, C - 1), win);
         if (i < C) {
             int64_t off = offsets[b];
             int T = (int)(offsets[b + 1] - off);
@@ -380,7 +377,7 @@ __global__ __launch_bounds__(BLOCK) void k_chunk_desc(const int64_t *offsets, in
         __syncthreads();   // the window is reused below
     }
     if (i0 < SC) {   // uniform
-        const int b = window_find_seq(sbase, (int)nseq, i0, min(i, SC - 1), win, &bl);
+        const int b = window_find_seq(sbase, (int)nseq, i0, min(i, SC - 1), win);
         if (i < SC) {
             SuperDesc d;
             d.off = offsets[b];
