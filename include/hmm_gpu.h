@@ -86,7 +86,14 @@ typedef enum {
  *   HMM_PREC_PLAIN_F32 / HMM_PREC_PLAIN_F64: the paper's recursion taken
  *     literally on the GPU: one thread per sequence, N log-sum-exps of N terms
  *     per step, alpha and beta stored, separate kernels (the baseline).
- *   HMM_PREC_BF16_SCALED / HMM_PREC_F16_SCALED: reserved. */
+ *   HMM_PREC_BF16_SCALED / HMM_PREC_F16_SCALED: the scaled (probability
+ *     space) recursion that section 3.2 sets aside for its underflow, kept
+ *     as a low-precision option for N > 64 and the multivariate families:
+ *     the vector-matrix products run on the matrix cores with bf16 / fp16
+ *     operands and FP32 accumulation, rescaled by a power of two at every
+ *     step; alpha, gamma, the log offsets and the statistics stay FP32 / FP64.
+ *     Their error against the FP64 path is a property of the format (about
+ *     1e-5 relative on log P for fp16, 1e-4 .. 1e-3 for bf16 at N = 256). */
 typedef enum {
     HMM_PREC_F64 = 0,
     HMM_PREC_F32 = 1,
@@ -167,38 +174,60 @@ size_t hmm_stats_len(const hmm_model *model);
 hmm_status hmm_workspace_size(hmm_op op, const hmm_model *model, const hmm_batch *batch,
                               hmm_precision prec, size_t *bytes);
 
-/* log b_j(y_t) for every step of every sequence: log_b is device
- * [sum T, N], float for HMM_PREC_F32 / PLAIN_F32, double for F64 / PLAIN_F64.
- * Observations outside a family's support give -inf; non-finite ones NaN. */
+/* Emission log-densities log b_j(y_t) (the densities of section 4: 4.1
+ * Gaussian and Poisson, 4.2 Gamma, 4.3 Student-t, 4.5 diagonal and full
+ * covariance) for every step of every sequence.  log_b: device [sum T, N],
+ * row-major, float for HMM_PREC_F32 / PLAIN_F32, double for F64 / PLAIN_F64
+ * (the scaled precisions
+ * write float).  Observations outside a family's support give -inf; non-finite
+ * ones NaN.  ws: hmm_workspace_size(HMM_OP_EMISSION) bytes. */
 hmm_status hmm_emission_logpdf(const hmm_model *model, const hmm_batch *batch,
                                hmm_precision prec, void *log_b, void *ws, size_t ws_bytes,
                                void *stream);
 
-/* Forward-backward over the batch.  loglik: device [B] FP64 log P(y^b | lambda)
- * (-inf for status 1, NaN for status 2).  gamma: device [sum T, N] of
- * gamma_t(j), float or double as for hmm_emission_logpdf, or NULL.
- * seq_status: device [B] int32 or NULL. */
+/* Forward-backward over the batch: the forward recursion of section 3.2
+ * (eq. loginit / logrec, log-sum-exp as in that section), the backward
+ * recursion it computes "analogously", and the smoothed occupancies
+ * gamma_t(j) = P(q_t = j | y) of section 3.1.  loglik: device [B] FP64
+ * log P(y^b | lambda) (-inf for status 1, NaN for status 2 and 4).
+ * gamma: device [sum T, N] row-major, float or double as for
+ * hmm_emission_logpdf, or NULL; rows of sequences with a non-zero status are
+ * zero.  seq_status: device [B] int32 or NULL.
+ * ws: hmm_workspace_size(HMM_OP_FORWARD_BACKWARD) bytes. */
 hmm_status hmm_forward_backward(const hmm_model *model, const hmm_batch *batch,
                                 hmm_precision prec, double *loglik, void *gamma,
                                 int32_t *seq_status, void *ws, size_t ws_bytes, void *stream);
 
-/* One Baum-Welch E-step: pooled statistics (layout of hmm_stats_len) into
- * device `stats` (FP64, overwritten).  loglik [B] and seq_status [B] are
- * optional device outputs.  The reduction order is fixed, so repeated calls
- * on the same inputs give bitwise-identical statistics. */
+/* One Baum-Welch E-step: the forward-backward recursions of section 3.2,
+ * the posteriors gamma and xi of section 3.1, and their weighted sums (the
+ * N_j and family sums that the M-steps of section 4 read), pooled over the
+ * sequences of the batch, into device `stats` (FP64, layout of
+ * hmm_stats_len, overwritten).  loglik [B] and seq_status [B] are optional
+ * device outputs.  The reduction order is fixed, so repeated calls on the
+ * same inputs give bitwise-identical statistics.
+ * ws: hmm_workspace_size(HMM_OP_ESTEP) bytes. */
 hmm_status hmm_estep_stats(const hmm_model *model, const hmm_batch *batch, hmm_precision prec,
                            double *stats, double *loglik, int32_t *seq_status, void *ws,
                            size_t ws_bytes, void *stream);
 
-/* Viterbi decoding (section 3.3).  path: device [sum T] int32 state indices;
- * path_logp: device [B] FP64 log-probability of the returned path (-inf if
- * none).  Ties are broken towards the lowest state index.  prec must be
- * HMM_PREC_F64 or HMM_PREC_F32. */
+/* Viterbi decoding (section 3.3): the max-product recursion in log space
+ * with backtrace.  path: device [sum T] int32 state indices (-1 on every
+ * step of a sequence with no path or a non-finite observation); path_logp:
+ * device [B] FP64 log-probability of the returned path (-inf if none, NaN
+ * for a non-finite observation).  Ties are broken towards the lowest state
+ * index.  n_ties: device [B] int32, or NULL: the near-ties met along the
+ * returned path, i.e. decisions (the final state and each backpointer taken)
+ * whose best and second-best scores, shifted per step, differ by less than
+ * 1e-12; a path may differ from another exact evaluation only at such
+ * decisions.  prec must be HMM_PREC_F64 or HMM_PREC_F32; N <= 64.
+ * ws: hmm_workspace_size(HMM_OP_VITERBI) bytes. */
 hmm_status hmm_viterbi(const hmm_model *model, const hmm_batch *batch, hmm_precision prec,
-                       int32_t *path, double *path_logp, void *ws, size_t ws_bytes,
-                       void *stream);
+                       int32_t *path, double *path_logp, int32_t *n_ties, void *ws,
+                       size_t ws_bytes, void *stream);
 
-/* Posterior decoding (section 3.4): path[t] = lowest argmax_j gamma_t(j). */
+/* Posterior decoding (section 3.4): path[t] = lowest argmax_j gamma_t(j);
+ * -1 on every step of a sequence whose status is not 0.  loglik: device [B]
+ * FP64 or NULL.  ws: hmm_workspace_size(HMM_OP_POSTERIOR_DECODE) bytes. */
 hmm_status hmm_posterior_decode(const hmm_model *model, const hmm_batch *batch,
                                 hmm_precision prec, int32_t *path, double *loglik,
                                 void *ws, size_t ws_bytes, void *stream);

@@ -102,7 +102,7 @@ def _load():
         "hmm_emission_logpdf": ([MP, BP, ctypes.c_int, P, P, sz, P], ctypes.c_int),
         "hmm_forward_backward": ([MP, BP, ctypes.c_int, P, P, P, P, sz, P], ctypes.c_int),
         "hmm_estep_stats": ([MP, BP, ctypes.c_int, P, P, P, P, sz, P], ctypes.c_int),
-        "hmm_viterbi": ([MP, BP, ctypes.c_int, P, P, P, sz, P], ctypes.c_int),
+        "hmm_viterbi": ([MP, BP, ctypes.c_int, P, P, P, P, sz, P], ctypes.c_int),
         "hmm_posterior_decode": ([MP, BP, ctypes.c_int, P, P, P, sz, P], ctypes.c_int),
         "hmm_mstep_default_opts": ([OPP], None),
         "hmm_mstep_transitions": ([MP, P, OPP, P, P, P], ctypes.c_int),
@@ -241,9 +241,10 @@ def hmm_estep_stats(model, batch, prec, stats, loglik, seq_status, ws, stream=No
                                 _nbytes(ws), _stream(stream)))
 
 
-def hmm_viterbi(model, batch, prec, path, path_logp, ws, stream=None):
+def hmm_viterbi(model, batch, prec, path, path_logp, n_ties, ws, stream=None):
     _check(_lib.hmm_viterbi(ctypes.byref(model.c), ctypes.byref(batch.c), PREC[prec],
-                            _ptr(path), _ptr(path_logp), _ptr(ws), _nbytes(ws), _stream(stream)))
+                            _ptr(path), _ptr(path_logp), _ptr(n_ties), _ptr(ws), _nbytes(ws),
+                            _stream(stream)))
 
 
 def hmm_posterior_decode(model, batch, prec, path, loglik, ws, stream=None):
@@ -363,14 +364,16 @@ def emission_logpdf(model, batch, prec="f32", ws=None, stream=None):
 
 
 def viterbi(model, batch, prec="f64", ws=None, stream=None):
-    """Returns (path [sum T] int32, path log-probability [B] float64)."""
+    """Returns (path [sum T] int32, path log-probability [B] float64,
+    near-ties met along each path [B] int32)."""
     import torch
     path = torch.empty(max(batch.total, 1), dtype=torch.int32, device="cuda")
     logp = torch.empty(max(batch.n_seq, 1), dtype=torch.float64, device="cuda")
+    ties = torch.empty(max(batch.n_seq, 1), dtype=torch.int32, device="cuda")
     if ws is None:
         ws = _ws(hmm_workspace_size("viterbi", model, batch, prec))
-    hmm_viterbi(model, batch, prec, path, logp, ws, stream)
-    return path[:batch.total], logp[:batch.n_seq]
+    hmm_viterbi(model, batch, prec, path, logp, ties, ws, stream)
+    return path[:batch.total], logp[:batch.n_seq], ties[:batch.n_seq]
 
 
 def posterior_decode(model, batch, prec="f32", ws=None, stream=None):

@@ -550,15 +550,20 @@ hmm_status hmm_posterior_decode(const hmm_model *model, const hmm_batch *batch,
     hipStream_t s = (hipStream_t)stream;
     char *w = (char *)ws;
     void *gam = w + p.gam;
-    if (p.f64) st = run_posterior_path<double>(model, batch, c, p, w, loglik, nullptr, gam, nullptr, s);
-    else st = run_posterior_path<float>(model, batch, c, p, w, loglik, nullptr, gam, nullptr, s);
+    int32_t *status = (int32_t *)(w + p.st);
+    if (p.f64) st = run_posterior_path<double>(model, batch, c, p, w, loglik, status, gam, nullptr, s);
+    else st = run_posterior_path<float>(model, batch, c, p, w, loglik, status, gam, nullptr, s);
     if (st != HMM_OK) return st;
-    if (c.total > 0) launch_argmax_rows(gam, p.f64, c.total, c.N, path, s);
+    if (c.total > 0) {
+        launch_argmax_rows(gam, p.f64, c.total, c.N, path, s);
+        launch_mask_paths(batch->offsets, status, c.B, path, s);
+    }
     return device_check("posterior decode");
 }
 
 hmm_status hmm_viterbi(const hmm_model *model, const hmm_batch *batch, hmm_precision prec,
-                       int32_t *path, double *path_logp, void *ws, size_t ws_bytes, void *stream) {
+                       int32_t *path, double *path_logp, int32_t *n_ties, void *ws,
+                       size_t ws_bytes, void *stream) {
     Checked c;
     hmm_status st = check_batch(batch, model, &c);
     if (st != HMM_OK) return st;
@@ -581,11 +586,11 @@ hmm_status hmm_viterbi(const hmm_model *model, const hmm_batch *batch, hmm_preci
     if (p.f64) {
         StagedModel<double> sm;
         launch_stage<double>(raw(model), w + p.staged, &sm, s);
-        run_viterbi<double>(sm, od, cbase, cdesc, p.C, psi, J, ql, qe, path, path_logp, s);
+        run_viterbi<double>(sm, od, cbase, cdesc, p.C, psi, J, ql, qe, path, path_logp, n_ties, s);
     } else {
         StagedModel<float> sm;
         launch_stage<float>(raw(model), w + p.staged, &sm, s);
-        run_viterbi<float>(sm, od, cbase, cdesc, p.C, psi, J, ql, qe, path, path_logp, s);
+        run_viterbi<float>(sm, od, cbase, cdesc, p.C, psi, J, ql, qe, path, path_logp, n_ties, s);
     }
     return device_check("Viterbi kernels");
 }

@@ -216,11 +216,17 @@ template <typename R>
 hmm_status run_emission(const StagedModel<R> &m, const ObsDesc &o, int64_t total_steps,
                         R *out, hipStream_t s);
 
-// Viterbi (N <= 64): psi [sum T * N] bytes, J [C * N], qlast [B], qend [C]
+// Viterbi (N <= 64): psi [sum T * N] bytes, J [C * N], qlast [B], qend [C];
+// n_ties [B] (or NULL): near-ties met along each returned path
 template <typename R>
 hmm_status run_viterbi(const StagedModel<R> &m, const ObsDesc &o, const int *cbase,
                        const ChunkDesc *cdesc, int C, uint8_t *psi, uint8_t *J, uint8_t *qlast,
-                       uint8_t *qend, int32_t *path, double *logp, hipStream_t s);
+                       uint8_t *qend, int32_t *path, double *logp, int32_t *n_ties,
+                       hipStream_t s);
+
+// path[t] = -1 on every step of the sequences whose status is not 0
+void launch_mask_paths(const int64_t *offsets, const int32_t *status, int64_t nseq, int32_t *path,
+                       hipStream_t s);
 
 // M-steps (section 4), FP64 on the device
 void launch_mstep_trans(int N, const double *stats, const double *log_A_in, double eps,

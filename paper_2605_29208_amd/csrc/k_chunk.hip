@@ -736,8 +736,9 @@ __global__ __launch_bounds__(BLOCK) void k_chunk_stats(ChunkGeom g, StagedModel<
             gs += gm;
             if constexpr (K > 0)
                 fam_accumulate<FAM, R, KK>(gm, ysh[grp][L - 1][0], ysh[grp][L - 1][1], k, fa);
+            // rows of excluded sequences are written too (zeros)
             if constexpr (WG) {
-                if (own) gamma_out[(off + t0 + len - 1) * N + p] = gm;
+                if (valid && live) gamma_out[(off + t0 + len - 1) * N + p] = gm;
             }
         }
         // beta_{t-1}(i) = sum_j a_ij e_t(j) beta_t(j).  Lane i gathers
@@ -769,7 +770,7 @@ __global__ __launch_bounds__(BLOCK) void k_chunk_stats(ChunkGeom g, StagedModel<
                     fam_accumulate<FAM, R, KK>(gm, ysh[grp][tt - 1][0], ysh[grp][tt - 1][1], k,
                                                fa);
                 if constexpr (WG) {
-                    if (ok) gamma_out[(off + t0 + (tt - 1 - tt0)) * N + p] = gm;
+                    if (valid && live && tt > tt0) gamma_out[(off + t0 + (tt - 1 - tt0)) * N + p] = gm;
                 }
             }
             // rescaled every nrm steps like the forward: after a rescale, max

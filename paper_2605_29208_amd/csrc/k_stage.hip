@@ -544,4 +544,20 @@ void launch_argmax_rows(const void *gamma, bool f64, int64_t rows, int N, int32_
                            rows, N, path);
 }
 
+// one block per sequence; sequences with a non-zero status get path -1
+__global__ __launch_bounds__(BLOCK) void k_mask_paths(const int64_t *__restrict__ offsets,
+                                                      const int32_t *__restrict__ status,
+                                                      int32_t *__restrict__ path) {
+    const int64_t b = blockIdx.x;
+    if (status[b] == 0) return;
+    const int64_t o0 = offsets[b], o1 = offsets[b + 1];
+    for (int64_t r = o0 + threadIdx.x; r < o1; r += BLOCK) path[r] = -1;
+}
+
+void launch_mask_paths(const int64_t *offsets, const int32_t *status, int64_t nseq, int32_t *path,
+                       hipStream_t s) {
+    if (nseq <= 0) return;
+    hipLaunchKernelGGL(k_mask_paths, dim3((unsigned)nseq), dim3(BLOCK), 0, s, offsets, status, path);
+}
+
 }  // namespace hmmk

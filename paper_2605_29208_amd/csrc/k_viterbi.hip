@@ -9,7 +9,11 @@
 // FP64 (an exact shift for the argmax; it keeps the values small).  The
 // additions happen in the same order as in the plain definition, so with
 // identical log b inputs the FP64 path reproduces it bit for bit.
-// psi is stored as one byte per (step, state).
+// psi is stored as one byte per (step, state): the predecessor in the low
+// seven bits and, in bit 7, whether the best and second-best candidates
+// differ by less than the tie threshold (a near-tie, section 3.3 breaks
+// such ties towards the lowest index; the backtrace counts the near-ties
+// met along the returned path).
 //
 // Backtrace in three kernels: per chunk of K = 64 steps a jump table
 // J_c[j] = state just before the chunk when the chunk ends in state j (the
@@ -23,6 +27,9 @@
 namespace hmmk {
 
 constexpr int VK = 64;   // steps per backtrace chunk and per emission window
+// a decision whose best and second-best candidates differ by less than this
+// (per-step shifted scores) is a near-tie
+constexpr double VIT_TIE_EPS = 1e-12;
 
 // log b_j(y) of the NMAX states of one step, computed by one lane into its
 // LDS row (without the state-independent part, which is returned in FP64).
@@ -90,7 +97,8 @@ __global__ __launch_bounds__(64) void k_vit_forward(StagedModel<R> m, ObsRef o, 
                                                     const int64_t *__restrict__ offsets,
                                                     uint8_t *__restrict__ psi,
                                                     double *__restrict__ logp,
-                                                    uint8_t *__restrict__ qlast) {
+                                                    uint8_t *__restrict__ qlast,
+                                                    int32_t *__restrict__ n_ties, R tie_eps) {
     __shared__ R lsh[VK][NMAX + 1];
     __shared__ double csh[VK];
     __shared__ __align__(16) R dsh[64];
@@ -123,12 +131,15 @@ __global__ __launch_bounds__(64) void k_vit_forward(StagedModel<R> m, ObsRef o, 
                 // max over predecessors by a pairwise tree over contiguous
                 // blocks (log2 NMAX dependent levels); the right block wins
                 // only if strictly larger, so ties keep the lowest index.
-                // Entries past N hold -inf (col and the dead lanes' d).
-                R vv[NMAX];
+                // The runner-up value rides along (the second largest of the
+                // candidates, whatever their order).  Entries past N hold
+                // -inf (col and the dead lanes' d).
+                R vv[NMAX], v2[NMAX];
                 int aa[NMAX];
 #pragma unroll
                 for (int i = 0; i < NMAX; ++i) {
                     vv[i] = dsh[i] + col[i];
+                    v2[i] = ninf;
                     aa[i] = i;
                 }
 #pragma unroll
@@ -136,15 +147,17 @@ __global__ __launch_bounds__(64) void k_vit_forward(StagedModel<R> m, ObsRef o, 
 #pragma unroll
                     for (int k = 0; k + st < NMAX; k += 2 * st) {
                         const bool right = vv[k + st] > vv[k];
+                        v2[k] = right ? fmax(vv[k], v2[k + st]) : fmax(v2[k], vv[k + st]);
                         vv[k] = right ? vv[k + st] : vv[k];
                         aa[k] = right ? aa[k + st] : aa[k];
                     }
                 }
                 const R best = vv[0];
                 const int arg = aa[0];
+                const bool tie = best - v2[0] < tie_eps;   // -inf - -inf is NaN: not a tie
                 wave_lds_order();
                 nd = live ? (R)(best + lt) : ninf;
-                if (live) psi[(off + t) * N + j] = (uint8_t)arg;
+                if (live) psi[(off + t) * N + j] = (uint8_t)(arg | (tie ? 128 : 0));
             }
             const R mt = wave_max_r(nd);
             if (mt == ninf) dead = true;
@@ -152,25 +165,31 @@ __global__ __launch_bounds__(64) void k_vit_forward(StagedModel<R> m, ObsRef o, 
             d = (mt == ninf) ? ninf : nd - mt;
         }
     }
-    // final state: lowest argmax
-    R best = ninf;
+    // final state: lowest argmax; a near-tie there counts once
+    R best = ninf, second = ninf;
     int q = 0;
     dsh[j] = d;
     __syncthreads();
     if (j == 0) {
-        for (int i = 0; i < N; ++i)
+        for (int i = 0; i < N; ++i) {
             if (dsh[i] > best) {
+                second = best;
                 best = dsh[i];
                 q = i;
+            } else if (dsh[i] > second) {
+                second = dsh[i];
             }
+        }
         logp[b] = dead ? -__builtin_inf() : offset + (double)best;
         qlast[b] = (uint8_t)(dead ? 255 : q);
+        if (n_ties) n_ties[b] = (!dead && best - second < tie_eps) ? 1 : 0;
     }
     // a non-finite observation anywhere makes the whole sequence undecodable
     const int badw = __any(bad);
     if (j == 0 && badw) {
         logp[b] = __builtin_nan("");
         qlast[b] = 255;
+        if (n_ties) n_ties[b] = 0;
     }
 }
 
@@ -191,7 +210,7 @@ __global__ __launch_bounds__(64) void k_vit_jump(const ChunkDesc *__restrict__ c
     if (tid < N) {
         int q = tid;
         const int stop = d.t0 == 0 ? 1 : 0;   // psi_0 does not exist
-        for (int tt = d.len - 1; tt >= stop; --tt) q = blk[tt * N + q];
+        for (int tt = d.len - 1; tt >= stop; --tt) q = blk[tt * N + q] & 127;
         J[(size_t)c * N + tid] = (uint8_t)q;
     }
 }
@@ -232,11 +251,14 @@ __global__ __launch_bounds__(64) void k_vit_chain(const int *__restrict__ cbase,
     }
 }
 
-// path of every chunk from its end state (one lane chases, the wave stages psi)
+// path of every chunk from its end state (one lane chases, the wave stages
+// psi); the near-ties met on the chunk's part of the path are added to the
+// sequence's count (integer atomics: the total does not depend on the order)
 __global__ __launch_bounds__(64) void k_vit_fill(const ChunkDesc *__restrict__ cdesc, int N,
                                                  const uint8_t *__restrict__ psi,
                                                  const uint8_t *__restrict__ qend,
-                                                 int32_t *__restrict__ path) {
+                                                 int32_t *__restrict__ path,
+                                                 int32_t *__restrict__ n_ties) {
     __shared__ uint8_t blk[VK * 64];
     __shared__ int32_t out[VK];
     const int c = blockIdx.x;
@@ -251,10 +273,16 @@ __global__ __launch_bounds__(64) void k_vit_fill(const ChunkDesc *__restrict__ c
         if (q == 255) {
             for (int tt = 0; tt < d.len; ++tt) out[tt] = -1;
         } else {
+            int ties = 0;
             for (int tt = d.len - 1; tt >= 0; --tt) {
                 out[tt] = q;
-                if (tt > 0 || d.t0 > 0) q = blk[tt * N + q];
+                if (tt > 0 || d.t0 > 0) {
+                    const int e = blk[tt * N + q];
+                    ties += e >> 7;
+                    q = e & 127;
+                }
             }
+            if (n_ties && ties) atomicAdd(n_ties + d.b, ties);
         }
     }
     __syncthreads();
@@ -263,41 +291,43 @@ __global__ __launch_bounds__(64) void k_vit_fill(const ChunkDesc *__restrict__ c
 
 template <typename R, int NMAX, int FAM>
 static void launch_vit_forward_f(const StagedModel<R> &m, const ObsDesc &o, uint8_t *psi,
-                                 double *logp, uint8_t *qlast, hipStream_t s) {
+                                 double *logp, uint8_t *qlast, int32_t *n_ties, hipStream_t s) {
     hipLaunchKernelGGL((k_vit_forward<R, NMAX, FAM>), dim3((unsigned)o.nseq), dim3(64), 0, s, m,
-                       ObsRef{o.obs, o.obs_f64}, o.nseq, o.offsets, psi, logp, qlast);
+                       ObsRef{o.obs, o.obs_f64}, o.nseq, o.offsets, psi, logp, qlast, n_ties,
+                       (R)VIT_TIE_EPS);
 }
 
 template <typename R, int NMAX>
 static void launch_vit_forward_n(const StagedModel<R> &m, const ObsDesc &o, uint8_t *psi,
-                                 double *logp, uint8_t *qlast, hipStream_t s) {
+                                 double *logp, uint8_t *qlast, int32_t *nt, hipStream_t s) {
     switch (m.family) {
-    case HMM_GAUSSIAN: return launch_vit_forward_f<R, NMAX, HMM_GAUSSIAN>(m, o, psi, logp, qlast, s);
-    case HMM_GAMMA: return launch_vit_forward_f<R, NMAX, HMM_GAMMA>(m, o, psi, logp, qlast, s);
-    case HMM_STUDENT_T: return launch_vit_forward_f<R, NMAX, HMM_STUDENT_T>(m, o, psi, logp, qlast, s);
-    case HMM_POISSON: return launch_vit_forward_f<R, NMAX, HMM_POISSON>(m, o, psi, logp, qlast, s);
-    case HMM_TABLE: return launch_vit_forward_f<R, NMAX, HMM_TABLE>(m, o, psi, logp, qlast, s);
-    default: return launch_vit_forward_f<R, NMAX, -1>(m, o, psi, logp, qlast, s);
+    case HMM_GAUSSIAN: return launch_vit_forward_f<R, NMAX, HMM_GAUSSIAN>(m, o, psi, logp, qlast, nt, s);
+    case HMM_GAMMA: return launch_vit_forward_f<R, NMAX, HMM_GAMMA>(m, o, psi, logp, qlast, nt, s);
+    case HMM_STUDENT_T: return launch_vit_forward_f<R, NMAX, HMM_STUDENT_T>(m, o, psi, logp, qlast, nt, s);
+    case HMM_POISSON: return launch_vit_forward_f<R, NMAX, HMM_POISSON>(m, o, psi, logp, qlast, nt, s);
+    case HMM_TABLE: return launch_vit_forward_f<R, NMAX, HMM_TABLE>(m, o, psi, logp, qlast, nt, s);
+    default: return launch_vit_forward_f<R, NMAX, -1>(m, o, psi, logp, qlast, nt, s);
     }
 }
 
 template <typename R>
 static void launch_vit_forward(const StagedModel<R> &m, const ObsDesc &o, uint8_t *psi,
-                               double *logp, uint8_t *qlast, hipStream_t s) {
-    if (m.N <= 8) launch_vit_forward_n<R, 8>(m, o, psi, logp, qlast, s);
-    else if (m.N <= 16) launch_vit_forward_n<R, 16>(m, o, psi, logp, qlast, s);
-    else if (m.N <= 32) launch_vit_forward_n<R, 32>(m, o, psi, logp, qlast, s);
-    else launch_vit_forward_n<R, 64>(m, o, psi, logp, qlast, s);
+                               double *logp, uint8_t *qlast, int32_t *nt, hipStream_t s) {
+    if (m.N <= 8) launch_vit_forward_n<R, 8>(m, o, psi, logp, qlast, nt, s);
+    else if (m.N <= 16) launch_vit_forward_n<R, 16>(m, o, psi, logp, qlast, nt, s);
+    else if (m.N <= 32) launch_vit_forward_n<R, 32>(m, o, psi, logp, qlast, nt, s);
+    else launch_vit_forward_n<R, 64>(m, o, psi, logp, qlast, nt, s);
 }
 
 template <typename R>
 hmm_status run_viterbi(const StagedModel<R> &m, const ObsDesc &o, const int *cbase,
                        const ChunkDesc *cdesc, int C, uint8_t *psi, uint8_t *J, uint8_t *qlast,
-                       uint8_t *qend, int32_t *path, double *logp, hipStream_t s) {
+                       uint8_t *qend, int32_t *path, double *logp, int32_t *n_ties,
+                       hipStream_t s) {
     if (o.nseq == 0) return HMM_OK;
     {
         ProfScope ps("vit_forward", s);
-        launch_vit_forward<R>(m, o, psi, logp, qlast, s);
+        launch_vit_forward<R>(m, o, psi, logp, qlast, n_ties, s);
     }
     {
         ProfScope ps("vit_jump", s);
@@ -312,16 +342,16 @@ hmm_status run_viterbi(const StagedModel<R> &m, const ObsDesc &o, const int *cba
     {
         ProfScope ps("vit_fill", s);
         hipLaunchKernelGGL(k_vit_fill, dim3((unsigned)C), dim3(64), 0, s, cdesc, m.N,
-                           (const uint8_t *)psi, (const uint8_t *)qend, path);
+                           (const uint8_t *)psi, (const uint8_t *)qend, path, n_ties);
     }
     return HMM_OK;
 }
 
 template hmm_status run_viterbi<float>(const StagedModel<float> &, const ObsDesc &, const int *,
                                        const ChunkDesc *, int, uint8_t *, uint8_t *, uint8_t *,
-                                       uint8_t *, int32_t *, double *, hipStream_t);
+                                       uint8_t *, int32_t *, double *, int32_t *, hipStream_t);
 template hmm_status run_viterbi<double>(const StagedModel<double> &, const ObsDesc &, const int *,
                                         const ChunkDesc *, int, uint8_t *, uint8_t *, uint8_t *,
-                                        uint8_t *, int32_t *, double *, hipStream_t);
+                                        uint8_t *, int32_t *, double *, int32_t *, hipStream_t);
 
 }  // namespace hmmk

@@ -317,8 +317,8 @@ void hmm_server::issue(Flight *f) {
     double *logp = (double *)(db + lay.o_logp);
     if (st == HMM_OK) {
         if (kind == HMM_REQ_VITERBI)
-            st = hmm_viterbi(&md.m, &b, (hmm_precision)opts.precision, path, logp, db + lay.o_ws,
-                             lay.ws_b, s);
+            st = hmm_viterbi(&md.m, &b, (hmm_precision)opts.precision, path, logp, nullptr,
+                             db + lay.o_ws, lay.ws_b, s);
         else
             st = hmm_posterior_decode(&md.m, &b, (hmm_precision)opts.precision, path, logp,
                                       db + lay.o_ws, lay.ws_b, s);

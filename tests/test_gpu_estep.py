@@ -145,6 +145,44 @@ def test_status_codes_and_exclusion(h):
         assert_stats_close(stats, ref["stats"], 4, "gamma", TOL[prec], f"status {prec}")
 
 
+@pytest.mark.parametrize("fam,n", [("gamma", 4), ("gamma", 8), ("gamma", 20), ("diag", 70)])
+def test_excluded_sequences_gamma_and_posterior_path(h, fam, n):
+    """Excluded sequences (status 1 or 2) get zero gamma rows and path -1 from
+    posterior decoding on every batched route (N <= 8 chunks, the wave path,
+    the large-state path); the other sequences' rows match the oracle."""
+    import torch
+    d = 2 if fam == "diag" else 1
+    w = workloads.random_workload(fam, n, d, [50, 60, 70, 80], 440 + n)
+    obs = w.obs.copy()
+    obs[w.offsets[1] + 5] = np.nan                       # status 2
+    if fam == "gamma":
+        obs[w.offsets[2] + 3] = -1.0                     # status 1
+    ref = oracle.estep(w.model, w.offsets, obs, want_gamma=True)
+    dm = h.DeviceModel.from_model(w.model)
+    for prec in ("f32", "f64"):
+        dt = np.float64 if prec == "f64" else np.float32
+        db = h.DeviceBatch(obs, w.offsets, dtype=dt)
+        # fill the outputs first so unwritten rows would show
+        ll, gam, st = h.forward_backward(dm, db, prec)
+        gam.fill_(7.0)
+        ws = h._ws(h.hmm_workspace_size("forward_backward", dm, db, prec))
+        h.hmm_forward_backward(dm, db, prec, ll, gam, st, ws)
+        path, _ = h.posterior_decode(dm, db, prec)
+        torch.cuda.synchronize()
+        g = gam.cpu().numpy()
+        pth = path.cpu().numpy()
+        stc = st.cpu().numpy()
+        assert list(stc) == list(ref["status"])
+        for b in range(4):
+            sl = slice(w.offsets[b], w.offsets[b + 1])
+            if stc[b] != 0:
+                assert np.all(g[sl] == 0), (prec, b)
+                assert np.all(pth[sl] == -1), (prec, b)
+            else:
+                np.testing.assert_allclose(g[sl], ref["gamma"][sl], atol=TOL[prec] * 10)
+                assert np.all(pth[sl] >= 0)
+
+
 def test_parameter_domain_error(h):
     w = workloads.random_workload("gaussian", 3, 1, [20, 30], 410)
     m = w.model.copy()

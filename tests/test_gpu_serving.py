@@ -65,7 +65,7 @@ def direct(h, dm, kind, obs, prec):
     dt = np.float64 if prec == "f64" else np.float32
     db = h.DeviceBatch(obs, np.array([0, len(obs)], dtype=np.int64), dtype=dt)
     if kind == "viterbi":
-        p, lp = h.viterbi(dm, db, prec)
+        p, lp, _ = h.viterbi(dm, db, prec)
     else:
         p, lp = h.posterior_decode(dm, db, prec)
     torch.cuda.synchronize()

@@ -252,3 +252,113 @@ def test_transition_mstep_rows():
     g1 = r["stats"][1:4]
     np.testing.assert_allclose(np.exp(lp), g1 / 2.0, rtol=1e-12)
     assert not kept.any()
+
+
+# ------------------------------------------------------- guards and flags
+
+def test_transition_row_keep_guard_threshold():
+    """Section 4.4's collapse guard applied to rows of A (reading R11): a row
+    whose expected transition count sum_j Xi_ij is below eps keeps its old
+    log-probabilities exactly; a row just above eps is re-estimated as
+    Xi_ij / sum_j Xi_ij.  Statistics are written by hand, so the expected
+    values follow from the definition alone."""
+    n = 4
+    rng = np.random.default_rng(11)
+    xi = rng.uniform(0.5, 2.0, (n, n))
+    xi[1] = 0.0                                  # never left: sum 0
+    xi[2] = np.array([1e-9, 2e-9, 1e-9, 1e-9])   # sum 5e-9 < 1e-8
+    xi[3] = np.array([5e-9, 5e-9, 5e-9, 5e-9])   # sum 2e-8 >= 1e-8
+    g1 = np.array([0.1, 0.2, 0.3, 0.4])
+    stats = np.concatenate([[0.0], g1, xi.ravel(), np.ones(n)])
+    old = np.log(rng.dirichlet(np.ones(n), size=n))
+    lp, la, kept = oracle.mstep_transitions(n, stats, old, eps=1e-8)
+    assert list(kept) == [0, 1, 1, 0]
+    assert np.array_equal(la[1], old[1]) and np.array_equal(la[2], old[2])
+    for i in (0, 3):
+        np.testing.assert_allclose(np.exp(la[i]), xi[i] / xi[i].sum(), rtol=1e-14)
+    np.testing.assert_allclose(np.exp(lp), g1 / g1.sum(), rtol=1e-14)
+
+
+def test_transition_row_keep_guard_unreachable_state():
+    """An E-step in which state 2 can never be entered (pi_2 = 0 and a_i2 = 0)
+    gives that row of Xi no mass; the M-step keeps its old row and the other
+    rows still sum to one.  The unreachable state's column stays zero."""
+    w = workloads.random_workload("gaussian", 3, 1, [120, 80], 61)
+    m = w.model.copy()
+    A = np.exp(m.log_A)
+    A[:, 2] = 0.0
+    A /= A.sum(1, keepdims=True)
+    with np.errstate(divide="ignore"):
+        m.log_A = np.log(A)
+        m.log_pi = np.log(np.array([0.5, 0.5, 0.0]))
+    r = oracle.estep(m, w.offsets, w.obs)
+    xi = r["stats"][4:13].reshape(3, 3)
+    assert xi[2].sum() == 0.0 and xi[:, 2].sum() == 0.0
+    lp, la, kept = oracle.mstep_transitions(3, r["stats"], m.log_A)
+    assert list(kept) == [0, 0, 1]
+    assert np.array_equal(la[2], m.log_A[2])
+    np.testing.assert_allclose(np.exp(la[:2]).sum(1), 1.0, atol=1e-14)
+    assert np.all(np.exp(la[:2, 2]) == 0.0) and np.exp(lp[2]) == 0.0
+
+
+def test_gamma_degenerate_statistic_flag():
+    """Section 4.2's shape equation log a - psi(a) = c has no finite root when
+    c = log ybar - mean log y is 0 (Jensen's gap vanishes exactly when every
+    weighted observation is equal).  Then the parameters are kept and the
+    state is flagged 2 (reading R6).  A tiny but resolvable gap (c ~ 1e-9) is
+    not flagged and gives the large shape the equation's asymptotics predict:
+    log a - psi(a) ~ 1/(2a), so a ~ 1/(2c)."""
+    n = 2
+    y = np.full(50, 2.5)
+    g = np.column_stack([np.ones(50), np.linspace(0.1, 1.0, 50)])
+    theta = np.array([3.0, 4.0, 1.5, 2.0])
+    st = weighted_stats("gamma", n, y, g, theta)
+    th, col, _ = oracle.mstep_emission("gamma", n, 1, theta, st)
+    assert list(col) == [2, 2]
+    assert np.array_equal(th, theta)
+    # two distinct values close together: c > 0 but small
+    y2 = np.where(np.arange(50) % 2 == 0, 2.5 * (1 + 1e-4), 2.5 * (1 - 1e-4))
+    st2 = weighted_stats("gamma", 1, y2, np.ones((50, 1)), np.array([1.0, 1.0]))
+    th2, col2, it2 = oracle.mstep_emission("gamma", 1, 1, np.array([1.0, 1.0]), st2)
+    ybar = y2.mean()
+    c = math.log(ybar) - np.log(y2).mean()
+    assert 1e-10 < c < 1e-7 and col2[0] == 0
+    a = th2[0]
+    assert abs(a * 2 * c - 1) < 1e-3             # a ~ 1/(2c) for small c
+    # the score residual at rounding level of log a (~18): cancellation, not the solver
+    assert abs(math.log(a) - special.digamma(a) - c) < 1e-14
+
+
+def test_full_covariance_not_positive_definite_flag():
+    """When the weighted scatter plus the ridge is not positive definite the
+    Cholesky factorisation of section 4.5 fails: the state keeps its
+    parameters and is flagged 3.  Observations on a line (second coordinate a
+    copy of the first) make the scatter exactly singular; a negative ridge
+    then makes it indefinite for certain.  With the default ridge the same
+    data factorise and the factor matches numpy."""
+    rng = np.random.default_rng(12)
+    T, n, d = 200, 2, 2
+    x = rng.normal(0.0, 1.0, T)
+    y = np.column_stack([x, x])
+    g = rng.dirichlet(np.ones(n), size=T)
+    mu_old = np.array([[0.1, -0.1], [0.2, 0.3]])
+    L_old = np.stack([np.eye(d) * 0.7, np.eye(d) * 1.3])
+    theta = np.concatenate([mu_old.ravel(), L_old.ravel()])
+    head = np.concatenate([[0.0], g[0], np.zeros(n * n), g.sum(0)])
+    blocks = []
+    for j in range(n):
+        dv = y - mu_old[j]
+        w = g[:, j]
+        first = (w[:, None] * dv).sum(0)
+        second = [np.sum(w * dv[:, r] * dv[:, c]) for r in range(d) for c in range(r + 1)]
+        blocks.append(np.concatenate([first, second]))
+    st = np.concatenate([head, np.concatenate(blocks)])
+    th, col, _ = oracle.mstep_emission("full", n, d, theta, st, oracle.default_mopts(ridge=-1e-9))
+    assert list(col) == [3, 3]
+    assert np.array_equal(th, theta)
+    th, col, _ = oracle.mstep_emission("full", n, d, theta, st)
+    assert list(col) == [0, 0]
+    for j in range(n):
+        S = np.cov(y.T, aweights=g[:, j], bias=True) + 1e-6 * np.eye(d)
+        np.testing.assert_allclose(th[n * d:].reshape(n, d, d)[j], np.linalg.cholesky(S),
+                                   rtol=1e-6, atol=1e-9)
