@@ -165,6 +165,11 @@ struct BlockBuffers {
     double *red;         // reduction scratch
 };
 int blk_xi_chunks(bool f64, int64_t total);
+// tiled forward (fwd) or backward sweeps of the large-state path, 64 < N <= 256
+template <typename R>
+void launch_sw_sweep(bool fwd, const StagedModel<R> &m, const int64_t *offsets, int64_t nseq,
+                     R *etab, const double *mt, R *alpha, int32_t *aexp, double *loglik,
+                     int32_t *status, R *gamma, hipStream_t s);
 int blk_gstats_tiles(int64_t total, int family);
 template <typename R>
 hmm_status run_block(const StagedModel<R> &m, const ObsDesc &o, const BlockBuffers &bb,

@@ -1321,6 +1321,9 @@ static void launch_blk_sweep(bool fwd, const StagedModel<R> &m, const ObsDesc &o
             return launch_blk_mfma<__bf16>(fwd, m, o, etab, bb, alpha, loglik, status, gamma, s);
         if (bb.mfma == 2)
             return launch_blk_mfma<_Float16>(fwd, m, o, etab, bb, alpha, loglik, status, gamma, s);
+        if (m.N > 64)
+            return launch_sw_sweep<R>(fwd, m, o.offsets, o.nseq, etab, bb.mt, alpha, bb.aexp,
+                                      loglik, status, gamma, s);
         // rows per thread RP = NC / (512 / NC): 8, 32, 96, 128
         switch (blk_nc(m.N)) {
         case 64:
@@ -1333,6 +1336,9 @@ static void launch_blk_sweep(bool fwd, const StagedModel<R> &m, const ObsDesc &o
             return launch_blk_sweep_t<R, 1024, 64, true, 256>(fwd, m, o, etab, bb, alpha, loglik, status, gamma, s);
         }
     } else {
+        if (m.N > 64)
+            return launch_sw_sweep<R>(fwd, m, o.offsets, o.nseq, etab, bb.mt, alpha, bb.aexp,
+                                      loglik, status, gamma, s);
         launch_blk_sweep_t<R, 256, 1, false, 0>(fwd, m, o, etab, bb, alpha, loglik, status, gamma, s);
     }
 }
