@@ -74,7 +74,7 @@ def algorithmic_flops(name, w):
     if name in ("block_fwd", "block_bwd"):
         # one vector-matrix product per step
         return 2.0 * steps * n * n
-    if name == "block_xi_gemm":
+    if name == "block_xi":
         return 2.0 * (steps - 1) * n * n
     return None
 

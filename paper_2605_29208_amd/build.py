@@ -21,7 +21,7 @@ LIB = os.path.join(HERE, "libhmmgpu.so")
 ARCH = "gfx950"
 
 SOURCES = ["abi.cpp", "k_stage.hip", "k_plain.hip", "k_chunk.hip", "k_viterbi.hip", "k_mstep.hip",
-           "k_wave.hip", "k_block.hip", "k_sweep.hip", "serve.cpp"]
+           "k_wave.hip", "k_block.hip", "k_sweep.hip", "k_xi.hip", "serve.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
@@ -49,8 +49,7 @@ def build(verbose: bool = False, jobs: int | None = None) -> str:
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = LIB + ".tmp"
-    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs,
-           "-L/opt/rocm/lib", "-lrocblas", "-Wl,-rpath,/opt/rocm/lib"]
+    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stderr}")

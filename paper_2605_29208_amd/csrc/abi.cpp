@@ -119,7 +119,8 @@ struct Plan {
     size_t ll = 0, st = 0, gam = 0;
     size_t logB = 0, alpha = 0, beta = 0, ps = 0;
     size_t red = 0;
-    size_t etab = 0, mt = 0, balpha = 0, aexp = 0, bgam = 0, xi = 0, g1 = 0, compact = 0;
+    size_t etab = 0, mt = 0, balpha = 0, aexp = 0, bgam = 0, xi = 0, xisum = 0, g1 = 0, compact = 0;
+    int xi_nsl = 1;
     bool mvw = false;   // multivariate family on the wave path (log-density table)
     size_t lt = 0, fpart = 0, red2 = 0;
     size_t total = 0;
@@ -186,7 +187,7 @@ hmm_status make_plan(hmm_op op, const Checked &c, hmm_precision prec, Plan *p) {
         const bool mvw = !scalar && N <= 64 && !p->mfma &&
                          (c.fam == HMM_DIAG_GAUSSIAN || c.fam == HMM_FULL_GAUSSIAN);
         if (!mvw && (!scalar || N > 64 || p->mfma)) {
-            // one workgroup per sequence, emission table, xi by GEMM
+            // one workgroup per sequence, emission table, xi by a matrix-core contraction
             if (N > 256)
                 return fail(HMM_ERR_UNSUPPORTED,
                             "batched path: this build covers N <= 256 (N = %d); use a PLAIN "
@@ -198,8 +199,9 @@ hmm_status make_plan(hmm_op op, const Checked &c, hmm_precision prec, Plan *p) {
             p->balpha = take(T * N * r);
             p->aexp = take(T * 4);
             if (op == HMM_OP_ESTEP || op == HMM_OP_FORWARD_BACKWARD) p->bgam = take(T * N * r);
-            const int nch = blk_xi_chunks(p->f64, c.total);
-            p->xi = take((size_t)nch * N * N * r + 256);
+            p->xi_nsl = xi_slices(p->f64, N, c.total);
+            p->xi = take((size_t)xi_part_entries(p->f64, N, c.total) * r);
+            p->xisum = take((size_t)N * N * 8);
             p->g1 = take((size_t)N * 8);
             const int64_t S2 = 1 + N + (int64_t)N * family_k(c.fam, c.D);
             const int ntile = blk_gstats_tiles(c.total, c.fam);
@@ -324,6 +326,8 @@ hmm_status run_posterior_path(const hmm_model *m, const hmm_batch *b, const Chec
         bb.aexp = (int32_t *)(ws + p.aexp);
         bb.gamma = p.bgam ? (void *)(ws + p.bgam) : nullptr;
         bb.xi = ws + p.xi;
+        bb.xi_nsl = p.xi_nsl;
+        bb.xisum = (double *)(ws + p.xisum);
         bb.g1 = (double *)(ws + p.g1);
         bb.partial = (double *)(ws + p.partial);
         bb.compact = (double *)(ws + p.compact);

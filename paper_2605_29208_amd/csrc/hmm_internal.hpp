@@ -145,8 +145,8 @@ hmm_status run_wave(const StagedModel<R> &m, const ObsDesc &o, const WaveBuffers
                     int64_t stats_len, hipStream_t s);
 
 // batched path for large N (<= 256) and the multivariate families: one
-// workgroup per sequence, emission table, stored alpha, xi by a GEMM
-constexpr int BLK_KC = 16384;   // steps per FP32 xi GEMM chunk (FP32 partial sums)
+// workgroup per sequence, emission table, stored alpha, xi by a contraction
+// over stored alpha and w' on the matrix cores
 constexpr int BLK_TS = 1024;    // steps per tile of the family-sum kernels
 constexpr int FULL_TS = 8192;   // steps per tile of the full-covariance family sums
 constexpr int BLK_GS_BLOCKS = 1024;   // blocks (partial rows) of the per-state family-sum kernel
@@ -158,13 +158,21 @@ struct BlockBuffers {
     void *alpha;         // [total * N] R  normalised alpha
     int32_t *aexp;       // [total]   binary exponent removed at each forward step
     void *gamma;         // [total * N] R  posteriors (when the caller gives none)
-    void *xi;            // [chunks * N * N] R  GEMM partial sums (column-major)
+    void *xi;            // [xi_part_entries] R  per-slice partial sums of the xi contraction
+    int xi_nsl;          // slices of the contraction
+    double *xisum;       // [N * N] sum_k alpha_k^T w'_{k+1}, row-major
     double *g1;          // [N]
     double *partial;     // [tiles * (1 + N + N*K)]
     double *compact;     // [1 + N + N*K]
     double *red;         // reduction scratch
 };
-int blk_xi_chunks(bool f64, int64_t total);
+// slices and partial-sum entries of the xi contraction
+int xi_slices(bool f64, int N, int64_t total);
+int64_t xi_part_entries(bool f64, int N, int64_t total);
+// out [N x N] FP64 = sum_k alpha[k]^T wp[k + 1] over k < K (K >= 1)
+template <typename R>
+void launch_xi_sum(const R *alpha, const R *wp, int N, int64_t K, R *part, int nsl, double *out,
+                   hipStream_t s);
 // tiled forward (fwd) or backward sweeps of the large-state path, 64 < N <= 256
 template <typename R>
 void launch_sw_sweep(bool fwd, const StagedModel<R> &m, const int64_t *offsets, int64_t nseq,

@@ -24,7 +24,6 @@
 //
 // Sweeps: 256 threads, thread (c, p) owns column c (state) and the p-th of
 // 256 / NC row blocks (NC = N rounded up to 64); partial products meet in LDS.
-#include <rocblas/rocblas.h>
 
 #include "dev_common.hpp"
 #include "hmm_internal.hpp"
@@ -1192,13 +1191,11 @@ __global__ __launch_bounds__(BT) void k_blk_zero(double *p, int64_t n) {
         p[i] = 0.0;
 }
 
-// stats = [sum logL | gamma_1 | xi (sum of GEMM chunks, column-major, times a_ij)
-//          | sum gamma | family]
+// stats = [sum logL | gamma_1 | xi (the contraction times a_ij) | sum gamma | family]
 template <typename R>
-__global__ __launch_bounds__(BT) void k_blk_assemble(StagedModel<R> m, const R *xi_chunks,
-                                                     int nch, const double *g1,
-                                                     const double *compact, int64_t S,
-                                                     double *stats) {
+__global__ __launch_bounds__(BT) void k_blk_assemble(StagedModel<R> m, const double *xisum,
+                                                     const double *g1, const double *compact,
+                                                     int64_t S, double *stats) {
     const int N = m.N;
     const int64_t NN = (int64_t)N * N;
     for (int64_t s = (int64_t)blockIdx.x * BT + threadIdx.x; s < S; s += (int64_t)gridDim.x * BT) {
@@ -1209,10 +1206,7 @@ __global__ __launch_bounds__(BT) void k_blk_assemble(StagedModel<R> m, const R *
             v = g1[s - 1];
         } else if (s <= N + NN) {
             const int64_t k = s - 1 - N;
-            const int i = (int)(k / N), j = (int)(k % N);
-            double acc = 0.0;
-            for (int q = 0; q < nch; ++q) acc += (double)xi_chunks[(int64_t)q * NN + (int64_t)j * N + i];
-            v = acc * (double)m.A[k];
+            v = xisum[k] * (double)m.A[k];
         } else {
             v = compact[s - NN - N];   // [sum gamma | family] follow sum logL in the compact vector
         }
@@ -1221,50 +1215,6 @@ __global__ __launch_bounds__(BT) void k_blk_assemble(StagedModel<R> m, const R *
 }
 
 // ---------------------------------------------------------------- host side
-static rocblas_handle blas_handle() {
-    thread_local rocblas_handle h = nullptr;
-    if (!h && rocblas_create_handle(&h) != rocblas_status_success) h = nullptr;
-    return h;
-}
-
-static hmm_status xi_gemm(const float *alpha, const float *wp, int N, int64_t K, int kc, float *C,
-                          int nch, hipStream_t s) {
-    rocblas_handle h = blas_handle();
-    if (!h || rocblas_set_stream(h, s) != rocblas_status_success) return HMM_ERR_DEVICE;
-    const float one = 1.0f, zero = 0.0f;
-    const int64_t full = K / kc, rem = K - full * kc;
-    if (full > 0 &&
-        rocblas_sgemm_strided_batched(h, rocblas_operation_none, rocblas_operation_transpose, N, N, kc,
-                                      &one, alpha, N, (rocblas_stride)kc * N, wp, N,
-                                      (rocblas_stride)kc * N, &zero, C, N, (rocblas_stride)N * N,
-                                      (rocblas_int)full) != rocblas_status_success)
-        return HMM_ERR_DEVICE;
-    if (rem > 0 &&
-        rocblas_sgemm(h, rocblas_operation_none, rocblas_operation_transpose, N, N, (rocblas_int)rem,
-                      &one, alpha + full * kc * N, N, wp + full * kc * N, N, &zero,
-                      C + full * (int64_t)N * N, N) != rocblas_status_success)
-        return HMM_ERR_DEVICE;
-    (void)nch;
-    return HMM_OK;
-}
-
-static hmm_status xi_gemm(const double *alpha, const double *wp, int N, int64_t K, int, double *C,
-                          int, hipStream_t s) {
-    rocblas_handle h = blas_handle();
-    if (!h || rocblas_set_stream(h, s) != rocblas_status_success) return HMM_ERR_DEVICE;
-    const double one = 1.0, zero = 0.0;
-    if (rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_transpose, N, N, (rocblas_int)K,
-                      &one, alpha, N, wp, N, &zero, C, N) != rocblas_status_success)
-        return HMM_ERR_DEVICE;
-    return HMM_OK;
-}
-
-int blk_xi_chunks(bool f64, int64_t total) {
-    if (f64 || total <= 1) return 1;
-    const int64_t K = total - 1;
-    return (int)((K + BLK_KC - 1) / BLK_KC);
-}
-
 int blk_gstats_tiles(int64_t total, int family) {
     const int64_t ts = family == HMM_FULL_GAUSSIAN ? FULL_TS : BLK_TS;
     return (int)((total + ts - 1) / ts);
@@ -1559,19 +1509,16 @@ hmm_status run_block(const StagedModel<R> &m, const ObsDesc &o, const BlockBuffe
     }
     // sum gamma and family sums into the compact vector (entry 0: sum logL)
     launch_reduce_stats(bb.partial, nparts, S2, loglik, status, o.nseq, bb.compact, bb.red, s);
-    const int nch = blk_xi_chunks(sizeof(R) == 8, total);
     if (total > 1) {
-        ProfScope ps("block_xi_gemm", s);
-        hmm_status st = xi_gemm(alpha, etab + N, N, total - 1, BLK_KC, (R *)bb.xi, nch, s);
-        if (st != HMM_OK) return st;
+        ProfScope ps("block_xi", s);
+        launch_xi_sum<R>(alpha, etab, N, total - 1, (R *)bb.xi, bb.xi_nsl, bb.xisum, s);
     } else {
-        hipLaunchKernelGGL(k_blk_zero, dim3(1), dim3(BT), 0, s, (double *)bb.xi,
-                           (int64_t)((size_t)N * N * sizeof(R) / 8 + 1));
+        hipLaunchKernelGGL(k_blk_zero, dim3(1), dim3(BT), 0, s, bb.xisum, (int64_t)N * N);
     }
     {
         ProfScope ps("block_assemble", s);
         hipLaunchKernelGGL(k_blk_assemble<R>, dim3((unsigned)((S + BT - 1) / BT < 1024 ? (S + BT - 1) / BT : 1024)),
-                           dim3(BT), 0, s, m, (const R *)bb.xi, nch, (const double *)bb.g1,
+                           dim3(BT), 0, s, m, (const double *)bb.xisum, (const double *)bb.g1,
                            (const double *)bb.compact, S, stats);
     }
     return HMM_OK;
