@@ -1,20 +1,21 @@
-"""Benchmark: one Baum-Welch E-step over a batch of ragged sequences.
+"""Benchmark: one Baum-Welch E-step over a batch of sequences.
 
-Default workload (--workload batched): 1024 sequences with lengths uniform in
-{500..5000}, N = 8 Gamma states (shape U[1,10], scale U[0.5,3]), sticky A
-(a_ii = 0.95).  --workload heavy: 512 sequences with log-normal lengths
-(median 3000, sigma 0.6, at most 20,000), N = 32 Student-t states.
---workload large: 256 sequences of 2048 steps, N = 256 diagonal Gaussian
-states in D = 16.  --workload full: the heavy workload's lengths with N = 32
-full-covariance Gaussian states in D = 32.  FP32 observations resident in
-device memory.  One step = one full E-step
-(parameter staging, emission log-densities, forward and backward
-recursions, posteriors and the pooled sufficient statistics).
+Headline (--workload large, --prec f64, the defaults): 256 sequences of 2048
+steps, N = 256 diagonal-Gaussian states in D = 16, FP64 arithmetic (the
+paper's).  One step = one full E-step (parameter staging, emission
+log-densities, forward and backward recursions, posteriors and the pooled
+sufficient statistics), observations resident in device memory, E-steps
+replayed from one captured HIP graph.
+
+Beside it, on the same GPU: the plain one-thread-per-sequence method; the
+same workload in FP32 and in the scaled bf16 / fp16 matrix-core forms with
+their error against the FP64 result; the batched ragged workload (1024
+sequences, N = 8 Gamma) with its graph-captured EM loop; the heavy-tailed and
+full-covariance workloads; a serving run with an unbatched baseline; and the
+FP64 CPU oracle timed on the host's cores.
 
 Prints one JSON line with the throughput in state transitions per second
-(sum_b T_b * N^2 per E-step), the plain one-thread-per-sequence GPU method
-on the same data, the dominant kernel's roofline figures and the FP64 CPU
-oracle timed on the host.
+(sum_b T_b * N^2 per E-step) and the dominant kernel's roofline figures.
 """
 import argparse
 import json
@@ -56,38 +57,41 @@ def kernel_table(records, steps):
 
 
 def algorithmic_flops(name, w):
-    """FLOPs of the method's arithmetic for one launch of kernel `name`."""
-    n = w.model.n_states
-    steps = w.total_steps
-    if name == "chunk_stats":
-        # forward alpha*A, backward A*w and the xi outer product: 3 FMA per transition
-        return 6.0 * steps * n * n
-    if name == "chunk_product":
-        # chunk transfer matrices: N^3 FMA per step after each sequence's first
-        return 2.0 * (steps - w.n_seq) * n ** 3
-    if name == "wave_stats":
-        # chunk forward alpha*A, backward A*w and the xi outer product
-        return 6.0 * steps * n * n
+    """FLOPs of the method's own arithmetic done by one launch of kernel
+    `name`: the forward product alpha A, the backward product A w and the xi
+    outer product are one FMA (2 flops) per transition each, 6 per transition
+    over the E-step.  Work that only a parallel formulation needs (the chunk
+    transfer matrices, recomputed chunk steps) is not counted."""
+    tr = float(w.transitions)
+    if name in ("block_fwd", "block_bwd", "block_xi"):
+        return 2.0 * tr
+    if name in ("chunk_stats", "wave_stats"):
+        # the statistics pass forms xi and the family sums (its re-run of
+        # chunk steps is recomputation)
+        return 2.0 * tr
     if name == "wave_sweep":
-        # forward alpha*A and backward A*w over every sequence
-        return 4.0 * steps * n * n
-    if name in ("block_fwd", "block_bwd"):
-        # one vector-matrix product per step
-        return 2.0 * steps * n * n
-    if name == "block_xi":
-        return 2.0 * (steps - 1) * n * n
+        return 4.0 * tr
+    return None
+
+
+def overhead_flops(name, w):
+    """FLOPs of the chunked scan's own work (not the method's): the N^3 per step
+    of the chunk transfer matrices."""
+    n = w.model.n_states
+    if name == "chunk_product":
+        return 2.0 * (w.total_steps - w.n_seq) * n ** 3
     return None
 
 
 WORKLOADS = {
-    "batched": ("batched ragged E-step: B=1024, T~U{500..5000}, N=8 Gamma, FP32 obs",
+    "large": ("large-state E-step: B=256, T=2048, N=256 diagonal Gaussian D=16",
+              lambda workloads: workloads.config3()),
+    "batched": ("batched ragged E-step: B=1024, T~U{500..5000}, N=8 Gamma",
                 lambda workloads: workloads.config2()),
     "heavy": ("heavy-tailed E-step: B=512, T~lognormal(median 3000, sigma 0.6, <=20000), "
-              "N=32 Student-t, FP32 obs", lambda workloads: workloads.config4b()),
-    "large": ("large-state E-step: B=256, T=2048, N=256 diagonal Gaussian D=16, FP32 obs",
-              lambda workloads: workloads.config3()),
+              "N=32 Student-t", lambda workloads: workloads.config4b()),
     "full": ("full-covariance E-step: B=512, T~lognormal(median 3000, sigma 0.6, <=20000), "
-             "N=32 full-covariance Gaussian D=32, FP32 obs", lambda workloads: workloads.config4a()),
+             "N=32 full-covariance Gaussian D=32", lambda workloads: workloads.config4a()),
 }
 
 
@@ -96,7 +100,8 @@ WORKLOADS = {
 # source is unchanged
 KERNEL_SOURCE = {"chunk_stats": "k_chunk.hip", "chunk_product": "k_chunk.hip",
                  "wave_stats": "k_wave.hip", "wave_sweep": "k_wave.hip",
-                 "block_fwd": "k_block.hip", "block_bwd": "k_block.hip"}
+                 "block_fwd": "k_sweep.hip", "block_bwd": "k_sweep.hip",
+                 "block_xi": "k_xi.hip"}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_counters.md")
 
 
@@ -109,7 +114,7 @@ def source_sha(kernel):
         return hashlib.sha256(fh.read()).hexdigest()
 
 
-def measured_traffic(kernel, workload):
+def measured_traffic(kernel, workload, prec):
     """HBM bytes per launch (fetch + write) from the committed summary, or None."""
     try:
         lines = open(TRAFFIC_FILE).read().splitlines()
@@ -119,8 +124,22 @@ def measured_traffic(kernel, workload):
     for ln in lines:
         if ln.startswith("traffic:"):
             f = dict(kv.split("=", 1) for kv in ln[len("traffic:"):].split())
-            if f.get("kernel") == kernel and f.get("workload") == workload and f.get("sha") == sha:
+            if (f.get("kernel") == kernel and f.get("workload") == workload and
+                    f.get("prec", "f32") == prec and f.get("sha") == sha):
                 return float(f["fetch_bytes"]) + float(f["write_bytes"])
+    return None
+
+
+def algorithmic_bytes(name, w, prec):
+    """Bytes a launch of `name` must move at the least (each array once)."""
+    r = 8 if prec == "f64" else 4
+    T, n = w.total_steps, w.model.n_states
+    if name == "block_fwd":     # emission rows in, alpha rows out
+        return 2.0 * T * n * r
+    if name == "block_bwd":     # alpha, emission rows in; gamma, w' out
+        return 4.0 * T * n * r
+    if name == "block_xi":      # alpha and w' in
+        return 2.0 * T * n * r
     return None
 
 
@@ -134,78 +153,296 @@ def cpu_model():
     return "unknown"
 
 
-def cpu_baseline(w, reps=2):
+def host_threads():
+    """Threads the oracle may use: the cores this process may run on, at most 16
+    (the host share of one GPU)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        n = os.cpu_count() or 1
+    return max(1, min(n, 16))
+
+
+def cpu_baseline(w, n_par=16, n_one=2):
+    """The FP64 oracle as it stands on a bounded sample of the workload: n_par
+    sequences, one per task, over the host's threads, and n_one sequences on
+    one thread.  The rate is scaled to transitions per second."""
+    import concurrent.futures as cf
+
     import oracle
     oracle._load()
+    threads = host_threads()
+    sub = w.subset(np.arange(min(n_par, w.n_seq)))
+    parts = [sub.subset(np.array([k])) for k in range(sub.n_seq)]
     t0 = time.perf_counter()
-    for _ in range(reps):
-        oracle.estep(w.model, w.offsets, w.obs)
+    with cf.ThreadPoolExecutor(max_workers=threads) as ex:
+        list(ex.map(lambda x: oracle.estep(x.model, x.offsets, x.obs), parts))
     dt = time.perf_counter() - t0
-    return {"value": reps * w.transitions / dt, "unit": "transitions/s", "cores": 1,
+    one = w.subset(np.arange(min(n_one, w.n_seq)))
+    t1 = time.perf_counter()
+    oracle.estep(one.model, one.offsets, one.obs)
+    dt1 = time.perf_counter() - t1
+    used = min(threads, len(parts))
+    return {"value": sub.transitions / dt, "unit": "transitions/s", "cores": used,
             "kind": "oracle",
-            "sample": f"full workload ({w.n_seq} sequences, {w.total_steps} steps) x{reps}, "
-                      f"FP64 oracle, 1 thread on {cpu_model()}, {dt:.1f} s"}
+            "sample": f"{sub.n_seq} of the {w.n_seq} sequences ({sub.total_steps} steps), one "
+                      f"sequence per task on {used} threads of {cpu_model()}, {dt:.1f} s; the "
+                      f"full workload extrapolates to {w.transitions / (sub.transitions / dt):.1f} s "
+                      f"per E-step",
+            "one_thread": {"value": one.transitions / dt1, "sequences": one.n_seq,
+                           "seconds": dt1}}
 
 
-def estep_time(h, w, prec, steps):
-    """Mean milliseconds of one E-step (events around `steps` calls) and the
-    per-kernel table."""
+def setup_estep(h, w, prec):
     import torch
     dm = h.DeviceModel.from_model(w.model)
-    db = h.DeviceBatch(w.obs, w.offsets, dtype=np.float64 if prec == "f64" else np.float32)
+    db = h.DeviceBatch(w.obs, w.offsets, dtype=np.float64 if prec in ("f64", "plain_f64") else np.float32)
     ws = h._ws(h.hmm_workspace_size("estep", dm, db, prec))
     S = h.hmm_stats_len(dm)
     stats = torch.empty(S, dtype=torch.float64, device="cuda")
     ll = torch.empty(w.n_seq, dtype=torch.float64, device="cuda")
     st = torch.empty(w.n_seq, dtype=torch.int32, device="cuda")
-    h.hmm_estep_stats(dm, db, prec, stats, ll, st, ws)
+    return dm, db, ws, stats, ll, st
+
+
+def timed_estep(h, w, prec, steps, warmup, graph=True):
+    """E-step timing: `steps` eager calls with per-kernel hipEvents (the kernel
+    table), then the same calls captured in one HIP graph and replayed (the
+    timed value).  Returns ms per E-step, the eager figure, the kernel table,
+    the results of the last call and whether every status was 0."""
+    import torch
+    dm, db, ws, stats, ll, st = setup_estep(h, w, prec)
+
+    def step():
+        h.hmm_estep_stats(dm, db, prec, stats, ll, st, ws)
+
+    for _ in range(warmup):
+        step()
     torch.cuda.synchronize()
     h.hmm_profile_reset()
     h.hmm_profile_enable(True)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
     for _ in range(steps):
-        h.hmm_estep_stats(dm, db, prec, stats, ll, st, ws)
+        step()
     e1.record()
     torch.cuda.synchronize()
+    eager_ms = e0.elapsed_time(e1) / steps
     recs = h.hmm_profile_records()
     h.hmm_profile_enable(False)
     h.hmm_profile_reset()
+    kt = kernel_table(recs, steps)
     ok = bool((st.cpu().numpy() == 0).all())
-    return e0.elapsed_time(e1) / steps, kernel_table(recs, steps), ok
+    ms = eager_ms
+    if graph:
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            step()
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            for _ in range(steps):
+                step()
+        g.replay()
+        torch.cuda.synchronize()
+        e0.record()
+        g.replay()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        del g
+        ok = ok and bool((st.cpu().numpy() == 0).all())
+    return {"ms": ms, "eager_ms": eager_ms, "kernels": kt, "ok": ok,
+            "stats": stats.cpu().numpy(), "loglik": ll.cpu().numpy()}
+
+
+def plain_time(h, w, prec, reps):
+    """The plain GPU method (one thread per sequence, literal log-sum-exp) on the
+    same data.  Its sequences run side by side, so its time is linear in the
+    longest sequence; for large N it is timed on the batch cut to its first
+    plain_t steps per sequence and scaled by T_max / plain_t."""
+    import torch
+    pprec = "plain_f64" if prec == "f64" else "plain_f32"
+    T_max = int(np.max(w.lengths))
+    plain_t = max(16, int(2e8 // (w.model.n_states ** 2 * 64)))
+    scale, note = 1.0, None
+    wp = w
+    if T_max > plain_t:
+        cut = np.minimum(w.lengths, plain_t)
+        offs = np.concatenate([[0], np.cumsum(cut)]).astype(np.int64)
+        rows = np.concatenate([np.arange(w.offsets[b], w.offsets[b] + cut[b]) for b in range(w.n_seq)])
+        import workloads
+        wp = workloads.Workload(w.name, w.model, cut, offs, w.obs[rows], w.states[rows])
+        scale = T_max / plain_t
+        note = (f"timed on the batch cut to its first {plain_t} steps per sequence, scaled by "
+                f"{scale:.1f} (linear in the longest sequence)")
+    dm, db, ws, stats, ll, st = setup_estep(h, wp, pprec)
+    h.hmm_estep_stats(dm, db, pprec, stats, ll, st, ws)
+    torch.cuda.synchronize()
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for _ in range(reps):
+        h.hmm_estep_stats(dm, db, pprec, stats, ll, st, ws)
+    t1.record()
+    torch.cuda.synchronize()
+    return t0.elapsed_time(t1) / reps * scale, note
+
+
+def rel_err(got, ref, floor):
+    got, ref = np.asarray(got, np.float64), np.asarray(ref, np.float64)
+    return float(np.max(np.abs(got - ref) / np.maximum(np.abs(ref), floor))) if ref.size else 0.0
+
+
+def errors_vs(res, ref, n):
+    """Largest relative errors of a run against the FP64 run of the same data:
+    log-likelihoods (floor 1), the xi block and the whole statistics vector
+    (floor 1e-6 of the block's largest entry)."""
+    s, r = res["stats"], ref["stats"]
+    xi = slice(1 + n, 1 + n + n * n)
+    return {"loglik_rel_err": rel_err(res["loglik"], ref["loglik"], 1.0),
+            "xi_rel_err": rel_err(s[xi], r[xi], 1e-6 * float(np.max(np.abs(r[xi])))),
+            "stats_rel_err": rel_err(s, r, 1e-6 * float(np.max(np.abs(r))))}
+
+
+def roofline_entry(name, kt, w, prec, workload_key):
+    fl = algorithmic_flops(name, w)
+    if fl is None or name not in kt:
+        return None
+    ms = kt[name]["ms_avg"]
+    ach = fl / (ms / 1e3) / 1e12
+    mfma_lp = prec in ("bf16_scaled", "f16_scaled") and name in ("block_fwd", "block_bwd")
+    if mfma_lp:
+        peak, bound = PEAK_BF16_MFMA_TFLOPS, "mfma"
+    elif name == "block_xi":
+        # the contraction runs on the matrix cores: FP64 matrix 78.6, FP32 matrix 157.3
+        peak, bound = (PEAK_FP64_VALU_TFLOPS if prec == "f64" else PEAK_FP32_VALU_TFLOPS), "mfma"
+    else:
+        peak = PEAK_FP64_VALU_TFLOPS if prec == "f64" else PEAK_FP32_VALU_TFLOPS
+        bound = "alu"
+    ab = algorithmic_bytes(name, w, prec)
+    tr = measured_traffic(name, workload_key, prec)
+    return {"bound": bound, "kernel": name, "achieved": ach, "peak": peak, "unit": "TFLOP/s",
+            "frac": ach / peak, "traffic": tr, "algorithmic_bytes": ab,
+            "traffic_over_algorithmic": None if (tr is None or not ab) else tr / ab,
+            "kernel_ms_avg": ms,
+            "work": "method's arithmetic only: one FMA per transition for each of the forward "
+                    "product, the backward product and the xi contraction"}
+
+
+def estep_roofline(w, ms, prec):
+    ach = 6.0 * w.transitions / (ms / 1e3) / 1e12
+    peak = PEAK_FP64_VALU_TFLOPS if prec == "f64" else PEAK_FP32_VALU_TFLOPS
+    return {"achieved": ach, "peak": peak, "unit": "TFLOP/s", "frac": ach / peak,
+            "work": "6 flops per transition (3 FMA) over the whole E-step"}
+
+
+def em_graph(h, w, prec, K):
+    """Baum-Welch: E-step + FP64 M-step of the family, K iterations captured once
+    in a HIP graph and replayed."""
+    import torch
+    import workloads
+    m0 = workloads.perturb(w.model, np.random.default_rng(1))
+    em_model = h.DeviceModel.from_model(m0)
+    db = h.DeviceBatch(w.obs, w.offsets, dtype=np.float64 if prec == "f64" else np.float32)
+    ws = h._ws(h.hmm_workspace_size("estep", em_model, db, prec))
+    S = h.hmm_stats_len(em_model)
+    loglik = torch.empty(w.n_seq, dtype=torch.float64, device="cuda")
+    status = torch.empty(w.n_seq, dtype=torch.int32, device="cuda")
+    em_stats = torch.zeros((K, S), dtype=torch.float64, device="cuda")
+    start = [t.clone() for t in (em_model.log_pi, em_model.log_A, em_model.theta)]
+
+    def em_loop():
+        for k in range(K):
+            h.em_iteration(em_model, db, prec, em_stats[k], loglik, status, ws)
+
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        em_loop()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        em_loop()
+    for dst, src in zip((em_model.log_pi, em_model.log_A, em_model.theta), start):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    graph.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    em_ms = e0.elapsed_time(e1)
+    traj = em_stats[:, 0].cpu().numpy()
+    return {"iterations": K, "ms_total": em_ms, "ms_per_iteration": em_ms / K,
+            "transitions_per_s": K * w.transitions / (em_ms / 1e3),
+            "loglik_first": float(traj[0]), "loglik_last": float(traj[-1]),
+            "loglik_non_decreasing": bool(np.all(np.diff(traj) >= -1e-6 * np.abs(traj[1:])))}
+
+
+def batched_section(h, workloads, steps, warmup, plain_reps, em_iters):
+    """The batched ragged workload (1024 sequences, N = 8 Gamma, FP32) with its
+    plain-method comparison and the graph-captured EM loop."""
+    w = workloads.config2()
+    r = timed_estep(h, w, "f32", steps, warmup)
+    out = {"workload": WORKLOADS["batched"][0], "sequences": w.n_seq, "total_steps": w.total_steps,
+           "precision": "f32", "ms_per_estep": r["ms"], "eager_ms_per_estep": r["eager_ms"],
+           "transitions_per_s": w.transitions / (r["ms"] / 1e3), "all_status_ok": r["ok"],
+           "estep_roofline": estep_roofline(w, r["ms"], "f32"),
+           "kernels_ms": {k: round(v["ms_avg"], 4) for k, v in r["kernels"].items()}}
+    if "chunk_product" in r["kernels"]:
+        cp = r["kernels"]["chunk_product"]["ms_avg"]
+        out["chunk_scan_overhead"] = {
+            "kernel": "chunk_product", "tflops": overhead_flops("chunk_product", w) / (cp / 1e3) / 1e12,
+            "note": "N^3 per step of the chunk transfer matrices: work of the time-parallel scan, "
+                    "not of the method"}
+    log(f"batched N=8 f32: {r['ms']:.3f} ms per E-step")
+    if plain_reps > 0:
+        pms, note = plain_time(h, w, "f32", plain_reps)
+        out["plain_gpu"] = {"ms_per_step": pms, "value": w.transitions / (pms / 1e3),
+                            "speedup": pms / r["ms"], "note": note}
+        log(f"batched plain: {pms:.3f} ms per E-step")
+    if em_iters > 0:
+        out["em_graph"] = em_graph(h, w, "f32", em_iters)
+        log(f"batched EM graph: {out['em_graph']['ms_per_iteration']:.3f} ms per iteration")
+    return out
 
 
 def other_workloads(h, workloads, steps):
-    """The other configurations' E-steps at full size (context for the
-    headline line): heavy-tailed N = 32 Student-t, large-state N = 256
-    diagonal Gaussian in FP32 and in the scaled bf16 / fp16 forms, and
-    full-covariance N = 32, D = 32."""
+    """The heavy-tailed (N = 32 Student-t) and full-covariance (N = 32, D = 32)
+    E-steps at full size in FP32 and FP64."""
     res = {}
-    for key, make, precs in (("heavy_student_t_n32", workloads.config4b, ("f32",)),
-                             ("large_diag_n256", workloads.config3, ("f32", "bf16_scaled", "f16_scaled")),
-                             ("full_cov_n32_d32", workloads.config4a, ("f32",))):
+    for key, make in (("heavy_student_t_n32", workloads.config4b),
+                      ("full_cov_n32_d32", workloads.config4a)):
         w = make()
-        for prec in precs:
-            ms, kt, ok = estep_time(h, w, prec, steps)
+        for prec in ("f32", "f64"):
+            r = timed_estep(h, w, prec, steps, 1, graph=False)
             res[f"{key}_{prec}"] = {
                 "sequences": w.n_seq, "total_steps": w.total_steps, "n_states": w.model.n_states,
-                "ms_per_estep": ms, "transitions_per_s": w.transitions / (ms / 1e3),
-                "all_status_ok": ok,
-                "kernels_ms": {k: round(v["ms_avg"], 4) for k, v in kt.items()}}
-            log(f"{key} {prec}: {ms:.3f} ms per E-step")
+                "ms_per_estep": r["ms"], "transitions_per_s": w.transitions / (r["ms"] / 1e3),
+                "all_status_ok": r["ok"], "estep_roofline": estep_roofline(w, r["ms"], prec),
+                "kernels_ms": {k: round(v["ms_avg"], 4) for k, v in r["kernels"].items()}}
+            log(f"{key} {prec}: {r['ms']:.3f} ms per E-step")
         del w
     return res
 
 
-def serving_bench(h, workloads, qps_list, seconds, pool_size=256, streams=SERVING_STREAMS):
+def serving_bench(h, workloads, qps_list, seconds, pool_size=256, streams=SERVING_STREAMS,
+                  max_batch=64):
     """Decode requests (half Viterbi, half posterior decoding) arriving as a
     Poisson process at each rate in qps_list against 16 resident models
     (N in {4, 16, 64}, Gaussian and Poisson emissions), lengths log-normal
     (median 2000, sigma 1.0, 16..100,000).  Latency = scheduled arrival ->
-    path in host memory; throughput in sequence steps per second."""
+    path in host memory; throughput in sequence steps per second.  The
+    request pool and arrival times depend only on the rates, so a run with
+    streams = max_batch = 1 (one request per launch, one launch at a time)
+    sees the same trace."""
     models = workloads.serving_models()
     rng = np.random.default_rng(5007)
-    srv = h.Server(hbm_budget=16 << 30, host_staging=1 << 30, max_batch=64, n_streams=streams)
+    srv = h.Server(hbm_budget=16 << 30, host_staging=1 << 30, max_batch=max_batch,
+                   n_streams=streams)
     try:
         ids = [srv.add_model(h.DeviceModel.from_model(m)) for m in models]
         lengths = workloads.serving_request_lengths(rng, pool_size)
@@ -272,21 +509,23 @@ def serving_bench(h, workloads, qps_list, seconds, pool_size=256, streams=SERVIN
     return {"models": "16 resident: 6 x N=4, 5 x N=16, 5 x N=64, Gaussian/Poisson alternating",
             "lengths": "log-normal median 2000, sigma 1.0, clipped 16..100000",
             "mix": "50% Viterbi, 50% posterior decode, FP32", "seconds_per_point": seconds,
+            "streams": streams, "max_batch": max_batch,
             "points": points, "launches": info["launches"], "pool_peak_bytes": info["pool_peak"]}
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", default="batched", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="large", choices=sorted(WORKLOADS))
+    ap.add_argument("--prec", default="f64", choices=["f64", "f32", "bf16_scaled", "f16_scaled"])
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--prec", default="f32", choices=["f32", "f64", "bf16_scaled", "f16_scaled"])
-    ap.add_argument("--plain-steps", type=int, default=2)
+    ap.add_argument("--plain-steps", type=int, default=2,
+                    help="plain-method E-steps timed beside each path (0 = skip)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--chunk", type=int, default=0, help="chunk length (0 = library default)")
     ap.add_argument("--em-iters", type=int, default=20,
-                    help="EM iterations captured in one HIP graph (0 = skip)")
+                    help="EM iterations of the batched workload captured in one HIP graph (0 = skip)")
     ap.add_argument("--serving-seconds", type=float, default=3.0,
                     help="seconds of Poisson arrivals per serving rate (0 = skip)")
     ap.add_argument("--serving-qps", default="100,1000,3000",
@@ -297,8 +536,8 @@ def main():
                     help="time eager calls only (no HIP graph capture), e.g. under counters")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run one 256 MiB device copy (reference for traffic counters)")
-    ap.add_argument("--others", type=int, default=3,
-                    help="E-steps timed on each secondary workload (0 = skip)")
+    ap.add_argument("--extras", type=int, default=1,
+                    help="0: the headline E-step alone (profiling runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; multi-GPU sharding of the "
@@ -312,167 +551,26 @@ def main():
     h.hmm_set_chunk_len(args.chunk)
     wl_name, wl_make = WORKLOADS[args.workload]
     w = wl_make(workloads)
-    dm = h.DeviceModel.from_model(w.model)
-    db = h.DeviceBatch(w.obs, w.offsets, dtype=np.float64 if args.prec == "f64" else np.float32)
     prec = args.prec
-    ws = h._ws(h.hmm_workspace_size("estep", dm, db, prec))
-    S = h.hmm_stats_len(dm)
-    stats = torch.empty(S, dtype=torch.float64, device="cuda")
-    loglik = torch.empty(w.n_seq, dtype=torch.float64, device="cuda")
-    status = torch.empty(w.n_seq, dtype=torch.int32, device="cuda")
-
-    def step(p=prec, wsp=ws):
-        h.hmm_estep_stats(dm, db, p, stats, loglik, status, wsp)
-
-    log(f"workload {args.workload}: {w.n_seq} sequences, {w.total_steps} steps, N={w.model.n_states}")
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    log("warm-up done")
-    # (1) eager calls with per-kernel hipEvents (the kernel table and roofline)
-    h.hmm_profile_enable(True)
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    ev0.record()
-    for _ in range(args.steps):
-        step()
-    ev1.record()
-    torch.cuda.synchronize()
-    eager_ms = ev0.elapsed_time(ev1) / args.steps
-    recs = h.hmm_profile_records()
-    h.hmm_profile_enable(False)
-    kt = kernel_table(recs, args.steps)
-    assert (status.cpu().numpy() == 0).all()
-    log(f"eager: {eager_ms:.3f} ms per E-step")
-    # (2) the same E-steps captured once in a HIP graph and replayed (the way an
-    # EM loop issues them): the timed value
-    if args.eager_only:
-        ms = eager_ms
-    else:
-        side = torch.cuda.Stream()
-        side.wait_stream(torch.cuda.current_stream())
-        with torch.cuda.stream(side):
-            step()
-        torch.cuda.current_stream().wait_stream(side)
-        torch.cuda.synchronize()
-        g_est = torch.cuda.CUDAGraph()
-        with torch.cuda.graph(g_est):
-            for _ in range(args.steps):
-                step()
-        g_est.replay()
-        torch.cuda.synchronize()
-        ev0.record()
-        g_est.replay()
-        ev1.record()
-        torch.cuda.synchronize()
-        ms = ev0.elapsed_time(ev1) / args.steps
-        del g_est
-        assert (status.cpu().numpy() == 0).all()
-    log(f"graph replay: {ms:.3f} ms per E-step")
-
-    # plain GPU method (one thread per sequence, literal log-sum-exp) on the same
-    # data.  Its sequences run side by side (one thread each), so its time is
-    # linear in the longest sequence; for large N it is timed on the same
-    # batch cut to its first plain_t steps and scaled by T / plain_t.
-    plain_ms, plain_note = None, None
-    if args.plain_steps > 0:
-        pprec = "plain_f64" if prec == "f64" else "plain_f32"
-        scale = 1.0
-        T_max = int(np.max(w.lengths))
-        plain_t = max(16, int(2e8 // (w.model.n_states ** 2 * 64)))
-        if T_max > plain_t:
-            cut = np.minimum(w.lengths, plain_t)
-            offs = np.concatenate([[0], np.cumsum(cut)]).astype(np.int64)
-            rows = np.concatenate([np.arange(w.offsets[b], w.offsets[b] + cut[b])
-                                   for b in range(w.n_seq)])
-            pdb = h.DeviceBatch(w.obs[rows], offs, dtype=np.float64 if prec == "f64" else np.float32)
-            scale = T_max / plain_t
-            plain_note = (f"timed on the batch cut to its first {plain_t} steps per sequence, "
-                          f"scaled by {scale:.1f} (linear in the longest sequence)")
-        else:
-            pdb = db
-        pws = h._ws(h.hmm_workspace_size("estep", dm, pdb, pprec))
-
-        def pstep():
-            h.hmm_estep_stats(dm, pdb, pprec, stats, loglik, status, pws)
-
-        pstep()
-        torch.cuda.synchronize()
-        log("plain warm-up done")
-        t0 = torch.cuda.Event(enable_timing=True)
-        t1 = torch.cuda.Event(enable_timing=True)
-        t0.record()
-        for _ in range(args.plain_steps):
-            pstep()
-        t1.record()
-        torch.cuda.synchronize()
-        plain_ms = t0.elapsed_time(t1) / args.plain_steps * scale
-        log(f"plain: {plain_ms:.3f} ms per E-step")
-        del pws
-
-    # Baum-Welch: E-step + FP64 M-step of the family (Gamma Newton, Student-t ECM),
-    # em_iters iterations
-    # captured once in a HIP graph and replayed
-    em = None
-    if args.em_iters > 0:
-        m0 = workloads.perturb(w.model, np.random.default_rng(1))
-        em_model = h.DeviceModel.from_model(m0)
-        K = args.em_iters
-        em_stats = torch.zeros((K, S), dtype=torch.float64, device="cuda")
-        start = [t.clone() for t in (em_model.log_pi, em_model.log_A, em_model.theta)]
-
-        def em_loop():
-            for k in range(K):
-                h.em_iteration(em_model, db, prec, em_stats[k], loglik, status, ws)
-
-        side = torch.cuda.Stream()
-        side.wait_stream(torch.cuda.current_stream())
-        with torch.cuda.stream(side):
-            em_loop()
-        torch.cuda.current_stream().wait_stream(side)
-        torch.cuda.synchronize()
-        graph = torch.cuda.CUDAGraph()
-        with torch.cuda.graph(graph):
-            em_loop()
-        for dst, src in zip((em_model.log_pi, em_model.log_A, em_model.theta), start):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        graph.replay()
-        e1.record()
-        torch.cuda.synchronize()
-        em_ms = e0.elapsed_time(e1)
-        traj = em_stats[:, 0].cpu().numpy()
-        log(f"EM graph: {em_ms / K:.3f} ms per iteration")
-        em = {"iterations": K, "ms_total": em_ms, "ms_per_iteration": em_ms / K,
-              "transitions_per_s": K * w.transitions / (em_ms / 1e3),
-              "loglik_first": float(traj[0]), "loglik_last": float(traj[-1]),
-              "loglik_non_decreasing": bool(np.all(np.diff(traj) >= -1e-6 * np.abs(traj[1:])))}
-
-    value = w.transitions / (ms / 1e3)
+    log(f"workload {args.workload}: {w.n_seq} sequences, {w.total_steps} steps, N={w.model.n_states}, "
+        f"{prec}")
+    r = timed_estep(h, w, prec, args.steps, args.warmup, graph=not args.eager_only)
+    assert r["ok"], "a sequence of the benchmark workload has a nonzero status"
+    ms, kt = r["ms"], r["kernels"]
+    log(f"{prec}: {ms:.3f} ms per E-step (eager {r['eager_ms']:.3f})")
     dom = max(kt, key=lambda k: kt[k]["ms_total"])
-    fl = algorithmic_flops(dom, w)
-    roof = None
-    if fl is not None:
-        ach = fl / (kt[dom]["ms_avg"] / 1e3) / 1e12
-        # the scaled low-precision sweeps run their products on the matrix cores
-        mfma = prec in ("bf16_scaled", "f16_scaled") and dom in ("block_fwd", "block_bwd")
-        peak = (PEAK_BF16_MFMA_TFLOPS if mfma else
-                PEAK_FP64_VALU_TFLOPS if prec == "f64" else PEAK_FP32_VALU_TFLOPS)
-        roof = {"bound": "mfma" if mfma else "alu", "kernel": dom, "achieved": ach, "peak": peak,
-                "unit": "TFLOP/s", "frac": ach / peak,
-                "traffic": measured_traffic(dom, args.workload),
-                "kernel_ms_avg": kt[dom]["ms_avg"]}
+    roof = roofline_entry(dom, kt, w, prec, args.workload)
+    others = {k: roofline_entry(k, kt, w, prec, args.workload) for k in kt
+              if k != dom and algorithmic_flops(k, w) is not None}
     out = {
         "metric": METRIC,
-        "value": value,
+        "value": w.transitions / (ms / 1e3),
         "unit": "transitions/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": ms,
-        "eager_ms_per_step": eager_ms,
+        "eager_ms_per_step": r["eager_ms"],
         "timing": ("eager calls (no graph)" if args.eager_only else
                    "E-steps replayed from one captured HIP graph; eager figure beside it"),
         "higher_is_better": True,
@@ -482,28 +580,51 @@ def main():
         "data": "synthetic",
         "config": {"workload": wl_name, "global_batch": w.n_seq, "total_steps": w.total_steps,
                    "transitions_per_step": w.transitions, "precision": prec},
-        "plain_gpu": None if plain_ms is None else {
-            "value": w.transitions / (plain_ms / 1e3), "ms_per_step": plain_ms,
-            "speedup": plain_ms / ms, "note": plain_note},
         "roofline": roof,
-        "em_graph": em,
+        "roofline_other_kernels": others,
+        "estep_roofline": estep_roofline(w, ms, prec),
         "kernels": kt,
     }
+    if args.plain_steps > 0 and prec in ("f64", "f32"):
+        pms, note = plain_time(h, w, prec, args.plain_steps)
+        out["plain_gpu"] = {"value": w.transitions / (pms / 1e3), "ms_per_step": pms,
+                            "speedup": pms / ms, "note": note}
+        log(f"plain {prec}: {pms:.3f} ms per E-step")
     if args.copy_calib:
         src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
         dst.copy_(src)
         torch.cuda.synchronize()
         log("copy calibration: 256 MiB copied")
-    if args.others > 0 and args.workload == "batched":
-        out["other_workloads"] = other_workloads(h, workloads, args.others)
-    if args.serving_seconds > 0:
+    if args.extras and args.workload == "large" and prec == "f64":
+        # the same workload in the narrower forms, with their error against the FP64 run
+        prs = {}
+        for p in ("f32", "bf16_scaled", "f16_scaled"):
+            rp = timed_estep(h, w, p, args.steps, args.warmup)
+            e = {"ms_per_estep": rp["ms"], "transitions_per_s": w.transitions / (rp["ms"] / 1e3),
+                 "all_status_ok": rp["ok"], "error_vs_f64": errors_vs(rp, r, w.model.n_states),
+                 "estep_roofline": estep_roofline(w, rp["ms"], "f32"),
+                 "kernels_ms": {k: round(v["ms_avg"], 4) for k, v in rp["kernels"].items()}}
+            if p == "f32" and args.plain_steps > 0:
+                pms, note = plain_time(h, w, "f32", args.plain_steps)
+                e["plain_gpu"] = {"ms_per_step": pms, "speedup": pms / rp["ms"], "note": note}
+            prs[p] = e
+            log(f"large {p}: {rp['ms']:.3f} ms per E-step")
+        out["precisions"] = prs
+        out["batched_n8"] = batched_section(h, workloads, args.steps, args.warmup,
+                                            args.plain_steps, args.em_iters)
+        out["other_workloads"] = other_workloads(h, workloads, 3)
+    if args.extras and args.serving_seconds > 0:
         qps = [float(x) for x in args.serving_qps.split(",") if x]
         out["serving"] = serving_bench(h, workloads, qps, args.serving_seconds,
                                        streams=args.serving_streams)
         log("serving done")
+        out["serving_unbatched"] = serving_bench(h, workloads, qps[:2], args.serving_seconds,
+                                                 streams=1, max_batch=1)
+        log("unbatched serving done")
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w)
+        log("cpu baseline done")
     print(json.dumps(out))
 
 

@@ -12,6 +12,7 @@ import torch  # noqa: F401  (imported at collection, outside the per-test time l
 
 import oracle
 import workloads
+from tests.oracle_pool import pooled_estep
 from tests.parity import TOL, assert_loglik_close, assert_stats_close
 
 pytestmark = pytest.mark.gpu
@@ -108,11 +109,16 @@ def test_config2_subset(h, prec):
 
 
 def test_config2_full_size(h):
-    """All 1024 sequences in the benchmark's launch configuration: sampled
-    sequences against the oracle, plus identities that hold at any size."""
+    """All 1024 sequences in the benchmark's launch configuration: every pooled
+    statistic and log-likelihood against the oracle (run on the host's
+    threads), sampled sequences, and identities that hold at any size."""
     w = workloads.config2()
     stats, ll, st = run_estep(h, w, "f32")
     assert (st == 0).all()
+    full = pooled_estep(w)
+    assert (full["status"] == 0).all()
+    assert_loglik_close(ll, full["loglik"], TOL["f32"], "config2 full f32")
+    assert_stats_close(stats, full["stats"], 8, "gamma", TOL["f32"], "config2 full f32")
     rng = np.random.default_rng(5)
     pick = np.sort(rng.choice(1024, 12, replace=False))
     sub = w.subset(pick)
@@ -126,10 +132,10 @@ def test_config2_full_size(h):
     assert abs(gs.sum() - w.total_steps) < 1e-4 * w.total_steps
     assert abs(xi.sum() - (w.total_steps - 1024)) < 1e-4 * w.total_steps
     assert abs(stats[0] - ll.sum()) < 1e-9 * abs(stats[0])
-    # the FP64 batched path agrees with the FP32 one on every pooled statistic
+    # the FP64 batched path against the oracle on every pooled statistic
     s64, ll64, _ = run_estep(h, w, "f64")
-    assert_loglik_close(ll, ll64, TOL["f32"], "config2 f32 vs f64")
-    assert_stats_close(stats, s64, N, "gamma", TOL["f32"], "config2 f32 vs f64")
+    assert_loglik_close(ll64, full["loglik"], TOL["f64"], "config2 full f64")
+    assert_stats_close(s64, full["stats"], N, "gamma", TOL["f64"], "config2 full f64")
 
 
 def test_status_codes_and_exclusion(h):

@@ -12,6 +12,7 @@ import torch  # noqa: F401  (imported at collection, outside the per-test time l
 
 import oracle
 import workloads
+from tests.oracle_pool import pooled_estep
 from tests.parity import TOL, assert_loglik_close, assert_stats_close
 
 pytestmark = pytest.mark.gpu
@@ -192,3 +193,64 @@ def test_config3_full_size(h):
     s64, ll64, _ = run_estep(h, w, "f64")
     assert_loglik_close(ll, ll64, TOL["f32"], "config3 f32 vs f64")
     assert_stats_close(stats, s64, N, "diag", TOL["f32"], "config3 f32 vs f64", d=16)
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_config3_multi_slice(h, prec):
+    """Nine sequences of 2048 steps (18,432 rows): the transition contraction
+    runs over many row slices whose partials are summed in FP64, and the
+    sweeps cross every prefetch window; every statistic against the oracle."""
+    w = workloads.config3(n_seq=9, T=2048)
+    ref = pooled_estep(w, groups=9)
+    stats, ll, st = run_estep(h, w, prec)
+    assert (st == 0).all() and (ref["status"] == 0).all()
+    assert_loglik_close(ll, ref["loglik"], TOL[prec], f"config3 9x2048 {prec}")
+    assert_stats_close(stats, ref["stats"], 256, "diag", TOL[prec], f"config3 9x2048 {prec}", d=16)
+
+
+def _config4a_prefix(min_steps):
+    """The first sequences of the full-covariance workload whose lengths add
+    up to more than min_steps."""
+    w = workloads.config4a()
+    k = int(np.searchsorted(np.cumsum(w.lengths), min_steps)) + 1
+    return w.subset(np.arange(k))
+
+
+def test_config4a_multi_tile(h):
+    """Full covariance, D = 32, FP32, on more than 2 x 8192 steps: the
+    matrix-core family sums run several step tiles and merge them; every
+    statistic against the oracle."""
+    w = _config4a_prefix(2 * 8192 + 1)
+    assert w.total_steps > 2 * 8192
+    ref = pooled_estep(w)
+    stats, ll, st = run_estep(h, w, "f32")
+    assert (st == 0).all() and (ref["status"] == 0).all()
+    assert_loglik_close(ll, ref["loglik"], TOL["f32"], "config4a multi-tile f32")
+    assert_stats_close(stats, ref["stats"], 32, "full", TOL["f32"], "config4a multi-tile f32", d=32)
+
+
+def test_config4a_full_size(h):
+    """All 512 full-covariance sequences as the benchmark launches them:
+    sampled sequences against the oracle, identities that hold at any size,
+    and the FP32 path against the FP64 one."""
+    w = workloads.config4a()
+    stats, ll, st = run_estep(h, w, "f32")
+    assert (st == 0).all()
+    B = w.n_seq
+    rng = np.random.default_rng(11)
+    pick = np.sort(rng.choice(B, 6, replace=False))
+    sub = w.subset(pick)
+    ref = pooled_estep(sub, groups=6)
+    assert_loglik_close(ll[pick], ref["loglik"], TOL["f32"], "config4a sampled")
+    N = 32
+    g1 = stats[1:1 + N]
+    xi = stats[1 + N:1 + N + N * N]
+    gs = stats[1 + N + N * N:1 + 2 * N + N * N]
+    total = w.total_steps
+    assert abs(g1.sum() - B) < 1e-4 * B
+    assert abs(gs.sum() - total) < 1e-4 * total
+    assert abs(xi.sum() - (total - B)) < 1e-4 * total
+    assert abs(stats[0] - ll.sum()) < 1e-9 * abs(stats[0])
+    s64, ll64, _ = run_estep(h, w, "f64")
+    assert_loglik_close(ll, ll64, TOL["f32"], "config4a f32 vs f64")
+    assert_stats_close(stats, s64, N, "full", TOL["f32"], "config4a f32 vs f64", d=32)
