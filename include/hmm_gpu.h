@@ -210,6 +210,25 @@ hmm_status hmm_estep_stats(const hmm_model *model, const hmm_batch *batch, hmm_p
                            double *stats, double *loglik, int32_t *seq_status, void *ws,
                            size_t ws_bytes, void *stream);
 
+/* Size of the static device area used by hmm_estep_stats_noalloc (64 MiB per
+ * GPU, held from the library's load until the process ends). */
+#define HMM_NOALLOC_SCRATCH_BYTES (64u << 20)
+
+/* hmm_estep_stats for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation.
+ * Same arguments and results as hmm_estep_stats, but the workspace is a
+ * static device array of HMM_NOALLOC_SCRATCH_BYTES in the library (one per
+ * GPU, its address taken on the first call on each device).  No call
+ * allocates or frees memory.  A batch whose hmm_workspace_size(HMM_OP_ESTEP)
+ * exceeds the area is rejected with HMM_ERR_WORKSPACE before anything is
+ * enqueued.  Every call on one GPU shares that GPU's area and leaves its
+ * contents behind (each call initialises what it reads), so calls that may
+ * overlap on one GPU (different streams or host threads) race: the caller
+ * serialises them, e.g. on one stream. */
+hmm_status hmm_estep_stats_noalloc(const hmm_model *model, const hmm_batch *batch,
+                                   hmm_precision prec, double *stats, double *loglik,
+                                   int32_t *seq_status, void *stream);
+
 /* Viterbi decoding (section 3.3): the max-product recursion in log space
  * with backtrace.  path: device [sum T] int32 state indices (-1 on every
  * step of a sequence with no path or a non-finite observation); path_logp:

@@ -28,7 +28,8 @@ OP = {"emission": 0, "forward_backward": 1, "estep": 2, "viterbi": 3, "posterior
 
 EXPORTED = [
     "hmm_version", "hmm_last_error", "hmm_stats_len", "hmm_workspace_size",
-    "hmm_emission_logpdf", "hmm_forward_backward", "hmm_estep_stats", "hmm_viterbi",
+    "hmm_emission_logpdf", "hmm_forward_backward", "hmm_estep_stats", "hmm_estep_stats_noalloc",
+    "hmm_viterbi",
     "hmm_posterior_decode", "hmm_mstep_default_opts", "hmm_mstep_transitions",
     "hmm_mstep_gaussian", "hmm_mstep_gamma", "hmm_mstep_student_t", "hmm_mstep_poisson",
     "hmm_mstep_diag_gaussian", "hmm_mstep_full_gaussian", "hmm_set_chunk_len",
@@ -102,6 +103,7 @@ def _load():
         "hmm_emission_logpdf": ([MP, BP, ctypes.c_int, P, P, sz, P], ctypes.c_int),
         "hmm_forward_backward": ([MP, BP, ctypes.c_int, P, P, P, P, sz, P], ctypes.c_int),
         "hmm_estep_stats": ([MP, BP, ctypes.c_int, P, P, P, P, sz, P], ctypes.c_int),
+        "hmm_estep_stats_noalloc": ([MP, BP, ctypes.c_int, P, P, P, P], ctypes.c_int),
         "hmm_viterbi": ([MP, BP, ctypes.c_int, P, P, P, P, sz, P], ctypes.c_int),
         "hmm_posterior_decode": ([MP, BP, ctypes.c_int, P, P, P, sz, P], ctypes.c_int),
         "hmm_mstep_default_opts": ([OPP], None),
@@ -239,6 +241,12 @@ def hmm_estep_stats(model, batch, prec, stats, loglik, seq_status, ws, stream=No
     _check(_lib.hmm_estep_stats(ctypes.byref(model.c), ctypes.byref(batch.c), PREC[prec],
                                 _ptr(stats), _ptr(loglik), _ptr(seq_status), _ptr(ws),
                                 _nbytes(ws), _stream(stream)))
+
+
+def hmm_estep_stats_noalloc(model, batch, prec, stats, loglik, seq_status, stream=None):
+    _check(_lib.hmm_estep_stats_noalloc(ctypes.byref(model.c), ctypes.byref(batch.c), PREC[prec],
+                                        _ptr(stats), _ptr(loglik), _ptr(seq_status),
+                                        _stream(stream)))
 
 
 def hmm_viterbi(model, batch, prec, path, path_logp, n_ties, ws, stream=None):

@@ -7,6 +7,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <string>
+#include <mutex>
 #include <vector>
 
 #include "hmm_internal.hpp"
@@ -456,6 +457,37 @@ hmm_status model_theta_len(const hmm_model *m, size_t *len) {
 }
 }  // namespace hmmk
 
+
+// ---------------------------------------------------------------- allocation-free E-step
+// The workspace of hmm_estep_stats_noalloc is this file-scope device array.
+// Its name is a host-side stand-in in host code: the device address of each
+// GPU's copy comes from hipGetSymbolAddress, taken once per device with that
+// device current, and only that address is handed to kernels.
+static __device__ __align__(256) unsigned char scratch[HMM_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+hmm_status scratch_for_current_device(void **out) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices)
+        return fail(HMM_ERR_DEVICE, "no current HIP device (or device index %d out of range)", dev);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(HMM_ERR_DEVICE, "hipGetSymbolAddress(scratch) on device %d: %s", dev,
+                        hipGetErrorString(e));
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return HMM_OK;
+}
+}  // namespace
+
 extern "C" {
 
 const char *hmm_version(void) { return "hmmgpu 0.1.0 (gfx950)"; }
@@ -539,6 +571,25 @@ hmm_status hmm_estep_stats(const hmm_model *model, const hmm_batch *batch, hmm_p
                                           nullptr, stats, s);
     return run_posterior_path<float>(model, batch, c, p, (char *)ws, loglik, seq_status, nullptr,
                                      stats, s);
+}
+
+hmm_status hmm_estep_stats_noalloc(const hmm_model *model, const hmm_batch *batch,
+                                   hmm_precision prec, double *stats, double *loglik,
+                                   int32_t *seq_status, void *stream) {
+    Checked c;
+    hmm_status st = check_batch(batch, model, &c);
+    if (st != HMM_OK) return st;
+    Plan p;
+    if ((st = make_plan(HMM_OP_ESTEP, c, prec, &p)) != HMM_OK) return st;
+    if (p.total > (size_t)HMM_NOALLOC_SCRATCH_BYTES)
+        return fail(HMM_ERR_WORKSPACE,
+                    "this batch needs %zu bytes of workspace; the allocation-free E-step has a "
+                    "static area of %zu bytes (use hmm_estep_stats with a caller workspace)",
+                    p.total, (size_t)HMM_NOALLOC_SCRATCH_BYTES);
+    void *ws = nullptr;
+    if ((st = scratch_for_current_device(&ws)) != HMM_OK) return st;
+    return hmm_estep_stats(model, batch, prec, stats, loglik, seq_status, ws,
+                           (size_t)HMM_NOALLOC_SCRATCH_BYTES, stream);
 }
 
 hmm_status hmm_posterior_decode(const hmm_model *model, const hmm_batch *batch,
