@@ -51,6 +51,7 @@ struct SwCfg {
     static constexpr int XV = 16 / (int)sizeof(R); // entries per 16-byte LDS read
     // steps of inputs prefetched into registers (fewer where the tile fills them)
     static constexpr int PF = (sizeof(R) == 8 && NC == 256) ? 2 : 4;
+    static constexpr int PFB = (sizeof(R) == 8 && NC == 256) ? 1 : 4;   // backward (three rings)
     static_assert(RR % XV == 0 && RL % XV == 0, "tile rows must fill 16-byte reads");
 };
 
@@ -60,8 +61,8 @@ struct SwShared {
     R psum[2][4][C::PG];
     R xw[C::NW][C::WR];
     R hw[C::NW][C::WR];   // backward: a_t o b_t of the wave's states, kept over the barrier
-    R gmax[2][4];
-    R gE[4];
+    uint32_t gmax[2][4];   // high words of group maxima (see hiword)
+    uint32_t gE[4];
     R zsum[2][4];
     double red[C::NW];
 };
@@ -110,6 +111,37 @@ __device__ __forceinline__ double pair_sum16(double x, double y) {
     return p + q;
 }
 
+// Rescaling needs only the binary exponent of a vector's largest entry.  The
+// entries are >= 0, so the exponent of the largest one is that of the largest
+// high word taken as an unsigned integer (the whole word in single precision,
+// the upper 32 bits in double): the maximum runs on integers, without the
+// quieting that floating-point max needs.
+__device__ __forceinline__ uint32_t hiword(float x) { return __builtin_bit_cast(uint32_t, x); }
+__device__ __forceinline__ uint32_t hiword(double x) {
+    return (uint32_t)(__builtin_bit_cast(uint64_t, x) >> 32);
+}
+template <typename R>
+__device__ __forceinline__ int hiword_exp(uint32_t u) {
+    if constexpr (sizeof(R) == 4)
+        return fexp(__builtin_bit_cast(float, u));
+    else
+        return fexp(__builtin_bit_cast(double, (uint64_t)u << 32));
+}
+__device__ __forceinline__ uint32_t umax(uint32_t a, uint32_t b) { return a > b ? a : b; }
+__device__ __forceinline__ uint32_t wave_umax(uint32_t v) {
+    v = umax(v, (uint32_t)dpp_i<DPP_QP_X1>((int)v));
+    v = umax(v, (uint32_t)dpp_i<DPP_QP_X2>((int)v));
+    v = umax(v, (uint32_t)dpp_i<DPP_HALF_MIRROR>((int)v));
+    v = umax(v, (uint32_t)dpp_i<DPP_ROW_MIRROR>((int)v));
+    auto r16 = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+    v = umax((uint32_t)r16[0], (uint32_t)r16[1]);
+    auto r32 = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+    return umax((uint32_t)r32[0], (uint32_t)r32[1]);
+}
+__device__ __forceinline__ uint32_t umax4(const uint32_t *g) {
+    return umax(umax(g[0], g[1]), umax(g[2], g[3]));
+}
+
 // The thread's view of the sweep: tile, lane roles and LDS positions.
 template <typename R, int NC>
 struct SwTile {
@@ -140,7 +172,11 @@ struct SwTile {
                 a[k][c] = (i < N && j < N) ? v : (R)0;
             }
         if constexpr (C::RL > 0) {
-            // LDS rows as 16-byte pairs of adjacent columns, lanes contiguous
+            // LDS rows as 16-byte pairs of adjacent columns, wave-major: entry
+            // e of lane l of wave w at ((w * EPL + e) * 64 + l), so a wave's
+            // read of one entry is 1 KB contiguous and a lane's entries lie
+            // 1 KB apart (all within the 16-bit LDS offset of one address)
+            constexpr int EPL = C::RL * (C::s / 2);
 #pragma unroll
             for (int k = 0; k < C::RL; ++k)
 #pragma unroll
@@ -151,7 +187,7 @@ struct SwTile {
                     V p;
                     p.x = (i < N && j < N) ? v0 : (R)0;
                     p.y = (i < N && j + 1 < N) ? v1 : (R)0;
-                    alds[(k * (C::s / 2) + cp) * C::NT + tid] = p;
+                    alds[(w * EPL + k * (C::s / 2) + cp) * 64 + l] = p;
                 }
         }
         const int lp = l % C::WR, cc = lp >> 3, mm = lp & 7;
@@ -180,7 +216,8 @@ struct SwTile {
             }
         }
         if constexpr (C::RL > 0) {
-            const int tid = threadIdx.x;
+            constexpr int EPL = C::RL * (C::s / 2);
+            const V *base = alds + w * EPL * 64 + l;
 #pragma unroll
             for (int k = 0; k < C::RL; k += C::XV) {
                 const V xv = *reinterpret_cast<const V *>(xr + C::RR + k);
@@ -189,7 +226,7 @@ struct SwTile {
                     const R xk = Vec16<R>::get(xv, kk);
 #pragma unroll
                     for (int cp = 0; cp < C::s / 2; ++cp) {
-                        const V av = alds[((k + kk) * (C::s / 2) + cp) * C::NT + tid];
+                        const V av = base[((k + kk) * (C::s / 2) + cp) * 64];
                         acc[2 * cp] = fma(xk, av.x, acc[2 * cp]);
                         acc[2 * cp + 1] = fma(xk, av.y, acc[2 * cp + 1]);
                     }
@@ -213,11 +250,6 @@ struct SwTile {
                (sh.psum[buf][2][ppos] + sh.psum[buf][3][ppos]);
     }
 };
-
-template <typename R>
-__device__ __forceinline__ R max4(const R *g) {
-    return fmax(fmax(g[0], g[1]), fmax(g[2], g[3]));
-}
 
 // ---------------------------------------------------------------- forward
 template <typename R, int NC>
@@ -243,34 +275,37 @@ __global__ __launch_bounds__(512) void k_sw_fwd(StagedModel<R> m, const int64_t 
     const int jc = min(tl.jrow, N - 1);
     const bool lead = tl.l == 0 && tl.cb_hi == 0;
     // t = 0: pi o e_0, normalised exactly
-    R v = tl.rlive ? m.pi[jc] * etab[off * N + jc] : (R)0;
+    // row pointers are uniform; lanes add their state index
+    const R *erow = etab + off * N;
+    R *arow = alpha + off * N;
+    R v = tl.rlive ? m.pi[jc] * erow[jc] : (R)0;
     {
-        const R wm = wave_max_r(v);
+        const uint32_t wm = wave_umax(hiword(v));
         if (lead) sh.gE[tl.q_hi] = wm;
     }
     __syncthreads();   // also publishes the LDS rows of the tile
-    int ex = fexp(max4(sh.gE));
+    int ex = __builtin_amdgcn_readfirstlane(hiword_exp<R>(umax4(sh.gE)));
     v = fldexp(v, -ex);
     int64_t E = ex;
-    if (tl.writer && tl.rlive) alpha[off * N + tl.jrow] = v;
+    if (tl.writer && tl.rlive) arow[tl.jrow] = v;
     if (threadIdx.x == 0) aexp[off] = ex;
     if (tl.l < C::WR) sh.xw[tl.w][tl.rho] = v;
     wave_lds_order();
     R ring[C::PF];
 #pragma unroll
-    for (int u = 0; u < C::PF; ++u) ring[u] = etab[(off + min(1 + u, T - 1)) * N + jc];
+    for (int u = 0; u < C::PF; ++u) ring[u] = (etab + (off + min(1 + u, T - 1)) * N)[jc];
     for (int t0 = 1; t0 < T; t0 += C::PF) {
 #pragma unroll
         for (int u = 0; u < C::PF; ++u) {
             const int t = t0 + u;
             if (t >= T) break;
             const R e = ring[u];
-            ring[u] = etab[(off + min(t + C::PF, T - 1)) * N + jc];
+            ring[u] = (etab + (off + min(t + C::PF, T - 1)) * N)[jc];
             const int buf = t & 1;
             const bool resc = !exact && (t % per) == 0;
             if (resc) {
                 // largest entry of this step's input vector
-                const R wm = wave_max_r(v);
+                const uint32_t wm = wave_umax(hiword(v));
                 if (lead) sh.gmax[buf][tl.q_hi] = wm;
             }
             tl.product(sh, alds, buf);
@@ -279,16 +314,17 @@ __global__ __launch_bounds__(512) void k_sw_fwd(StagedModel<R> m, const int64_t 
             raw = tl.rlive ? raw * e : (R)0;
             ex = 0;
             if (exact) {
-                const R wm = wave_max_r(raw);
+                const uint32_t wm = wave_umax(hiword(raw));
                 if (lead) sh.gE[tl.q_hi] = wm;
                 __syncthreads();
-                ex = fexp(max4(sh.gE));
+                ex = hiword_exp<R>(umax4(sh.gE));
             } else if (resc) {
-                ex = fexp(max4(sh.gmax[buf]));
+                ex = hiword_exp<R>(umax4(sh.gmax[buf]));
             }
+            ex = __builtin_amdgcn_readfirstlane(ex);   // uniform: kept in scalar registers
             v = fldexp(raw, -ex);
             E += ex;
-            if (tl.writer && tl.rlive) alpha[(off + t) * N + tl.jrow] = v;
+            if (tl.writer && tl.rlive) (arow + (int64_t)t * N)[tl.jrow] = v;
             if (threadIdx.x == 0) aexp[off + t] = ex;
             if (tl.l < C::WR) sh.xw[tl.w][tl.rho] = v;
             wave_lds_order();
@@ -353,27 +389,27 @@ __global__ __launch_bounds__(512) void k_sw_bwd(StagedModel<R> m, const int64_t 
     const int jc = min(tl.jrow, N - 1);
     const bool lead = tl.l == 0 && tl.cb_hi == 0;
     R bt = tl.rlive ? (R)1 : (R)0;   // b_{T-1}
-    R ra[C::PF], re[C::PF];
-    int rx[C::PF];
+    R ra[C::PFB], re[C::PFB];
+    int rx[C::PFB];
 #pragma unroll
-    for (int u = 0; u < C::PF; ++u) {
+    for (int u = 0; u < C::PFB; ++u) {
         const int64_t row = off + max(T - 1 - u, 0);
-        ra[u] = alpha[row * N + jc];
-        re[u] = etab[row * N + jc];
+        ra[u] = (alpha + row * N)[jc];
+        re[u] = (etab + row * N)[jc];
         rx[u] = aexp[row];
     }
     __syncthreads();   // the LDS rows of the tile
-    for (int t0 = T - 1; t0 >= 1; t0 -= C::PF) {
+    for (int t0 = T - 1; t0 >= 1; t0 -= C::PFB) {
 #pragma unroll
-        for (int u = 0; u < C::PF; ++u) {
+        for (int u = 0; u < C::PFB; ++u) {
             const int t = t0 - u;
             if (t < 1) break;
             const R a = tl.rlive ? ra[u] : (R)0, e = tl.rlive ? re[u] : (R)0;
             const int xt = rx[u];
             {
-                const int64_t row = off + max(t - C::PF, 0);
-                ra[u] = alpha[row * N + jc];
-                re[u] = etab[row * N + jc];
+                const int64_t row = off + max(t - C::PFB, 0);
+                ra[u] = (alpha + row * N)[jc];
+                re[u] = (etab + row * N)[jc];
                 rx[u] = aexp[row];
             }
             const int buf = t & 1;
@@ -384,7 +420,7 @@ __global__ __launch_bounds__(512) void k_sw_bwd(StagedModel<R> m, const int64_t 
             }
             const bool resc = !exact && ((T - 1 - t) % per) == 0;
             if (resc) {
-                const R wm = wave_max_r(wv);
+                const uint32_t wm = wave_umax(hiword(wv));
                 if (lead) sh.gmax[buf][tl.q_hi] = wm;
             }
             if (tl.l < C::WR) {
@@ -399,20 +435,21 @@ __global__ __launch_bounds__(512) void k_sw_bwd(StagedModel<R> m, const int64_t 
             if (tl.writer && tl.rlive) {
                 // h and w of this lane's state, read back from the wave's own slots
                 const int64_t row = off + t;
-                gamma[row * N + tl.jrow] = use ? sh.hw[tl.w][tl.rho] * rz : (R)0;
-                etab[row * N + tl.jrow] = use ? fldexp(sh.xw[tl.w][tl.rho] * rz, -xt) : (R)0;
+                (gamma + row * N)[tl.jrow] = use ? sh.hw[tl.w][tl.rho] * rz : (R)0;
+                (etab + row * N)[tl.jrow] = use ? fldexp(sh.xw[tl.w][tl.rho] * rz, -xt) : (R)0;
             }
             R raw = tl.gather(sh, buf);
             raw = tl.rlive ? raw : (R)0;
             int ex = 0;
             if (exact) {
-                const R wm = wave_max_r(raw);
+                const uint32_t wm = wave_umax(hiword(raw));
                 if (lead) sh.gE[tl.q_hi] = wm;
                 __syncthreads();
-                ex = fexp(max4(sh.gE));
+                ex = hiword_exp<R>(umax4(sh.gE));
             } else if (resc) {
-                ex = fexp(max4(sh.gmax[buf]));
+                ex = hiword_exp<R>(umax4(sh.gmax[buf]));
             }
+            ex = __builtin_amdgcn_readfirstlane(ex);
             bt = fldexp(raw, -ex);
         }
     }
@@ -422,8 +459,8 @@ __global__ __launch_bounds__(512) void k_sw_bwd(StagedModel<R> m, const int64_t 
         // for row max(t - PF, 0) = 0
         R a0 = ra[0];
 #pragma unroll
-        for (int u = 1; u < C::PF; ++u)
-            if ((T - 1) % C::PF == u) a0 = ra[u];
+        for (int u = 1; u < C::PFB; ++u)
+            if ((T - 1) % C::PFB == u) a0 = ra[u];
         const R a = tl.rlive ? a0 : (R)0;
         const R h = a * bt;
         const R zs = wave_sum_r(tl.l < C::WR ? h : (R)0);
