@@ -46,8 +46,19 @@ struct SwCfg {
     static constexpr int RL = r - RR;              // rows in LDS
     static constexpr int WR = NC / 4;              // states a wave produces (= 8 s)
     static constexpr int SV = s / 4;               // column sums per lane after the reduce
-    static constexpr int PADC = 40;                // psum pitch per column residue (>= 32 blocks)
-    static constexpr int PG = s * PADC;            // psum entries per row group
+    static constexpr int PG = NC;                  // psum entries per row group
+    // psum position of output column (cb, c): s cb + (c ^ H(cb)).  The XOR
+    // swizzle puts the writers of one LDS pass (16 column blocks, one or two
+    // residues c) and the readers (consecutive columns) on distinct banks,
+    // for 4- and 8-byte entries alike (checked exhaustively on the host).
+    __host__ __device__ static constexpr int H(int cbk) {
+        return sizeof(R) == 4
+                   ? (s == 8 ? (((cbk >> 2) & 1) | ((cbk >> 2) & 2) << 1) : 2 * ((cbk >> 3) & 1))
+                   : (s == 8 ? (cbk >> 1) & 7 : (cbk >> 2) & 3);
+    }
+    __host__ __device__ static constexpr int pos(int col) {
+        return s * (col / s) + ((col % s) ^ H(col / s));
+    }
     static constexpr int XV = 16 / (int)sizeof(R); // entries per 16-byte LDS read
     // steps of inputs prefetched into registers (fewer where the tile fills them)
     static constexpr int PF = (sizeof(R) == 8 && NC == 256) ? 2 : 4;
@@ -190,10 +201,9 @@ struct SwTile {
                     alds[(w * EPL + k * (C::s / 2) + cp) * 64 + l] = p;
                 }
         }
-        const int lp = l % C::WR, cc = lp >> 3, mm = lp & 7;
-        jrow = q_hi * C::WR + C::s * mm + cc;
-        rho = C::s * mm + cc;
-        ppos = cc * C::PADC + 8 * q_hi + mm;
+        rho = l % C::WR;
+        jrow = q_hi * C::WR + rho;
+        ppos = C::pos(jrow);
         rlive = jrow < N;
         writer = cb_hi == 0 && l < C::WR;
     }
@@ -241,7 +251,7 @@ struct SwTile {
 #pragma unroll
         for (int e = 0; e < C::SV; ++e) {
             const R u = pair_sum16(v1[e], v1[e + C::SV]);
-            sh.psum[buf][q_hi][(C::SV * q_lo + e) * C::PADC + cb] = u;
+            sh.psum[buf][q_hi][C::pos(C::s * cb + C::SV * q_lo + e)] = u;
         }
     }
 
