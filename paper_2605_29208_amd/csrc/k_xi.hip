@@ -53,35 +53,31 @@ struct XiCfg {
     static constexpr int64_t PER_SLICE = (int64_t)NC * NC;   // partial entries per slice
 };
 
-// four consecutive entries of row `row` starting at column c (zero where c + e >= N)
+// four consecutive entries of row `row` starting at column c (clamped to
+// column 0 past the row's end)
 template <typename R, bool VEC>
-__device__ __forceinline__ void load4(const R *__restrict__ base, int64_t row, int c, int N, bool ok,
+__device__ __forceinline__ void load4(const R *__restrict__ base, int64_t row, int c, int N,
                                       R (&v)[4]) {
     if constexpr (VEC) {
         // N % 4 == 0: a group of four is wholly inside or outside the row
-        const bool in = ok && c < N;
-        const R *p = base + row * N + (in ? c : 0);
+        const R *p = base + row * N + (c < N ? c : 0);
         if constexpr (sizeof(R) == 4) {
             const float4 q = *reinterpret_cast<const float4 *>(p);
-            v[0] = in ? q.x : 0.f;
-            v[1] = in ? q.y : 0.f;
-            v[2] = in ? q.z : 0.f;
-            v[3] = in ? q.w : 0.f;
+            v[0] = q.x;
+            v[1] = q.y;
+            v[2] = q.z;
+            v[3] = q.w;
         } else {
             const double2 q0 = *reinterpret_cast<const double2 *>(p);
             const double2 q1 = *reinterpret_cast<const double2 *>(p + 2);
-            v[0] = in ? q0.x : 0.0;
-            v[1] = in ? q0.y : 0.0;
-            v[2] = in ? q1.x : 0.0;
-            v[3] = in ? q1.y : 0.0;
+            v[0] = q0.x;
+            v[1] = q0.y;
+            v[2] = q1.x;
+            v[3] = q1.y;
         }
     } else {
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const bool in = ok && c + e < N;
-            const R x = base[row * N + (in ? c + e : 0)];
-            v[e] = in ? x : (R)0;
-        }
+        for (int e = 0; e < 4; ++e) v[e] = base[row * N + (c + e < N ? c + e : 0)];
     }
 }
 
@@ -106,33 +102,45 @@ __global__ __launch_bounds__((XiCfg<R, NC>::NT)) void k_xi_mfma(const R *__restr
     for (int u = 0; u < 4; ++u)
 #pragma unroll
         for (int v = 0; v < 8; ++v) acc[u][v] = acc_t{0, 0, 0, 0};
-    R fa[4], fb[8];
+    // No masks: columns outside the matrix only reach output entries that the
+    // reduction drops, and a row at or past the slice end pairs alpha row
+    // kbeg with w' row 0, which the backward sweep zeroes (no transition
+    // enters a sequence's first step), so it adds nothing.
     auto fetch = [&](int64_t k0, R (&xa)[4], R (&xb)[8]) {
         const int64_t k = k0 + (l >> 4);
         const bool ok = k < kend;
-        const int64_t kc = ok ? k : kbeg;
-        load4<R, VEC>(alpha, kc, i0, N, ok, xa);
+        load4<R, VEC>(alpha, ok ? k : kbeg, i0, N, xa);
         R t0[4], t1[4];
-        load4<R, VEC>(wp, kc + 1, j0, N, ok, t0);
-        load4<R, VEC>(wp, kc + 1, j0 + 64, N, ok, t1);
+        load4<R, VEC>(wp, ok ? k + 1 : 0, j0, N, t0);
+        load4<R, VEC>(wp, ok ? k + 1 : 0, j0 + 64, N, t1);
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
             xb[e] = t0[e];
             xb[4 + e] = t1[e];
         }
     };
-    fetch(kbeg, fa, fb);
-    for (int64_t k0 = kbeg; k0 < kend; k0 += 4) {
-        R na[4], nb[8];
-        fetch(k0 + 4, na, nb);   // next rows in flight during this group's products
+    // NB groups of four rows in flight, each refilled right after its 32
+    // products: a group's loads are issued NB - 1 groups before its use (the
+    // compiler still waits for all loads once per pass over the NB groups,
+    // so NB is as large as the registers allow)
+    constexpr int NB = sizeof(R) == 8 ? 6 : 4;
+    R ra[NB][4], rb[NB][8];
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
+    for (int g = 0; g < NB; ++g) fetch(kbeg + 4 * g, ra[g], rb[g]);
+    for (int64_t k0 = kbeg; k0 < kend; k0 += 4 * NB) {
 #pragma unroll
-            for (int v = 0; v < 8; ++v) acc[u][v] = XiMfma<R>::op(fa[u], fb[v], acc[u][v]);
+        for (int g = 0; g < NB; ++g) {
 #pragma unroll
-        for (int e = 0; e < 4; ++e) fa[e] = na[e];
+            for (int u = 0; u < 4; ++u)
 #pragma unroll
-        for (int e = 0; e < 8; ++e) fb[e] = nb[e];
+                for (int v = 0; v < 8; ++v) acc[u][v] = XiMfma<R>::op(ra[g][u], rb[g][v], acc[u][v]);
+            // refill this group's registers right behind its products (kept in
+            // place: hoisting the loads would make the compiler rotate
+            // registers and wait for every load at the end of the loop)
+            __builtin_amdgcn_sched_barrier(0);
+            fetch(k0 + 4 * (g + NB), ra[g], rb[g]);
+            __builtin_amdgcn_sched_barrier(0);
+        }
     }
     // block order: ((jh WJ + wj) WI + wi) * 32 + 8 u + v, then lane, then the
     // four result rows of the lane
