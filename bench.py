@@ -205,11 +205,13 @@ def setup_estep(h, w, prec):
     return dm, db, ws, stats, ll, st
 
 
-def timed_estep(h, w, prec, steps, warmup, graph=True):
-    """E-step timing: `steps` eager calls with per-kernel hipEvents (the kernel
-    table), then the same calls captured in one HIP graph and replayed (the
-    timed value).  Returns ms per E-step, the eager figure, the kernel table,
-    the results of the last call and whether every status was 0."""
+def timed_estep(h, w, prec, steps, warmup, graph=True, tune=True):
+    """E-step timing: warm-up calls and the autotuner (every schedule variant
+    of the route timed on this batch, the fastest kept), then `steps` eager
+    calls with per-kernel hipEvents (the kernel table), then the same calls
+    captured in one HIP graph and replayed (the timed value).  Returns ms per
+    E-step, the eager figure, the kernel table, the tuner's choice, the
+    results of the last call and whether every status was 0."""
     import torch
     dm, db, ws, stats, ll, st = setup_estep(h, w, prec)
 
@@ -219,6 +221,11 @@ def timed_estep(h, w, prec, steps, warmup, graph=True):
     for _ in range(warmup):
         step()
     torch.cuda.synchronize()
+    tuning = None
+    if tune:
+        v, vms = h.hmm_autotune(dm, db, prec, stats, ll, st, ws)
+        tuning = {"variant": v, "variant_ms": vms}
+        torch.cuda.synchronize()
     h.hmm_profile_reset()
     h.hmm_profile_enable(True)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -254,7 +261,7 @@ def timed_estep(h, w, prec, steps, warmup, graph=True):
         ms = e0.elapsed_time(e1) / steps
         del g
         ok = ok and bool((st.cpu().numpy() == 0).all())
-    return {"ms": ms, "eager_ms": eager_ms, "kernels": kt, "ok": ok,
+    return {"ms": ms, "eager_ms": eager_ms, "kernels": kt, "ok": ok, "tuning": tuning,
             "stats": stats.cpu().numpy(), "loglik": ll.cpu().numpy()}
 
 
@@ -390,7 +397,7 @@ def batched_section(h, workloads, steps, warmup, plain_reps, em_iters):
     out = {"workload": WORKLOADS["batched"][0], "sequences": w.n_seq, "total_steps": w.total_steps,
            "precision": "f32", "ms_per_estep": r["ms"], "eager_ms_per_estep": r["eager_ms"],
            "transitions_per_s": w.transitions / (r["ms"] / 1e3), "all_status_ok": r["ok"],
-           "estep_roofline": estep_roofline(w, r["ms"], "f32"),
+           "estep_roofline": estep_roofline(w, r["ms"], "f32"), "tuning": r["tuning"],
            "kernels_ms": {k: round(v["ms_avg"], 4) for k, v in r["kernels"].items()}}
     if "chunk_product" in r["kernels"]:
         cp = r["kernels"]["chunk_product"]["ms_avg"]
@@ -418,7 +425,7 @@ def other_workloads(h, workloads, steps):
                       ("full_cov_n32_d32", workloads.config4a)):
         w = make()
         for prec in ("f32", "f64"):
-            r = timed_estep(h, w, prec, steps, 1, graph=False)
+            r = timed_estep(h, w, prec, steps, 1, graph=False, tune=False)
             res[f"{key}_{prec}"] = {
                 "sequences": w.n_seq, "total_steps": w.total_steps, "n_states": w.model.n_states,
                 "ms_per_estep": r["ms"], "transitions_per_s": w.transitions / (r["ms"] / 1e3),
@@ -536,6 +543,8 @@ def main():
                     help="time eager calls only (no HIP graph capture), e.g. under counters")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run one 256 MiB device copy (reference for traffic counters)")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="skip the autotuner (the untuned default variant)")
     ap.add_argument("--extras", type=int, default=1,
                     help="0: the headline E-step alone (profiling runs)")
     args = ap.parse_args()
@@ -554,7 +563,8 @@ def main():
     prec = args.prec
     log(f"workload {args.workload}: {w.n_seq} sequences, {w.total_steps} steps, N={w.model.n_states}, "
         f"{prec}")
-    r = timed_estep(h, w, prec, args.steps, args.warmup, graph=not args.eager_only)
+    r = timed_estep(h, w, prec, args.steps, args.warmup, graph=not args.eager_only,
+                    tune=not args.no_tune)
     assert r["ok"], "a sequence of the benchmark workload has a nonzero status"
     ms, kt = r["ms"], r["kernels"]
     log(f"{prec}: {ms:.3f} ms per E-step (eager {r['eager_ms']:.3f})")
@@ -583,6 +593,7 @@ def main():
         "roofline": roof,
         "roofline_other_kernels": others,
         "estep_roofline": estep_roofline(w, ms, prec),
+        "tuning": r["tuning"],
         "kernels": kt,
     }
     if args.plain_steps > 0 and prec in ("f64", "f32"):
@@ -603,7 +614,7 @@ def main():
             rp = timed_estep(h, w, p, args.steps, args.warmup)
             e = {"ms_per_estep": rp["ms"], "transitions_per_s": w.transitions / (rp["ms"] / 1e3),
                  "all_status_ok": rp["ok"], "error_vs_f64": errors_vs(rp, r, w.model.n_states),
-                 "estep_roofline": estep_roofline(w, rp["ms"], "f32"),
+                 "estep_roofline": estep_roofline(w, rp["ms"], "f32"), "tuning": rp["tuning"],
                  "kernels_ms": {k: round(v["ms_avg"], 4) for k, v in rp["kernels"].items()}}
             if p == "f32" and args.plain_steps > 0:
                 pms, note = plain_time(h, w, "f32", args.plain_steps)

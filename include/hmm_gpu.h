@@ -292,8 +292,43 @@ hmm_status hmm_mstep_full_gaussian(const hmm_model *model, const double *stats,
 
 /* Tuning: chunk length (time steps per chunk) of the batched path; 0 restores
  * the built-in choice.  Affects speed only, never the set of results beyond
- * rounding.  Returns HMM_ERR_ARG for values other than 0, 16, 32, 64. */
+ * rounding.  Returns HMM_ERR_ARG for values other than 0, 16, 32, 64.  When
+ * nonzero it overrides the chunk length of the tuned variant. */
 hmm_status hmm_set_chunk_len(int32_t steps);
+
+/* Autotuning of the E-step's schedule.  Each batched route has a few
+ * variants that compute the same quantities in a different schedule:
+ *   N <= 8 (time-parallel chunks): variant 0/1/2 = chunks of 16/32/64 steps
+ *     (FP64: 16/32);
+ *   64 < N <= 256 or multivariate N > 64: variant 0/1/2 = the nominal, half
+ *     or double number of row slices of the transition contraction;
+ *   other routes: one variant.
+ * hmm_autotune runs every variant of the route that (model, batch, prec)
+ * takes, once to warm up and three times timed with hipEvents on `stream`
+ * (it synchronises on them, so it is a set-up call, not for graph capture),
+ * and keeps the fastest (median) for the call's key: device architecture,
+ * family, N, D, precision, route and the batch's sequence count, mean and
+ * longest length rounded up to powers of two.  Later calls with the same key
+ * take that variant.  stats, loglik, seq_status, ws and ws_bytes are as for
+ * hmm_estep_stats (ws: hmm_workspace_size(HMM_OP_ESTEP), which covers every
+ * variant); they hold the last variant's results on return.  variant (host,
+ * or NULL) receives the choice; ms (host float[4], or NULL) the median
+ * milliseconds of each variant.  If the environment variable HMM_TUNE_CACHE
+ * names a file, choices are appended to it ("key variant ms..." per line)
+ * and read back at the first lookup of a later process. */
+hmm_status hmm_autotune(const hmm_model *model, const hmm_batch *batch, hmm_precision prec,
+                        double *stats, double *loglik, int32_t *seq_status, void *ws,
+                        size_t ws_bytes, void *stream, int32_t *variant, float *ms);
+
+/* Forces variant `variant` (clamped to the route's count) on every later call
+ * of this process; -1 returns to tuned choices.  The environment variable
+ * HMM_FORCE_VARIANT sets the initial value. */
+hmm_status hmm_set_variant(int32_t variant);
+
+/* The variant an E-step on (model, batch, prec) would take now, and the
+ * number of variants of its route (either pointer may be NULL). */
+hmm_status hmm_get_variant(const hmm_model *model, const hmm_batch *batch, hmm_precision prec,
+                           int32_t *variant, int32_t *n_variants);
 
 /* Kernel timing (tracing).  While enabled, every kernel the library enqueues
  * on this thread is bracketed by two hipEvents recorded on its stream; the

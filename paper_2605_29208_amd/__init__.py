@@ -34,6 +34,7 @@ EXPORTED = [
     "hmm_mstep_gaussian", "hmm_mstep_gamma", "hmm_mstep_student_t", "hmm_mstep_poisson",
     "hmm_mstep_diag_gaussian", "hmm_mstep_full_gaussian", "hmm_set_chunk_len",
     "hmm_profile_enable", "hmm_profile_count", "hmm_profile_get", "hmm_profile_reset",
+    "hmm_autotune", "hmm_set_variant", "hmm_get_variant",
     # include/hmm_serve.h
     "hmm_server_default_opts", "hmm_server_now", "hmm_server_create", "hmm_server_destroy",
     "hmm_server_add_model", "hmm_server_submit", "hmm_server_poll", "hmm_server_get_info",
@@ -109,6 +110,11 @@ def _load():
         "hmm_mstep_default_opts": ([OPP], None),
         "hmm_mstep_transitions": ([MP, P, OPP, P, P, P], ctypes.c_int),
         "hmm_set_chunk_len": ([i32], ctypes.c_int),
+        "hmm_autotune": ([MP, BP, ctypes.c_int, P, P, P, P, sz, P, ctypes.POINTER(i32),
+                          ctypes.POINTER(ctypes.c_float)], ctypes.c_int),
+        "hmm_set_variant": ([i32], ctypes.c_int),
+        "hmm_get_variant": ([MP, BP, ctypes.c_int, ctypes.POINTER(i32), ctypes.POINTER(i32)],
+                            ctypes.c_int),
         "hmm_profile_enable": ([i32], ctypes.c_int),
         "hmm_profile_count": ([], i32),
         "hmm_profile_get": ([i32, ctypes.POINTER(ctypes.c_char_p), ctypes.POINTER(ctypes.c_float)],
@@ -297,6 +303,32 @@ def em_iteration(model, batch, prec, stats, loglik, status, ws, opts=None, strea
 
 def hmm_set_chunk_len(steps: int):
     _check(_lib.hmm_set_chunk_len(int(steps)))
+
+
+def hmm_autotune(model, batch, prec, stats, loglik, seq_status, ws, stream=None):
+    """Times every variant of the call's route and keeps the fastest; returns
+    (variant, [median ms of each variant])."""
+    v = ctypes.c_int32(-1)
+    ms = (ctypes.c_float * 4)()
+    _check(_lib.hmm_autotune(ctypes.byref(model.c), ctypes.byref(batch.c), PREC[prec],
+                             _ptr(stats), _ptr(loglik), _ptr(seq_status), _ptr(ws), _nbytes(ws),
+                             _stream(stream), ctypes.byref(v), ms))
+    n = ctypes.c_int32(0)
+    _check(_lib.hmm_get_variant(ctypes.byref(model.c), ctypes.byref(batch.c), PREC[prec], None,
+                                ctypes.byref(n)))
+    return int(v.value), [float(ms[k]) for k in range(n.value)]
+
+
+def hmm_set_variant(variant: int):
+    _check(_lib.hmm_set_variant(int(variant)))
+
+
+def hmm_get_variant(model, batch, prec):
+    """(variant the next E-step takes, number of variants of its route)."""
+    v, n = ctypes.c_int32(0), ctypes.c_int32(0)
+    _check(_lib.hmm_get_variant(ctypes.byref(model.c), ctypes.byref(batch.c), PREC[prec],
+                                ctypes.byref(v), ctypes.byref(n)))
+    return int(v.value), int(n.value)
 
 
 def hmm_profile_enable(on: bool):

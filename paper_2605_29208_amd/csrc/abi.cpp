@@ -6,7 +6,9 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <string>
+#include <map>
 #include <mutex>
 #include <vector>
 
@@ -123,9 +125,137 @@ struct Plan {
     size_t etab = 0, mt = 0, balpha = 0, aexp = 0, bgam = 0, xi = 0, xisum = 0, g1 = 0, compact = 0;
     int xi_nsl = 1;
     bool mvw = false;   // multivariate family on the wave path (log-density table)
+    int route = 0;      // ROUTE_* of the batched path taken
+    int variant = 0;    // tuned variant of that route
     size_t lt = 0, fpart = 0, red2 = 0;
     size_t total = 0;
 };
+
+// ---------------------------------------------------------------- variants and the tuner
+// Each batched route has a few runtime variants (a schedule choice that does
+// not change the arithmetic's definition):
+//   chunked N <= 8: chunk length 16, 32 or 64 steps (FP64: 16 or 32);
+//   large-state:    slices of the transition contraction, nominal, half or
+//                   double (the split of its row dimension over workgroups);
+//   wave, plain:    one variant.
+// hmm_autotune times every variant of a call's route on the caller's data and
+// keeps the fastest for the call's key; HMM_FORCE_VARIANT (environment) or
+// hmm_set_variant forces one.  The key is the device architecture, family,
+// N, D, precision, route and the batch's shape in powers of two (sequence
+// count, mean and longest length).  HMM_TUNE_CACHE names a text file that
+// keeps the choices across processes ("key variant" per line).
+enum { ROUTE_PLAIN = 0, ROUTE_CHUNK = 1, ROUTE_WAVE = 2, ROUTE_BLOCK = 3 };
+
+int route_variants(int route, bool f64) {
+    if (route == ROUTE_CHUNK) return f64 ? 2 : 3;
+    if (route == ROUTE_BLOCK) return 3;
+    return 1;
+}
+
+std::mutex g_tune_mu;
+std::map<std::string, int> g_tune;
+bool g_tune_loaded = false;
+std::atomic<int> g_force_variant{-2};   // -2: environment not read yet, -1: none
+
+int force_variant() {
+    int v = g_force_variant.load();
+    if (v == -2) {
+        const char *e = getenv("HMM_FORCE_VARIANT");
+        v = (e && *e) ? atoi(e) : -1;
+        if (v < -1) v = -1;
+        int expect = -2;
+        g_force_variant.compare_exchange_strong(expect, v);
+        v = g_force_variant.load();
+    }
+    return v;
+}
+
+const char *tune_cache_path() {
+    const char *e = getenv("HMM_TUNE_CACHE");
+    return (e && *e) ? e : nullptr;
+}
+
+void tune_load_locked() {
+    if (g_tune_loaded) return;
+    g_tune_loaded = true;
+    const char *path = tune_cache_path();
+    if (!path) return;
+    FILE *f = fopen(path, "r");
+    if (!f) return;
+    char key[512];
+    int v;
+    while (fscanf(f, "%511s %d%*[^\n]", key, &v) == 2) g_tune[key] = v;
+    fclose(f);
+}
+
+int ilog2_ceil(int64_t x) {
+    int k = 0;
+    while (((int64_t)1 << k) < x && k < 62) ++k;
+    return k;
+}
+
+std::string device_arch() {
+    static std::mutex mu;
+    static std::map<int, std::string> names;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return "unknown";
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = names.find(dev);
+    if (it != names.end()) return it->second;
+    hipDeviceProp_t prop;
+    std::string n = "unknown";
+    if (hipGetDeviceProperties(&prop, dev) == hipSuccess) {
+        n = prop.gcnArchName;
+        for (char &ch : n)
+            if (ch == ' ') ch = '_';
+    }
+    names[dev] = n;
+    return n;
+}
+
+std::string tune_key(const Checked &c, hmm_precision prec, int route) {
+    char buf[400];
+    const int64_t mean = c.B > 0 ? (c.total + c.B - 1) / c.B : 0;
+    snprintf(buf, sizeof buf, "%s|fam%d|N%d|D%d|prec%d|route%d|B%d|Tmean%d|Tmax%d",
+             device_arch().c_str(), c.fam, c.N, c.D, (int)prec, route, ilog2_ceil(c.B),
+             ilog2_ceil(mean), ilog2_ceil(c.Tmax));
+    return buf;
+}
+
+// the variant a call takes: forced, else tuned for its key, else 0
+int resolve_variant(const Checked &c, hmm_precision prec, int route) {
+    const int nv = route_variants(route, is_f64(prec));
+    const int fv = force_variant();
+    if (fv >= 0) return fv < nv ? fv : nv - 1;
+    if (nv == 1) return 0;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    tune_load_locked();
+    auto it = g_tune.find(tune_key(c, prec, route));
+    if (it == g_tune.end() || it->second < 0 || it->second >= nv) return 0;
+    return it->second;
+}
+
+void tune_store(const Checked &c, hmm_precision prec, int route, int v, const float *ms, int nv) {
+    const std::string key = tune_key(c, prec, route);
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    tune_load_locked();
+    g_tune[key] = v;
+    const char *path = tune_cache_path();
+    if (!path) return;
+    FILE *f = fopen(path, "a");
+    if (!f) return;
+    fprintf(f, "%s %d", key.c_str(), v);
+    for (int k = 0; k < nv; ++k) fprintf(f, " %.4f", ms[k]);
+    fprintf(f, "\n");
+    fclose(f);
+}
+
+int chunk_len_of(int variant, bool f64) {
+    static const int L[3] = {16, 32, 64};
+    int v = variant < 0 ? 0 : (variant > 2 ? 2 : variant);
+    if (f64 && v > 1) v = 1;
+    return L[v];
+}
 
 int default_chunk_len(bool f64) {
     int v = g_chunk_len.load();
@@ -134,7 +264,8 @@ int default_chunk_len(bool f64) {
     return v;
 }
 
-hmm_status make_plan(hmm_op op, const Checked &c, hmm_precision prec, Plan *p) {
+// variant < 0: the resolved variant of the call (forced, tuned or 0)
+hmm_status make_plan(hmm_op op, const Checked &c, hmm_precision prec, Plan *p, int variant = -1) {
     if (prec < HMM_PREC_F64 || prec > HMM_PREC_PLAIN_F64)
         return fail(HMM_ERR_ARG, "unknown precision %d", (int)prec);
     p->f64 = is_f64(prec);
@@ -194,14 +325,26 @@ hmm_status make_plan(hmm_op op, const Checked &c, hmm_precision prec, Plan *p) {
                             "batched path: this build covers N <= 256 (N = %d); use a PLAIN "
                             "precision", N);
             p->block = true;
+            p->route = ROUTE_BLOCK;
+            p->variant = variant >= 0 ? variant : resolve_variant(c, prec, ROUTE_BLOCK);
             const size_t T = (size_t)c.total;
             p->etab = take(T * N * r);
             p->mt = take(T * 8);
             p->balpha = take(T * N * r);
             p->aexp = take(T * 4);
             if (op == HMM_OP_ESTEP || op == HMM_OP_FORWARD_BACKWARD) p->bgam = take(T * N * r);
-            p->xi_nsl = xi_slices(p->f64, N, c.total);
-            p->xi = take((size_t)xi_part_entries(p->f64, N, c.total) * r);
+            {
+                // variant 1 halves the nominal slice count, variant 2 doubles it
+                const int nom = xi_slices(p->f64, N, c.total);
+                const int64_t K = c.total - 1;
+                int nsl = p->variant == 1 ? (nom + 1) / 2 : (p->variant == 2 ? 2 * nom : nom);
+                const int64_t by_rows = K > 0 ? (K + 15) / 16 : 1;   // at least 16 rows a slice
+                if (nsl > by_rows) nsl = (int)by_rows;
+                if (nsl < 1) nsl = 1;
+                p->xi_nsl = nsl;
+                const int64_t nc = xi_nc(N);
+                p->xi = take((size_t)nsl * nc * nc * r);
+            }
             p->xisum = take((size_t)N * N * 8);
             p->g1 = take((size_t)N * 8);
             const int64_t S2 = 1 + N + (int64_t)N * family_k(c.fam, c.D);
@@ -215,6 +358,7 @@ hmm_status make_plan(hmm_op op, const Checked &c, hmm_precision prec, Plan *p) {
         if (N > 8 || mvw) {
             // per-sequence sweeps + one wave per chunk of WAVE_L steps
             p->wave = true;
+            p->route = ROUTE_WAVE;
             p->L = WAVE_L;
             int64_t C = 0;
             for (int64_t b = 0; b < c.B; ++b) C += (c.h_off[b + 1] - c.h_off[b] + WAVE_L - 1) / WAVE_L;
@@ -245,8 +389,11 @@ hmm_status make_plan(hmm_op op, const Checked &c, hmm_precision prec, Plan *p) {
             return HMM_OK;
         }
         p->chunked = true;
+        p->route = ROUTE_CHUNK;
         p->G = N <= 4 ? 4 : 8;
-        p->L = default_chunk_len(p->f64);
+        p->variant = variant >= 0 ? variant : resolve_variant(c, prec, ROUTE_CHUNK);
+        // hmm_set_chunk_len, when set, overrides the variant's length
+        p->L = g_chunk_len.load() != 0 ? default_chunk_len(p->f64) : chunk_len_of(p->variant, p->f64);
         int64_t C = 0, SC = 0;
         for (int64_t b = 0; b < c.B; ++b) {
             int64_t T = c.h_off[b + 1] - c.h_off[b];
@@ -507,10 +654,19 @@ hmm_status hmm_workspace_size(hmm_op op, const hmm_model *model, const hmm_batch
     Checked c;
     hmm_status st = check_batch(batch, model, &c);
     if (st != HMM_OK) return st;
+    // large enough for every variant of the route, so a tuned or forced
+    // variant always fits the caller's workspace
     Plan p;
-    st = make_plan(op, c, prec, &p);
+    st = make_plan(op, c, prec, &p, 0);
     if (st != HMM_OK) return st;
-    *bytes = p.total;
+    size_t need = p.total;
+    const int nv = route_variants(p.route, p.f64);
+    for (int v = 1; v < nv; ++v) {
+        Plan q;
+        if ((st = make_plan(op, c, prec, &q, v)) != HMM_OK) return st;
+        if (q.total > need) need = q.total;
+    }
+    *bytes = need;
     return ok();
 }
 
@@ -762,6 +918,77 @@ hmm_status hmm_profile_get(int32_t i, const char **name, float *ms) {
 hmm_status hmm_profile_reset(void) {
     g_prof.clear();
     g_pool_used = 0;
+    return ok();
+}
+
+hmm_status hmm_set_variant(int32_t variant) {
+    if (variant < -1) return fail(HMM_ERR_ARG, "variant must be -1 (tuned) or >= 0");
+    force_variant();   // read the environment first so it cannot overwrite this
+    g_force_variant.store(variant);
+    return ok();
+}
+
+hmm_status hmm_get_variant(const hmm_model *model, const hmm_batch *batch, hmm_precision prec,
+                           int32_t *variant, int32_t *n_variants) {
+    Checked c;
+    hmm_status st = check_batch(batch, model, &c);
+    if (st != HMM_OK) return st;
+    Plan p;
+    if ((st = make_plan(HMM_OP_ESTEP, c, prec, &p)) != HMM_OK) return st;
+    if (variant) *variant = p.variant;
+    if (n_variants) *n_variants = route_variants(p.route, p.f64);
+    return ok();
+}
+
+hmm_status hmm_autotune(const hmm_model *model, const hmm_batch *batch, hmm_precision prec,
+                        double *stats, double *loglik, int32_t *seq_status, void *ws,
+                        size_t ws_bytes, void *stream, int32_t *variant, float *ms) {
+    Checked c;
+    hmm_status st = check_batch(batch, model, &c);
+    if (st != HMM_OK) return st;
+    if (!stats) return fail(HMM_ERR_ARG, "stats is NULL");
+    Plan p0;
+    if ((st = make_plan(HMM_OP_ESTEP, c, prec, &p0, 0)) != HMM_OK) return st;
+    const int nv = route_variants(p0.route, p0.f64);
+    hipStream_t s = (hipStream_t)stream;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        if (e0) hipEventDestroy(e0);
+        return fail(HMM_ERR_DEVICE, "hmm_autotune: cannot create events");
+    }
+    float t[4] = {0, 0, 0, 0};
+    hmm_status r = HMM_OK;
+    for (int v = 0; v < nv && r == HMM_OK; ++v) {
+        Plan p;
+        if ((r = make_plan(HMM_OP_ESTEP, c, prec, &p, v)) != HMM_OK) break;
+        if ((r = check_ws(p, ws, ws_bytes)) != HMM_OK) break;
+        float rep[3];
+        for (int k = 0; k < 4 && r == HMM_OK; ++k) {   // one warm-up, three timed
+            hipEventRecord(e0, s);
+            r = p.f64 ? run_posterior_path<double>(model, batch, c, p, (char *)ws, loglik,
+                                                   seq_status, nullptr, stats, s)
+                      : run_posterior_path<float>(model, batch, c, p, (char *)ws, loglik,
+                                                  seq_status, nullptr, stats, s);
+            hipEventRecord(e1, s);
+            if (r == HMM_OK && hipEventSynchronize(e1) != hipSuccess)
+                r = fail(HMM_ERR_DEVICE, "hmm_autotune: E-step failed on the device");
+            if (r == HMM_OK && k > 0) hipEventElapsedTime(&rep[k - 1], e0, e1);
+        }
+        if (r != HMM_OK) break;
+        // median of the three
+        float a = rep[0], b = rep[1], d = rep[2];
+        t[v] = a > b ? (b > d ? b : (a > d ? d : a)) : (a > d ? a : (b > d ? d : b));
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (r != HMM_OK) return r;
+    int best = 0;
+    for (int v = 1; v < nv; ++v)
+        if (t[v] < t[best]) best = v;
+    tune_store(c, prec, p0.route, best, t, nv);
+    if (variant) *variant = best;
+    if (ms)
+        for (int v = 0; v < nv; ++v) ms[v] = t[v];
     return ok();
 }
 

@@ -158,7 +158,7 @@ struct BlockBuffers {
     void *alpha;         // [total * N] R  normalised alpha
     int32_t *aexp;       // [total]   binary exponent removed at each forward step
     void *gamma;         // [total * N] R  posteriors (when the caller gives none)
-    void *xi;            // [xi_part_entries] R  per-slice partial sums of the xi contraction
+    void *xi;            // [xi_nsl * xi_nc(N)^2] R  per-slice partial sums of the xi contraction
     int xi_nsl;          // slices of the contraction
     double *xisum;       // [N * N] sum_k alpha_k^T w'_{k+1}, row-major
     double *g1;          // [N]
@@ -166,9 +166,9 @@ struct BlockBuffers {
     double *compact;     // [1 + N + N*K]
     double *red;         // reduction scratch
 };
-// slices and partial-sum entries of the xi contraction
+// nominal slice count of the xi contraction
+int xi_nc(int N);   // padded state count of the contraction (128 or 256)
 int xi_slices(bool f64, int N, int64_t total);
-int64_t xi_part_entries(bool f64, int N, int64_t total);
 // out [N x N] FP64 = sum_k alpha[k]^T wp[k + 1] over k < K (K >= 1)
 template <typename R>
 void launch_xi_sum(const R *alpha, const R *wp, int N, int64_t K, R *part, int nsl, double *out,

@@ -196,11 +196,6 @@ int xi_slices(bool f64, int N, int64_t total) {
     return (int)(by_rows < target ? by_rows : target);
 }
 
-int64_t xi_part_entries(bool f64, int N, int64_t total) {
-    const int64_t nc = xi_nc(N);
-    return (int64_t)xi_slices(f64, N, total) * nc * nc;
-}
-
 template <typename R, int NC>
 static void launch_xi_t(const R *alpha, const R *wp, int N, int64_t K, R *part, int nsl,
                         double *out, hipStream_t s) {

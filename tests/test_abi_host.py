@@ -153,3 +153,43 @@ def test_server_host_validation(h):
     assert lib.hmm_server_submit(None, 0, 0, None, 0, 1, None, ctypes.byref(rid)) == h.HMM_ERR_ARG
     t0 = h.hmm_server_now()
     assert h.hmm_server_now() >= t0
+
+
+def get_variant(h, m, b, prec):
+    v, n = ctypes.c_int32(-9), ctypes.c_int32(-9)
+    st = h._lib.hmm_get_variant(ctypes.byref(m), ctypes.byref(b), h.PREC[prec], ctypes.byref(v),
+                                ctypes.byref(n))
+    assert st == h.HMM_OK, h.last_error()
+    return v.value, n.value
+
+
+def test_variant_counts_and_forcing(h):
+    """Each route reports its number of schedule variants; a forced variant is
+    clamped to the route's count and -1 returns to the untuned default; the
+    workspace size covers every variant of the route."""
+    chunk = (fake_model(h, 8, "gamma"), fake_batch(h, [100, 64, 1])[0])
+    wave = (fake_model(h, 32, "gaussian"), fake_batch(h, [100, 64, 1])[0])
+    block = (fake_model(h, 150, "gaussian"), fake_batch(h, [3000, 64, 1])[0])
+    try:
+        assert get_variant(h, *chunk, "f32") == (0, 3)
+        assert get_variant(h, *chunk, "f64") == (0, 2)
+        assert get_variant(h, *wave, "f32") == (0, 1)
+        assert get_variant(h, *block, "f64") == (0, 3)
+        sizes = []
+        for v in (0, 1, 2):
+            assert h._lib.hmm_set_variant(v) == h.HMM_OK
+            assert get_variant(h, *block, "f32") == (v, 3)
+            assert get_variant(h, *chunk, "f64")[0] == min(v, 1)
+            assert get_variant(h, *wave, "f32")[0] == 0
+        assert h._lib.hmm_set_variant(-1) == h.HMM_OK
+        assert get_variant(h, *block, "f32") == (0, 3)
+        assert h._lib.hmm_set_variant(-2) == h.HMM_ERR_ARG
+        st, full = ws_size(h, "estep", *block, "f32")
+        assert st == h.HMM_OK
+        for v in (0, 1, 2):
+            h._lib.hmm_set_variant(v)
+            # the size does not depend on the forced variant: it covers them all
+            assert ws_size(h, "estep", *block, "f32") == (h.HMM_OK, full)
+            sizes.append(full)
+    finally:
+        h._lib.hmm_set_variant(-1)
