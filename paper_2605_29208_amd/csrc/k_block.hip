@@ -5,9 +5,8 @@
 //      with m_t = max_j log b_j(y_t), and m_t plus the state-independent part
 //      in FP64;
 //   2. forward sweep (section 3.1 recursion, normalised): alpha^_t = (alpha^_{t-1} A) o e_t
-//      scaled by 2^-x_t (x_t = binary exponent of its largest entry); every
-//      alpha^_t row and x_t are kept, with log P(y) = sum_t m_t + ln2 sum_t x_t
-//      + log sum_j alpha^_{T-1}(j);
+//      scaled by 2^-x_t; every alpha^_t row and x_t are kept, with
+//      log P(y) = sum_t m_t + ln2 sum_t x_t + log sum_j alpha^_{T-1}(j);
 //   3. backward sweep: beta^_{t-1} = A (e_t o beta^_t) rescaled the same way,
 //      and at each step the posterior gamma_t = alpha^_t o beta^_t / Z_t
 //      (Z_t = sum_j alpha^_t(j) beta^_t(j)) and
@@ -16,14 +15,15 @@
 //      xi_t, sum_ij alpha^_{t-1}(i) a_ij e_t(j) beta^_t(j), equals 2^x_t Z_t);
 //      w'_t overwrites e_t in place;
 //   4. sum_t xi_t = (sum_t alpha^_{t-1}^T w'_t) o A: a dense contraction over
-//      all steps of all sequences, done as one library GEMM (rows of the first
-//      step of a sequence have w' = 0, so pairing row r of alpha^ with row
-//      r + 1 of w' across the whole batch is exact);
+//      all steps of all sequences on the matrix cores (k_xi.hip; rows of the
+//      first step of a sequence have w' = 0, so pairing row r of alpha^ with
+//      row r + 1 of w' across the whole batch is exact);
 //   5. gamma-weighted family sums (all steps in parallel, one thread per
 //      (state, dimension)), gamma_1, and the assembly of the statistics.
 //
-// Sweeps: 256 threads, thread (c, p) owns column c (state) and the p-th of
-// 256 / NC row blocks (NC = N rounded up to 64); partial products meet in LDS.
+// The vector-ALU sweeps of steps 2-3 are in k_sweep.hip; this file holds
+// the emission and family-sum kernels, the scaled bf16/fp16 matrix-core
+// sweeps, and the host side of the path.
 
 #include "dev_common.hpp"
 #include "hmm_internal.hpp"
@@ -217,315 +217,6 @@ __global__ __launch_bounds__(64) void k_blk_emit_full(int N, int D_, ObsRef o, i
 
 // largest entry of a non-negative vector spread over the block (every part
 // holds the same values; the waves of part 0 publish their maxima)
-template <typename R>
-__device__ __forceinline__ R blk_max(R v, R *wred, int NC) {
-    if (threadIdx.x < (unsigned)NC) {   // whole waves (NC is a multiple of 64)
-        const R w = wave_max_r(v);
-        if ((threadIdx.x & 63) == 0) wred[threadIdx.x / 64] = w;
-    }
-    __syncthreads();
-    R mx = wred[0];
-    for (int k = 1; k < NC / 64; ++k) mx = fmax(mx, wred[k]);
-    return mx;
-}
-
-// Thread (col, p) of a sweep: its share sum_{i in row block p} x_i M[i][col]
-// of a vector-matrix product (M = A for the forward, A^T for the backward,
-// both row-major N x N).  AREG keeps the thread's RP entries of M in
-// registers for the whole sequence (single precision); otherwise they are
-// read from global memory (L2) at every step.
-template <typename R, int RPM, bool AREG>
-struct PartDot {
-    R a[AREG ? RPM : 1];
-    int i0, RP, N, col;
-    bool live;
-    __device__ __forceinline__ void init(const R *M, int n, int c, int p, int rp, bool lv) {
-        N = n;
-        col = c;
-        RP = rp;
-        i0 = p * rp;
-        live = lv;
-        if constexpr (AREG) {
-            // unconditional loads at clamped indices (straight-line code),
-            // entries outside the matrix set to zero
-            const int cc = min(col, N - 1);
-#pragma unroll
-            for (int k = 0; k < RPM; ++k) {
-                const int i = i0 + k;
-                const R v = M[min(i, N - 1) * N + cc];
-                a[k] = (live && k < RP && i < N) ? v : (R)0;
-            }
-        }
-    }
-    __device__ __forceinline__ R dot(const R *x, const R *M) const {
-        R acc0 = (R)0, acc1 = (R)0;
-        if constexpr (AREG) {
-            // RP == RPM (a multiple of 4) and i0 a multiple of RP: the shared
-            // vector is read four entries per broadcast load
-            const float4 *xv = reinterpret_cast<const float4 *>(x + i0);
-#pragma unroll
-            for (int k = 0; k < RPM; k += 4) {
-                // at most 16 broadcast values in flight: the thread's RPM
-                // matrix entries already hold most of its registers
-                if (k % 16 == 0) __builtin_amdgcn_sched_barrier(0);
-                const float4 q = xv[k / 4];
-                acc0 = fma(q.x, a[k], acc0);
-                acc1 = fma(q.y, a[k + 1], acc1);
-                acc0 = fma(q.z, a[k + 2], acc0);
-                acc1 = fma(q.w, a[k + 3], acc1);
-            }
-        } else {
-            for (int k = 0; k + 1 < RP; k += 2) {
-                const int i = i0 + k;
-                if (i + 1 < N) {
-                    acc0 = fma(x[i], live ? M[i * N + col] : (R)0, acc0);
-                    acc1 = fma(x[i + 1], live ? M[(i + 1) * N + col] : (R)0, acc1);
-                } else if (i < N) {
-                    acc0 = fma(x[i], live ? M[i * N + col] : (R)0, acc0);
-                }
-            }
-        }
-        return acc0 + acc1;
-    }
-};
-
-// ---------------------------------------------------------------- 2. forward
-// NT threads: NC = N rounded up to 64 columns, P = NT / NC row blocks of
-// RP = NC / P rows (threads beyond P * NC only take part in the barriers).
-template <typename R, int NT, int RPM, bool AREG, int NCT>
-__global__ __launch_bounds__(NT) void k_blk_fwd(StagedModel<R> m, const int64_t *__restrict__ offsets,
-                                                const R *__restrict__ etab,
-                                                const double *__restrict__ mt, R *__restrict__ alpha,
-                                                int32_t *__restrict__ aexp,
-                                                double *__restrict__ loglik,
-                                                int32_t *__restrict__ status) {
-    __shared__ __align__(16) R x[NT + 8];
-    __shared__ R psum[8][256];
-    __shared__ R wred[4];
-    __shared__ R wsum[4];
-    __shared__ R etile[2][PF][256];
-    __shared__ double mtile[2][PF];
-    // NCT > 0: the column count is a compile-time constant
-    const int N = m.N, NC = NCT > 0 ? NCT : blk_nc(N), P = NT / NC, RP = NC / P;
-    const int tid = threadIdx.x, c = tid % NC, p = tid / NC;
-    const bool live = c < N;
-    PartDot<R, RPM, AREG> pd;
-    pd.init(m.A, N, c, p, RP, live);
-    const int64_t b = blockIdx.x;
-    const int64_t off = offsets[b];
-    const int T = (int)(offsets[b + 1] - off);
-    const int nrm = *m.nrm;   // steps between rescalings: 1, 2 or 4
-    // t = 0
-    R v = live ? m.pi[c] * etab[off * N + c] : (R)0;
-    int ex = fexp(blk_max(v, wred, NC));
-    v = fldexp(v, -ex);
-    int64_t E = ex;
-    double logS = mt[off];
-    if (p == 0) x[c] = v;
-    if (p == 0 && live) alpha[off * N + c] = v;
-    if (tid == 0) aexp[off] = ex;
-    __syncthreads();
-    // Inputs of the next window of PF steps (emission rows, log shifts) are
-    // loaded into a few registers while the current window runs from an LDS
-    // tile, then parked in the other tile (indices clamped to the sequence).
-    constexpr int EPTM = (PF * 256 + NT - 1) / NT;   // tile entries per thread, at most
-    const int EPT = (PF * NC + NT - 1) / NT;         // tile entries per thread
-    auto fetch = [&](int w0, R *ev, double *mv) {
-        for (int k = 0; k < EPTM; ++k) {
-            const int idx = tid + k * NT;
-            if (k < EPT && idx < PF * NC) {
-                const int sl = idx / NC, col = idx % NC;
-                const int64_t rr = off + min(w0 + sl, T - 1);
-                ev[k] = col < N ? etab[rr * N + col] : (R)0;
-            }
-        }
-        if (tid < PF) *mv = mt[off + min(w0 + tid, T - 1)];
-    };
-    auto park = [&](int buf, const R *ev, double mv) {
-        for (int k = 0; k < EPTM; ++k) {
-            const int idx = tid + k * NT;
-            if (k < EPT && idx < PF * NC) etile[buf][idx / NC][idx % NC] = ev[k];
-        }
-        if (tid < PF) mtile[buf][tid] = mv;
-    };
-    R ev[EPTM];
-#pragma unroll
-    for (int k = 0; k < EPTM; ++k) ev[k] = (R)0;
-    double mv = 0.0;
-    fetch(1, ev, &mv);
-    park(0, ev, mv);
-    __syncthreads();
-    int buf = 0;
-    for (int w0 = 1; w0 < T; w0 += PF) {
-        fetch(w0 + PF, ev, &mv);
-        for (int sl = 0; sl < PF; ++sl) {
-            const int t = w0 + sl;
-            if (t >= T) break;
-            const int64_t row = off + t;
-            const R e = etile[buf][sl][c];
-            const R acc = pd.dot(x, m.A);
-            if (p < 8) psum[p][c] = acc;
-            __syncthreads();
-            // only part 0 forms the new vector; the rescaling (every nrm steps
-            // and at the last step) is uniform, so its block maximum is skipped
-            // on the other steps
-            if (p == 0) {
-                R s = psum[0][c];
-                for (int q = 1; q < P; ++q) s += psum[q][c];
-                v = s * e;
-            }
-            ex = 0;
-            if ((t & (nrm - 1)) == nrm - 1 || t == T - 1) {
-                ex = fexp(blk_max(v, wred, NC));
-                v = fldexp(v, -ex);
-            }
-            if (p == 0) x[c] = v;
-            if (p == 0 && live) alpha[row * N + c] = v;
-            if (tid == 0) aexp[row] = ex;
-            E += ex;
-            logS += mtile[buf][sl];
-            __syncthreads();
-        }
-        buf ^= 1;
-        park(buf, ev, mv);
-        __syncthreads();
-    }
-    // log P(y): sum of the last normalised alpha (part 0 waves)
-    R tot = wave_sum_r((p == 0) ? v : (R)0);
-    if (tid < NC && (tid & 63) == 0) wsum[tid / 64] = tot;
-    __syncthreads();
-    if (tid == 0) {
-        R z = wsum[0];
-        for (int q = 1; q < NC / 64; ++q) z += wsum[q];
-        double ll;
-        int st;
-        if (*m.perr) {
-            ll = __builtin_nan("");
-            st = 4;
-        } else if (isnan(logS)) {
-            ll = __builtin_nan("");
-            st = 2;
-        } else if (!(z > (R)0) || isinf(logS)) {
-            ll = -__builtin_inf();
-            st = 1;
-        } else {
-            ll = logS + (double)E * 0.69314718055994530942 + log((double)z);
-            st = 0;
-        }
-        loglik[b] = ll;
-        status[b] = st;
-    }
-}
-
-// ---------------------------------------------------------------- 3. backward
-template <typename R, int NT, int RPM, bool AREG, int NCT>
-__global__ __launch_bounds__(NT) void k_blk_bwd(StagedModel<R> m, const int64_t *__restrict__ offsets,
-                                                R *__restrict__ etab, const R *__restrict__ alpha,
-                                                const int32_t *__restrict__ aexp,
-                                                const int32_t *__restrict__ status,
-                                                R *__restrict__ gamma) {
-    __shared__ __align__(16) R xw[NT + 8];
-    __shared__ R psum[8][256];
-    __shared__ R wred[4];
-    __shared__ R wsum[4];
-    __shared__ R atile[2][PF][256];
-    __shared__ R etile[2][PF][256];
-    __shared__ int xtile[2][PF];
-    const int N = m.N, NC = NCT > 0 ? NCT : blk_nc(N), P = NT / NC, RP = NC / P;
-    const int tid = threadIdx.x, r = tid % NC, p = tid / NC;
-    const bool live = r < N;
-    PartDot<R, RPM, AREG> pd;
-    pd.init(m.AT, N, r, p, RP, live);
-    const int64_t b = blockIdx.x;
-    const int64_t off = offsets[b];
-    const int T = (int)(offsets[b + 1] - off);
-    const bool use = status[b] == 0;
-    const int nrm = *m.nrm;
-    R bt = live ? (R)1 : (R)0;   // beta^_t of state r (identical in every part)
-    // alpha and emission rows and exponents of the next window of PF steps
-    // are loaded into registers while the current window runs from LDS
-    // tiles (indices clamped to the sequence)
-    constexpr int EPTM = (PF * 256 + NT - 1) / NT;
-    const int EPT = (PF * NC + NT - 1) / NT;
-    auto fetch = [&](int w0, R *av, R *ev, int *xv) {
-        for (int k = 0; k < EPTM; ++k) {
-            const int idx = tid + k * NT;
-            if (k < EPT && idx < PF * NC) {
-                const int sl = idx / NC, col = idx % NC;
-                const int64_t rr = off + max(w0 - sl, 0);
-                av[k] = col < N ? alpha[rr * N + col] : (R)0;
-                ev[k] = col < N ? etab[rr * N + col] : (R)0;
-            }
-        }
-        if (tid < PF) *xv = aexp[off + max(w0 - tid, 0)];
-    };
-    auto park = [&](int bf, const R *av, const R *ev, int xv) {
-        for (int k = 0; k < EPTM; ++k) {
-            const int idx = tid + k * NT;
-            if (k < EPT && idx < PF * NC) {
-                atile[bf][idx / NC][idx % NC] = av[k];
-                etile[bf][idx / NC][idx % NC] = ev[k];
-            }
-        }
-        if (tid < PF) xtile[bf][tid] = xv;
-    };
-    R av[EPTM], ev[EPTM];
-#pragma unroll
-    for (int k = 0; k < EPTM; ++k) av[k] = ev[k] = (R)0;
-    int xv = 0;
-    fetch(T - 1, av, ev, &xv);
-    park(0, av, ev, xv);
-    __syncthreads();
-    int buf = 0;
-    for (int w0 = T - 1; w0 >= 0; w0 -= PF) {
-        fetch(w0 - PF, av, ev, &xv);
-        bool done = false;
-        for (int sl = 0; sl < PF; ++sl) {
-            const int t = w0 - sl;
-            if (t < 0) break;
-            const int64_t row = off + t;
-            const R a = atile[buf][sl][r];
-            const R e = etile[buf][sl][r];
-            const int xt = xtile[buf][sl];
-            const R h = a * bt;
-            const R w = e * bt;
-            if (p == 0) xw[r] = w;
-            const R hs = wave_sum_r((p == 0) ? h : (R)0);
-            if (tid < NC && (tid & 63) == 0) wsum[tid / 64] = hs;
-            __syncthreads();
-            R Z = wsum[0];
-            for (int q = 1; q < NC / 64; ++q) Z += wsum[q];
-            const R rz = (R)1 / Z;
-            if (p == 0 && live) {
-                gamma[row * N + r] = use ? h * rz : (R)0;
-                etab[row * N + r] = (use && t > 0) ? fldexp(w * rz, -xt) : (R)0;
-            }
-            if (t == 0) {
-                done = true;
-                break;
-            }
-            const R acc = pd.dot(xw, m.AT);
-            if (p < 8) psum[p][r] = acc;
-            __syncthreads();
-            R s = psum[0][r];
-            for (int q = 1; q < P; ++q) s += psum[q][r];
-            // rescaled every nrm steps (beta never grows; the staging bound on
-            // its shrinking holds as for the forward)
-            if (((T - 1 - t) & (nrm - 1)) == nrm - 1) {
-                const int ex = fexp(blk_max(s, wred, NC));
-                bt = fldexp(s, -ex);
-            } else {
-                bt = s;
-            }
-        }
-        if (done) break;
-        buf ^= 1;
-        __syncthreads();   // every lane is done with the tiles of this window
-        park(buf, av, ev, xv);
-        __syncthreads();
-    }
-}
-
 // ---------------------------------------------------------------- scaled low precision
 // Sweeps with the vector-matrix product on the matrix cores: the normalised
 // FP32 vector is rounded to bf16 or fp16 (T16) and multiplied by A (forward)
@@ -1220,22 +911,6 @@ int blk_gstats_tiles(int64_t total, int family) {
     return (int)((total + ts - 1) / ts);
 }
 
-// single precision keeps A in registers (512 threads, up to 128 entries each);
-// double precision reads it from L2 at every step
-template <typename R, int NT, int RPM, bool AREG, int NCT>
-static void launch_blk_sweep_t(bool fwd, const StagedModel<R> &m, const ObsDesc &o, R *etab,
-                               const BlockBuffers &bb, R *alpha, double *loglik, int32_t *status,
-                               R *gamma, hipStream_t s) {
-    if (fwd)
-        hipLaunchKernelGGL((k_blk_fwd<R, NT, RPM, AREG, NCT>), dim3((unsigned)o.nseq), dim3(NT), 0, s, m,
-                           o.offsets, (const R *)etab, (const double *)bb.mt, alpha, bb.aexp, loglik,
-                           status);
-    else
-        hipLaunchKernelGGL((k_blk_bwd<R, NT, RPM, AREG, NCT>), dim3((unsigned)o.nseq), dim3(NT), 0, s, m,
-                           o.offsets, etab, (const R *)alpha, (const int32_t *)bb.aexp,
-                           (const int32_t *)status, gamma);
-}
-
 template <typename T16, int NCT>
 static void launch_blk_mfma_t(bool fwd, const StagedModel<float> &m, const ObsDesc &o, float *etab,
                               const BlockBuffers &bb, float *alpha, double *loglik,
@@ -1262,6 +937,8 @@ static void launch_blk_mfma(bool fwd, const StagedModel<float> &m, const ObsDesc
     }
 }
 
+// The vector-ALU sweeps (FP32/FP64, 64 < N <= 256) are in k_sweep.hip; the
+// scaled low-precision options run here on the matrix cores (any N <= 256).
 template <typename R>
 static void launch_blk_sweep(bool fwd, const StagedModel<R> &m, const ObsDesc &o, R *etab,
                              const BlockBuffers &bb, R *alpha, double *loglik, int32_t *status,
@@ -1271,26 +948,10 @@ static void launch_blk_sweep(bool fwd, const StagedModel<R> &m, const ObsDesc &o
             return launch_blk_mfma<__bf16>(fwd, m, o, etab, bb, alpha, loglik, status, gamma, s);
         if (bb.mfma == 2)
             return launch_blk_mfma<_Float16>(fwd, m, o, etab, bb, alpha, loglik, status, gamma, s);
-        if (m.N > 64)
-            return launch_sw_sweep<R>(fwd, m, o.offsets, o.nseq, etab, bb.mt, alpha, bb.aexp,
-                                      loglik, status, gamma, s);
-        // rows per thread RP = NC / (512 / NC): 8, 32, 96, 128
-        switch (blk_nc(m.N)) {
-        case 64:
-            return launch_blk_sweep_t<R, 512, 8, true, 64>(fwd, m, o, etab, bb, alpha, loglik, status, gamma, s);
-        case 128:
-            return launch_blk_sweep_t<R, 1024, 16, true, 128>(fwd, m, o, etab, bb, alpha, loglik, status, gamma, s);
-        case 192:
-            return launch_blk_sweep_t<R, 768, 48, true, 192>(fwd, m, o, etab, bb, alpha, loglik, status, gamma, s);
-        default:
-            return launch_blk_sweep_t<R, 1024, 64, true, 256>(fwd, m, o, etab, bb, alpha, loglik, status, gamma, s);
-        }
-    } else {
-        if (m.N > 64)
-            return launch_sw_sweep<R>(fwd, m, o.offsets, o.nseq, etab, bb.mt, alpha, bb.aexp,
-                                      loglik, status, gamma, s);
-        launch_blk_sweep_t<R, 256, 1, false, 0>(fwd, m, o, etab, bb, alpha, loglik, status, gamma, s);
     }
+    // the planner sends N <= 64 to the wave path unless a scaled option is asked for
+    launch_sw_sweep<R>(fwd, m, o.offsets, o.nseq, etab, bb.mt, alpha, bb.aexp, loglik, status,
+                       gamma, s);
 }
 
 // Full-covariance family sums in single precision for D <= 32 on the matrix
