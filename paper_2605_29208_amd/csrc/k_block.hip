@@ -81,10 +81,16 @@ __global__ __launch_bounds__(BT) void k_blk_emit(StagedModel<R> m, ObsRef o, int
 // forms the per-step maximum and writes the factors (coalesced rows).
 // RAW: the rows receive log b itself (NaN for a non-finite observation) and
 // mt is not written -- the log-emission table of the wave route.
-constexpr int ES = 32;
+// Blocks take tiles in turn (grid-stride), so each thread loads its state's
+// constants once for many tiles; double precision uses half-size tiles so
+// that four blocks fit a compute unit's LDS.
+template <typename R>
+constexpr int emit_es() { return sizeof(R) == 8 ? 16 : 32; }
+constexpr int EMIT_BLOCKS = 2048;
 template <typename R, int DM, bool RAW>
 __global__ __launch_bounds__(BT) void k_blk_emit_diag(StagedModel<R> m, ObsRef o, int64_t total,
                                                       R *__restrict__ etab, double *__restrict__ mt) {
+    constexpr int ES = emit_es<R>();
     __shared__ R ysh[ES][DM];
     __shared__ R lsh[ES][BT + 1];
     __shared__ int bsh[ES];
@@ -1101,8 +1107,8 @@ static void launch_blk_emission(const StagedModel<R> &m, const ObsRef &obs, int6
     const int N = m.N;
     ProfScope ps("block_emit", s);
     if (m.family == HMM_DIAG_GAUSSIAN && m.D <= 64) {
-        const int64_t nb = (total + ES - 1) / ES;
-        const dim3 g((unsigned)(nb < 16384 ? nb : 16384));
+        const int64_t nb = (total + emit_es<R>() - 1) / emit_es<R>();
+        const dim3 g((unsigned)(nb < EMIT_BLOCKS ? nb : EMIT_BLOCKS));
         if (m.D <= 16)
             hipLaunchKernelGGL((k_blk_emit_diag<R, 16, RAW>), g, dim3(BT), 0, s, m, obs, total, etab, mt);
         else
