@@ -563,8 +563,24 @@ __global__ __launch_bounds__(BT) void k_blk_gamma1(int N, int64_t nseq, const in
     const int c = blockIdx.x * BT + threadIdx.x;
     if (c >= N) return;
     double s = 0.0;
-    for (int64_t b = 0; b < nseq; ++b)
-        if (status[b] == 0) s += (double)gamma[offsets[b] * N + c];
+    // sixteen sequences' loads in flight at clamped indices, added in order
+    constexpr int U = 16;
+    for (int64_t b0 = 0; b0 < nseq; b0 += U) {
+        int64_t off[U];
+        int32_t st[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t b = b0 + u < nseq ? b0 + u : nseq - 1;
+            off[u] = offsets[b];
+            st[u] = status[b];
+        }
+        R g[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) g[u] = gamma[off[u] * N + c];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (b0 + u < nseq && st[u] == 0) s += (double)g[u];
+    }
     g1[c] = s;
 }
 
@@ -715,9 +731,15 @@ template <typename R, int DM>
 __global__ __launch_bounds__(BT) void k_blk_gstats_diag(StagedModel<R> m, ObsRef o, int64_t total,
                                                         const R *__restrict__ gamma,
                                                         double *__restrict__ partial, int64_t S2) {
+    // Double precision sums the raw moments sum g y and sum g y^2 (two FMA per
+    // state, step and dimension, y^2 staged beside y) and shifts them by mu
+    // at the end; the cancellation costs about log10(mu^2 / var) digits,
+    // which FP64 affords.  Single precision keeps the centred form.
+    constexpr bool RAWM = sizeof(R) == 8;
     constexpr int SB = 64;
     static_assert((SB * DM) % BT == 0, "whole staging rounds");
     __shared__ __align__(16) R ysh[SB][DM];
+    __shared__ __align__(16) R y2sh[RAWM ? SB : 1][DM];
     const int N = m.N, D = m.D, c = threadIdx.x;
     const bool live = c < N;
     R mu[DM];
@@ -746,7 +768,9 @@ __global__ __launch_bounds__(BT) void k_blk_gstats_diag(StagedModel<R> m, ObsRef
 #pragma unroll
                 for (int u = 0; u < SB * DM / BT; ++u) {
                     const int k = c + u * BT, st = k / DM, d = k % DM;
-                    ysh[st][d] = (st < ns && d < D) ? yv[u] : (R)0;
+                    const R y = (st < ns && d < D) ? yv[u] : (R)0;
+                    ysh[st][d] = y;
+                    if constexpr (RAWM) y2sh[st][d] = y * y;
                 }
             }
             __syncthreads();
@@ -768,10 +792,15 @@ __global__ __launch_bounds__(BT) void k_blk_gstats_diag(StagedModel<R> m, ObsRef
                     g += gm;
 #pragma unroll
                     for (int d = 0; d < DM; ++d) {
-                        const R dv = ysh[s0 + u][d] - mu[d];
-                        const R gd = gm * dv;
-                        a1[d] += gd;
-                        a2[d] = fma(gd, dv, a2[d]);
+                        if constexpr (RAWM) {
+                            a1[d] = fma(gm, ysh[s0 + u][d], a1[d]);
+                            a2[d] = fma(gm, y2sh[s0 + u][d], a2[d]);
+                        } else {
+                            const R dv = ysh[s0 + u][d] - mu[d];
+                            const R gd = gm * dv;
+                            a1[d] += gd;
+                            a2[d] = fma(gd, dv, a2[d]);
+                        }
                     }
                 }
             }
@@ -790,8 +819,15 @@ __global__ __launch_bounds__(BT) void k_blk_gstats_diag(StagedModel<R> m, ObsRef
 #pragma unroll
     for (int d = 0; d < DM; ++d)
         if (d < D) {
-            f[d] = s1[d];
-            f[D + d] = s2[d];
+            if constexpr (RAWM) {
+                // sum g (y - mu) and sum g (y - mu)^2 from the raw moments
+                const double md = (double)mu[d];
+                f[d] = s1[d] - md * G;
+                f[D + d] = (s2[d] - 2.0 * md * s1[d]) + md * md * G;
+            } else {
+                f[d] = s1[d];
+                f[D + d] = s2[d];
+            }
         }
 }
 
