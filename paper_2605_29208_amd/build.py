@@ -21,7 +21,7 @@ LIB = os.path.join(HERE, "libhmmgpu.so")
 ARCH = "gfx950"
 
 SOURCES = ["abi.cpp", "k_stage.hip", "k_plain.hip", "k_chunk.hip", "k_viterbi.hip", "k_mstep.hip",
-           "k_wave.hip", "k_block.hip", "k_sweep.hip", "k_xi.hip", "serve.cpp"]
+           "k_wave.hip", "k_block.hip", "k_sweep.hip", "k_xi.hip", "k_grp.hip", "serve.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

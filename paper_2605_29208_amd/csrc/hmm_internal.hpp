@@ -178,6 +178,11 @@ template <typename R>
 void launch_sw_sweep(bool fwd, const StagedModel<R> &m, const int64_t *offsets, int64_t nseq,
                      R *etab, const double *mt, R *alpha, int32_t *aexp, double *loglik,
                      int32_t *status, R *gamma, hipStream_t s);
+// scaled bf16 (bf16 true) or fp16 sweeps of the large-state path, sixteen
+// sequences per workgroup on the matrix cores, N <= 256
+void launch_grp_sweep(bool fwd, bool bf16, const StagedModel<float> &m, const int64_t *offsets,
+                      int64_t nseq, float *etab, const double *mt, float *alpha, int32_t *aexp,
+                      double *loglik, int32_t *status, float *gamma, hipStream_t s);
 int blk_gstats_tiles(int64_t total, int family);
 template <typename R>
 hmm_status run_block(const StagedModel<R> &m, const ObsDesc &o, const BlockBuffers &bb,

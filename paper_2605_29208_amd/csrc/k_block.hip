@@ -21,9 +21,9 @@
 //   5. gamma-weighted family sums (all steps in parallel, one thread per
 //      (state, dimension)), gamma_1, and the assembly of the statistics.
 //
-// The vector-ALU sweeps of steps 2-3 are in k_sweep.hip; this file holds
-// the emission and family-sum kernels, the scaled bf16/fp16 matrix-core
-// sweeps, and the host side of the path.
+// The vector-ALU sweeps of steps 2-3 are in k_sweep.hip and the scaled
+// bf16/fp16 matrix-core sweeps in k_grp.hip; this file holds the emission and
+// family-sum kernels and the host side of the path.
 
 #include "dev_common.hpp"
 #include "hmm_internal.hpp"
@@ -31,7 +31,6 @@
 namespace hmmk {
 
 constexpr int BT = 256;   // threads of the sweep and emission blocks
-constexpr int PF = 8;     // steps of sweep inputs loaded ahead
 
 __device__ __forceinline__ double wave_max_dbl(double v) {
     return wave_all(v, [](double x, double y) { return fmax(x, y); });
@@ -219,339 +218,6 @@ __global__ __launch_bounds__(64) void k_blk_emit_full(int N, int D_, ObsRef o, i
         out[j] = (l == neg_inf<R>()) ? (R)0 : fexp_e(l - mx);
     }
     mt[row] = bad ? __builtin_nan("") : (double)mx;
-}
-
-// largest entry of a non-negative vector spread over the block (every part
-// holds the same values; the waves of part 0 publish their maxima)
-// ---------------------------------------------------------------- scaled low precision
-// Sweeps with the vector-matrix product on the matrix cores: the normalised
-// FP32 vector is rounded to bf16 or fp16 (T16) and multiplied by A (forward)
-// or A^T (backward) held in registers as T16 MFMA operands, with FP32
-// accumulation (v_mfma_f32_16x16x32_{bf16,f16}); the result is rescaled by a
-// power of two every step as in the FP32 path, and everything else (alpha,
-// gamma, w', log offsets) stays FP32 / FP64.  The single vector occupies row
-// 0 of the 16-row operand.  Operand layout of the 16x16x32 instruction (lane
-// l): A row l%16, k = 8(l/16) + q; B column l%16, k = 8(l/16) + q; result
-// column l%16, rows 4(l/16) + i.  Wave w owns the column tiles w, w + 4, ...
-// (TPW = NC / 64 tiles of 16 columns); the first 16 lanes hold row 0 of each.
-typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
-typedef _Float16 half8_t __attribute__((ext_vector_type(8)));
-typedef float floatx4_t __attribute__((ext_vector_type(4)));
-
-template <typename T16> struct MfmaT;
-template <> struct MfmaT<__bf16> {
-    using V = bf16x8_t;
-    static __device__ __forceinline__ floatx4_t mma(V a, V b, floatx4_t c) {
-        return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
-    }
-};
-template <> struct MfmaT<_Float16> {
-    using V = half8_t;
-    static __device__ __forceinline__ floatx4_t mma(V a, V b, floatx4_t c) {
-        return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
-    }
-};
-
-// B operands of wave w: TPW tiles x KCH chunks of M (row-major N x N):
-// entry (k, n) = M[k][n] (TRANS = false) or M[n][k] (TRANS = true)
-template <typename T16, int TPW, int KCH, bool TRANS>
-__device__ __forceinline__ void mfma_load_b(const float *M, int N, int w, int l,
-                                            typename MfmaT<T16>::V (&bv)[TPW][KCH]) {
-#pragma unroll
-    for (int tw = 0; tw < TPW; ++tw) {
-        const int n = 16 * (w + 4 * tw) + (l & 15);
-#pragma unroll
-        for (int kc = 0; kc < KCH; ++kc) {
-#pragma unroll
-            for (int q = 0; q < 8; ++q) {
-                const int k = 32 * kc + 8 * (l >> 4) + q;
-                const bool in = n < N && k < N;
-                const int kk = min(k, N - 1), nn = min(n, N - 1);
-                const float v = TRANS ? M[nn * N + kk] : M[kk * N + nn];
-                bv[tw][kc][q] = (T16)(in ? v : 0.0f);
-            }
-        }
-    }
-}
-
-// y (row 0 of the product) for the TPW tiles of this wave: lanes 0..15
-template <typename T16, int TPW, int KCH>
-__device__ __forceinline__ void mfma_row(const float *xs, int l,
-                                         const typename MfmaT<T16>::V (&bv)[TPW][KCH],
-                                         float (&y)[TPW]) {
-    using V = typename MfmaT<T16>::V;
-    V av[KCH];
-#pragma unroll
-    for (int kc = 0; kc < KCH; ++kc) {
-        const float4 *p4 = reinterpret_cast<const float4 *>(xs + 32 * kc + 8 * (l >> 4));
-        const float4 u0 = p4[0], u1 = p4[1];
-        const bool r0 = (l & 15) == 0;
-        av[kc][0] = (T16)(r0 ? u0.x : 0.0f);
-        av[kc][1] = (T16)(r0 ? u0.y : 0.0f);
-        av[kc][2] = (T16)(r0 ? u0.z : 0.0f);
-        av[kc][3] = (T16)(r0 ? u0.w : 0.0f);
-        av[kc][4] = (T16)(r0 ? u1.x : 0.0f);
-        av[kc][5] = (T16)(r0 ? u1.y : 0.0f);
-        av[kc][6] = (T16)(r0 ? u1.z : 0.0f);
-        av[kc][7] = (T16)(r0 ? u1.w : 0.0f);
-    }
-#pragma unroll
-    for (int tw = 0; tw < TPW; ++tw) {
-        floatx4_t acc = {0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-        for (int kc = 0; kc < KCH; ++kc) acc = MfmaT<T16>::mma(av[kc], bv[tw][kc], acc);
-        y[tw] = acc[0];   // row 0 in lanes 0..15
-    }
-}
-
-template <typename T16, int NCT>
-__global__ __launch_bounds__(256) void k_blk_fwd_mfma(StagedModel<float> m,
-                                                      const int64_t *__restrict__ offsets,
-                                                      const float *__restrict__ etab,
-                                                      const double *__restrict__ mt,
-                                                      float *__restrict__ alpha,
-                                                      int32_t *__restrict__ aexp,
-                                                      double *__restrict__ loglik,
-                                                      int32_t *__restrict__ status) {
-    constexpr int NT = 256, TPW = NCT / 64, KCH = NCT / 32;
-    constexpr int EPTM = (PF * 256 + NT - 1) / NT;
-    __shared__ __align__(16) float xs[256 + 8];
-    __shared__ float wred[4];
-    __shared__ float wsum[4];
-    __shared__ float etile[2][PF][256];
-    __shared__ double mtile[2][PF];
-    const int N = m.N, tid = threadIdx.x, l = tid & 63, w = tid >> 6;
-    typename MfmaT<T16>::V bv[TPW][KCH];
-    mfma_load_b<T16, TPW, KCH, false>(m.A, N, w, l, bv);
-    const int64_t b = blockIdx.x;
-    const int64_t off = offsets[b];
-    const int T = (int)(offsets[b + 1] - off);
-    auto col = [&](int tw) { return 16 * (w + 4 * tw) + (l & 15); };
-    const bool r0 = l < 16;
-    // t = 0 (one element per thread: column tid)
-    float v0 = (tid < N) ? m.pi[tid] * etab[off * N + tid] : 0.0f;
-    const float w0m = wave_max_r(v0);
-    if (l == 0) wred[w] = w0m;
-    __syncthreads();
-    float mx = fmaxf(fmaxf(wred[0], wred[1]), fmaxf(wred[2], wred[3]));
-    int ex = fexp(mx);
-    v0 = fldexp(v0, -ex);
-    xs[tid] = v0;
-    if (tid < N) alpha[off * N + tid] = v0;
-    if (tid == 0) aexp[off] = ex;
-    int64_t E = ex;
-    double logS = mt[off];
-    float y[TPW];
-#pragma unroll
-    for (int tw = 0; tw < TPW; ++tw) y[tw] = 0.0f;
-    const int EPT = (PF * NCT + NT - 1) / NT;
-    auto fetch = [&](int wb, float *ev, double *mv) {
-        for (int k = 0; k < EPTM; ++k) {
-            const int idx = tid + k * NT;
-            if (k < EPT && idx < PF * NCT) {
-                const int sl = idx / NCT, cc = idx % NCT;
-                const int64_t rr = off + min(wb + sl, T - 1);
-                ev[k] = cc < N ? etab[rr * N + cc] : 0.0f;
-            }
-        }
-        if (tid < PF) *mv = mt[off + min(wb + tid, T - 1)];
-    };
-    auto park = [&](int bf, const float *ev, double mv) {
-        for (int k = 0; k < EPTM; ++k) {
-            const int idx = tid + k * NT;
-            if (k < EPT && idx < PF * NCT) etile[bf][idx / NCT][idx % NCT] = ev[k];
-        }
-        if (tid < PF) mtile[bf][tid] = mv;
-    };
-    float ev[EPTM];
-#pragma unroll
-    for (int k = 0; k < EPTM; ++k) ev[k] = 0.0f;
-    double mv = 0.0;
-    fetch(1, ev, &mv);
-    park(0, ev, mv);
-    __syncthreads();
-    int buf = 0;
-    for (int wb = 1; wb < T; wb += PF) {
-        fetch(wb + PF, ev, &mv);
-        for (int sl = 0; sl < PF; ++sl) {
-            const int t = wb + sl;
-            if (t >= T) break;
-            const int64_t row = off + t;
-            mfma_row<T16, TPW, KCH>(xs, l, bv, y);
-            float lm = 0.0f;
-#pragma unroll
-            for (int tw = 0; tw < TPW; ++tw) {
-                const int cc = col(tw);
-                y[tw] = (r0 && cc < N) ? y[tw] * etile[buf][sl][cc] : 0.0f;
-                lm = fmaxf(lm, y[tw]);
-            }
-            lm = wave_max_r(lm);
-            if (l == 0) wred[w] = lm;
-            __syncthreads();   // also: every lane has read xs for this step
-            mx = fmaxf(fmaxf(wred[0], wred[1]), fmaxf(wred[2], wred[3]));
-            ex = fexp(mx);
-#pragma unroll
-            for (int tw = 0; tw < TPW; ++tw) {
-                const int cc = col(tw);
-                const float a = fldexp(y[tw], -ex);
-                if (r0) {
-                    xs[cc] = a;
-                    if (cc < N) alpha[row * N + cc] = a;
-                }
-            }
-            if (tid == 0) aexp[row] = ex;
-            E += ex;
-            logS += mtile[buf][sl];
-            __syncthreads();
-        }
-        buf ^= 1;
-        park(buf, ev, mv);
-        __syncthreads();
-    }
-    // log P(y) from the last alpha^ (held in xs)
-    float tv = (tid < N) ? xs[tid] : 0.0f;
-    tv = wave_sum_r(tv);
-    if (l == 0) wsum[w] = tv;
-    __syncthreads();
-    if (tid == 0) {
-        const float z = (wsum[0] + wsum[1]) + (wsum[2] + wsum[3]);
-        double ll;
-        int st;
-        if (*m.perr) {
-            ll = __builtin_nan("");
-            st = 4;
-        } else if (isnan(logS)) {
-            ll = __builtin_nan("");
-            st = 2;
-        } else if (!(z > 0.0f) || isinf(logS)) {
-            ll = -__builtin_inf();
-            st = 1;
-        } else {
-            ll = logS + (double)E * 0.69314718055994530942 + log((double)z);
-            st = 0;
-        }
-        loglik[b] = ll;
-        status[b] = st;
-    }
-}
-
-template <typename T16, int NCT>
-__global__ __launch_bounds__(256) void k_blk_bwd_mfma(StagedModel<float> m,
-                                                      const int64_t *__restrict__ offsets,
-                                                      float *__restrict__ etab,
-                                                      const float *__restrict__ alpha,
-                                                      const int32_t *__restrict__ aexp,
-                                                      const int32_t *__restrict__ status,
-                                                      float *__restrict__ gamma) {
-    constexpr int NT = 256, TPW = NCT / 64, KCH = NCT / 32;
-    constexpr int EPTM = (PF * 256 + NT - 1) / NT;
-    __shared__ __align__(16) float xw[256 + 8];
-    __shared__ float wred[4];
-    __shared__ float wsum[4];
-    __shared__ float atile[2][PF][256];
-    __shared__ float etile[2][PF][256];
-    __shared__ int xtile[2][PF];
-    const int N = m.N, tid = threadIdx.x, l = tid & 63, w = tid >> 6;
-    typename MfmaT<T16>::V bv[TPW][KCH];
-    mfma_load_b<T16, TPW, KCH, true>(m.A, N, w, l, bv);
-    const int64_t b = blockIdx.x;
-    const int64_t off = offsets[b];
-    const int T = (int)(offsets[b + 1] - off);
-    const bool use = status[b] == 0;
-    auto col = [&](int tw) { return 16 * (w + 4 * tw) + (l & 15); };
-    const bool r0 = l < 16;
-    float bt[TPW];   // beta^_t of state col(tw) (lanes 0..15)
-#pragma unroll
-    for (int tw = 0; tw < TPW; ++tw) bt[tw] = (r0 && col(tw) < N) ? 1.0f : 0.0f;
-    const int EPT = (PF * NCT + NT - 1) / NT;
-    auto fetch = [&](int wb, float *av, float *ev, int *xv) {
-        for (int k = 0; k < EPTM; ++k) {
-            const int idx = tid + k * NT;
-            if (k < EPT && idx < PF * NCT) {
-                const int sl = idx / NCT, cc = idx % NCT;
-                const int64_t rr = off + max(wb - sl, 0);
-                av[k] = cc < N ? alpha[rr * N + cc] : 0.0f;
-                ev[k] = cc < N ? etab[rr * N + cc] : 0.0f;
-            }
-        }
-        if (tid < PF) *xv = aexp[off + max(wb - tid, 0)];
-    };
-    auto park = [&](int bf, const float *av, const float *ev, int xv) {
-        for (int k = 0; k < EPTM; ++k) {
-            const int idx = tid + k * NT;
-            if (k < EPT && idx < PF * NCT) {
-                atile[bf][idx / NCT][idx % NCT] = av[k];
-                etile[bf][idx / NCT][idx % NCT] = ev[k];
-            }
-        }
-        if (tid < PF) xtile[bf][tid] = xv;
-    };
-    float av[EPTM], ev[EPTM];
-#pragma unroll
-    for (int k = 0; k < EPTM; ++k) av[k] = ev[k] = 0.0f;
-    int xv = 0;
-    fetch(T - 1, av, ev, &xv);
-    park(0, av, ev, xv);
-    __syncthreads();
-    int buf = 0;
-    float y[TPW];
-    for (int wb = T - 1; wb >= 0; wb -= PF) {
-        fetch(wb - PF, av, ev, &xv);
-        bool done = false;
-        for (int sl = 0; sl < PF; ++sl) {
-            const int t = wb - sl;
-            if (t < 0) break;
-            const int64_t row = off + t;
-            const int xt = xtile[buf][sl];
-            float hs = 0.0f, hv[TPW], wv[TPW];
-#pragma unroll
-            for (int tw = 0; tw < TPW; ++tw) {
-                const int cc = col(tw);
-                const bool ok = r0 && cc < N;
-                const float a = ok ? atile[buf][sl][cc] : 0.0f;
-                const float e = ok ? etile[buf][sl][cc] : 0.0f;
-                hv[tw] = a * bt[tw];
-                wv[tw] = e * bt[tw];
-                hs += hv[tw];
-                if (r0) xw[cc] = wv[tw];
-            }
-            hs = wave_sum_r(hs);
-            if (l == 0) wsum[w] = hs;
-            __syncthreads();
-            const float Z = (wsum[0] + wsum[1]) + (wsum[2] + wsum[3]);
-            const float rz = 1.0f / Z;
-#pragma unroll
-            for (int tw = 0; tw < TPW; ++tw) {
-                const int cc = col(tw);
-                if (r0 && cc < N) {
-                    gamma[row * N + cc] = use ? hv[tw] * rz : 0.0f;
-                    etab[row * N + cc] = (use && t > 0) ? fldexp(wv[tw] * rz, -xt) : 0.0f;
-                }
-            }
-            if (t == 0) {
-                done = true;
-                break;
-            }
-            mfma_row<T16, TPW, KCH>(xw, l, bv, y);
-            float lm = 0.0f;
-#pragma unroll
-            for (int tw = 0; tw < TPW; ++tw) {
-                y[tw] = (r0 && col(tw) < N) ? y[tw] : 0.0f;
-                lm = fmaxf(lm, y[tw]);
-            }
-            lm = wave_max_r(lm);
-            if (l == 0) wred[w] = lm;
-            __syncthreads();   // also: every lane has read xw for this step
-            const int ex = fexp(fmaxf(fmaxf(wred[0], wred[1]), fmaxf(wred[2], wred[3])));
-#pragma unroll
-            for (int tw = 0; tw < TPW; ++tw) bt[tw] = fldexp(y[tw], -ex);
-        }
-        if (done) break;
-        buf ^= 1;
-        __syncthreads();
-        park(buf, av, ev, xv);
-        __syncthreads();
-    }
 }
 
 // ---------------------------------------------------------------- 5. statistics
@@ -953,43 +619,16 @@ int blk_gstats_tiles(int64_t total, int family) {
     return (int)((total + ts - 1) / ts);
 }
 
-template <typename T16, int NCT>
-static void launch_blk_mfma_t(bool fwd, const StagedModel<float> &m, const ObsDesc &o, float *etab,
-                              const BlockBuffers &bb, float *alpha, double *loglik,
-                              int32_t *status, float *gamma, hipStream_t s) {
-    if (fwd)
-        hipLaunchKernelGGL((k_blk_fwd_mfma<T16, NCT>), dim3((unsigned)o.nseq), dim3(256), 0, s, m,
-                           o.offsets, (const float *)etab, (const double *)bb.mt, alpha, bb.aexp,
-                           loglik, status);
-    else
-        hipLaunchKernelGGL((k_blk_bwd_mfma<T16, NCT>), dim3((unsigned)o.nseq), dim3(256), 0, s, m,
-                           o.offsets, etab, (const float *)alpha, (const int32_t *)bb.aexp,
-                           (const int32_t *)status, gamma);
-}
-
-template <typename T16>
-static void launch_blk_mfma(bool fwd, const StagedModel<float> &m, const ObsDesc &o, float *etab,
-                            const BlockBuffers &bb, float *alpha, double *loglik, int32_t *status,
-                            float *gamma, hipStream_t s) {
-    switch (blk_nc(m.N)) {
-    case 64: return launch_blk_mfma_t<T16, 64>(fwd, m, o, etab, bb, alpha, loglik, status, gamma, s);
-    case 128: return launch_blk_mfma_t<T16, 128>(fwd, m, o, etab, bb, alpha, loglik, status, gamma, s);
-    case 192: return launch_blk_mfma_t<T16, 192>(fwd, m, o, etab, bb, alpha, loglik, status, gamma, s);
-    default: return launch_blk_mfma_t<T16, 256>(fwd, m, o, etab, bb, alpha, loglik, status, gamma, s);
-    }
-}
-
 // The vector-ALU sweeps (FP32/FP64, 64 < N <= 256) are in k_sweep.hip; the
-// scaled low-precision options run here on the matrix cores (any N <= 256).
+// scaled low-precision options (any N <= 256) are in k_grp.hip.
 template <typename R>
 static void launch_blk_sweep(bool fwd, const StagedModel<R> &m, const ObsDesc &o, R *etab,
                              const BlockBuffers &bb, R *alpha, double *loglik, int32_t *status,
                              R *gamma, hipStream_t s) {
     if constexpr (sizeof(R) == 4) {
-        if (bb.mfma == 1)
-            return launch_blk_mfma<__bf16>(fwd, m, o, etab, bb, alpha, loglik, status, gamma, s);
-        if (bb.mfma == 2)
-            return launch_blk_mfma<_Float16>(fwd, m, o, etab, bb, alpha, loglik, status, gamma, s);
+        if (bb.mfma == 1 || bb.mfma == 2)
+            return launch_grp_sweep(fwd, bb.mfma == 1, m, o.offsets, o.nseq, etab, bb.mt, alpha,
+                                    bb.aexp, loglik, status, gamma, s);
     }
     // the planner sends N <= 64 to the wave path unless a scaled option is asked for
     launch_sw_sweep<R>(fwd, m, o.offsets, o.nseq, etab, bb.mt, alpha, bb.aexp, loglik, status,

@@ -1,0 +1,732 @@
+// k_grp.hip -- the scaled bf16/fp16 sweeps of the large-state path, sixteen
+// sequences per workgroup on the matrix cores.
+//
+// The scaled alternative to log-space (section 3.2) multiplies normalised
+// vectors by A in a narrow format with FP32 accumulation and rescales by
+// powers of two.  One vector per sequence fills only one row of a 16-row
+// MFMA operand, so a workgroup steps sixteen sequences together and takes
+// the transposed product
+//     D[c][s] = sum_k Mop[c][k] x_s[k]     (v_mfma_f32_16x16x32_{bf16,f16})
+// with the matrix as operand A (Mop[c][k] = a_kc forward, a_ck backward, in
+// registers) and the sixteen input vectors as operand B (from LDS).  Operand
+// layout (lane l): A row l % 16, k = 8 (l / 16) + q; B column l % 16, same k;
+// result column l % 16, rows 4 (l / 16) + i.  So lane l of compute wave w owns
+// sequence slot l % 16 and, in each of its TPW tiles of 16 output states, the
+// four consecutive states 16 (w + 4 tw) + 4 (l / 16) + i; a sequence's
+// maximum or sum needs two permlane swaps inside the wave plus one LDS
+// exchange across the four compute waves.
+//
+// The workgroup is split by role.  Waves 0-3 compute: LDS in, matrix-core
+// products, scaling, LDS out; they touch no global memory inside the sweep.
+// Waves 4-7 move data for four of the sequences each: they stage the rows a
+// step reads (emission factors; alpha and the exponents backward) into
+// double-buffered LDS one step ahead of use, from a register ring filled D
+// steps ahead, and store the rows a step wrote (alpha and its exponent;
+// gamma and w' backward) from LDS to HBM a step or two later, each
+// instruction a whole 1 KiB row rather than sixteen 64-byte pieces.  The two
+// roles run separate loops with the same number of barriers per step (the
+// hardware barrier counts waves, not code sites), so neither role's registers
+// are held while the other role's code runs.
+//
+// bf16 keeps FP32's exponent range: a step's output is scaled by the
+// exponent of the largest entry of the step's input, folded into the
+// emission factors before the product, one barrier per step.  fp16 has a
+// 5-bit exponent, so each vector is normalised exactly (largest entry in
+// [1/2, 1)) before it is rounded, at the cost of a second barrier per step.
+//
+// The sixteen sequences of a group are consecutive in the batch and step in
+// lockstep for the group's longest length, in whole passes of D steps; a
+// shorter member keeps computing on clamped rows (finite values in its own
+// column only) and stores nothing after its end (forward) or before its
+// start (backward, which runs each sequence from its own last step).
+#include "dev_common.hpp"
+
+namespace hmmk {
+
+typedef __bf16 gbf16x8_t __attribute__((ext_vector_type(8)));
+typedef _Float16 ghalf8_t __attribute__((ext_vector_type(8)));
+typedef __bf16 gbf16x4_t __attribute__((ext_vector_type(4)));
+typedef _Float16 ghalf4_t __attribute__((ext_vector_type(4)));
+typedef float gfloatx4_t __attribute__((ext_vector_type(4)));
+typedef float gfloatx8_t __attribute__((ext_vector_type(8)));
+
+template <typename T16>
+struct GMfma;
+template <>
+struct GMfma<__bf16> {
+    using V8 = gbf16x8_t;
+    using V4 = gbf16x4_t;
+    static constexpr bool EXACT = false;
+    static __device__ __forceinline__ gfloatx4_t mma(V8 a, V8 b, gfloatx4_t c) {
+        return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+    }
+};
+template <>
+struct GMfma<_Float16> {
+    using V8 = ghalf8_t;
+    using V4 = ghalf4_t;
+    static constexpr bool EXACT = true;
+    static __device__ __forceinline__ gfloatx4_t mma(V8 a, V8 b, gfloatx4_t c) {
+        return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+    }
+};
+
+constexpr int GS = 16;   // sequences per workgroup
+
+template <int NCT>
+struct GCfg {
+    static constexpr int NT = 512;         // four compute waves, then four load waves
+    static constexpr int TPW = NCT / 64;   // tiles of 16 output states per compute wave
+    static constexpr int KCH = NCT / 32;   // k-chunks of the 16x16x32 instruction
+    static constexpr int XP = NCT + 8;     // LDS row pitch of an input vector (T16)
+    static constexpr int EP = NCT + 4;     // LDS row pitch of a staged FP32 row
+    static constexpr int HK = NCT / 64;    // 16-byte chunks per load-wave lane, table and step
+    static constexpr int D = 4;            // steps between a load's issue and its staging
+};
+
+__device__ __forceinline__ uint32_t ghi(float x) { return __builtin_bit_cast(uint32_t, x); }
+__device__ __forceinline__ uint32_t gumax(uint32_t a, uint32_t b) { return a > b ? a : b; }
+// exponent of the largest of four non-negative floats given as bit patterns
+__device__ __forceinline__ int gexp4(const uint32_t *g) {
+    return fexp(__builtin_bit_cast(float, gumax(gumax(g[0], g[1]), gumax(g[2], g[3]))));
+}
+// maximum over the four lanes of one sequence slot (l, l^16, l^32, l^48)
+__device__ __forceinline__ uint32_t slot_umax(uint32_t u) {
+    auto r16 = __builtin_amdgcn_permlane16_swap(u, u, false, false);
+    u = gumax((uint32_t)r16[0], (uint32_t)r16[1]);
+    auto r32 = __builtin_amdgcn_permlane32_swap(u, u, false, false);
+    return gumax((uint32_t)r32[0], (uint32_t)r32[1]);
+}
+__device__ __forceinline__ float slot_sum(float x) {
+    const uint32_t u = __builtin_bit_cast(uint32_t, x);
+    auto r16 = __builtin_amdgcn_permlane16_swap(u, u, false, false);
+    x = __builtin_bit_cast(float, (uint32_t)r16[0]) + __builtin_bit_cast(float, (uint32_t)r16[1]);
+    const uint32_t v = __builtin_bit_cast(uint32_t, x);
+    auto r32 = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+    return __builtin_bit_cast(float, (uint32_t)r32[0]) + __builtin_bit_cast(float, (uint32_t)r32[1]);
+}
+__device__ __forceinline__ double slot_sum(double x) {
+    const uint64_t u = __builtin_bit_cast(uint64_t, x);
+    auto l16 = __builtin_amdgcn_permlane16_swap((uint32_t)u, (uint32_t)u, false, false);
+    auto h16 = __builtin_amdgcn_permlane16_swap((uint32_t)(u >> 32), (uint32_t)(u >> 32), false, false);
+    x = __builtin_bit_cast(double, ((uint64_t)(uint32_t)h16[0] << 32) | (uint32_t)l16[0]) +
+        __builtin_bit_cast(double, ((uint64_t)(uint32_t)h16[1] << 32) | (uint32_t)l16[1]);
+    const uint64_t v = __builtin_bit_cast(uint64_t, x);
+    auto l32 = __builtin_amdgcn_permlane32_swap((uint32_t)v, (uint32_t)v, false, false);
+    auto h32 = __builtin_amdgcn_permlane32_swap((uint32_t)(v >> 32), (uint32_t)(v >> 32), false, false);
+    return __builtin_bit_cast(double, ((uint64_t)(uint32_t)h32[0] << 32) | (uint32_t)l32[0]) +
+           __builtin_bit_cast(double, ((uint64_t)(uint32_t)h32[1] << 32) | (uint32_t)l32[1]);
+}
+
+// four consecutive FP32 entries of row `row` from column c.  Columns at or
+// past N read a copy of an entry inside the row instead (no branch around the
+// load, so the load waves' waits stay exact); the sweeps multiply every such
+// column by a zero row of the matrix operand or a zero beta entry.
+template <bool VEC>
+__device__ __forceinline__ float4 gload4(const float *__restrict__ base, int64_t row, int c, int N) {
+    if constexpr (VEC) {   // N % 4 == 0: wholly inside or outside the row
+        return *reinterpret_cast<const float4 *>(base + row * N + min(c, N - 4));
+    } else {
+        const float *p = base + row * N;
+        return make_float4(p[min(c, N - 1)], p[min(c + 1, N - 1)], p[min(c + 2, N - 1)],
+                           p[min(c + 3, N - 1)]);
+    }
+}
+
+// A load wave's store of one staged 16-byte chunk (columns at or past N are
+// not written).
+template <bool VEC>
+__device__ __forceinline__ void hstore4(float *__restrict__ base, int64_t row, int c, int N, float4 v) {
+    if constexpr (VEC) {
+        if (c < N) *reinterpret_cast<float4 *>(base + row * N + c) = v;
+    } else {
+        const float a[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            if (c + i < N) base[row * N + c + i] = a[i];
+    }
+}
+
+__device__ __forceinline__ float f4at(const float4 &v, int i) {
+    return i == 0 ? v.x : (i == 1 ? v.y : (i == 2 ? v.z : v.w));
+}
+__device__ __forceinline__ float4 lds4(const float *p) { return *reinterpret_cast<const float4 *>(p); }
+
+// the compute wave's operand-A registers: Mop[c][k] for c = 16 (w + 4 tw) +
+// l % 16, k = 32 kc + 8 (l / 16) + q, read from M[c][k] (M = A^T forward,
+// A backward), zero outside N x N
+template <typename T16, int NCT>
+__device__ __forceinline__ void gload_aop(const float *M, int N, int w, int l,
+                                          typename GMfma<T16>::V8 (&aop)[GCfg<NCT>::TPW][GCfg<NCT>::KCH]) {
+    using C = GCfg<NCT>;
+#pragma unroll
+    for (int tw = 0; tw < C::TPW; ++tw) {
+        const int c = 16 * (w + 4 * tw) + (l & 15);
+#pragma unroll
+        for (int kc = 0; kc < C::KCH; ++kc) {
+            gfloatx8_t f;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const int k = 32 * kc + 8 * (l >> 4) + q;
+                const float v = M[min(c, N - 1) * N + min(k, N - 1)];
+                f[q] = (c < N && k < N) ? v : 0.0f;
+            }
+            // converted here, as packed pairs (kept from sinking the conversion
+            // to the loop, which would hold every entry as FP32 until then)
+            aop[tw][kc] = __builtin_convertvector(f, typename GMfma<T16>::V8);
+            asm volatile("" : "+v"(aop[tw][kc]));
+        }
+        // one tile's loads in flight at a time (all of them at once would
+        // need a register per entry)
+        __builtin_amdgcn_sched_barrier(0);
+    }
+}
+
+// D = Mop x for the wave's tiles, x = the sixteen input vectors in xs
+template <typename T16, int NCT>
+__device__ __forceinline__ void gproduct(const T16 *xs, int l,
+                                         const typename GMfma<T16>::V8 (&aop)[GCfg<NCT>::TPW][GCfg<NCT>::KCH],
+                                         float (&out)[GCfg<NCT>::TPW][4]) {
+    using C = GCfg<NCT>;
+    using V8 = typename GMfma<T16>::V8;
+    gfloatx4_t acc[C::TPW];
+#pragma unroll
+    for (int tw = 0; tw < C::TPW; ++tw) acc[tw] = gfloatx4_t{0.f, 0.f, 0.f, 0.f};
+    const T16 *row = xs + (l & 15) * C::XP + 8 * (l >> 4);
+#pragma unroll
+    for (int kc = 0; kc < C::KCH; ++kc) {
+        const V8 b = *reinterpret_cast<const V8 *>(row + 32 * kc);
+#pragma unroll
+        for (int tw = 0; tw < C::TPW; ++tw) acc[tw] = GMfma<T16>::mma(aop[tw][kc], b, acc[tw]);
+    }
+#pragma unroll
+    for (int tw = 0; tw < C::TPW; ++tw)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) out[tw][i] = acc[tw][i];
+}
+
+// the lane's outputs as T16 into its sequence's LDS row
+template <typename T16, int NCT>
+__device__ __forceinline__ void gput(T16 *xs, int w, int l, const float (&x)[GCfg<NCT>::TPW][4]) {
+    using C = GCfg<NCT>;
+    using V4 = typename GMfma<T16>::V4;
+    T16 *row = xs + (l & 15) * C::XP + 4 * (l >> 4);
+#pragma unroll
+    for (int tw = 0; tw < C::TPW; ++tw) {
+        V4 v;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) v[i] = (T16)x[tw][i];
+        *reinterpret_cast<V4 *>(row + 16 * (w + 4 * tw)) = v;
+    }
+}
+
+// A load wave's share of the staging: its lane l moves, per table and step,
+// the 16-byte chunks q = 64 k + l (k < HK) of the four rows of sequences
+// 4 h .. 4 h + 3 (h = wave - 4): row r = q / (NCT / 4), column 4 (q % (NCT / 4)).
+template <int NCT>
+struct LoadShare {
+    int64_t off[GCfg<NCT>::HK];
+    int T[GCfg<NCT>::HK];
+    int lds[GCfg<NCT>::HK];   // offset of the chunk in a staged table
+    int col[GCfg<NCT>::HK];
+    __device__ void init(const int64_t *offsets, int64_t nseq, int64_t g0, int h, int l) {
+        constexpr int CPR = NCT / 4;
+#pragma unroll
+        for (int k = 0; k < GCfg<NCT>::HK; ++k) {
+            const int q = 64 * k + l, r = q / CPR;
+            col[k] = 4 * (q % CPR);
+            lds[k] = (4 * h + r) * GCfg<NCT>::EP + col[k];
+            const int64_t s = g0 + 4 * h + r;
+            off[k] = s < nseq ? offsets[s] : 0;
+            T[k] = s < nseq ? (int)(offsets[s + 1] - off[k]) : 0;
+        }
+    }
+};
+
+// ---------------------------------------------------------------- forward
+template <typename T16, int NCT, bool VEC>
+__global__ __launch_bounds__(512) void k_grp_fwd(StagedModel<float> m, const int64_t *__restrict__ offsets,
+                                                 int64_t nseq, const float *__restrict__ etab,
+                                                 const double *__restrict__ mt,
+                                                 float *__restrict__ alpha, int32_t *__restrict__ aexp,
+                                                 double *__restrict__ loglik,
+                                                 int32_t *__restrict__ status) {
+    using C = GCfg<NCT>;
+    using G = GMfma<T16>;
+    constexpr int TPW = C::TPW, HK = C::HK, D = C::D, EP = C::EP;
+    __shared__ __align__(16) float es[2][GS * EP];    // e_t, staged by the load waves
+    __shared__ __align__(16) float ast[2][GS * EP];   // alpha^_t, staged for the load waves' stores
+    __shared__ __align__(16) T16 xs[2][GS * C::XP];
+    __shared__ int axs[2][GS];
+    __shared__ uint32_t gm[2][GS][4];
+    __shared__ uint32_t gE[GS][4];
+    __shared__ float zz[GS][4];
+    __shared__ double ls[GS][4];
+    const int N = m.N, tid = threadIdx.x, l = tid & 63;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int64_t g0 = (int64_t)blockIdx.x * GS;
+    const int sl = l & 15, ig = l >> 4;
+    const int64_t sidx = g0 + sl;
+    const bool sv = sidx < nseq;
+    const int64_t off = sv ? offsets[sidx] : 0;
+    const int T = sv ? (int)(offsets[sidx + 1] - off) : 0;
+    const int Tg = __builtin_amdgcn_readfirstlane(wave_max_i(T));   // the group's longest
+    // steps 1 .. tl run in whole passes of D (steps past Tg are masked like
+    // any step past a member's end)
+    const int tl = Tg > 1 ? D * ((Tg - 1 + D - 1) / D) : 0;
+    auto col0 = [&](int tw) { return 16 * (w + 4 * tw) + 4 * ig; };
+
+    if (w < 4) {
+        // ------------------------------------------------ compute waves
+        typename G::V8 aop[TPW][C::KCH];
+        gload_aop<T16, NCT>(m.AT, N, w, l, aop);
+        float x[TPW][4];
+        auto stage = [&](int b, int ex) {
+#pragma unroll
+            for (int tw = 0; tw < TPW; ++tw)
+                *reinterpret_cast<float4 *>(&ast[b][sl * EP + col0(tw)]) =
+                    make_float4(x[tw][0], x[tw][1], x[tw][2], x[tw][3]);
+            if (w == 0 && ig == 0) axs[b][sl] = ex;
+        };
+        __syncthreads();   // e_0, e_1 staged
+        // t = 0: pi o e_0, normalised exactly
+        {
+            uint32_t mx = 0;
+#pragma unroll
+            for (int tw = 0; tw < TPW; ++tw) {
+                const float4 e = lds4(&es[0][sl * EP + col0(tw)]);
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int c = col0(tw) + i;
+                    x[tw][i] = (T > 0 && c < N) ? m.pi[min(c, N - 1)] * f4at(e, i) : 0.f;
+                    mx = gumax(mx, ghi(x[tw][i]));
+                }
+            }
+            mx = slot_umax(mx);
+            if (ig == 0) gE[sl][w] = mx;
+        }
+        __syncthreads();
+        const int ex0 = gexp4(gE[sl]);
+        int64_t E = ex0;
+        {
+            uint32_t mx = 0;
+            float zl = 0.f;
+#pragma unroll
+            for (int tw = 0; tw < TPW; ++tw)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    x[tw][i] = fldexp(x[tw][i], -ex0);
+                    mx = gumax(mx, ghi(x[tw][i]));
+                    zl += x[tw][i];
+                }
+            stage(0, ex0);
+            mx = slot_umax(mx);
+            zl = slot_sum(zl);
+            if (ig == 0) {
+                gm[0][sl][w] = mx;
+                if (T == 1) zz[sl][w] = zl;
+            }
+            gput<T16, NCT>(xs[0], w, l, x);
+        }
+        __syncthreads();
+        for (int t0 = 1; t0 < tl; t0 += D) {
+#pragma unroll
+            for (int u = 0; u < D; ++u) {
+                const int t = t0 + u;
+                const int pb = (t - 1) & 1, cb = t & 1;
+                float ev[TPW][4];
+                int exs = 0;
+                if constexpr (!G::EXACT) {
+                    // the step's scale 2^-x (x = exponent of the input's largest
+                    // entry, at least -126 so that the factor stays finite) goes
+                    // into the emission factors while the products run
+                    exs = max(gexp4(gm[pb][sl]), -126);
+                    const float sc = fldexp(1.0f, -exs);
+#pragma unroll
+                    for (int tw = 0; tw < TPW; ++tw) {
+                        const float4 e = lds4(&es[cb][sl * EP + col0(tw)]);
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) ev[tw][i] = f4at(e, i) * sc;
+                    }
+                } else {
+#pragma unroll
+                    for (int tw = 0; tw < TPW; ++tw) {
+                        const float4 e = lds4(&es[cb][sl * EP + col0(tw)]);
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) ev[tw][i] = f4at(e, i);
+                    }
+                }
+                gproduct<T16, NCT>(xs[pb], l, aop, x);
+#pragma unroll
+                for (int tw = 0; tw < TPW; ++tw)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) x[tw][i] *= ev[tw][i];
+                if constexpr (G::EXACT) {
+                    uint32_t mx = 0;
+#pragma unroll
+                    for (int tw = 0; tw < TPW; ++tw)
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) mx = gumax(mx, ghi(x[tw][i]));
+                    mx = slot_umax(mx);
+                    if (ig == 0) gE[sl][w] = mx;
+                    __syncthreads();
+                    exs = gexp4(gE[sl]);
+#pragma unroll
+                    for (int tw = 0; tw < TPW; ++tw)
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) x[tw][i] = fldexp(x[tw][i], -exs);
+                }
+                E += t < T ? exs : 0;
+                stage(cb, exs);
+                if constexpr (!G::EXACT) {
+                    uint32_t mx = 0;
+#pragma unroll
+                    for (int tw = 0; tw < TPW; ++tw)
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) mx = gumax(mx, ghi(x[tw][i]));
+                    mx = slot_umax(mx);
+                    if (ig == 0) gm[cb][sl][w] = mx;
+                }
+                if (t == T - 1) {   // the member's last step: sum_j alpha^_{T-1}(j)
+                    float zl = 0.f;
+#pragma unroll
+                    for (int tw = 0; tw < TPW; ++tw)
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) zl += x[tw][i];
+                    zl = slot_sum(zl);
+                    if (ig == 0) zz[sl][w] = zl;
+                }
+                gput<T16, NCT>(xs[cb], w, l, x);
+                __syncthreads();
+            }
+        }
+        // log P(y) = sum of the per-step log shifts + E log 2 + log sum_j alpha^_{T-1}(j)
+        double lsum = 0.0;
+        for (int t = 4 * w + ig; t < T; t += 16) lsum += mt[off + t];
+        lsum = slot_sum(lsum);
+        if (ig == 0) ls[sl][w] = lsum;
+        __syncthreads();
+        if (w == 0 && ig == 0 && sv) {
+            const double logS = (ls[sl][0] + ls[sl][1]) + (ls[sl][2] + ls[sl][3]);
+            const float z = (zz[sl][0] + zz[sl][1]) + (zz[sl][2] + zz[sl][3]);
+            double ll;
+            int st;
+            if (*m.perr) {
+                ll = __builtin_nan("");
+                st = 4;
+            } else if (isnan(logS)) {
+                ll = __builtin_nan("");
+                st = 2;
+            } else if (!(z > 0.0f) || isinf(logS)) {
+                ll = -__builtin_inf();
+                st = 1;
+            } else {
+                ll = logS + (double)E * 0.69314718055994530942 + log((double)z);
+                st = 0;
+            }
+            loglik[sidx] = ll;
+            status[sidx] = st;
+        }
+    } else {
+        // ------------------------------------------------ load waves
+        const int h = w - 4;
+        LoadShare<NCT> sh;
+        sh.init(offsets, nseq, g0, h, l);
+        // lane l also moves the exponents of sequence 4 h + l % 4
+        const int64_t sx = g0 + 4 * h + (l & 3);
+        const int64_t offx = sx < nseq ? offsets[sx] : 0;
+        const int Tx = sx < nseq ? (int)(offsets[sx + 1] - offx) : 0;
+        auto row = [&](int k, int s) { return sh.off[k] + (sh.T[k] > 0 ? min(s, sh.T[k] - 1) : 0); };
+        // alpha^_s and its exponent from the staging buffer to HBM (whole rows)
+        auto store_step = [&](int s) {
+#pragma unroll
+            for (int k = 0; k < HK; ++k)
+                if (s < sh.T[k])
+                    hstore4<VEC>(alpha, sh.off[k] + s, sh.col[k], N, lds4(&ast[s & 1][sh.lds[k]]));
+            if (l < 4 && s < Tx) aexp[offx + s] = axs[s & 1][4 * h + l];
+        };
+        float4 ring[D][HK];
+#pragma unroll
+        for (int k = 0; k < HK; ++k) {
+            *reinterpret_cast<float4 *>(&es[0][sh.lds[k]]) = gload4<VEC>(etab, row(k, 0), sh.col[k], N);
+            *reinterpret_cast<float4 *>(&es[1][sh.lds[k]]) = gload4<VEC>(etab, row(k, 1), sh.col[k], N);
+        }
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int k = 0; k < HK; ++k) ring[j][k] = gload4<VEC>(etab, row(k, 2 + j), sh.col[k], N);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        // nothing in flight on entry to the loop, so that the compiler's
+        // count of loads outstanding at the top of a pass is the steady one
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();   // e_0, e_1 staged
+        __syncthreads();   // step 0, first half
+        __syncthreads();   // step 0
+        for (int t0 = 1; t0 < tl; t0 += D) {
+#pragma unroll
+            for (int u = 0; u < D; ++u) {
+                const int t = t0 + u;
+                // e_{t+1} (ring slot u) goes to the buffer step t + 1 reads;
+                // the slot is refilled with e_{t+1+D}; then step t - 1 is stored
+#pragma unroll
+                for (int k = 0; k < HK; ++k)
+                    *reinterpret_cast<float4 *>(&es[(t + 1) & 1][sh.lds[k]]) = ring[u][k];
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int k = 0; k < HK; ++k) ring[u][k] = gload4<VEC>(etab, row(k, t + 1 + D), sh.col[k], N);
+                __builtin_amdgcn_sched_barrier(0);
+                store_step(t - 1);
+                if constexpr (G::EXACT) __syncthreads();
+                __syncthreads();
+            }
+        }
+        store_step(tl);    // staged before the last barrier
+        __syncthreads();   // the log-likelihood exchange
+    }
+}
+
+// ---------------------------------------------------------------- backward
+// Forms gamma_t = alpha^_t o b_t / Z_t and w'_t = e_t o b_t 2^{-x_t} / Z_t
+// (written over e_t; zero on each sequence's first step), Z_t = sum_j
+// alpha^_t(j) b_t(j).  Step tau of the sweep is step T - 1 - tau of a member.
+template <typename T16, int NCT, bool VEC>
+__global__ __launch_bounds__(512) void k_grp_bwd(StagedModel<float> m, const int64_t *__restrict__ offsets,
+                                                 int64_t nseq, float *__restrict__ etab,
+                                                 const float *__restrict__ alpha,
+                                                 const int32_t *__restrict__ aexp,
+                                                 const int32_t *__restrict__ status,
+                                                 float *__restrict__ gamma) {
+    using C = GCfg<NCT>;
+    using G = GMfma<T16>;
+    constexpr int TPW = C::TPW, HK = C::HK, D = C::D, EP = C::EP;
+    __shared__ __align__(16) float as[2][GS * EP];    // alpha^_t, staged by the load waves
+    __shared__ __align__(16) float es[2][GS * EP];    // e_t
+    __shared__ __align__(16) float gst[2][GS * EP];   // gamma_t, staged for the load waves' stores
+    __shared__ __align__(16) float wst[2][GS * EP];   // w'_t
+    __shared__ __align__(16) T16 xs[2][GS * C::XP];
+    __shared__ int ax[2][GS];
+    __shared__ uint32_t gm[2][GS][4];
+    __shared__ float zp[2][GS][4];
+    const int N = m.N, tid = threadIdx.x, l = tid & 63;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int64_t g0 = (int64_t)blockIdx.x * GS;
+    const int sl = l & 15, ig = l >> 4;
+    const int64_t sidx = g0 + sl;
+    const bool sv = sidx < nseq;
+    const int64_t off = sv ? offsets[sidx] : 0;
+    const int T = sv ? (int)(offsets[sidx + 1] - off) : 0;
+    const int Tg = __builtin_amdgcn_readfirstlane(wave_max_i(T));
+    const int taul = D * ((Tg + D - 1) / D) - 1;   // last step of the whole passes
+    auto col0 = [&](int tw) { return 16 * (w + 4 * tw) + 4 * ig; };
+
+    if (w < 4) {
+        // ------------------------------------------------ compute waves
+        const bool use = sv && status[sidx] == 0;
+        typename G::V8 aop[TPW][C::KCH];
+        gload_aop<T16, NCT>(m.A, N, w, l, aop);
+        float bt[TPW][4];
+#pragma unroll
+        for (int tw = 0; tw < TPW; ++tw)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) bt[tw][i] = (T > 0 && col0(tw) + i < N) ? 1.0f : 0.0f;
+        __syncthreads();   // step 0 staged
+        for (int u0 = 0; u0 <= taul; u0 += D) {
+#pragma unroll
+            for (int u = 0; u < D; ++u) {
+                const int tau = u0 + u;
+                const int t = T - 1 - tau;
+                const int cb = tau & 1;
+                const int xt = ax[cb][sl];
+                float hv[TPW][4], wv[TPW][4];
+                float hl = 0.f;
+                uint32_t mx = 0;
+#pragma unroll
+                for (int tw = 0; tw < TPW; ++tw) {
+                    const float4 a = lds4(&as[cb][sl * EP + col0(tw)]);
+                    const float4 e = lds4(&es[cb][sl * EP + col0(tw)]);
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        hv[tw][i] = f4at(a, i) * bt[tw][i];
+                        wv[tw][i] = f4at(e, i) * bt[tw][i];
+                        hl += hv[tw][i];
+                        mx = gumax(mx, ghi(wv[tw][i]));
+                    }
+                }
+                hl = slot_sum(hl);
+                mx = slot_umax(mx);
+                if (ig == 0) {
+                    zp[cb][sl][w] = hl;
+                    gm[cb][sl][w] = mx;
+                }
+                int exw = 0;
+                if constexpr (G::EXACT) {
+                    // fp16: the input is normalised exactly before it is rounded
+                    __syncthreads();
+                    exw = gexp4(gm[cb][sl]);
+#pragma unroll
+                    for (int tw = 0; tw < TPW; ++tw)
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) wv[tw][i] = fldexp(wv[tw][i], -exw);
+                }
+                gput<T16, NCT>(xs[cb], w, l, wv);
+                __syncthreads();
+                const float Z = (zp[cb][sl][0] + zp[cb][sl][1]) + (zp[cb][sl][2] + zp[cb][sl][3]);
+                const float rz = 1.0f / Z;
+                const float gz = use ? rz : 0.f;
+                const float wz = (use && t > 0) ? fldexp(rz, exw - xt) : 0.f;
+#pragma unroll
+                for (int tw = 0; tw < TPW; ++tw) {
+                    *reinterpret_cast<float4 *>(&gst[cb][sl * EP + col0(tw)]) =
+                        make_float4(hv[tw][0] * gz, hv[tw][1] * gz, hv[tw][2] * gz, hv[tw][3] * gz);
+                    *reinterpret_cast<float4 *>(&wst[cb][sl * EP + col0(tw)]) =
+                        make_float4(wv[tw][0] * wz, wv[tw][1] * wz, wv[tw][2] * wz, wv[tw][3] * wz);
+                }
+                gproduct<T16, NCT>(xs[cb], l, aop, bt);
+                if constexpr (!G::EXACT) {
+                    // bf16: scaled by the exponent of the input's largest entry
+                    // (the fp16 input was normalised, so its product already is)
+                    const float sc = fldexp(1.0f, -max(gexp4(gm[cb][sl]), -126));
+#pragma unroll
+                    for (int tw = 0; tw < TPW; ++tw)
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) bt[tw][i] *= sc;
+                }
+            }
+        }
+        __syncthreads();   // the last step's gamma and w' staged
+    } else {
+        // ------------------------------------------------ load waves
+        const int h = w - 4;
+        LoadShare<NCT> sh;
+        sh.init(offsets, nseq, g0, h, l);
+        // lane l also moves the exponents of sequence 4 h + l % 4
+        const int64_t sx = g0 + 4 * h + (l & 3);
+        const int64_t offx = sx < nseq ? offsets[sx] : 0;
+        const int Tx = sx < nseq ? (int)(offsets[sx + 1] - offx) : 0;
+        auto row = [&](int k, int s) { return sh.off[k] + (sh.T[k] > 0 ? max(sh.T[k] - 1 - s, 0) : 0); };
+        auto rowx = [&](int s) { return offx + (Tx > 0 ? max(Tx - 1 - s, 0) : 0); };
+        // gamma and w' of sweep step s from the staging buffers to HBM
+        auto store_step = [&](int s) {
+#pragma unroll
+            for (int k = 0; k < HK; ++k) {
+                const int t = sh.T[k] - 1 - s;
+                if (t >= 0) {
+                    hstore4<VEC>(gamma, sh.off[k] + t, sh.col[k], N, lds4(&gst[s & 1][sh.lds[k]]));
+                    hstore4<VEC>(etab, sh.off[k] + t, sh.col[k], N, lds4(&wst[s & 1][sh.lds[k]]));
+                }
+            }
+        };
+        float4 ra[D][HK], re[D][HK];
+        int rx[D];
+#pragma unroll
+        for (int k = 0; k < HK; ++k) {
+            *reinterpret_cast<float4 *>(&as[0][sh.lds[k]]) = gload4<VEC>(alpha, row(k, 0), sh.col[k], N);
+            *reinterpret_cast<float4 *>(&es[0][sh.lds[k]]) = gload4<VEC>(etab, row(k, 0), sh.col[k], N);
+        }
+        {
+            const int x0 = aexp[rowx(0)];
+            if (l < 4) ax[0][4 * h + l] = x0;
+        }
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int k = 0; k < HK; ++k) {
+                ra[j][k] = gload4<VEC>(alpha, row(k, 1 + j), sh.col[k], N);
+                re[j][k] = gload4<VEC>(etab, row(k, 1 + j), sh.col[k], N);
+            }
+            rx[j] = aexp[rowx(1 + j)];
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        __builtin_amdgcn_s_waitcnt(0);   // as in the forward sweep
+        __syncthreads();   // step 0 staged
+        for (int u0 = 0; u0 <= taul; u0 += D) {
+#pragma unroll
+            for (int u = 0; u < D; ++u) {
+                const int tau = u0 + u;
+                const int nb = (tau + 1) & 1;
+                // step tau + 1's rows (ring slot u) go to the buffers it reads;
+                // the slot is refilled with step tau + 1 + D; then the results of
+                // step tau - 2 (staged two barriers ago) are stored
+#pragma unroll
+                for (int k = 0; k < HK; ++k) {
+                    *reinterpret_cast<float4 *>(&as[nb][sh.lds[k]]) = ra[u][k];
+                    *reinterpret_cast<float4 *>(&es[nb][sh.lds[k]]) = re[u][k];
+                }
+                if (l < 4) ax[nb][4 * h + l] = rx[u];
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int k = 0; k < HK; ++k) {
+                    ra[u][k] = gload4<VEC>(alpha, row(k, tau + 1 + D), sh.col[k], N);
+                    re[u][k] = gload4<VEC>(etab, row(k, tau + 1 + D), sh.col[k], N);
+                }
+                rx[u] = aexp[rowx(tau + 1 + D)];
+                __builtin_amdgcn_sched_barrier(0);
+                if (tau >= 2) store_step(tau - 2);
+                if constexpr (G::EXACT) __syncthreads();
+                __syncthreads();
+            }
+        }
+        __syncthreads();   // the last step's gamma and w' staged
+        store_step(taul - 1);
+        store_step(taul);
+    }
+}
+
+template <typename T16, int NCT>
+static void launch_grp_t(bool fwd, const StagedModel<float> &m, const int64_t *offsets,
+                         int64_t nseq, float *etab, const double *mt, float *alpha,
+                         int32_t *aexp, double *loglik, int32_t *status, float *gamma,
+                         hipStream_t s) {
+    const dim3 grid((unsigned)((nseq + GS - 1) / GS));
+    const dim3 block(GCfg<NCT>::NT);
+    const bool vec = m.N % 4 == 0;
+    if (fwd) {
+        if (vec)
+            hipLaunchKernelGGL((k_grp_fwd<T16, NCT, true>), grid, block, 0, s, m, offsets, nseq,
+                               (const float *)etab, mt, alpha, aexp, loglik, status);
+        else
+            hipLaunchKernelGGL((k_grp_fwd<T16, NCT, false>), grid, block, 0, s, m, offsets, nseq,
+                               (const float *)etab, mt, alpha, aexp, loglik, status);
+    } else {
+        if (vec)
+            hipLaunchKernelGGL((k_grp_bwd<T16, NCT, true>), grid, block, 0, s, m, offsets, nseq,
+                               etab, (const float *)alpha, (const int32_t *)aexp,
+                               (const int32_t *)status, gamma);
+        else
+            hipLaunchKernelGGL((k_grp_bwd<T16, NCT, false>), grid, block, 0, s, m, offsets, nseq,
+                               etab, (const float *)alpha, (const int32_t *)aexp,
+                               (const int32_t *)status, gamma);
+    }
+}
+
+template <typename T16>
+static void launch_grp_nc(bool fwd, const StagedModel<float> &m, const int64_t *offsets,
+                          int64_t nseq, float *etab, const double *mt, float *alpha,
+                          int32_t *aexp, double *loglik, int32_t *status, float *gamma,
+                          hipStream_t s) {
+    const int nc = ((m.N + 63) / 64) * 64;
+    switch (nc) {
+    case 64:
+        return launch_grp_t<T16, 64>(fwd, m, offsets, nseq, etab, mt, alpha, aexp, loglik, status, gamma, s);
+    case 128:
+        return launch_grp_t<T16, 128>(fwd, m, offsets, nseq, etab, mt, alpha, aexp, loglik, status, gamma, s);
+    case 192:
+        return launch_grp_t<T16, 192>(fwd, m, offsets, nseq, etab, mt, alpha, aexp, loglik, status, gamma, s);
+    default:
+        return launch_grp_t<T16, 256>(fwd, m, offsets, nseq, etab, mt, alpha, aexp, loglik, status, gamma, s);
+    }
+}
+
+void launch_grp_sweep(bool fwd, bool bf16, const StagedModel<float> &m, const int64_t *offsets,
+                      int64_t nseq, float *etab, const double *mt, float *alpha, int32_t *aexp,
+                      double *loglik, int32_t *status, float *gamma, hipStream_t s) {
+    if (bf16)
+        launch_grp_nc<__bf16>(fwd, m, offsets, nseq, etab, mt, alpha, aexp, loglik, status, gamma, s);
+    else
+        launch_grp_nc<_Float16>(fwd, m, offsets, nseq, etab, mt, alpha, aexp, loglik, status, gamma, s);
+}
+
+}  // namespace hmmk

@@ -91,3 +91,22 @@ def test_config3_precision_study(h):
               "stats rel " + ", ".join(f"{k} {v:.2e}" for k, v in e_s.items()))
         b_ll, b_g, b_s = BOUNDS[prec]
         assert e_ll <= b_ll and e_g <= b_g and max(e_s.values()) <= b_s
+
+
+@pytest.mark.parametrize("prec", ["bf16_scaled", "f16_scaled"])
+@pytest.mark.parametrize("n", [96, 193])
+def test_scaled_many_groups(h, prec, n):
+    """Thirty-seven sequences of mixed lengths (1 to 400 steps): the scaled
+    sweeps step sixteen sequences per workgroup, so this spans two full
+    groups, a partial third one and members that end long before the
+    group's longest; every sequence must meet the same bounds."""
+    rng = np.random.default_rng(77 + n)
+    lengths = [1, 2, 400] + [int(x) for x in rng.integers(1, 260, size=34)]
+    w = workloads.random_workload("gaussian", n, 1, lengths, 3100 + n)
+    e_ll, e_g, e_s, g, s = errors(h, w, prec)
+    print(f"\n[precision] {prec:12s} 37 sequences N={n}: loglik rel {e_ll:.2e}, gamma abs "
+          f"{e_g:.2e}, stats rel " + ", ".join(f"{k} {v:.2e}" for k, v in e_s.items()))
+    b_ll, b_g, b_s = BOUNDS[prec]
+    assert e_ll <= b_ll and e_g <= b_g
+    assert max(e_s.values()) <= b_s
+    assert np.allclose(g.sum(axis=1), 1.0, atol=1e-5)
