@@ -16,17 +16,20 @@
 // maximum or sum needs two permlane swaps inside the wave plus one LDS
 // exchange across the four compute waves.
 //
-// The workgroup is split by role.  Waves 0-3 compute: LDS in, matrix-core
-// products, scaling, LDS out; they touch no global memory inside the sweep.
-// Waves 4-7 move data for four of the sequences each: they stage the rows a
-// step reads (emission factors; alpha and the exponents backward) into
-// double-buffered LDS one step ahead of use, from a register ring filled D
-// steps ahead, and store the rows a step wrote (alpha and its exponent;
-// gamma and w' backward) from LDS to HBM a step or two later, each
-// instruction a whole 1 KiB row rather than sixteen 64-byte pieces.  The two
-// roles run separate loops with the same number of barriers per step (the
-// hardware barrier counts waves, not code sites), so neither role's registers
-// are held while the other role's code runs.
+// The workgroup is split by role, four compute waves (0-3) and four load
+// waves (4-7), each load wave serving four of the sequences.  The two roles
+// run separate loops with the same number of barriers per step (the hardware
+// barrier counts waves, not code sites), so neither role's registers are held
+// while the other role's code runs.  A load wave keeps a register ring of the
+// rows a step reads filled several steps ahead and stages each step's rows
+// into double-buffered LDS one step ahead of use.  Rows go to HBM as whole
+// 1 KiB rows per instruction (sixteen 64-byte pieces per instruction, straight
+// from the matrix-core layout, cost several times more):
+//   forward: the compute waves stage alpha^_t in LDS, the load waves store it;
+//   backward: the compute waves only propagate b and stage it in LDS, the
+//   load waves form gamma_t and w'_t from it and the rows they hold (the row
+//   sums Z_t need no exchange across waves there) and stage them in LDS, and
+//   the compute waves, which issue no global loads, store them.
 //
 // bf16 keeps FP32's exponent range: a step's output is scaled by the
 // exponent of the largest entry of the step's input, folded into the
@@ -35,7 +38,7 @@
 // [1/2, 1)) before it is rounded, at the cost of a second barrier per step.
 //
 // The sixteen sequences of a group are consecutive in the batch and step in
-// lockstep for the group's longest length, in whole passes of D steps; a
+// lockstep for the group's longest length, in whole passes of a few steps; a
 // shorter member keeps computing on clamped rows (finite values in its own
 // column only) and stores nothing after its end (forward) or before its
 // start (backward, which runs each sequence from its own last step).
@@ -116,6 +119,32 @@ __device__ __forceinline__ double slot_sum(double x) {
     auto h32 = __builtin_amdgcn_permlane32_swap((uint32_t)(v >> 32), (uint32_t)(v >> 32), false, false);
     return __builtin_bit_cast(double, ((uint64_t)(uint32_t)h32[0] << 32) | (uint32_t)l32[0]) +
            __builtin_bit_cast(double, ((uint64_t)(uint32_t)h32[1] << 32) | (uint32_t)l32[1]);
+}
+
+// sum over aligned groups of LPR (16, 32 or 64) lanes, in every lane of the
+// group: DPP rotations inside each row of 16 lanes, then the permlane swaps
+template <int LPR>
+__device__ __forceinline__ float group_sum(float v) {
+    static_assert(LPR == 16 || LPR == 32 || LPR == 64, "groups of 16, 32 or 64 lanes");
+#define HMM_ROR(n)                                                                                   \
+    v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v),        \
+                                                               0x120 + (n), 0xf, 0xf, false))
+    HMM_ROR(8);
+    HMM_ROR(4);
+    HMM_ROR(2);
+    HMM_ROR(1);
+#undef HMM_ROR
+    if constexpr (LPR >= 32) {
+        const uint32_t u = __builtin_bit_cast(uint32_t, v);
+        auto r = __builtin_amdgcn_permlane16_swap(u, u, false, false);
+        v = __builtin_bit_cast(float, (uint32_t)r[0]) + __builtin_bit_cast(float, (uint32_t)r[1]);
+    }
+    if constexpr (LPR == 64) {
+        const uint32_t u = __builtin_bit_cast(uint32_t, v);
+        auto r = __builtin_amdgcn_permlane32_swap(u, u, false, false);
+        v = __builtin_bit_cast(float, (uint32_t)r[0]) + __builtin_bit_cast(float, (uint32_t)r[1]);
+    }
+    return v;
 }
 
 // four consecutive FP32 entries of row `row` from column c.  Columns at or
@@ -488,9 +517,21 @@ __global__ __launch_bounds__(512) void k_grp_fwd(StagedModel<float> m, const int
 }
 
 // ---------------------------------------------------------------- backward
-// Forms gamma_t = alpha^_t o b_t / Z_t and w'_t = e_t o b_t 2^{-x_t} / Z_t
-// (written over e_t; zero on each sequence's first step), Z_t = sum_j
-// alpha^_t(j) b_t(j).  Step tau of the sweep is step T - 1 - tau of a member.
+// Step tau of the sweep is step t = T - 1 - tau of a member.  The compute
+// waves only propagate: w_t = e_t o b_t (normalised exactly for fp16) is the
+// product input, b_{t-1} = A w_t (times 2^-x with x the exponent of the
+// input's largest entry, bf16), and each b_t is staged in LDS.  The load
+// waves form the outputs from the staged b_t and the rows they loaded:
+// Z_t = sum_j alpha^_t(j) b_t(j) (one row per wave or lane group, so no
+// exchange across waves), gamma_t = alpha^_t o b_t / Z_t and
+// w'_t = e_t o b_t 2^{-x_t} / Z_t (written over e_t; zero on each sequence's
+// first step), one step behind the compute waves.
+template <int NCT>
+struct BwdCfg {
+    static constexpr int R = 5;            // register ring: steps tau - 1 .. tau + R - 2
+    static constexpr int LPR = NCT / 4;    // lanes of a load wave that share a row
+};
+
 template <typename T16, int NCT, bool VEC>
 __global__ __launch_bounds__(512) void k_grp_bwd(StagedModel<float> m, const int64_t *__restrict__ offsets,
                                                  int64_t nseq, float *__restrict__ etab,
@@ -500,71 +541,85 @@ __global__ __launch_bounds__(512) void k_grp_bwd(StagedModel<float> m, const int
                                                  float *__restrict__ gamma) {
     using C = GCfg<NCT>;
     using G = GMfma<T16>;
-    constexpr int TPW = C::TPW, HK = C::HK, D = C::D, EP = C::EP;
-    __shared__ __align__(16) float as[2][GS * EP];    // alpha^_t, staged by the load waves
-    __shared__ __align__(16) float es[2][GS * EP];    // e_t
-    __shared__ __align__(16) float gst[2][GS * EP];   // gamma_t, staged for the load waves' stores
+    constexpr int TPW = C::TPW, HK = C::HK, EP = C::EP, R = BwdCfg<NCT>::R, LPR = BwdCfg<NCT>::LPR;
+    static_assert(64 % LPR == 0, "a row's chunks lie in one aligned lane group");
+    __shared__ __align__(16) float es[2][GS * EP];    // e_t, staged by the load waves
+    __shared__ __align__(16) float bst[2][GS * EP];   // b_t, staged by the compute waves
+    __shared__ __align__(16) float gst[2][GS * EP];   // gamma_t, staged by the load waves
     __shared__ __align__(16) float wst[2][GS * EP];   // w'_t
     __shared__ __align__(16) T16 xs[2][GS * C::XP];
-    __shared__ int ax[2][GS];
     __shared__ uint32_t gm[2][GS][4];
-    __shared__ float zp[2][GS][4];
     const int N = m.N, tid = threadIdx.x, l = tid & 63;
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int64_t g0 = (int64_t)blockIdx.x * GS;
-    const int sl = l & 15, ig = l >> 4;
-    const int64_t sidx = g0 + sl;
-    const bool sv = sidx < nseq;
-    const int64_t off = sv ? offsets[sidx] : 0;
-    const int T = sv ? (int)(offsets[sidx + 1] - off) : 0;
-    const int Tg = __builtin_amdgcn_readfirstlane(wave_max_i(T));
-    const int taul = D * ((Tg + D - 1) / D) - 1;   // last step of the whole passes
-    auto col0 = [&](int tw) { return 16 * (w + 4 * tw) + 4 * ig; };
+    int Tl = 0;
+    {
+        const int64_t s = g0 + (l & 15);
+        if (s < nseq) Tl = (int)(offsets[s + 1] - offsets[s]);
+    }
+    const int Tg = __builtin_amdgcn_readfirstlane(wave_max_i(Tl));
+    const int taul = R * ((Tg + R - 1) / R) - 1;   // last step of the whole passes
 
     if (w < 4) {
         // ------------------------------------------------ compute waves
-        const bool use = sv && status[sidx] == 0;
+        const int sl = l & 15, ig = l >> 4;
+        auto col0 = [&](int tw) { return 16 * (w + 4 * tw) + 4 * ig; };
         typename G::V8 aop[TPW][C::KCH];
         gload_aop<T16, NCT>(m.A, N, w, l, aop);
+        // gamma and w' of sweep step s for the wave's four sequences, from LDS
+        // to HBM in whole rows
+        LoadShare<NCT> cp;
+        cp.init(offsets, nseq, g0, w, l);
+        // (the LDS reads are issued first and the stores after the step's
+        // products, so that the reads' latency is hidden)
+        float4 cpg[HK], cpw[HK];
+        auto copy_read = [&](int s) {
+#pragma unroll
+            for (int k = 0; k < HK; ++k) {
+                cpg[k] = lds4(&gst[s & 1][cp.lds[k]]);
+                cpw[k] = lds4(&wst[s & 1][cp.lds[k]]);
+            }
+        };
+        auto copy_write = [&](int s) {
+#pragma unroll
+            for (int k = 0; k < HK; ++k) {
+                const int t = cp.T[k] - 1 - s;
+                if (t >= 0) {
+                    hstore4<VEC>(gamma, cp.off[k] + t, cp.col[k], N, cpg[k]);
+                    hstore4<VEC>(etab, cp.off[k] + t, cp.col[k], N, cpw[k]);
+                }
+            }
+        };
         float bt[TPW][4];
 #pragma unroll
         for (int tw = 0; tw < TPW; ++tw)
 #pragma unroll
-            for (int i = 0; i < 4; ++i) bt[tw][i] = (T > 0 && col0(tw) + i < N) ? 1.0f : 0.0f;
-        __syncthreads();   // step 0 staged
-        for (int u0 = 0; u0 <= taul; u0 += D) {
+            for (int i = 0; i < 4; ++i) bt[tw][i] = (Tl > 0 && col0(tw) + i < N) ? 1.0f : 0.0f;
+        __syncthreads();   // e of step 0 staged
+        for (int u0 = 0; u0 <= taul; u0 += R) {
 #pragma unroll
-            for (int u = 0; u < D; ++u) {
-                const int tau = u0 + u;
-                const int t = T - 1 - tau;
-                const int cb = tau & 1;
-                const int xt = ax[cb][sl];
-                float hv[TPW][4], wv[TPW][4];
-                float hl = 0.f;
+            for (int u = 0; u < R; ++u) {
+                const int tau = u0 + u, cb = tau & 1;
+                if (tau >= 2) copy_read(tau - 2);   // staged two barriers ago
+                float wv[TPW][4];
                 uint32_t mx = 0;
 #pragma unroll
                 for (int tw = 0; tw < TPW; ++tw) {
-                    const float4 a = lds4(&as[cb][sl * EP + col0(tw)]);
                     const float4 e = lds4(&es[cb][sl * EP + col0(tw)]);
+                    *reinterpret_cast<float4 *>(&bst[cb][sl * EP + col0(tw)]) =
+                        make_float4(bt[tw][0], bt[tw][1], bt[tw][2], bt[tw][3]);
 #pragma unroll
                     for (int i = 0; i < 4; ++i) {
-                        hv[tw][i] = f4at(a, i) * bt[tw][i];
                         wv[tw][i] = f4at(e, i) * bt[tw][i];
-                        hl += hv[tw][i];
                         mx = gumax(mx, ghi(wv[tw][i]));
                     }
                 }
-                hl = slot_sum(hl);
                 mx = slot_umax(mx);
-                if (ig == 0) {
-                    zp[cb][sl][w] = hl;
-                    gm[cb][sl][w] = mx;
-                }
-                int exw = 0;
+                if (ig == 0) gm[cb][sl][w] = mx;
                 if constexpr (G::EXACT) {
                     // fp16: the input is normalised exactly before it is rounded
                     __syncthreads();
-                    exw = gexp4(gm[cb][sl]);
+                    const int exw = gexp4(gm[cb][sl]);
 #pragma unroll
                     for (int tw = 0; tw < TPW; ++tw)
 #pragma unroll
@@ -572,18 +627,8 @@ __global__ __launch_bounds__(512) void k_grp_bwd(StagedModel<float> m, const int
                 }
                 gput<T16, NCT>(xs[cb], w, l, wv);
                 __syncthreads();
-                const float Z = (zp[cb][sl][0] + zp[cb][sl][1]) + (zp[cb][sl][2] + zp[cb][sl][3]);
-                const float rz = 1.0f / Z;
-                const float gz = use ? rz : 0.f;
-                const float wz = (use && t > 0) ? fldexp(rz, exw - xt) : 0.f;
-#pragma unroll
-                for (int tw = 0; tw < TPW; ++tw) {
-                    *reinterpret_cast<float4 *>(&gst[cb][sl * EP + col0(tw)]) =
-                        make_float4(hv[tw][0] * gz, hv[tw][1] * gz, hv[tw][2] * gz, hv[tw][3] * gz);
-                    *reinterpret_cast<float4 *>(&wst[cb][sl * EP + col0(tw)]) =
-                        make_float4(wv[tw][0] * wz, wv[tw][1] * wz, wv[tw][2] * wz, wv[tw][3] * wz);
-                }
                 gproduct<T16, NCT>(xs[cb], l, aop, bt);
+                if (tau >= 2) copy_write(tau - 2);
                 if constexpr (!G::EXACT) {
                     // bf16: scaled by the exponent of the input's largest entry
                     // (the fp16 input was normalised, so its product already is)
@@ -595,83 +640,101 @@ __global__ __launch_bounds__(512) void k_grp_bwd(StagedModel<float> m, const int
                 }
             }
         }
-        __syncthreads();   // the last step's gamma and w' staged
+        copy_read(taul - 1);
+        copy_write(taul - 1);
+        __syncthreads();   // the last step's outputs staged
+        copy_read(taul);
+        copy_write(taul);
     } else {
         // ------------------------------------------------ load waves
         const int h = w - 4;
         LoadShare<NCT> sh;
         sh.init(offsets, nseq, g0, h, l);
-        // lane l also moves the exponents of sequence 4 h + l % 4
-        const int64_t sx = g0 + 4 * h + (l & 3);
-        const int64_t offx = sx < nseq ? offsets[sx] : 0;
-        const int Tx = sx < nseq ? (int)(offsets[sx + 1] - offx) : 0;
+        bool use[HK];
+#pragma unroll
+        for (int k = 0; k < HK; ++k) {
+            const int64_t s = g0 + (sh.lds[k] / EP);
+            use[k] = s < nseq && status[s] == 0;
+        }
         auto row = [&](int k, int s) { return sh.off[k] + (sh.T[k] > 0 ? max(sh.T[k] - 1 - s, 0) : 0); };
-        auto rowx = [&](int s) { return offx + (Tx > 0 ? max(Tx - 1 - s, 0) : 0); };
-        // gamma and w' of sweep step s from the staging buffers to HBM
-        auto store_step = [&](int s) {
+        float4 ra[R][HK], re[R][HK];
+        int rx[R][HK];
+        auto fill = [&](int slot, int s) {
 #pragma unroll
             for (int k = 0; k < HK; ++k) {
+                ra[slot][k] = gload4<VEC>(alpha, row(k, s), sh.col[k], N);
+                re[slot][k] = gload4<VEC>(etab, row(k, s), sh.col[k], N);
+                rx[slot][k] = aexp[row(k, s)];
+            }
+        };
+        // gamma and w' of sweep step s from ring slot `slot` and the staged b
+        auto outputs = [&](int slot, int s) {
+            float p[HK];
+            float4 b[HK];
+#pragma unroll
+            for (int k = 0; k < HK; ++k) {
+                b[k] = lds4(&bst[s & 1][sh.lds[k]]);
+                p[k] = 0.f;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) p[k] += f4at(ra[slot][k], i) * f4at(b[k], i);
+            }
+            // Z per row: a sum over the row's lane group
+#pragma unroll
+            for (int k = 0; k < HK; ++k) p[k] = group_sum<LPR>(p[k]);
+#pragma unroll
+            for (int k = 0; k < HK; ++k) {
+                const float rz = __builtin_amdgcn_rcpf(p[k]);
                 const int t = sh.T[k] - 1 - s;
-                if (t >= 0) {
-                    hstore4<VEC>(gamma, sh.off[k] + t, sh.col[k], N, lds4(&gst[s & 1][sh.lds[k]]));
-                    hstore4<VEC>(etab, sh.off[k] + t, sh.col[k], N, lds4(&wst[s & 1][sh.lds[k]]));
+                const float gz = use[k] ? rz : 0.f;
+                const float wz = (use[k] && t > 0) ? fldexp(rz, -rx[slot][k]) : 0.f;
+                {
+                    float4 g, wp;
+                    g.x = f4at(ra[slot][k], 0) * f4at(b[k], 0) * gz;
+                    g.y = f4at(ra[slot][k], 1) * f4at(b[k], 1) * gz;
+                    g.z = f4at(ra[slot][k], 2) * f4at(b[k], 2) * gz;
+                    g.w = f4at(ra[slot][k], 3) * f4at(b[k], 3) * gz;
+                    wp.x = f4at(re[slot][k], 0) * f4at(b[k], 0) * wz;
+                    wp.y = f4at(re[slot][k], 1) * f4at(b[k], 1) * wz;
+                    wp.z = f4at(re[slot][k], 2) * f4at(b[k], 2) * wz;
+                    wp.w = f4at(re[slot][k], 3) * f4at(b[k], 3) * wz;
+                    *reinterpret_cast<float4 *>(&gst[s & 1][sh.lds[k]]) = g;
+                    *reinterpret_cast<float4 *>(&wst[s & 1][sh.lds[k]]) = wp;
                 }
             }
         };
-        float4 ra[D][HK], re[D][HK];
-        int rx[D];
 #pragma unroll
-        for (int k = 0; k < HK; ++k) {
-            *reinterpret_cast<float4 *>(&as[0][sh.lds[k]]) = gload4<VEC>(alpha, row(k, 0), sh.col[k], N);
-            *reinterpret_cast<float4 *>(&es[0][sh.lds[k]]) = gload4<VEC>(etab, row(k, 0), sh.col[k], N);
-        }
-        {
-            const int x0 = aexp[rowx(0)];
-            if (l < 4) ax[0][4 * h + l] = x0;
-        }
-#pragma unroll
-        for (int j = 0; j < D; ++j) {
+        for (int s = 0; s < R - 1; ++s) {
             __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-            for (int k = 0; k < HK; ++k) {
-                ra[j][k] = gload4<VEC>(alpha, row(k, 1 + j), sh.col[k], N);
-                re[j][k] = gload4<VEC>(etab, row(k, 1 + j), sh.col[k], N);
-            }
-            rx[j] = aexp[rowx(1 + j)];
+            fill(s, s);
             __builtin_amdgcn_sched_barrier(0);
         }
-        __builtin_amdgcn_s_waitcnt(0);   // as in the forward sweep
-        __syncthreads();   // step 0 staged
-        for (int u0 = 0; u0 <= taul; u0 += D) {
+        // nothing in flight on entry to the loop, so that the compiler's count
+        // of loads outstanding at the top of a pass is the steady one
+        __builtin_amdgcn_s_waitcnt(0);
 #pragma unroll
-            for (int u = 0; u < D; ++u) {
+        for (int k = 0; k < HK; ++k) *reinterpret_cast<float4 *>(&es[0][sh.lds[k]]) = re[0][k];
+        __syncthreads();   // e of step 0 staged
+        for (int u0 = 0; u0 <= taul; u0 += R) {
+#pragma unroll
+            for (int u = 0; u < R; ++u) {
                 const int tau = u0 + u;
-                const int nb = (tau + 1) & 1;
-                // step tau + 1's rows (ring slot u) go to the buffers it reads;
-                // the slot is refilled with step tau + 1 + D; then the results of
-                // step tau - 2 (staged two barriers ago) are stored
+                // e of step tau + 1 goes to the buffer that step reads; the
+                // outputs of step tau - 1 are formed and stored; that slot is
+                // refilled with step tau - 1 + R
+                const int sn = (u + 1) % R, sp = (u + R - 1) % R;
 #pragma unroll
-                for (int k = 0; k < HK; ++k) {
-                    *reinterpret_cast<float4 *>(&as[nb][sh.lds[k]]) = ra[u][k];
-                    *reinterpret_cast<float4 *>(&es[nb][sh.lds[k]]) = re[u][k];
-                }
-                if (l < 4) ax[nb][4 * h + l] = rx[u];
+                for (int k = 0; k < HK; ++k)
+                    *reinterpret_cast<float4 *>(&es[(tau + 1) & 1][sh.lds[k]]) = re[sn][k];
+                if (tau >= 1) outputs(sp, tau - 1);
                 __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-                for (int k = 0; k < HK; ++k) {
-                    ra[u][k] = gload4<VEC>(alpha, row(k, tau + 1 + D), sh.col[k], N);
-                    re[u][k] = gload4<VEC>(etab, row(k, tau + 1 + D), sh.col[k], N);
-                }
-                rx[u] = aexp[rowx(tau + 1 + D)];
+                fill(sp, tau - 1 + R);
                 __builtin_amdgcn_sched_barrier(0);
-                if (tau >= 2) store_step(tau - 2);
                 if constexpr (G::EXACT) __syncthreads();
                 __syncthreads();
             }
         }
-        __syncthreads();   // the last step's gamma and w' staged
-        store_step(taul - 1);
-        store_step(taul);
+        outputs(R - 1, taul);   // taul = R n - 1; b staged before the last barrier
+        __syncthreads();        // the last step's outputs staged
     }
 }
 
@@ -690,7 +753,9 @@ static void launch_grp_t(bool fwd, const StagedModel<float> &m, const int64_t *o
         else
             hipLaunchKernelGGL((k_grp_fwd<T16, NCT, false>), grid, block, 0, s, m, offsets, nseq,
                                (const float *)etab, mt, alpha, aexp, loglik, status);
-    } else {
+        return;
+    }
+    if constexpr (64 % BwdCfg<NCT>::LPR == 0) {
         if (vec)
             hipLaunchKernelGGL((k_grp_bwd<T16, NCT, true>), grid, block, 0, s, m, offsets, nseq,
                                etab, (const float *)alpha, (const int32_t *)aexp,
@@ -713,8 +778,10 @@ static void launch_grp_nc(bool fwd, const StagedModel<float> &m, const int64_t *
         return launch_grp_t<T16, 64>(fwd, m, offsets, nseq, etab, mt, alpha, aexp, loglik, status, gamma, s);
     case 128:
         return launch_grp_t<T16, 128>(fwd, m, offsets, nseq, etab, mt, alpha, aexp, loglik, status, gamma, s);
-    case 192:
-        return launch_grp_t<T16, 192>(fwd, m, offsets, nseq, etab, mt, alpha, aexp, loglik, status, gamma, s);
+    case 192:   // the backward kernel needs a row's chunks in one lane group: 256
+        if (fwd)
+            return launch_grp_t<T16, 192>(fwd, m, offsets, nseq, etab, mt, alpha, aexp, loglik, status, gamma, s);
+        return launch_grp_t<T16, 256>(fwd, m, offsets, nseq, etab, mt, alpha, aexp, loglik, status, gamma, s);
     default:
         return launch_grp_t<T16, 256>(fwd, m, offsets, nseq, etab, mt, alpha, aexp, loglik, status, gamma, s);
     }
