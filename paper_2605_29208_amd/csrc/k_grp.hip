@@ -74,7 +74,7 @@ struct GMfma<_Float16> {
     }
 };
 
-constexpr int GS = 16;   // sequences per workgroup
+constexpr int GS = 16;   // sequence slots of the matrix-core operand
 
 template <int NCT>
 struct GCfg {
@@ -83,7 +83,15 @@ struct GCfg {
     static constexpr int KCH = NCT / 32;   // k-chunks of the 16x16x32 instruction
     static constexpr int XP = NCT + 8;     // LDS row pitch of an input vector (T16)
     static constexpr int EP = NCT + 4;     // LDS row pitch of a staged FP32 row
-    static constexpr int HK = NCT / 64;    // 16-byte chunks per load-wave lane, table and step
+    static constexpr int CPR = NCT / 4;    // 16-byte chunks of a row
+    // Rows (sequences) per load wave, one chunk per lane, and sequences per
+    // workgroup: 4 for N > 128, so that the rows a step moves are spread over
+    // a quarter as many sequences per compute unit (one compute unit's loads
+    // in flight cannot cover sixteen sequences' rows per step); the unused
+    // operand columns cost nothing, the product's issue time being the same.
+    static constexpr int RPH = CPR >= 64 ? 1 : 64 / CPR;
+    static constexpr int GSZ = 4 * RPH;
+    static constexpr int HK = 1;           // chunks per load-wave lane, table and step
     static constexpr int D = 4;            // steps between a load's issue and its staging
 };
 
@@ -249,28 +257,38 @@ __device__ __forceinline__ void gput(T16 *xs, int w, int l, const float (&x)[GCf
     }
 }
 
-// A load wave's share of the staging: its lane l moves, per table and step,
-// the 16-byte chunks q = 64 k + l (k < HK) of the four rows of sequences
-// 4 h .. 4 h + 3 (h = wave - 4): row r = q / (NCT / 4), column 4 (q % (NCT / 4)).
+// A load wave's share of the staging: its lane l < RPH CPR moves, per table
+// and step, chunk l % CPR (columns 4 (l % CPR) ..) of the row of sequence slot
+// h RPH + l / CPR (h = wave - 4); lanes past RPH CPR (N in (128, 192]) idle.
 template <int NCT>
 struct LoadShare {
     int64_t off[GCfg<NCT>::HK];
     int T[GCfg<NCT>::HK];
     int lds[GCfg<NCT>::HK];   // offset of the chunk in a staged table
     int col[GCfg<NCT>::HK];
+    bool act;
     __device__ void init(const int64_t *offsets, int64_t nseq, int64_t g0, int h, int l) {
-        constexpr int CPR = NCT / 4;
-#pragma unroll
-        for (int k = 0; k < GCfg<NCT>::HK; ++k) {
-            const int q = 64 * k + l, r = q / CPR;
-            col[k] = 4 * (q % CPR);
-            lds[k] = (4 * h + r) * GCfg<NCT>::EP + col[k];
-            const int64_t s = g0 + 4 * h + r;
-            off[k] = s < nseq ? offsets[s] : 0;
-            T[k] = s < nseq ? (int)(offsets[s + 1] - off[k]) : 0;
-        }
+        using C = GCfg<NCT>;
+        act = l < C::RPH * C::CPR;
+        const int r = act ? l / C::CPR : 0;
+        col[0] = act ? 4 * (l % C::CPR) : 0;
+        const int slot = h * C::RPH + r;
+        lds[0] = slot * C::EP + col[0];
+        const int64_t s = g0 + slot;
+        const bool v = act && s < nseq;
+        off[0] = v ? offsets[s] : 0;
+        T[0] = v ? (int)(offsets[s + 1] - off[0]) : 0;
     }
 };
+
+// zero the staged emission rows of the operand's unused sequence slots, so
+// that their columns stay finite (compute waves, before the first barrier)
+template <int NCT>
+__device__ __forceinline__ void zero_unused_rows(float (&es)[2][GS * GCfg<NCT>::EP], int tid) {
+    using C = GCfg<NCT>;
+    constexpr int n = (GS - C::GSZ) * C::EP;
+    for (int i = tid; i < 2 * n; i += 256) es[i / n][C::GSZ * C::EP + i % n] = 0.f;
+}
 
 // ---------------------------------------------------------------- forward
 template <typename T16, int NCT, bool VEC>
@@ -293,10 +311,10 @@ __global__ __launch_bounds__(512) void k_grp_fwd(StagedModel<float> m, const int
     __shared__ double ls[GS][4];
     const int N = m.N, tid = threadIdx.x, l = tid & 63;
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int64_t g0 = (int64_t)blockIdx.x * GS;
+    const int64_t g0 = (int64_t)blockIdx.x * C::GSZ;
     const int sl = l & 15, ig = l >> 4;
     const int64_t sidx = g0 + sl;
-    const bool sv = sidx < nseq;
+    const bool sv = sl < C::GSZ && sidx < nseq;
     const int64_t off = sv ? offsets[sidx] : 0;
     const int T = sv ? (int)(offsets[sidx + 1] - off) : 0;
     const int Tg = __builtin_amdgcn_readfirstlane(wave_max_i(T));   // the group's longest
@@ -309,6 +327,7 @@ __global__ __launch_bounds__(512) void k_grp_fwd(StagedModel<float> m, const int
         // ------------------------------------------------ compute waves
         typename G::V8 aop[TPW][C::KCH];
         gload_aop<T16, NCT>(m.AT, N, w, l, aop);
+        zero_unused_rows<NCT>(es, tid);
         float x[TPW][4];
         auto stage = [&](int b, int ex) {
 #pragma unroll
@@ -461,8 +480,8 @@ __global__ __launch_bounds__(512) void k_grp_fwd(StagedModel<float> m, const int
         const int h = w - 4;
         LoadShare<NCT> sh;
         sh.init(offsets, nseq, g0, h, l);
-        // lane l also moves the exponents of sequence 4 h + l % 4
-        const int64_t sx = g0 + 4 * h + (l & 3);
+        // lane l < RPH also stores the exponents of sequence slot h RPH + l
+        const int64_t sx = g0 + h * C::RPH + (l % C::RPH);
         const int64_t offx = sx < nseq ? offsets[sx] : 0;
         const int Tx = sx < nseq ? (int)(offsets[sx + 1] - offx) : 0;
         auto row = [&](int k, int s) { return sh.off[k] + (sh.T[k] > 0 ? min(s, sh.T[k] - 1) : 0); };
@@ -472,13 +491,17 @@ __global__ __launch_bounds__(512) void k_grp_fwd(StagedModel<float> m, const int
             for (int k = 0; k < HK; ++k)
                 if (s < sh.T[k])
                     hstore4<VEC>(alpha, sh.off[k] + s, sh.col[k], N, lds4(&ast[s & 1][sh.lds[k]]));
-            if (l < 4 && s < Tx) aexp[offx + s] = axs[s & 1][4 * h + l];
+            if (l < C::RPH && s < Tx) aexp[offx + s] = axs[s & 1][h * C::RPH + l];
         };
         float4 ring[D][HK];
 #pragma unroll
         for (int k = 0; k < HK; ++k) {
-            *reinterpret_cast<float4 *>(&es[0][sh.lds[k]]) = gload4<VEC>(etab, row(k, 0), sh.col[k], N);
-            *reinterpret_cast<float4 *>(&es[1][sh.lds[k]]) = gload4<VEC>(etab, row(k, 1), sh.col[k], N);
+            const float4 e0 = gload4<VEC>(etab, row(k, 0), sh.col[k], N);
+            const float4 e1 = gload4<VEC>(etab, row(k, 1), sh.col[k], N);
+            if (sh.act) {
+                *reinterpret_cast<float4 *>(&es[0][sh.lds[k]]) = e0;
+                *reinterpret_cast<float4 *>(&es[1][sh.lds[k]]) = e1;
+            }
         }
 #pragma unroll
         for (int j = 0; j < D; ++j) {
@@ -501,7 +524,7 @@ __global__ __launch_bounds__(512) void k_grp_fwd(StagedModel<float> m, const int
                 // the slot is refilled with e_{t+1+D}; then step t - 1 is stored
 #pragma unroll
                 for (int k = 0; k < HK; ++k)
-                    *reinterpret_cast<float4 *>(&es[(t + 1) & 1][sh.lds[k]]) = ring[u][k];
+                    if (sh.act) *reinterpret_cast<float4 *>(&es[(t + 1) & 1][sh.lds[k]]) = ring[u][k];
                 __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
                 for (int k = 0; k < HK; ++k) ring[u][k] = gload4<VEC>(etab, row(k, t + 1 + D), sh.col[k], N);
@@ -551,11 +574,11 @@ __global__ __launch_bounds__(512) void k_grp_bwd(StagedModel<float> m, const int
     __shared__ uint32_t gm[2][GS][4];
     const int N = m.N, tid = threadIdx.x, l = tid & 63;
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int64_t g0 = (int64_t)blockIdx.x * GS;
+    const int64_t g0 = (int64_t)blockIdx.x * C::GSZ;
     int Tl = 0;
     {
         const int64_t s = g0 + (l & 15);
-        if (s < nseq) Tl = (int)(offsets[s + 1] - offsets[s]);
+        if ((l & 15) < C::GSZ && s < nseq) Tl = (int)(offsets[s + 1] - offsets[s]);
     }
     const int Tg = __builtin_amdgcn_readfirstlane(wave_max_i(Tl));
     const int taul = R * ((Tg + R - 1) / R) - 1;   // last step of the whole passes
@@ -566,6 +589,7 @@ __global__ __launch_bounds__(512) void k_grp_bwd(StagedModel<float> m, const int
         auto col0 = [&](int tw) { return 16 * (w + 4 * tw) + 4 * ig; };
         typename G::V8 aop[TPW][C::KCH];
         gload_aop<T16, NCT>(m.A, N, w, l, aop);
+        zero_unused_rows<NCT>(es, tid);
         // gamma and w' of sweep step s for the wave's four sequences, from LDS
         // to HBM in whole rows
         LoadShare<NCT> cp;
@@ -654,7 +678,7 @@ __global__ __launch_bounds__(512) void k_grp_bwd(StagedModel<float> m, const int
 #pragma unroll
         for (int k = 0; k < HK; ++k) {
             const int64_t s = g0 + (sh.lds[k] / EP);
-            use[k] = s < nseq && status[s] == 0;
+            use[k] = sh.T[k] > 0 && status[s] == 0;
         }
         auto row = [&](int k, int s) { return sh.off[k] + (sh.T[k] > 0 ? max(sh.T[k] - 1 - s, 0) : 0); };
         float4 ra[R][HK], re[R][HK];
@@ -687,7 +711,7 @@ __global__ __launch_bounds__(512) void k_grp_bwd(StagedModel<float> m, const int
                 const int t = sh.T[k] - 1 - s;
                 const float gz = use[k] ? rz : 0.f;
                 const float wz = (use[k] && t > 0) ? fldexp(rz, -rx[slot][k]) : 0.f;
-                {
+                if (sh.act) {
                     float4 g, wp;
                     g.x = f4at(ra[slot][k], 0) * f4at(b[k], 0) * gz;
                     g.y = f4at(ra[slot][k], 1) * f4at(b[k], 1) * gz;
@@ -712,7 +736,8 @@ __global__ __launch_bounds__(512) void k_grp_bwd(StagedModel<float> m, const int
         // of loads outstanding at the top of a pass is the steady one
         __builtin_amdgcn_s_waitcnt(0);
 #pragma unroll
-        for (int k = 0; k < HK; ++k) *reinterpret_cast<float4 *>(&es[0][sh.lds[k]]) = re[0][k];
+        for (int k = 0; k < HK; ++k)
+            if (sh.act) *reinterpret_cast<float4 *>(&es[0][sh.lds[k]]) = re[0][k];
         __syncthreads();   // e of step 0 staged
         for (int u0 = 0; u0 <= taul; u0 += R) {
 #pragma unroll
@@ -724,7 +749,7 @@ __global__ __launch_bounds__(512) void k_grp_bwd(StagedModel<float> m, const int
                 const int sn = (u + 1) % R, sp = (u + R - 1) % R;
 #pragma unroll
                 for (int k = 0; k < HK; ++k)
-                    *reinterpret_cast<float4 *>(&es[(tau + 1) & 1][sh.lds[k]]) = re[sn][k];
+                    if (sh.act) *reinterpret_cast<float4 *>(&es[(tau + 1) & 1][sh.lds[k]]) = re[sn][k];
                 if (tau >= 1) outputs(sp, tau - 1);
                 __builtin_amdgcn_sched_barrier(0);
                 fill(sp, tau - 1 + R);
@@ -743,7 +768,7 @@ static void launch_grp_t(bool fwd, const StagedModel<float> &m, const int64_t *o
                          int64_t nseq, float *etab, const double *mt, float *alpha,
                          int32_t *aexp, double *loglik, int32_t *status, float *gamma,
                          hipStream_t s) {
-    const dim3 grid((unsigned)((nseq + GS - 1) / GS));
+    const dim3 grid((unsigned)((nseq + GCfg<NCT>::GSZ - 1) / GCfg<NCT>::GSZ));
     const dim3 block(GCfg<NCT>::NT);
     const bool vec = m.N % 4 == 0;
     if (fwd) {

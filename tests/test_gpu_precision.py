@@ -110,3 +110,38 @@ def test_scaled_many_groups(h, prec, n):
     assert e_ll <= b_ll and e_g <= b_g
     assert max(e_s.values()) <= b_s
     assert np.allclose(g.sum(axis=1), 1.0, atol=1e-5)
+
+
+@pytest.mark.parametrize("prec", ["bf16_scaled", "f16_scaled"])
+def test_scaled_status_codes_and_exclusion(h, prec):
+    """A non-finite observation (status 2) and one outside the Gamma support
+    (status 1) inside one group of the scaled sweeps: those two sequences
+    get zero posteriors and add nothing to the statistics; the other two
+    meet the format's bounds."""
+    import torch
+    w = workloads.random_workload("gamma", 80, 1, [50, 60, 70, 33], 860)
+    obs = w.obs.copy()
+    obs[w.offsets[1] + 5] = np.nan
+    obs[w.offsets[2] + 40] = -1.0
+    dm = h.DeviceModel.from_model(w.model)
+    db = h.DeviceBatch(obs, w.offsets, dtype=np.float32)
+    stats, ll, st = h.estep_stats(dm, db, prec)
+    llg, gam, st2 = h.forward_backward(dm, db, prec)
+    torch.cuda.synchronize()
+    ref = oracle.estep(w.model, w.offsets, obs, want_gamma=True)
+    assert list(st.cpu().numpy()) == list(st2.cpu().numpy()) == list(ref["status"]) == [0, 2, 1, 0]
+    ll = ll.cpu().numpy()
+    assert ll[2] == -np.inf and np.isnan(ll[1])
+    b_ll, b_g, b_s = BOUNDS[prec]
+    ok = [0, 3]
+    rl = ref["loglik"][ok]
+    assert np.max(np.abs(ll[ok] - rl) / np.abs(rl)) <= b_ll
+    g = gam.cpu().numpy().astype(np.float64)
+    o = w.offsets
+    assert not g[o[1]:o[3]].any()
+    rows = np.r_[o[0]:o[1], o[3]:o[4]]
+    assert np.max(np.abs(g[rows] - ref["gamma"][rows])) <= b_g
+    s, rs = stats.cpu().numpy(), ref["stats"]
+    n = w.model.n_states
+    for sl in (slice(1, 1 + n), slice(1 + n, 1 + n + n * n), slice(1 + n + n * n, 1 + 2 * n + n * n)):
+        assert np.max(np.abs(s[sl] - rs[sl])) <= b_s * max(np.max(np.abs(rs[sl])), 1e-300)
