@@ -1,14 +1,15 @@
-// k_grp.hip -- the scaled bf16/fp16 sweeps of the large-state path, sixteen
+// k_grp.hip -- the scaled bf16/fp16 sweeps of the large-state path, several
 // sequences per workgroup on the matrix cores.
 //
 // The scaled alternative to log-space (section 3.2) multiplies normalised
 // vectors by A in a narrow format with FP32 accumulation and rescales by
 // powers of two.  One vector per sequence fills only one row of a 16-row
-// MFMA operand, so a workgroup steps sixteen sequences together and takes
-// the transposed product
+// MFMA operand, so a workgroup steps several sequences together (GSZ: 4 for
+// N > 128, 8 for N <= 128, 16 for N <= 64) and takes the transposed product
 //     D[c][s] = sum_k Mop[c][k] x_s[k]     (v_mfma_f32_16x16x32_{bf16,f16})
 // with the matrix as operand A (Mop[c][k] = a_kc forward, a_ck backward, in
-// registers) and the sixteen input vectors as operand B (from LDS).  Operand
+// registers) and the input vectors as operand B (from LDS; the columns of
+// unused slots are zero).  Operand
 // layout (lane l): A row l % 16, k = 8 (l / 16) + q; B column l % 16, same k;
 // result column l % 16, rows 4 (l / 16) + i.  So lane l of compute wave w owns
 // sequence slot l % 16 and, in each of its TPW tiles of 16 output states, the
@@ -17,7 +18,7 @@
 // exchange across the four compute waves.
 //
 // The workgroup is split by role, four compute waves (0-3) and four load
-// waves (4-7), each load wave serving four of the sequences.  The two roles
+// waves (4-7), each load wave serving a quarter of the group.  The two roles
 // run separate loops with the same number of barriers per step (the hardware
 // barrier counts waves, not code sites), so neither role's registers are held
 // while the other role's code runs.  A load wave keeps a register ring of the
@@ -37,7 +38,7 @@
 // 5-bit exponent, so each vector is normalised exactly (largest entry in
 // [1/2, 1)) before it is rounded, at the cost of a second barrier per step.
 //
-// The sixteen sequences of a group are consecutive in the batch and step in
+// The sequences of a group are consecutive in the batch and step in
 // lockstep for the group's longest length, in whole passes of a few steps; a
 // shorter member keeps computing on clamped rows (finite values in its own
 // column only) and stores nothing after its end (forward) or before its
@@ -219,7 +220,7 @@ __device__ __forceinline__ void gload_aop(const float *M, int N, int w, int l,
     }
 }
 
-// D = Mop x for the wave's tiles, x = the sixteen input vectors in xs
+// D = Mop x for the wave's tiles, x = the sixteen operand columns in xs
 template <typename T16, int NCT>
 __device__ __forceinline__ void gproduct(const T16 *xs, int l,
                                          const typename GMfma<T16>::V8 (&aop)[GCfg<NCT>::TPW][GCfg<NCT>::KCH],
