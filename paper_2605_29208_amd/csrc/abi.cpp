@@ -316,9 +316,14 @@ hmm_status make_plan(hmm_op op, const Checked &c, hmm_precision prec, Plan *p, i
     } else {
         const bool scalar = c.fam <= HMM_POISSON || c.fam == HMM_TABLE;
         p->mfma = prec == HMM_PREC_BF16_SCALED ? 1 : (prec == HMM_PREC_F16_SCALED ? 2 : 0);
-        const bool mvw = !scalar && N <= 64 && !p->mfma &&
+        // FP64 with 32 < N <= 64 takes the one-workgroup-per-sequence path: the
+        // wave path's statistics kernel would hold both A's column and row and
+        // the 64 xi accumulators in FP64 per lane, more than the register file
+        // (measured 1.6-1.8x slower on 256 sequences of 500-3000 steps)
+        const bool f64big = p->f64 && N > 32;
+        const bool mvw = !scalar && N <= 64 && !p->mfma && !f64big &&
                          (c.fam == HMM_DIAG_GAUSSIAN || c.fam == HMM_FULL_GAUSSIAN);
-        if (!mvw && (!scalar || N > 64 || p->mfma)) {
+        if (!mvw && (!scalar || N > 64 || p->mfma || f64big)) {
             // one workgroup per sequence, emission table, xi by a matrix-core contraction
             if (N > 256)
                 return fail(HMM_ERR_UNSUPPORTED,

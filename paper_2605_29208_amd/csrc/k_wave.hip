@@ -747,7 +747,9 @@ hmm_status run_wave(const StagedModel<R> &m, const ObsDesc &o, const WaveBuffers
     case 32:
         return run_wave_fam<R, 32>(m, o, wb, loglik, status, (R *)gamma_out, stats, S, s);
     default:
-        return run_wave_fam<R, 64>(m, o, wb, loglik, status, (R *)gamma_out, stats, S, s);
+        // FP64 with N > 32 is planned onto the large-state path instead
+        if constexpr (sizeof(R) == 8) return HMM_ERR_UNSUPPORTED;
+        else return run_wave_fam<R, 64>(m, o, wb, loglik, status, (R *)gamma_out, stats, S, s);
     }
 }
 
