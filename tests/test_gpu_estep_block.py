@@ -254,3 +254,54 @@ def test_config4a_full_size(h):
     s64, ll64, _ = run_estep(h, w, "f64")
     assert_loglik_close(ll, ll64, TOL["f32"], "config4a f32 vs f64")
     assert_stats_close(stats, s64, N, "full", TOL["f32"], "config4a f32 vs f64", d=32)
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64", "bf16_scaled"])
+def test_block_estep_in_hip_graph_fresh_thread(h, prec):
+    """A large-state E-step captured in a HIP graph from a host thread that
+    never called the library before: nothing in the call allocates or sets
+    itself up lazily, and every replay (with eager work and synchronisation
+    between replays) equals the eager call bit for bit."""
+    import threading
+    import torch
+    w = workloads.random_workload("gaussian", 100, 1, [300, 1000, 77, 1, 500], 880)
+    dm = h.DeviceModel.from_model(w.model)
+    db = h.DeviceBatch(w.obs, w.offsets, dtype=np.float64 if prec == "f64" else np.float32)
+    S = h.hmm_stats_len(dm)
+    stats = torch.zeros(S, dtype=torch.float64, device="cuda")
+    ll = torch.empty(w.n_seq, dtype=torch.float64, device="cuda")
+    st = torch.empty(w.n_seq, dtype=torch.int32, device="cuda")
+    ws = h._ws(h.hmm_workspace_size("estep", dm, db, prec))
+    h.hmm_estep_stats(dm, db, prec, stats, ll, st, ws)
+    torch.cuda.synchronize()
+    eager = (stats.clone(), ll.clone(), st.clone())
+    assert (st.cpu().numpy() == 0).all()
+    out = {}
+
+    def capture_and_replay():
+        try:
+            g = torch.cuda.CUDAGraph()
+            side = torch.cuda.Stream()
+            side.wait_stream(torch.cuda.current_stream())
+            torch.cuda.synchronize()
+            with torch.cuda.graph(g, stream=side):
+                h.hmm_estep_stats(dm, db, prec, stats, ll, st, ws)
+            for rep in range(3):
+                stats.zero_()
+                ll.zero_()
+                torch.cuda.synchronize()
+                g.replay()
+                torch.cuda.synchronize()
+                assert torch.equal(stats, eager[0]) and torch.equal(ll, eager[1]), rep
+                assert torch.equal(st, eager[2]), rep
+                _ = (stats * 2).sum().item()   # eager work between replays
+            out["ok"] = True
+        except BaseException as e:   # reported in the test's own thread
+            out["err"] = e
+
+    t = threading.Thread(target=capture_and_replay)
+    t.start()
+    t.join()
+    if "err" in out:
+        raise out["err"]
+    assert out.get("ok")

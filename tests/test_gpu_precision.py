@@ -23,7 +23,7 @@ pytestmark = pytest.mark.gpu
 # bounds per format: (log-likelihood relative, gamma absolute, statistics
 # relative to their natural scale)
 BOUNDS = {"bf16_scaled": (2e-3, 0.08, 0.05), "f16_scaled": (3e-4, 0.02, 0.01),
-          "f32": (1e-4, 1e-4, 1e-4)}
+          "f32": (1e-4, 1e-4, 1e-4), "f64": (1e-10, 1e-9, 1e-9)}
 
 
 @pytest.fixture(scope="module")
@@ -37,7 +37,7 @@ def h():
 def errors(h, w, prec):
     import torch
     dm = h.DeviceModel.from_model(w.model)
-    db = h.DeviceBatch(w.obs, w.offsets, dtype=np.float32)
+    db = h.DeviceBatch(w.obs, w.offsets, dtype=np.float64 if prec == "f64" else np.float32)
     stats, ll, st = h.estep_stats(dm, db, prec)
     llg, gam, _ = h.forward_backward(dm, db, prec)
     torch.cuda.synchronize()
@@ -84,9 +84,7 @@ def test_config3_precision_study(h):
     every precision's error against the oracle, printed side by side."""
     w = workloads.config3(n_seq=3)
     for prec in ("f64", "f32", "bf16_scaled", "f16_scaled"):
-        e_ll, e_g, e_s, _, _ = errors(h, w, prec) if prec != "f64" else (None,) * 5
-        if prec == "f64":
-            continue
+        e_ll, e_g, e_s, _, _ = errors(h, w, prec)
         print(f"\n[precision] config3 {prec:12s}: loglik rel {e_ll:.2e}, gamma abs {e_g:.2e}, "
               "stats rel " + ", ".join(f"{k} {v:.2e}" for k, v in e_s.items()))
         b_ll, b_g, b_s = BOUNDS[prec]
