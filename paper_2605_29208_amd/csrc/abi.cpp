@@ -128,6 +128,7 @@ struct Plan {
     int route = 0;      // ROUTE_* of the batched path taken
     int variant = 0;    // tuned variant of that route
     size_t lt = 0, fpart = 0, red2 = 0;
+    size_t lsc = 0, segJ = 0, seginc = 0, segbad = 0, segver = 0, seglim = 0;
     size_t total = 0;
 };
 
@@ -137,7 +138,9 @@ struct Plan {
 //   chunked N <= 8: chunk length 16, 32 or 64 steps (FP64: 16 or 32);
 //   large-state:    slices of the transition contraction, nominal, half or
 //                   double (the split of its row dimension over workgroups);
-//   wave, plain:    one variant.
+//   wave:           sweep segments of 1024 steps, whole sequences, 512 or
+//                   2048 steps;
+//   plain:          one variant.
 // hmm_autotune times every variant of a call's route on the caller's data and
 // keeps the fastest for the call's key; HMM_FORCE_VARIANT (environment) or
 // hmm_set_variant forces one.  The key is the device architecture, family,
@@ -149,6 +152,7 @@ enum { ROUTE_PLAIN = 0, ROUTE_CHUNK = 1, ROUTE_WAVE = 2, ROUTE_BLOCK = 3 };
 int route_variants(int route, bool f64) {
     if (route == ROUTE_CHUNK) return f64 ? 2 : 3;
     if (route == ROUTE_BLOCK) return 3;
+    if (route == ROUTE_WAVE) return 4;
     return 1;
 }
 
@@ -365,15 +369,29 @@ hmm_status make_plan(hmm_op op, const Checked &c, hmm_precision prec, Plan *p, i
             p->wave = true;
             p->route = ROUTE_WAVE;
             p->L = WAVE_L;
-            int64_t C = 0;
-            for (int64_t b = 0; b < c.B; ++b) C += (c.h_off[b + 1] - c.h_off[b] + WAVE_L - 1) / WAVE_L;
+            p->variant = variant >= 0 ? variant : resolve_variant(c, prec, ROUTE_WAVE);
+            p->SS = wave_seg_chunks(p->variant);
+            int64_t C = 0, SC = 0;
+            for (int64_t b = 0; b < c.B; ++b) {
+                const int64_t nc = (c.h_off[b + 1] - c.h_off[b] + WAVE_L - 1) / WAVE_L;
+                C += nc;
+                SC += (nc + p->SS - 1) / p->SS;
+            }
             if (C > INT32_MAX / 64) return fail(HMM_ERR_UNSUPPORTED, "too many chunks");
             p->C = (int)C;
+            p->SC = (int)SC;
             p->nblk = wave_stats_blocks((int)C, N);
             const int np = wave_np(N);
             p->cbase = take((size_t)(c.B + 1) * 4);
             p->sbase = take((size_t)(c.B + 1) * 4);
             p->cdesc = take((size_t)C * sizeof(ChunkDesc));
+            p->sdesc = take((size_t)SC * sizeof(SuperDesc));
+            p->lsc = take((size_t)C * 8);
+            p->segJ = take((size_t)SC * 8);
+            p->seginc = take((size_t)SC * 8);
+            p->segbad = take((size_t)SC * 4);
+            p->segver = take((size_t)SC * 8);
+            p->seglim = take((size_t)SC * 8);
             p->F = take((size_t)C * np * r);
             p->Gb = take((size_t)C * np * r);
             p->partial = take((size_t)p->nblk * p->S * 8);
@@ -497,8 +515,20 @@ hmm_status run_posterior_path(const hmm_model *m, const hmm_batch *b, const Chec
         wb.partial = (double *)(ws + p.partial);
         wb.red = (double *)(ws + p.red);
         int *sbase = (int *)(ws + p.sbase);
-        launch_plan_chunks(b->offsets, c.B, p.L, 1, wb.cbase, sbase, s);
-        launch_chunk_desc(b->offsets, c.B, p.L, 1, wb.cbase, sbase, p.C, 0, wb.cdesc, nullptr, s);
+        SuperDesc *sdesc = (SuperDesc *)(ws + p.sdesc);
+        wb.SC = p.SC;
+        wb.vmax = WAVE_VMAX;
+        wb.sbase = sbase;
+        wb.sdesc = sdesc;
+        wb.lsc = (double *)(ws + p.lsc);
+        wb.segJ = (double *)(ws + p.segJ);
+        wb.seginc = (double *)(ws + p.seginc);
+        wb.segbad = (int32_t *)(ws + p.segbad);
+        wb.segver = (int32_t *)(ws + p.segver);
+        wb.seglim = (int32_t *)(ws + p.seglim);
+        launch_plan_chunks(b->offsets, c.B, p.L, p.SS, wb.cbase, sbase, s);
+        launch_chunk_desc(b->offsets, c.B, p.L, p.SS, wb.cbase, sbase, p.C, p.SC, wb.cdesc, sdesc,
+                          s);
         if (p.mvw) {
             MvBuffers mb;
             mb.total = c.total;

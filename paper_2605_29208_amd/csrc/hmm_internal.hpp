@@ -135,8 +135,20 @@ struct WaveBuffers {
     void *Gb;            // [C*NP] R  beta at each chunk end (normalised)
     double *partial;     // [nblk * S]
     double *red;         // reduction scratch (reduce_scratch_len doubles)
+    // sweep segments (superchunks of seg_chunks chunks; SC == B: none split)
+    int SC, vmax;        // segments, chunks a second sweep may run
+    const int *sbase;    // [B+1] segments before each sequence
+    const SuperDesc *sdesc;   // [SC]
+    double *lsc;         // [C]   forward log scale at each chunk end
+    double *segJ;        // [SC]  log sum of each segment's forward end vector
+    double *seginc;      // [SC]  forward log-likelihood increment
+    int32_t *segbad;     // [SC]  invalid emission values
+    int32_t *segver;     // [2SC] second sweep agreed (forward, backward)
+    int32_t *seglim;     // [2SC] first chunk / last slot still from the first sweep
 };
 constexpr int WAVE_L = 32;          // chunk length of the wave path
+constexpr int WAVE_VMAX = 24;       // chunks a second sweep of a segment may run
+int wave_seg_chunks(int variant);   // chunks per sweep segment of a wave-route variant
 int wave_np(int N);                 // lanes per group = padded state count (16, 32 or 64)
 int wave_stats_blocks(int C, int N);   // blocks (= partial rows) of the statistics kernel
 template <typename R>

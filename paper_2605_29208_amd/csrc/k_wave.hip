@@ -296,114 +296,174 @@ __device__ __forceinline__ double add_quarters(double x) {
     return add_halves(a + b);
 }
 
-// Task 2b is the forward sweep of sequence b (alpha at chunk ends, logL and
-// status), task 2b + 1 its backward sweep (beta at chunk ends), one task per
-// wave.  SPL = 64 / NP lanes per state: for NP = 32 half h of the lanes takes
-// rows h NP/2 .. of the vector-matrix product and the halves are added across
-// the wave, which halves the dependent chain of the step; SPL = 4 does the
-// same with four lanes per state for NP = 16.
-template <typename R, int NP, int FAM, int SPL>
-__global__ __launch_bounds__(64) void k_wave_sweep(WaveGeom g, StagedModel<R> m, R *__restrict__ F,
-                                                   R *__restrict__ Gb, double *__restrict__ loglik,
-                                                   int32_t *__restrict__ status) {
-    static_assert(NP * SPL == 64, "one task per wave");
-    constexpr int LPT = NP * SPL;   // lanes per task
-    constexpr int NG = 64 / LPT;    // tasks per wave (one)
-    constexpr int RPL = NP / SPL;   // rows of the product per lane
-    constexpr int VS = NP + 4;
-    // a window of the emission table holds two chunks
-    __shared__ R esh[NG][2 * WL][NP + 1];
-    __shared__ __align__(16) R vsh[NG][VS];
-    using ET = typename EmitTraits<FAM, R>::T;
-    const ET *ep = consts_ptr<FAM, R>(m);
-    const int lane = threadIdx.x;
-    const int grp = lane / LPT, sl = lane % LPT, j = sl % NP, h = sl / NP;
-    const int64_t task = (int64_t)blockIdx.x * NG + grp;
-    const bool tv = task < 2 * g.nseq;
-    const int64_t b = tv ? (task >> 1) : 0;
-    // one task per wave: the direction is uniform, so its branches are scalar
-    const bool fwd = __builtin_amdgcn_readfirstlane((int)((task & 1) == 0)) != 0;
-    const int N = m.N;
-    const bool live = j < N;
-    const int64_t off = g.offsets[b];
-    int T = tv ? (int)(g.offsets[b + 1] - off) : 0;
-    int cb = g.cbase[b];
-    // uniform per wave: keep the loop control scalar
-    T = __builtin_amdgcn_readfirstlane(T);
-    cb = __builtin_amdgcn_readfirstlane(cb);
-    const int nc = (T + WL - 1) / WL;
-    // the lane's column (forward) or row (backward) of A: clamped loads, all
-    // in flight before the masking
-    R coef[RPL];
-#pragma unroll
-    for (int r = 0; r < RPL; ++r) {
-        const int i = min(h * RPL + r, N - 1), jj = min(j, N - 1);
-        coef[r] = fwd ? m.A[i * N + jj] : m.A[jj * N + i];
-    }
-    __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-    for (int r = 0; r < RPL; ++r) coef[r] = (live && h * RPL + r < N) ? coef[r] : (R)0;
-    bool bad = false;
-    const int nrm = *m.nrm;   // steps between rescalings (both directions)
-    R v = (tv && live) ? (R)1 : (R)0;   // running alpha (forward) or beta (backward)
-    double logS = 0.0;
-    int64_t E = 0;
-    if (tv && !fwd && h == 0) Gb[(size_t)(cb + nc - 1) * NP + j] = v;
+// ---------------------------------------------------------------- segmented sweeps
+// A sequence is cut into segments of whole windows (a fixed number of chunks;
+// one segment when it is not split), and each (segment, direction) is swept
+// by its own wave, so a sweep's serial chain is one segment long.  The vector
+// entering a segment is not known when its sweep starts, so there are three
+// launches:
+//   1. every segment is swept from a vector of ones (the first segment's
+//      forward from pi and the last one's backward from beta_{T-1} = 1, both
+//      exact), storing its boundary vectors, and the forward its log scale at
+//      each chunk end and the log of its end vector's sum;
+//   2. every segment is swept again, from the vector that launch 1 stored for
+//      its neighbour (the previous segment's last alpha, the next segment's
+//      first beta), re-storing its boundaries until its vector agrees with
+//      the stored one at a chunk boundary: entrywise within a relative 2^-16
+//      (FP32) or 2^-40 (FP64) once scaled by the ratio of the sums, zero
+//      entries in the same places.  From
+//      there on the stored vectors are those of a sweep from that start, to
+//      the same relative distance, since a nonnegative matrix never
+//      increases the projective (Hilbert) distance of two vectors;
+//   3. one wave per sequence and direction walks its segments in order,
+//      re-running from the true entering vector every segment whose second
+//      sweep found no agreement or started from a vector that was itself
+//      re-run without agreement, and adds up the forward's log-likelihood
+//      increments.
+// A mixing chain forgets its start within a few hundred steps, so launch 2
+// stops early and launch 3 only adds; a chain that does not is re-run segment
+// by segment, which is the unsplit sweep's own serial cost.  The second sweep
+// never runs its segment's last chunk (forward) or first chunk (backward):
+// those boundaries are the entering vectors its neighbours read.
+//
+// Log-likelihood increment of a segment entered with w: log sum(M w) -
+// log sum(w), M the product of its steps.  Launch 1 keeps J = log sum(M 1)
+// and the log scale l1(c) of each chunk end (the stored vector times e^l1 is
+// the unnormalised one).  A sweep from w that agrees at chunk c, with log
+// scale l(c) and sum ratio rho, has M w = rho e^{l(c) - l1(c)} M 1, so its
+// increment is log rho + l(c) - l1(c) + J - log sum(w).
 
-    // One task per wave: the direction, the length and the step are
-    // uniform, so the loops below have scalar control.  A window is two
-    // chunks (64 steps, one step per lane for the emission table), and the
-    // observations of the next window are loaded into registers while the
-    // current one runs, so the table of a window waits on no memory.
-    // Rescaling points and stored boundaries are those of one-chunk
-    // windows: forward after steps t = nrm - 1 (mod nrm), the last step and
-    // t = 0, boundary at every chunk end; backward after the steps whose
-    // distance to their chunk's end is nrm - 1 (mod nrm) and at the chunk's
-    // first step, boundary beta at the end of the previous chunk.
-    constexpr int WW = 2 * WL;
-    static_assert(WW == LPT, "one window step per lane");
-    const int nw = (T + WW - 1) / WW;
-    // window k covers steps [lo, hi); the backward skips chunk 0
-    auto wlo = [&](int k) { return fwd ? k * WW : max(k * WW, WL); };
-    auto whi = [&](int k) { return min(T, k * WW + WW); };
-    const int k0 = fwd ? 0 : nw - 1, kstep = fwd ? 1 : -1;
-    const int kend = fwd ? nw : -1;
-    StepObs<R, NP, FAM> pre;
-    if (k0 != kend && wlo(k0) < whi(k0))
-        pre = load_step_obs<R, NP, FAM>(g, N, off + min(wlo(k0) + sl, whi(k0) - 1));
-    for (int k = k0; k != kend; k += kstep) {
-        const int lo = wlo(k), hi = whi(k), wn = hi - lo;
-        if (wn <= 0) continue;
-        __syncthreads();
-        double msum = 0.0;
-        if (sl < wn) {
-            R y, ly;
-            msum = tab_step_obs<R, NP, FAM>(pre, N, ep, &esh[0][sl][0], &y, &ly, &bad);
+template <typename R>
+struct SegTol;
+template <>
+struct SegTol<float> {
+    static constexpr float rel = 1.52587890625e-05f;   // 2^-16
+};
+template <>
+struct SegTol<double> {
+    static constexpr double rel = 9.094947017729282379e-13;   // 2^-40
+};
+
+constexpr double LN2_D = 0.69314718055994530942;
+
+// One wave sweeping one direction of one segment: lane p = sl holds state
+// j = sl % NP of the vector (SPL copies, h = sl / NP picks the rows of the
+// product it takes).
+template <typename R, int NP, int FAM, int SPL>
+struct SegSweep {
+    static constexpr int LPT = 64;
+    static constexpr int RPL = NP / SPL;
+    static constexpr int WW = 2 * WL;
+    static_assert(NP * SPL == LPT && WW == LPT, "one task per wave, one window step per lane");
+    using ET = typename EmitTraits<FAM, R>::T;
+
+    const WaveGeom &g;
+    const StagedModel<R> &m;
+    const ET *ep;
+    R (*esh)[NP + 1];
+    R *vsh;
+    R coef[RPL];
+    int j, h, sl, N, nrm;
+    bool live;
+
+    __device__ __forceinline__ SegSweep(const WaveGeom &g_, const StagedModel<R> &m_,
+                                        R (*esh_)[NP + 1], R *vsh_, bool fwd)
+        : g(g_), m(m_), ep(consts_ptr<FAM, R>(m_)), esh(esh_), vsh(vsh_) {
+        sl = threadIdx.x;
+        j = sl % NP;
+        h = sl / NP;
+        N = m.N;
+        nrm = *m.nrm;
+        live = j < N;
+        // the lane's column (forward) or row (backward) of A: clamped loads,
+        // all in flight before the masking
+#pragma unroll
+        for (int r = 0; r < RPL; ++r) {
+            const int i = min(h * RPL + r, N - 1), jj = min(j, N - 1);
+            coef[r] = fwd ? m.A[i * N + jj] : m.A[jj * N + i];
         }
-        const double wsum = grp_all<LPT, false>(msum);
-        if (fwd) logS += wsum;
-        __syncthreads();
-        // the next window's observations, in flight during this window
-        const int kn = k + kstep;
-        if (kn != kend && wlo(kn) < whi(kn))
-            pre = load_step_obs<R, NP, FAM>(g, N, off + min(wlo(kn) + sl, whi(kn) - 1));
-        if (fwd) {
-            R e_cur = esh[0][0][j];
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int r = 0; r < RPL; ++r) coef[r] = (live && h * RPL + r < N) ? coef[r] : (R)0;
+    }
+
+    // sum of the vector (one copy of each state)
+    __device__ __forceinline__ R vsum(R x) const { return grp_all<LPT, false>(h == 0 ? x : (R)0); }
+
+    // sum_i x_i coef_i with x broadcast through LDS
+    __device__ __forceinline__ R product(R x) const {
+        vsh[j] = x;
+        wave_lds_order();
+        R acc = lds_dot<R, RPL>(&vsh[h * RPL], coef);
+        if constexpr (SPL == 2) acc = add_halves(acc);
+        if constexpr (SPL == 4) acc = add_quarters(acc);
+        return acc;
+    }
+
+    // v and s equal up to a positive factor (the tolerance above); *lrho =
+    // log(sum v / sum s).  Identical result in every lane.
+    __device__ __forceinline__ bool agree(R v, R s, double *lrho) const {
+        const R sv = vsum(v), ss = vsum(s);
+        const R a = (sv / ss) * s;
+        // no absolute slack: an entry zero on one side only never agrees, so the
+        // two vectors have the same support
+        const bool ok = v == a || fabs(v - a) <= SegTol<R>::rel * fmax(v, a);
+        const R nbad = grp_all<LPT, true>(ok ? (R)0 : (R)1);
+        *lrho = log((double)sv) - log((double)ss);
+        const bool r = sv > (R)0 && ss > (R)0 && nbad == (R)0 && isfinite(*lrho);
+        return __builtin_amdgcn_readfirstlane((int)r) != 0;
+    }
+
+    // Forward steps [ta, tb) of the sequence at row off (T steps, first chunk
+    // cb0), from the lane's entry v of the vector entering step ta (ta = 0:
+    // pi, step 0 peeled).  At each chunk end c: with CMP and c >= cmin,
+    // compare with F[c] and stop at the first agreement (*at = c, *lrho, *l1
+    // = lsc[c]); otherwise with ST store v into F[c] (and with LS the log
+    // scale into lsc[c]).  *ls = log scale at the stop or the range's end.
+    // Returns whether it stopped at an agreement.
+    __device__ __forceinline__ bool fwd(R &v, bool &bad, int64_t off, int T, int cb0, int ta, int tb, bool cmp,
+                        bool st, bool lsst, int cmin, R *F, double *lsc, double *ls, double *lrho,
+                        double *l1, int *at) const {
+        const int k0 = ta / WW, k1 = (tb + WW - 1) / WW;
+        double logS = 0.0;
+        int64_t E = 0;
+        bool stop = false;
+        StepObs<R, NP, FAM> pre = load_step_obs<R, NP, FAM>(g, N, off + min(k0 * WW + sl, tb - 1));
+        for (int k = k0; k < k1; ++k) {
+            const int lo = k * WW, hi = min(tb, lo + WW), wn = hi - lo;
+            __syncthreads();
+            double msum = 0.0;
+            if (sl < wn) {
+                R y, ly;
+                msum = tab_step_obs<R, NP, FAM>(pre, N, ep, &esh[sl][0], &y, &ly, &bad);
+            }
+            // log offsets of the window's first and second chunk
+            double wa, wb;
+            swap_pair<32>(grp_all<32, false>(msum), &wa, &wb);
+            __syncthreads();
+            if (k + 1 < k1) pre = load_step_obs<R, NP, FAM>(g, N, off + min(lo + WW + sl, tb - 1));
+            // stored boundaries of the window's chunk ends, requested now
+            R s0 = (R)0, s1 = (R)0;
+            double q0 = 0.0, q1 = 0.0;
+            if (cmp) {
+                const int ca = cb0 + lo / WL, cb = cb0 + (hi - 1) / WL;
+                s0 = F[(size_t)ca * NP + j];
+                s1 = F[(size_t)cb * NP + j];
+                q0 = lsc[ca];
+                q1 = lsc[cb];
+            }
+            R e_cur = esh[0][j];
             for (int t = lo; t < hi; ++t) {
                 const int q = t - lo;
                 R nv;
                 if (t == 0) {   // alpha_0 = pi o e_0
                     nv = live ? m.pi[j] * e_cur : (R)0;
                 } else {
-                    vsh[0][j] = v;   // both halves store the same value
-                    wave_lds_order();
-                    R acc = lds_dot<R, RPL>(&vsh[0][h * RPL], coef);
-                    if constexpr (SPL == 2) acc = add_halves(acc);
-                    if constexpr (SPL == 4) acc = add_quarters(acc);
+                    const R acc = product(v);
                     wave_lds_order();
                     nv = e_cur * acc;
                 }
-                e_cur = esh[0][q + 1 < wn ? q + 1 : q][j];
+                e_cur = esh[q + 1 < wn ? q + 1 : q][j];
                 if (t == 0 || (t & (nrm - 1)) == nrm - 1 || t == T - 1) {
                     const int ex = fexp(grp_max_nn<LPT>(nv));
                     v = fldexp(nv, -ex);
@@ -411,18 +471,68 @@ __global__ __launch_bounds__(64) void k_wave_sweep(WaveGeom g, StagedModel<R> m,
                 } else {
                     v = nv;
                 }
-                if ((t % WL == WL - 1 || t == T - 1) && h == 0) F[(size_t)(cb + t / WL) * NP + j] = v;
+                if (t % WL == WL - 1 || t == T - 1) {
+                    const int c = cb0 + t / WL;
+                    const double lc = logS + wa + (q < WL ? 0.0 : wb) + (double)E * LN2_D;
+                    if (cmp && c >= cmin) {
+                        double lr;
+                        if (agree(v, q < WL ? s0 : s1, &lr)) {
+                            *ls = lc;
+                            *lrho = lr;
+                            *l1 = q < WL ? q0 : q1;
+                            *at = c;
+                            stop = true;
+                            break;
+                        }
+                    }
+                    if (st && h == 0) F[(size_t)c * NP + j] = v;
+                    if (lsst && sl == 0) lsc[c] = lc;
+                }
             }
-        } else {
-            R e_cur = esh[0][wn - 1][j];
+            if (stop) break;
+            logS += wa + wb;
+        }
+        if (!stop) *ls = logS + (double)E * LN2_D;
+        return stop;
+    }
+
+    // Backward steps t = tb - 1 down to max(ta, WL), from the lane's entry v
+    // of beta_{tb-1}.  At a chunk start t = c WL the vector is beta at the end
+    // of chunk c - 1, slot cb0 + c - 1: with CMP and slot <= smax compare with
+    // Gb there and stop at the first agreement (*at = slot); otherwise with ST
+    // store it.
+    __device__ __forceinline__ bool bwd(R &v, int64_t off, int T, int cb0, int ta, int tb, bool cmp, bool st,
+                        int smax, R *Gb, int *at) const {
+        const int lo_all = max(ta, WL);
+        if (lo_all >= tb) return false;
+        const int kA = (tb - 1) / WW, kB = lo_all / WW;
+        bool stop = false, bad = false;
+        StepObs<R, NP, FAM> pre =
+            load_step_obs<R, NP, FAM>(g, N, off + min(max(kA * WW, lo_all) + sl, tb - 1));
+        for (int k = kA; k >= kB; --k) {
+            const int lo = max(k * WW, lo_all), hi = min(tb, k * WW + WW), wn = hi - lo;
+            __syncthreads();
+            if (sl < wn) {
+                R y, ly;
+                (void)tab_step_obs<R, NP, FAM>(pre, N, ep, &esh[sl][0], &y, &ly, &bad);
+            }
+            __syncthreads();
+            if (k > kB) {
+                const int nlo = max((k - 1) * WW, lo_all), nhi = min(tb, k * WW);
+                pre = load_step_obs<R, NP, FAM>(g, N, off + min(nlo + sl, nhi - 1));
+            }
+            // stored boundaries at the window's chunk starts (lo, lo + WL)
+            R s0 = (R)0, s1 = (R)0;
+            if (cmp) {
+                const int sa = cb0 + lo / WL - 1;
+                s0 = Gb[(size_t)sa * NP + j];
+                s1 = Gb[(size_t)(lo + WL < hi ? sa + 1 : sa) * NP + j];
+            }
+            R e_cur = esh[wn - 1][j];
             for (int t = hi - 1; t >= lo; --t) {
                 const int q = t - lo;
-                vsh[0][j] = e_cur * v;
-                wave_lds_order();
-                R acc = lds_dot<R, RPL>(&vsh[0][h * RPL], coef);
-                if constexpr (SPL == 2) acc = add_halves(acc);
-                if constexpr (SPL == 4) acc = add_quarters(acc);
-                e_cur = esh[0][q > 0 ? q - 1 : q][j];
+                const R acc = product(e_cur * v);
+                e_cur = esh[q > 0 ? q - 1 : q][j];
                 wave_lds_order();
                 const int c = t / WL;
                 const int dist = min(T, c * WL + WL) - 1 - t;   // to the chunk's last step
@@ -432,32 +542,213 @@ __global__ __launch_bounds__(64) void k_wave_sweep(WaveGeom g, StagedModel<R> m,
                 } else {
                     v = acc;
                 }
-                if (t == c * WL && h == 0) Gb[(size_t)(cb + c - 1) * NP + j] = v;
+                if (t == c * WL) {
+                    const int slot = cb0 + c - 1;
+                    double lr;
+                    if (cmp && slot <= smax && agree(v, t == lo ? s0 : s1, &lr)) {
+                        *at = slot;
+                        stop = true;
+                        break;
+                    }
+                    if (st && h == 0) Gb[(size_t)slot * NP + j] = v;
+                }
+            }
+            if (stop) break;
+        }
+        return stop;
+    }
+};
+
+struct SegArgs {
+    const SuperDesc *sdesc;   // [SC] segments (superchunks of seg chunks)
+    const int *sbase;         // [B+1] segments before each sequence
+    int vmax;                 // chunks a second sweep may run
+    double *lsc;              // [C] launch-1 forward log scale at each chunk end
+    double *J;                // [SC] launch-1 log sum of the forward end vector
+    double *inc;              // [SC] forward increment found by the second sweep
+    int32_t *bad;             // [SC] invalid emission values seen by the forward
+    int32_t *ver;             // [2 SC] second sweep agreed (forward, backward)
+    int32_t *lim;             // [2 SC] first chunk (forward) / last slot (backward)
+                              //        still holding launch-1 vectors
+};
+
+__device__ __forceinline__ void seg_bounds(const SuperDesc &d, int *ta, int *tb, int *cb0) {
+    *ta = d.t0;
+    *tb = min(d.T, d.t0 + d.n * WL);
+    *cb0 = d.lo - d.t0 / WL;
+}
+
+__device__ __forceinline__ void seq_result(double ll, bool anybad, bool perr, double *loglik,
+                                           int32_t *status) {
+    if (perr) {
+        *loglik = __builtin_nan("");
+        *status = 4;
+    } else if (anybad || isnan(ll)) {
+        *loglik = __builtin_nan("");
+        *status = 2;
+    } else if (!(ll > -__builtin_inf())) {
+        *loglik = -__builtin_inf();
+        *status = 1;
+    } else {
+        *loglik = ll;
+        *status = 0;
+    }
+}
+
+// Launch 1: task 2s is the forward of segment s, task 2s + 1 its backward.
+// A sequence of one segment gets its log-likelihood and status here.
+template <typename R, int NP, int FAM, int SPL>
+__global__ __launch_bounds__(64) void k_wave_sweep(WaveGeom g, StagedModel<R> m, SegArgs sa,
+                                                   R *__restrict__ F, R *__restrict__ Gb,
+                                                   double *__restrict__ loglik,
+                                                   int32_t *__restrict__ status) {
+    __shared__ R esh[2 * WL][NP + 1];
+    __shared__ __align__(16) R vsh[NP + 4];
+    const int seg = blockIdx.x >> 1;
+    const bool fwd = (blockIdx.x & 1) == 0;
+    const SuperDesc d = sa.sdesc[seg];
+    int ta, tb, cb0;
+    seg_bounds(d, &ta, &tb, &cb0);
+    const bool tail = tb == d.T;
+    SegSweep<R, NP, FAM, SPL> w(g, m, esh, vsh, fwd);
+    R v = w.live ? (R)1 : (R)0;
+    if (fwd) {
+        bool bad = false;
+        double ls, lr, l1;
+        int at;
+        w.fwd(v, bad, d.off, d.T, cb0, ta, tb, false, true, true, 0, F, sa.lsc, &ls, &lr, &l1, &at);
+        const double J = ls + log((double)w.vsum(v));
+        const bool anybad = __ballot(bad) != 0;
+        if (w.sl == 0) {
+            sa.J[seg] = J;
+            sa.bad[seg] = anybad ? 1 : 0;
+            if (d.head && tail) seq_result(J, anybad, *m.perr != 0, loglik + d.b, status + d.b);
+        }
+    } else {
+        if (tail && w.h == 0) Gb[(size_t)(d.lo + d.n - 1) * NP + w.j] = v;
+        int at;
+        w.bwd(v, d.off, d.T, cb0, ta, tb, false, true, 0, Gb, &at);
+    }
+}
+
+// Launch 2: the second sweep of each segment (see above).
+template <typename R, int NP, int FAM, int SPL>
+__global__ __launch_bounds__(64) void k_wave_verify(WaveGeom g, StagedModel<R> m, SegArgs sa,
+                                                    R *__restrict__ F, R *__restrict__ Gb) {
+    __shared__ R esh[2 * WL][NP + 1];
+    __shared__ __align__(16) R vsh[NP + 4];
+    const int seg = blockIdx.x >> 1;
+    const int dir = blockIdx.x & 1;
+    const SuperDesc d = sa.sdesc[seg];
+    int ta, tb, cb0;
+    seg_bounds(d, &ta, &tb, &cb0);
+    const bool tail = tb == d.T;
+    const int nv = min(sa.vmax, d.n - 1);
+    if ((dir == 0 && d.head) || (dir == 1 && tail)) {   // entered exactly
+        if (threadIdx.x == 0) {
+            sa.ver[2 * seg + dir] = 1;
+            sa.lim[2 * seg + dir] = dir == 0 ? d.lo : d.lo + d.n - 1;
+        }
+        return;
+    }
+    SegSweep<R, NP, FAM, SPL> w(g, m, esh, vsh, dir == 0);
+    const int slot_in = dir == 0 ? d.lo - 1 : d.lo + d.n - 1;
+    R v = w.live ? (dir == 0 ? F : Gb)[(size_t)slot_in * NP + w.j] : (R)0;
+    const R sw = w.vsum(v);
+    int ok = 0, lim;
+    if (dir == 0) {
+        lim = d.lo + max(nv, 0);
+        if (nv > 0 && sw > (R)0) {
+            bool bad = false;
+            double ls, lr, l1;
+            int at;
+            if (w.fwd(v, bad, d.off, d.T, cb0, ta, ta + nv * WL, true, true, false, 0, F, sa.lsc,
+                      &ls, &lr, &l1, &at)) {
+                ok = 1;
+                lim = at;
+                if (threadIdx.x == 0) sa.inc[seg] = lr + ls - l1 + sa.J[seg] - log((double)sw);
+            }
+        }
+    } else {
+        lim = d.lo + d.n - 2 - max(nv, 0);
+        if (nv > 0 && sw > (R)0) {
+            int at;
+            if (w.bwd(v, d.off, d.T, cb0, max(ta, tb - nv * WL), tb, true, true, INT32_MAX, Gb,
+                      &at)) {
+                ok = 1;
+                lim = at;
             }
         }
     }
-    const R tot = grp_all<LPT, false>((fwd && h == 0) ? v : (R)0);
-    const uint64_t bal = __ballot(bad);
-    const uint64_t gmask = (LPT == 64) ? ~0ull : (((1ull << (LPT & 63)) - 1) << (grp * LPT));
-    const bool anybad = (bal & gmask) != 0;
-    if (tv && fwd && sl == 0) {
-        double ll;
-        int st;
-        if (*m.perr) {
-            ll = __builtin_nan("");
-            st = 4;
-        } else if (anybad || isnan(logS)) {
-            ll = __builtin_nan("");
-            st = 2;
-        } else if (!(tot > (R)0) || isinf(logS)) {
-            ll = -__builtin_inf();
-            st = 1;
-        } else {
-            ll = logS + (double)E * 0.69314718055994530942 + log((double)tot);
-            st = 0;
+    if (threadIdx.x == 0) {
+        sa.ver[2 * seg + dir] = ok;
+        sa.lim[2 * seg + dir] = lim;
+    }
+}
+
+// Launch 3: task 2b walks the forward segments of sequence b, task 2b + 1 the
+// backward ones (sequences of one segment have nothing to do).
+template <typename R, int NP, int FAM, int SPL>
+__global__ __launch_bounds__(64) void k_wave_fixup(WaveGeom g, StagedModel<R> m, SegArgs sa,
+                                                   R *__restrict__ F, R *__restrict__ Gb,
+                                                   double *__restrict__ loglik,
+                                                   int32_t *__restrict__ status) {
+    __shared__ R esh[2 * WL][NP + 1];
+    __shared__ __align__(16) R vsh[NP + 4];
+    const int b = blockIdx.x >> 1;
+    const bool fwd = (blockIdx.x & 1) == 0;
+    const int s0 = sa.sbase[b], s1 = sa.sbase[b + 1];
+    if (s1 - s0 <= 1) return;
+    SegSweep<R, NP, FAM, SPL> w(g, m, esh, vsh, fwd);
+    R v = (R)0;
+    bool ok = true, have = false;   // entering vector: stored one right / held in v
+    if (fwd) {
+        double ll = sa.J[s0];
+        bool anybad = sa.bad[s0] != 0;
+        for (int s = s0 + 1; s < s1; ++s) {
+            anybad |= sa.bad[s] != 0;
+            if (anybad || !(ll > -__builtin_inf())) continue;
+            if (ok && sa.ver[2 * s]) {
+                ll += sa.inc[s];
+                continue;
+            }
+            const SuperDesc d = sa.sdesc[s];
+            int ta, tb, cb0;
+            seg_bounds(d, &ta, &tb, &cb0);
+            if (!have) v = w.live ? F[(size_t)(d.lo - 1) * NP + w.j] : (R)0;
+            const R sw = w.vsum(v);
+            if (!(sw > (R)0)) {
+                ll = -__builtin_inf();
+                continue;
+            }
+            bool bad = false;
+            double ls, lr, l1;
+            int at;
+            if (w.fwd(v, bad, d.off, d.T, cb0, ta, tb, true, true, false, sa.lim[2 * s], F,
+                      sa.lsc, &ls, &lr, &l1, &at)) {
+                ll += lr + ls - l1 + sa.J[s] - log((double)sw);
+                ok = true;
+                have = false;
+            } else {
+                ll += ls + log((double)w.vsum(v)) - log((double)sw);
+                ok = false;
+                have = true;
+            }
         }
-        loglik[b] = ll;
-        status[b] = st;
+        if (threadIdx.x == 0) seq_result(ll, anybad, *m.perr != 0, loglik + b, status + b);
+    } else {
+        for (int s = s1 - 2; s >= s0; --s) {   // the last segment is entered exactly
+            if (ok && sa.ver[2 * s + 1]) continue;
+            const SuperDesc d = sa.sdesc[s];
+            int ta, tb, cb0;
+            seg_bounds(d, &ta, &tb, &cb0);
+            if (!have) v = w.live ? Gb[(size_t)(d.lo + d.n - 1) * NP + w.j] : (R)0;
+            if (!(w.vsum(v) > (R)0)) break;   // no path: the forward reports it
+            int at;
+            const bool hit = w.bwd(v, d.off, d.T, cb0, ta, tb, true, true, sa.lim[2 * s + 1], Gb, &at);
+            ok = hit;
+            have = !hit;
+        }
     }
 }
 
@@ -677,14 +968,26 @@ static hmm_status run_wave_np(const StagedModel<R> &m, const ObsDesc &o, const W
                               int64_t S, hipStream_t s) {
     // sweeps: one task per wave (two lanes per state for 32 states, four for 16)
     constexpr int SPL = 64 / NP;
-    constexpr int NG = 64 / (NP * SPL);
     WaveGeom g{o.nseq, o.offsets, wb.cbase, wb.cdesc, wb.C, ObsRef{o.obs, o.obs_f64}};
     R *F = (R *)wb.F, *Gb = (R *)wb.Gb;
+    const SegArgs sa{wb.sdesc, wb.sbase, wb.vmax, wb.lsc, wb.segJ, wb.seginc,
+                     wb.segbad, wb.segver, wb.seglim};
     {
         ProfScope ps("wave_sweep", s);
-        const unsigned nb = (unsigned)((2 * o.nseq + NG - 1) / NG);
-        hipLaunchKernelGGL((k_wave_sweep<R, NP, FAM, SPL>), dim3(nb), dim3(64), 0, s, g, m, F, Gb,
-                           loglik, status);
+        hipLaunchKernelGGL((k_wave_sweep<R, NP, FAM, SPL>), dim3((unsigned)(2 * wb.SC)), dim3(64),
+                           0, s, g, m, sa, F, Gb, loglik, status);
+    }
+    if (wb.SC > o.nseq) {   // some sequence is split
+        {
+            ProfScope ps("wave_verify", s);
+            hipLaunchKernelGGL((k_wave_verify<R, NP, FAM, SPL>), dim3((unsigned)(2 * wb.SC)),
+                               dim3(64), 0, s, g, m, sa, F, Gb);
+        }
+        {
+            ProfScope ps("wave_fixup", s);
+            hipLaunchKernelGGL((k_wave_fixup<R, NP, FAM, SPL>), dim3((unsigned)(2 * o.nseq)),
+                               dim3(64), 0, s, g, m, sa, F, Gb, loglik, status);
+        }
     }
     if (!gamma_out && !stats) return HMM_OK;
     {
@@ -728,6 +1031,12 @@ static hmm_status run_wave_fam(const StagedModel<R> &m, const ObsDesc &o, const 
 }
 
 int wave_np(int N) { return N <= 16 ? 16 : (N <= 32 ? 32 : 64); }
+
+int wave_seg_chunks(int variant) {
+    // whole windows (an even number of chunks); 2^28 chunks never splits
+    static const int K[4] = {32, 1 << 28, 16, 64};
+    return K[variant < 0 ? 0 : (variant > 3 ? 3 : variant)];
+}
 
 int wave_stats_blocks(int C, int N) {
     const int ng = 64 / wave_np(N);

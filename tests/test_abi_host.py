@@ -173,14 +173,17 @@ def test_variant_counts_and_forcing(h):
     try:
         assert get_variant(h, *chunk, "f32") == (0, 3)
         assert get_variant(h, *chunk, "f64") == (0, 2)
-        assert get_variant(h, *wave, "f32") == (0, 1)
+        assert get_variant(h, *wave, "f32") == (0, 4)
         assert get_variant(h, *block, "f64") == (0, 3)
         sizes = []
         for v in (0, 1, 2):
             assert h._lib.hmm_set_variant(v) == h.HMM_OK
             assert get_variant(h, *block, "f32") == (v, 3)
             assert get_variant(h, *chunk, "f64")[0] == min(v, 1)
-            assert get_variant(h, *wave, "f32")[0] == 0
+            assert get_variant(h, *wave, "f32")[0] == v
+        assert h._lib.hmm_set_variant(3) == h.HMM_OK
+        assert get_variant(h, *wave, "f32") == (3, 4)
+        assert get_variant(h, *block, "f32") == (2, 3)
         assert h._lib.hmm_set_variant(-1) == h.HMM_OK
         assert get_variant(h, *block, "f32") == (0, 3)
         assert h._lib.hmm_set_variant(-2) == h.HMM_ERR_ARG

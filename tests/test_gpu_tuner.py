@@ -2,7 +2,8 @@
 
 Every variant the tuner can pick (chunk lengths 16/32/64 of the N <= 8
 route, half/nominal/double slicing of the large-state transition
-contraction) is forced in turn and compared with the FP64 oracle; the tuner
+contraction, sweep segments of 1024 steps, whole sequences, 512 or 2048
+steps for 8 < N <= 64) is forced in turn and compared with the FP64 oracle; the tuner
 itself must return one of them, make later calls take it, and append its
 choice to the file named by HMM_TUNE_CACHE."""
 import os
@@ -41,7 +42,8 @@ CASES = [("gamma", 8, 1, [1, 15, 16, 17, 63, 64, 65, 300, 1025, 4100], 1401),
          ("poisson", 3, 1, [2, 31, 33, 257, 700], 1402),
          ("gaussian", 150, 1, [1, 64, 200, 1900], 1403),
          ("diag", 100, 4, [1, 40, 700], 1404),
-         ("gaussian", 256, 1, [3, 129, 1200], 1405)]
+         ("gaussian", 256, 1, [3, 129, 1200], 1405),
+         ("student_t", 32, 1, [1, 33, 600, 1025, 2100, 2600], 1406)]
 
 
 @pytest.mark.parametrize("fam,n,d,lengths,seed", CASES)
@@ -53,7 +55,8 @@ def test_every_variant_matches_oracle(h, fam, n, d, lengths, seed, prec):
         h.hmm_set_variant(0)
         _, _, _, dm, db = run(h, w, prec)
         _, nv = h.hmm_get_variant(dm, db, prec)
-        assert nv == (1 if 8 < n <= 64 else (2 if (n <= 8 and prec == "f64") else 3))
+        wave = 8 < n <= (32 if prec == "f64" else 64)
+        assert nv == (4 if wave else (2 if (n <= 8 and prec == "f64") else 3))
         for v in range(nv):
             h.hmm_set_variant(v)
             stats, ll, st, dm, db = run(h, w, prec)
