@@ -323,8 +323,10 @@ __device__ __forceinline__ double add_quarters(double x) {
 // A mixing chain forgets its start within a few hundred steps, so launch 2
 // stops early and launch 3 only adds; a chain that does not is re-run segment
 // by segment, which is the unsplit sweep's own serial cost.  The second sweep
-// never runs its segment's last chunk (forward) or first chunk (backward):
-// those boundaries are the entering vectors its neighbours read.
+// never runs a segment's last chunk (forward) or first chunk (backward) where
+// a neighbour reads that boundary as its entering vector; where none does
+// (the last segment's forward, the first one's backward) it may run the whole
+// segment, whose values are then right with or without an agreement.
 //
 // Log-likelihood increment of a segment entered with w: log sum(M w) -
 // log sum(w), M the product of its steps.  Launch 1 keeps J = log sum(M 1)
@@ -559,6 +561,15 @@ struct SegSweep {
     }
 };
 
+// value of lane k (uniform k)
+__device__ __forceinline__ int lane_int(int x, int k) { return __builtin_amdgcn_readlane(x, k); }
+__device__ __forceinline__ double lane_dbl(double x, int k) {
+    const uint64_t u = __builtin_bit_cast(uint64_t, x);
+    const uint32_t lo = __builtin_amdgcn_readlane((int)(uint32_t)u, k);
+    const uint32_t hi = __builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), k);
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
 struct SegArgs {
     const SuperDesc *sdesc;   // [SC] segments (superchunks of seg chunks)
     const int *sbase;         // [B+1] segments before each sequence
@@ -643,7 +654,11 @@ __global__ __launch_bounds__(64) void k_wave_verify(WaveGeom g, StagedModel<R> m
     int ta, tb, cb0;
     seg_bounds(d, &ta, &tb, &cb0);
     const bool tail = tb == d.T;
-    const int nv = min(sa.vmax, d.n - 1);
+    // the sweep may run the whole segment where no neighbour reads the
+    // boundary it ends on (the last segment's forward, the first one's
+    // backward); it then holds the right values even without an agreement
+    const bool whole = dir == 0 ? tail : d.head != 0;
+    const int nv = whole ? d.n : min(sa.vmax, d.n - 1);
     if ((dir == 0 && d.head) || (dir == 1 && tail)) {   // entered exactly
         if (threadIdx.x == 0) {
             sa.ver[2 * seg + dir] = 1;
@@ -662,21 +677,27 @@ __global__ __launch_bounds__(64) void k_wave_verify(WaveGeom g, StagedModel<R> m
             bool bad = false;
             double ls, lr, l1;
             int at;
-            if (w.fwd(v, bad, d.off, d.T, cb0, ta, ta + nv * WL, true, true, false, 0, F, sa.lsc,
-                      &ls, &lr, &l1, &at)) {
+            if (w.fwd(v, bad, d.off, d.T, cb0, ta, whole ? tb : ta + nv * WL, true, true, false, 0,
+                      F, sa.lsc, &ls, &lr, &l1, &at)) {
                 ok = 1;
                 lim = at;
                 if (threadIdx.x == 0) sa.inc[seg] = lr + ls - l1 + sa.J[seg] - log((double)sw);
+            } else if (whole) {
+                const double inc = ls + log((double)w.vsum(v)) - log((double)sw);
+                ok = 1;
+                if (threadIdx.x == 0) sa.inc[seg] = inc;
             }
         }
     } else {
-        lim = d.lo + d.n - 2 - max(nv, 0);
+        lim = whole ? d.lo - 1 : d.lo + d.n - 2 - max(nv, 0);
         if (nv > 0 && sw > (R)0) {
             int at;
-            if (w.bwd(v, d.off, d.T, cb0, max(ta, tb - nv * WL), tb, true, true, INT32_MAX, Gb,
-                      &at)) {
+            if (w.bwd(v, d.off, d.T, cb0, whole ? ta : max(ta, tb - nv * WL), tb, true, true,
+                      INT32_MAX, Gb, &at)) {
                 ok = 1;
                 lim = at;
+            } else if (whole) {
+                ok = 1;
             }
         }
     }
@@ -702,52 +723,72 @@ __global__ __launch_bounds__(64) void k_wave_fixup(WaveGeom g, StagedModel<R> m,
     SegSweep<R, NP, FAM, SPL> w(g, m, esh, vsh, fwd);
     R v = (R)0;
     bool ok = true, have = false;   // entering vector: stored one right / held in v
+    const int lane = threadIdx.x;
     if (fwd) {
-        double ll = sa.J[s0];
-        bool anybad = sa.bad[s0] != 0;
-        for (int s = s0 + 1; s < s1; ++s) {
-            anybad |= sa.bad[s] != 0;
-            if (anybad || !(ll > -__builtin_inf())) continue;
-            if (ok && sa.ver[2 * s]) {
-                ll += sa.inc[s];
-                continue;
-            }
-            const SuperDesc d = sa.sdesc[s];
-            int ta, tb, cb0;
-            seg_bounds(d, &ta, &tb, &cb0);
-            if (!have) v = w.live ? F[(size_t)(d.lo - 1) * NP + w.j] : (R)0;
-            const R sw = w.vsum(v);
-            if (!(sw > (R)0)) {
-                ll = -__builtin_inf();
-                continue;
-            }
-            bool bad = false;
-            double ls, lr, l1;
-            int at;
-            if (w.fwd(v, bad, d.off, d.T, cb0, ta, tb, true, true, false, sa.lim[2 * s], F,
-                      sa.lsc, &ls, &lr, &l1, &at)) {
-                ll += lr + ls - l1 + sa.J[s] - log((double)sw);
-                ok = true;
-                have = false;
-            } else {
-                ll += ls + log((double)w.vsum(v)) - log((double)sw);
-                ok = false;
-                have = true;
+        double ll = 0.0;
+        bool anybad = false;
+        // the flags of 64 segments at a time, one per lane, requested together
+        for (int g0 = s0; g0 < s1; g0 += 64) {
+            const int sq = min(g0 + lane, s1 - 1);
+            const int qbad = sa.bad[sq], qver = sa.ver[2 * sq];
+            const double qinc = sq == s0 ? sa.J[s0] : sa.inc[sq];
+            const int cnt = min(64, s1 - g0);
+            for (int k = 0; k < cnt; ++k) {
+                const int s = g0 + k;
+                anybad |= lane_int(qbad, k) != 0;
+                if (anybad || !(ll > -__builtin_inf())) continue;
+                if (s == s0 || (ok && lane_int(qver, k))) {
+                    ll += lane_dbl(qinc, k);
+                    continue;
+                }
+                const SuperDesc d = sa.sdesc[s];
+                int ta, tb, cb0;
+                seg_bounds(d, &ta, &tb, &cb0);
+                if (!have) v = w.live ? F[(size_t)(d.lo - 1) * NP + w.j] : (R)0;
+                const R sw = w.vsum(v);
+                if (!(sw > (R)0)) {
+                    ll = -__builtin_inf();
+                    continue;
+                }
+                bool bad = false;
+                double ls, lr, l1;
+                int at;
+                if (w.fwd(v, bad, d.off, d.T, cb0, ta, tb, true, true, false, sa.lim[2 * s], F,
+                          sa.lsc, &ls, &lr, &l1, &at)) {
+                    ll += lr + ls - l1 + sa.J[s] - log((double)sw);
+                    ok = true;
+                    have = false;
+                } else {
+                    ll += ls + log((double)w.vsum(v)) - log((double)sw);
+                    ok = false;
+                    have = true;
+                }
             }
         }
-        if (threadIdx.x == 0) seq_result(ll, anybad, *m.perr != 0, loglik + b, status + b);
+        if (lane == 0) seq_result(ll, anybad, *m.perr != 0, loglik + b, status + b);
     } else {
-        for (int s = s1 - 2; s >= s0; --s) {   // the last segment is entered exactly
-            if (ok && sa.ver[2 * s + 1]) continue;
-            const SuperDesc d = sa.sdesc[s];
-            int ta, tb, cb0;
-            seg_bounds(d, &ta, &tb, &cb0);
-            if (!have) v = w.live ? Gb[(size_t)(d.lo + d.n - 1) * NP + w.j] : (R)0;
-            if (!(w.vsum(v) > (R)0)) break;   // no path: the forward reports it
-            int at;
-            const bool hit = w.bwd(v, d.off, d.T, cb0, ta, tb, true, true, sa.lim[2 * s + 1], Gb, &at);
-            ok = hit;
-            have = !hit;
+        // the last segment is entered exactly; the others from the top down
+        bool dead = false;
+        for (int top = s1 - 2; top >= s0 && !dead; top -= 64) {
+            const int qver = sa.ver[2 * max(top - lane, s0) + 1];
+            const int cnt = min(64, top - s0 + 1);
+            for (int k = 0; k < cnt; ++k) {
+                const int s = top - k;
+                if (ok && lane_int(qver, k)) continue;
+                const SuperDesc d = sa.sdesc[s];
+                int ta, tb, cb0;
+                seg_bounds(d, &ta, &tb, &cb0);
+                if (!have) v = w.live ? Gb[(size_t)(d.lo + d.n - 1) * NP + w.j] : (R)0;
+                if (!(w.vsum(v) > (R)0)) {   // no path: the forward reports it
+                    dead = true;
+                    break;
+                }
+                int at;
+                const bool hit =
+                    w.bwd(v, d.off, d.T, cb0, ta, tb, true, true, sa.lim[2 * s + 1], Gb, &at);
+                ok = hit;
+                have = !hit;
+            }
         }
     }
 }
