@@ -640,10 +640,13 @@ static void launch_blk_sweep(bool fwd, const StagedModel<R> &m, const ObsDesc &o
 // is the product (diag(gamma) V)^T V over the tile's centred observations V,
 // taken two steps per v_mfma_f32_32x32x2_f32 (lane l holds dimension l % 32
 // of step 2q + l / 32 as both operands, the left one scaled by gamma).  One
-// wave per (state, tile of FULL_TS steps); the FP32 accumulators are added
-// into FP64 every 64 steps.  Result element (i, j) sits in lane
-// j + 32 ((i / 4) % 2), register 4 (i / 8) + i % 4.
+// wave per (group of FG states, tile of FULL_TS steps): a step's observation
+// and the group's gamma values are loaded once and serve the FG states, whose
+// products are independent MFMA chains.  The FP32 accumulators are added into
+// FP64 every 64 steps.  Result element (i, j) sits in lane j + 32 ((i / 4) %
+// 2), register 4 (i / 8) + i % 4.
 typedef float floatx16_t __attribute__((ext_vector_type(16)));
+constexpr int FG = 2;   // states per wave
 template <typename Y>
 __global__ __launch_bounds__(64) void k_blk_gstats_full_mfma(int N, int D, const Y *__restrict__ obs,
                                                             int64_t total,
@@ -651,58 +654,86 @@ __global__ __launch_bounds__(64) void k_blk_gstats_full_mfma(int N, int D, const
                                                             const float *__restrict__ gamma,
                                                             double *__restrict__ partial,
                                                             int64_t S2) {
-    const int c = blockIdx.x, l = threadIdx.x, i = l & 31, k = l >> 5;
+    const int c0 = blockIdx.x * FG, l = threadIdx.x, i = l & 31, k = l >> 5;
     const int ic = i < D ? i : D - 1;
     const int K = D + D * (D + 1) / 2;
     const int64_t t0 = (int64_t)blockIdx.y * FULL_TS;
     const int64_t t1 = t0 + FULL_TS < total ? t0 + FULL_TS : total;
-    const float mui = mu[(size_t)c * D + ic];
-    double S[16], F = 0.0, G = 0.0;
+    int cs[FG];
+    float mui[FG];
 #pragma unroll
-    for (int v = 0; v < 16; ++v) S[v] = 0.0;
+    for (int g = 0; g < FG; ++g) {
+        cs[g] = c0 + g < N ? c0 + g : N - 1;
+        mui[g] = mu[(size_t)cs[g] * D + ic];
+    }
+    double S[FG][16], F[FG], G[FG];
+#pragma unroll
+    for (int g = 0; g < FG; ++g) {
+        F[g] = 0.0;
+        G[g] = 0.0;
+#pragma unroll
+        for (int v = 0; v < 16; ++v) S[g][v] = 0.0;
+    }
     for (int64_t base = t0; base < t1; base += 64) {
-        floatx16_t acc;
+        floatx16_t acc[FG];
+        float f[FG], gs[FG];
 #pragma unroll
-        for (int v = 0; v < 16; ++v) acc[v] = 0.0f;
-        float f = 0.0f, g = 0.0f;
+        for (int g = 0; g < FG; ++g) {
+#pragma unroll
+            for (int v = 0; v < 16; ++v) acc[g][v] = 0.0f;
+            f[g] = 0.0f;
+            gs[g] = 0.0f;
+        }
         // batches of 8 step pairs: all loads first, at clamped indices (always
         // in bounds, no branches), so they are in flight together
         for (int q0 = 0; q0 < 32; q0 += 8) {
-            float gr[8], yr[8];
+            float gr[8][FG], yr[8];
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
                 const int64_t t = base + 2 * (q0 + u) + k;
                 const int64_t tc = t < t1 ? t : t1 - 1;
-                gr[u] = gamma[tc * N + c];
                 yr[u] = (float)obs[tc * D + ic];
+#pragma unroll
+                for (int g = 0; g < FG; ++g) gr[u][g] = gamma[tc * N + cs[g]];
             }
             __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
                 const bool on = base + 2 * (q0 + u) + k < t1;
-                const float gm = on ? gr[u] : 0.0f;
-                const float dv = (on && i < D) ? yr[u] - mui : 0.0f;
-                const float a = gm * dv;
-                acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a, dv, acc, 0, 0, 0);
-                f += a;
-                g += gm;
+#pragma unroll
+                for (int g = 0; g < FG; ++g) {
+                    const float gm = on ? gr[u][g] : 0.0f;
+                    const float dv = (on && i < D) ? yr[u] - mui[g] : 0.0f;
+                    const float a = gm * dv;
+                    acc[g] = __builtin_amdgcn_mfma_f32_32x32x2f32(a, dv, acc[g], 0, 0, 0);
+                    f[g] += a;
+                    gs[g] += gm;
+                }
             }
         }
 #pragma unroll
-        for (int v = 0; v < 16; ++v) S[v] += (double)acc[v];
-        F += (double)f;
-        G += (double)g;
-    }
-    // first moments and sum gamma: add the two step parities (lanes l and l ^ 32)
-    const double Fo = __shfl_xor(F, 32, 64), Go = __shfl_xor(G, 32, 64);
-    double *row = partial + (int64_t)blockIdx.y * S2;
-    if (l == 0) row[1 + c] = G + Go;
-    double *fr = row + 1 + N + (int64_t)c * K;
-    if (k == 0 && i < D) fr[i] = F + Fo;
+        for (int g = 0; g < FG; ++g) {
 #pragma unroll
-    for (int v = 0; v < 16; ++v) {
-        const int ii = 8 * (v / 4) + 4 * k + (v % 4), jj = i;
-        if (ii < D && jj <= ii) fr[D + ii * (ii + 1) / 2 + jj] = S[v];
+            for (int v = 0; v < 16; ++v) S[g][v] += (double)acc[g][v];
+            F[g] += (double)f[g];
+            G[g] += (double)gs[g];
+        }
+    }
+    double *row = partial + (int64_t)blockIdx.y * S2;
+#pragma unroll
+    for (int g = 0; g < FG; ++g) {
+        const int c = c0 + g;
+        // first moments and sum gamma: add the two step parities (lanes l and l ^ 32)
+        const double Fo = __shfl_xor(F[g], 32, 64), Go = __shfl_xor(G[g], 32, 64);
+        if (c >= N) continue;   // uniform
+        if (l == 0) row[1 + c] = G[g] + Go;
+        double *fr = row + 1 + N + (int64_t)c * K;
+        if (k == 0 && i < D) fr[i] = F[g] + Fo;
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+            const int ii = 8 * (v / 4) + 4 * k + (v % 4), jj = i;
+            if (ii < D && jj <= ii) fr[D + ii * (ii + 1) / 2 + jj] = S[g][v];
+        }
     }
 }
 
@@ -719,12 +750,13 @@ static int launch_family_sums(const StagedModel<R> &m, const ObsRef &obs, int64_
         const dim3 g((unsigned)N, (unsigned)nparts);
         if constexpr (sizeof(R) == 4) {
             if (m.D <= 32) {
+                const dim3 gm((unsigned)((N + FG - 1) / FG), (unsigned)nparts);
                 if (obs.f64)
-                    hipLaunchKernelGGL(k_blk_gstats_full_mfma<double>, g, dim3(64), 0, s, N, m.D,
+                    hipLaunchKernelGGL(k_blk_gstats_full_mfma<double>, gm, dim3(64), 0, s, N, m.D,
                                        (const double *)obs.p, total, (const float *)m.mv,
                                        (const float *)gamma, partial, S2);
                 else
-                    hipLaunchKernelGGL(k_blk_gstats_full_mfma<float>, g, dim3(64), 0, s, N, m.D,
+                    hipLaunchKernelGGL(k_blk_gstats_full_mfma<float>, gm, dim3(64), 0, s, N, m.D,
                                        (const float *)obs.p, total, (const float *)m.mv,
                                        (const float *)gamma, partial, S2);
                 return nparts;
