@@ -300,8 +300,14 @@ hmm_status hmm_set_chunk_len(int32_t steps);
  * variants that compute the same quantities in a different schedule:
  *   N <= 8 (time-parallel chunks): variant 0/1/2 = chunks of 16/32/64 steps
  *     (FP64: 16/32);
- *   64 < N <= 256 or multivariate N > 64: variant 0/1/2 = the nominal, half
- *     or double number of row slices of the transition contraction;
+ *   8 < N <= 64 and multivariate N <= 64 (FP64: N <= 32): variant 0/1/2/3 =
+ *     forward and backward sweeps cut into segments of 1024 steps, whole
+ *     sequences, 512 or 2048 steps (segments swept in parallel, each checked
+ *     by a second sweep from its neighbour's vector and re-run in order where
+ *     that finds no agreement);
+ *   64 < N <= 256 (FP64: 32 < N <= 256) or multivariate N > 64: variant
+ *     0/1/2 = the nominal, half or double number of row slices of the
+ *     transition contraction;
  *   other routes: one variant.
  * hmm_autotune runs every variant of the route that (model, batch, prec)
  * takes, once to warm up and three times timed with hipEvents on `stream`
