@@ -174,3 +174,54 @@ def test_segments_batch_invariance_and_posteriors(h):
         assert err <= atol_ref, (prec, err)
         diff = np.abs(gams[0] - gams[1]).max()
         assert diff <= atol_split, (prec, diff)
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_segments_in_hip_graph_fresh_thread(h, prec):
+    """The segmented E-step (three sweep launches) captured in a HIP graph
+    from a host thread that never called the library before; every replay,
+    with eager work and synchronisation between replays, equals the eager
+    call bit for bit."""
+    import threading
+    import torch
+    w = workloads.random_workload("student_t", 32, 1, [5000, 40, 2100, 1100], 740)
+    dm = h.DeviceModel.from_model(w.model)
+    db = h.DeviceBatch(w.obs, w.offsets, dtype=np.float64 if prec == "f64" else np.float32)
+    S = h.hmm_stats_len(dm)
+    stats = torch.zeros(S, dtype=torch.float64, device="cuda")
+    ll = torch.empty(w.n_seq, dtype=torch.float64, device="cuda")
+    st = torch.empty(w.n_seq, dtype=torch.int32, device="cuda")
+    ws = h._ws(h.hmm_workspace_size("estep", dm, db, prec))
+    h.hmm_estep_stats(dm, db, prec, stats, ll, st, ws)
+    torch.cuda.synchronize()
+    eager = (stats.clone(), ll.clone(), st.clone())
+    assert (st.cpu().numpy() == 0).all()
+    out = {}
+
+    def capture_and_replay():
+        try:
+            g = torch.cuda.CUDAGraph()
+            side = torch.cuda.Stream()
+            side.wait_stream(torch.cuda.current_stream())
+            torch.cuda.synchronize()
+            with torch.cuda.graph(g, stream=side):
+                h.hmm_estep_stats(dm, db, prec, stats, ll, st, ws)
+            for rep in range(3):
+                stats.zero_()
+                ll.zero_()
+                torch.cuda.synchronize()
+                g.replay()
+                torch.cuda.synchronize()
+                assert torch.equal(stats, eager[0]) and torch.equal(ll, eager[1]), rep
+                assert torch.equal(st, eager[2]), rep
+                _ = (stats * 2).sum().item()   # eager work between replays
+            out["ok"] = True
+        except BaseException as e:   # reported in the test's own thread
+            out["err"] = e
+
+    t = threading.Thread(target=capture_and_replay)
+    t.start()
+    t.join()
+    if "err" in out:
+        raise out["err"]
+    assert out.get("ok")
