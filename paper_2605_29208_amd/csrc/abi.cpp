@@ -292,10 +292,25 @@ hmm_status make_plan(hmm_op op, const Checked &c, hmm_precision prec, Plan *p, i
         if (p->plain || prec == HMM_PREC_BF16_SCALED || prec == HMM_PREC_F16_SCALED)
             return fail(HMM_ERR_UNSUPPORTED, "Viterbi runs in HMM_PREC_F64 or HMM_PREC_F32");
         if (N > 64) return fail(HMM_ERR_UNSUPPORTED, "Viterbi: this build covers N <= 64 (N = %d)", N);
-        int64_t C = 0;
-        for (int64_t b = 0; b < c.B; ++b) C += (c.h_off[b + 1] - c.h_off[b] + 63) / 64;
+        int64_t C = 0, SC = 0;
+        const int vs = vit_seg_chunks();
+        for (int64_t b = 0; b < c.B; ++b) {
+            const int64_t nc = (c.h_off[b + 1] - c.h_off[b] + 63) / 64;
+            C += nc;
+            SC += (nc + vs - 1) / vs;
+        }
         if (C > INT32_MAX / 64) return fail(HMM_ERR_UNSUPPORTED, "too many chunks");
         p->C = (int)C;
+        p->SC = (int)SC;
+        p->SS = vs;
+        p->sdesc = take((size_t)SC * sizeof(SuperDesc));
+        p->lt = take((size_t)C * 64 * (p->f64 ? 8 : 4));   // shifted scores at chunk ends
+        p->lsc = take((size_t)C * 8);
+        p->segJ = take((size_t)SC * 8);
+        p->seginc = take((size_t)SC * 8);
+        p->segbad = take((size_t)SC * 4);
+        p->segver = take((size_t)SC * 4);
+        p->seglim = take((size_t)SC * 4);
         p->vpsi = take((size_t)c.total * N);
         p->vJ = take((size_t)C * N);
         p->vqlast = take((size_t)c.B);
@@ -824,19 +839,33 @@ hmm_status hmm_viterbi(const hmm_model *model, const hmm_batch *batch, hmm_preci
     if (c.B == 0) return ok();
     int *cbase = (int *)(w + p.cbase);
     ChunkDesc *cdesc = (ChunkDesc *)(w + p.cdesc);
-    launch_plan_chunks(batch->offsets, c.B, 64, 1, cbase, (int *)(w + p.sbase), s);
-    launch_chunk_desc(batch->offsets, c.B, 64, 1, cbase, (int *)(w + p.sbase), p.C, 0, cdesc,
-                      nullptr, s);
+    int *sbase = (int *)(w + p.sbase);
+    SuperDesc *sdesc = (SuperDesc *)(w + p.sdesc);
+    launch_plan_chunks(batch->offsets, c.B, 64, p.SS, cbase, sbase, s);
+    launch_chunk_desc(batch->offsets, c.B, 64, p.SS, cbase, sbase, p.C, p.SC, cdesc, sdesc, s);
+    VitBuffers vb;
+    vb.SC = p.SC;
+    vb.sbase = sbase;
+    vb.sdesc = sdesc;
+    vb.vd = w + p.lt;
+    vb.voff = (double *)(w + p.lsc);
+    vb.J = (double *)(w + p.segJ);
+    vb.inc = (double *)(w + p.seginc);
+    vb.flag = (int32_t *)(w + p.segbad);
+    vb.ver = (int32_t *)(w + p.segver);
+    vb.lim = (int32_t *)(w + p.seglim);
     uint8_t *psi = (uint8_t *)(w + p.vpsi), *J = (uint8_t *)(w + p.vJ);
     uint8_t *ql = (uint8_t *)(w + p.vqlast), *qe = (uint8_t *)(w + p.vqend);
     if (p.f64) {
         StagedModel<double> sm;
         launch_stage<double>(raw(model), w + p.staged, &sm, s);
-        run_viterbi<double>(sm, od, cbase, cdesc, p.C, psi, J, ql, qe, path, path_logp, n_ties, s);
+        run_viterbi<double>(sm, od, cbase, cdesc, p.C, vb, psi, J, ql, qe, path, path_logp,
+                            n_ties, s);
     } else {
         StagedModel<float> sm;
         launch_stage<float>(raw(model), w + p.staged, &sm, s);
-        run_viterbi<float>(sm, od, cbase, cdesc, p.C, psi, J, ql, qe, path, path_logp, n_ties, s);
+        run_viterbi<float>(sm, od, cbase, cdesc, p.C, vb, psi, J, ql, qe, path, path_logp,
+                           n_ties, s);
     }
     return device_check("Viterbi kernels");
 }

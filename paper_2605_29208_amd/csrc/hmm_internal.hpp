@@ -247,12 +247,25 @@ hmm_status run_emission(const StagedModel<R> &m, const ObsDesc &o, int64_t total
                         R *out, hipStream_t s);
 
 // Viterbi (N <= 64): psi [sum T * N] bytes, J [C * N], qlast [B], qend [C];
-// n_ties [B] (or NULL): near-ties met along each returned path
+// n_ties [B] (or NULL): near-ties met along each returned path.  The forward
+// recursion runs in segments of vit_seg_chunks() chunks of 64 steps (SC ==
+// B: none split).
+struct VitBuffers {
+    int SC;                   // segments
+    const int *sbase;         // [B+1] segments before each sequence
+    const SuperDesc *sdesc;   // [SC]
+    void *vd;                 // [C x 64] R  shifted score vector at each chunk end
+    double *voff;             // [C]  shift sum at each chunk end
+    double *J;                // [SC]
+    double *inc;              // [SC]
+    int32_t *flag, *ver, *lim;   // [SC] each
+};
+int vit_seg_chunks();
 template <typename R>
 hmm_status run_viterbi(const StagedModel<R> &m, const ObsDesc &o, const int *cbase,
-                       const ChunkDesc *cdesc, int C, uint8_t *psi, uint8_t *J, uint8_t *qlast,
-                       uint8_t *qend, int32_t *path, double *logp, int32_t *n_ties,
-                       hipStream_t s);
+                       const ChunkDesc *cdesc, int C, const VitBuffers &vb, uint8_t *psi,
+                       uint8_t *J, uint8_t *qlast, uint8_t *qend, int32_t *path, double *logp,
+                       int32_t *n_ties, hipStream_t s);
 
 // path[t] = -1 on every step of the sequences whose status is not 0
 void launch_mask_paths(const int64_t *offsets, const int32_t *status, int64_t nseq, int32_t *path,
