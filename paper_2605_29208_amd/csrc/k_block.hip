@@ -674,6 +674,9 @@ __global__ __launch_bounds__(64) void k_blk_gstats_full_mfma(int N, int D, const
 #pragma unroll
         for (int v = 0; v < 16; ++v) S[g][v] = 0.0;
     }
+    const Y *ot = obs + t0 * D;
+    const float *gt = gamma + t0 * N;
+    const int nrow = (int)(t1 - t0);
     for (int64_t base = t0; base < t1; base += 64) {
         floatx16_t acc[FG];
         float f[FG], gs[FG];
@@ -686,15 +689,17 @@ __global__ __launch_bounds__(64) void k_blk_gstats_full_mfma(int N, int D, const
         }
         // batches of 8 step pairs: all loads first, at clamped indices (always
         // in bounds, no branches), so they are in flight together
+        // rows addressed from the tile's first row in 32-bit offsets (a tile
+        // holds at most FULL_TS steps)
         for (int q0 = 0; q0 < 32; q0 += 8) {
             float gr[8][FG], yr[8];
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
-                const int64_t t = base + 2 * (q0 + u) + k;
-                const int64_t tc = t < t1 ? t : t1 - 1;
-                yr[u] = (float)obs[tc * D + ic];
+                const int tr = (int)(base - t0) + 2 * (q0 + u) + k;
+                const int tc = tr < nrow ? tr : nrow - 1;
+                yr[u] = (float)ot[tc * D + ic];
 #pragma unroll
-                for (int g = 0; g < FG; ++g) gr[u][g] = gamma[tc * N + cs[g]];
+                for (int g = 0; g < FG; ++g) gr[u][g] = gt[tc * N + cs[g]];
             }
             __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
