@@ -43,7 +43,7 @@ def check_against_oracle(m, logB, offs, path, lp, nt, what, exact_ties=True):
         assert abs(lp[b] - rlp) <= 1e-12 * abs(rlp), (what, b, lp[b], rlp)
 
 
-@pytest.mark.parametrize("n", [3, 8, 16, 40, 64])
+@pytest.mark.parametrize("n", [1, 2, 3, 8, 16, 33, 40, 64])
 def test_viterbi_segments_table_f64(h, n):
     rng = np.random.default_rng(760 + n)
     offs = np.concatenate([[0], np.cumsum(LENGTHS)])

@@ -53,7 +53,10 @@ def estep(h, model, offsets, obs, prec, variant):
 
 @pytest.mark.parametrize("fam,n,precs", [("student_t", 32, ("f32", "f64")),
                                          ("gaussian", 16, ("f32", "f64")),
-                                         ("poisson", 64, ("f32",))])
+                                         ("poisson", 64, ("f32",)),
+                                         ("gamma", 9, ("f32", "f64")),
+                                         ("gaussian", 17, ("f64",)),
+                                         ("student_t", 47, ("f32",))])
 def test_segments_every_variant(h, fam, n, precs):
     w = workloads.random_workload(fam, n, 1, LENGTHS, 700 + n)
     ref = oracle.estep(w.model, w.offsets, w.obs)
