@@ -415,9 +415,23 @@ __global__ __launch_bounds__(BT) void k_blk_gstats_diag(StagedModel<R> m, ObsRef
 #pragma unroll
     for (int d = 0; d < DM; ++d) s1[d] = s2[d] = 0.0;
     const int ntile = (int)((total + BLK_TS - 1) / BLK_TS);
+    const int cc = live ? c : N - 1;
+    // gamma of 8 steps of a staged block starting at sb (rows clamped into
+    // the block's ns steps)
+    auto gload = [&](R (&dst)[8], int64_t sbb, int s0b, int nsb) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int st = s0b + u < nsb ? s0b + u : nsb - 1;
+            dst[u] = gamma[(sbb + st) * N + cc];
+        }
+    };
     for (int tile = blockIdx.x; tile < ntile; tile += gridDim.x) {
         const int64_t t0 = (int64_t)tile * BLK_TS;
         const int64_t t1 = t0 + BLK_TS < total ? t0 + BLK_TS : total;
+        // each batch's gamma is requested one batch ahead, so its latency
+        // overlaps the previous batch's sums
+        R gr[8];
+        gload(gr, t0, 0, (int)(t1 - t0 < SB ? t1 - t0 : SB));
         for (int64_t sb = t0; sb < t1; sb += SB) {
             const int ns = (int)(t1 - sb < SB ? t1 - sb : SB);
             __syncthreads();
@@ -443,13 +457,16 @@ __global__ __launch_bounds__(BT) void k_blk_gstats_diag(StagedModel<R> m, ObsRef
             R a1[DM], a2[DM], g = (R)0;
 #pragma unroll
             for (int d = 0; d < DM; ++d) a1[d] = a2[d] = (R)0;
-            const int cc = live ? c : N - 1;
             for (int s0 = 0; s0 < SB; s0 += 8) {
-                R gr[8];
+                // the next batch: later in this block, else the tile's next block
+                R gn[8];
+                const bool same = s0 + 8 < SB;
+                const int64_t nsb = same ? sb : sb + SB;
+                if (nsb < t1) {   // uniform
+                    gload(gn, nsb, same ? s0 + 8 : 0, (int)(t1 - nsb < SB ? t1 - nsb : SB));
+                } else {
 #pragma unroll
-                for (int u = 0; u < 8; ++u) {
-                    const int st = s0 + u < ns ? s0 + u : ns - 1;
-                    gr[u] = gamma[(sb + st) * N + cc];
+                    for (int u = 0; u < 8; ++u) gn[u] = (R)0;
                 }
 #pragma unroll
                 for (int u = 0; u < 8; ++u) {
@@ -469,6 +486,8 @@ __global__ __launch_bounds__(BT) void k_blk_gstats_diag(StagedModel<R> m, ObsRef
                         }
                     }
                 }
+#pragma unroll
+                for (int u = 0; u < 8; ++u) gr[u] = gn[u];
             }
 #pragma unroll
             for (int d = 0; d < DM; ++d) {
