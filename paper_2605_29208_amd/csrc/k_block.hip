@@ -102,6 +102,17 @@ __global__ __launch_bounds__(BT) void k_blk_emit_diag(StagedModel<R> m, ObsRef o
         wq[d] = (live && d < D) ? m.mv[(size_t)N * D + (size_t)j * D + d] : (R)0;
     }
     const R c0 = live ? m.ep[j * EP_STRIDE] : (R)0;
+    // FP64 expands w (y - mu)^2 = y (w y - 2 w mu) + w mu^2: two FMA per
+    // dimension instead of three operations; the cancellation costs about
+    // log10(mu^2 / var) digits, which FP64 affords.  FP32 keeps the centred form.
+    constexpr bool EXPD = sizeof(R) == 8;
+    R bq[DM];
+    R c1 = c0;
+#pragma unroll
+    for (int d = 0; d < DM; ++d) {
+        bq[d] = (R)-2 * wq[d] * mu[d];
+        if constexpr (EXPD) c1 = fma(wq[d] * mu[d], mu[d], c1);
+    }
     for (int64_t base = (int64_t)blockIdx.x * ES; base < total; base += (int64_t)gridDim.x * ES) {
         const int ns = (int)((total - base) < ES ? (total - base) : ES);
         __syncthreads();
@@ -116,12 +127,17 @@ __global__ __launch_bounds__(BT) void k_blk_emit_diag(StagedModel<R> m, ObsRef o
         __syncthreads();
         if (live) {
             for (int sidx = 0; sidx < ns; ++sidx) {
-                R acc = c0;
+                R acc = EXPD ? c1 : c0;
 #pragma unroll
                 for (int d = 0; d < DM; ++d) {
                     if (d < D) {
-                        const R dv = ysh[sidx][d] - mu[d];
-                        acc = fma(wq[d], dv * dv, acc);
+                        const R y = ysh[sidx][d];
+                        if constexpr (EXPD) {
+                            acc = fma(y, fma(wq[d], y, bq[d]), acc);
+                        } else {
+                            const R dv = y - mu[d];
+                            acc = fma(wq[d], dv * dv, acc);
+                        }
                     }
                 }
                 lsh[sidx][j] = acc;
