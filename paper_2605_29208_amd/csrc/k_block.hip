@@ -242,28 +242,33 @@ template <typename R>
 __global__ __launch_bounds__(BT) void k_blk_gamma1(int N, int64_t nseq, const int64_t *offsets,
                                                    const int32_t *status, const R *gamma,
                                                    double *g1) {
-    const int c = blockIdx.x * BT + threadIdx.x;
-    if (c >= N) return;
+    __shared__ int64_t osh[BT];
+    __shared__ int32_t ssh[BT];
+    const int tid = threadIdx.x, c = blockIdx.x * BT + tid;
     double s = 0.0;
-    // sixteen sequences' loads in flight at clamped indices, added in order
-    constexpr int U = 16;
-    for (int64_t b0 = 0; b0 < nseq; b0 += U) {
-        int64_t off[U];
-        int32_t st[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int64_t b = b0 + u < nseq ? b0 + u : nseq - 1;
-            off[u] = offsets[b];
-            st[u] = status[b];
+    // the offsets and statuses of BT sequences staged in LDS in one round,
+    // then 32 sequences' loads in flight at clamped indices, added in order
+    constexpr int U = 32;
+    for (int64_t b0 = 0; b0 < nseq; b0 += BT) {
+        const int nb = (int)(nseq - b0 < BT ? nseq - b0 : BT);
+        __syncthreads();
+        if (tid < nb) {
+            osh[tid] = offsets[b0 + tid];
+            ssh[tid] = status[b0 + tid];
         }
-        R g[U];
+        __syncthreads();
+        if (c < N) {
+            for (int u0 = 0; u0 < nb; u0 += U) {
+                R g[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) g[u] = gamma[off[u] * N + c];
+                for (int u = 0; u < U; ++u) g[u] = gamma[osh[u0 + u < nb ? u0 + u : nb - 1] * N + c];
 #pragma unroll
-        for (int u = 0; u < U; ++u)
-            if (b0 + u < nseq && st[u] == 0) s += (double)g[u];
+                for (int u = 0; u < U; ++u)
+                    if (u0 + u < nb && ssh[u0 + u] == 0) s += (double)g[u];
+            }
+        }
     }
-    g1[c] = s;
+    if (c < N) g1[c] = s;
 }
 
 // gamma-weighted family sums.  Thread (state c, dimension d); the blocks
