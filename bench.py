@@ -462,12 +462,18 @@ def serving_bench(h, workloads, qps_list, seconds, pool_size=256, streams=SERVIN
             w = workloads.simulate("serve", models[k], [int(lengths[i])], rng)
             kind = "viterbi" if rng.random() < 0.5 else "posterior_decode"
             pool.append((k, kind, np.ascontiguousarray(w.obs, dtype=np.float32)))
-        # warm-up: every (model, kind) once
+        # warm-up: every (model, kind) once, on a short request and on one long
+        # enough to be cut into sweep segments, so that every kernel a timed
+        # request can reach has been loaded before the timed points
         warm = 0
+        wrng = np.random.default_rng(5008)
         for k in range(len(models)):
+            long_obs = np.ascontiguousarray(
+                workloads.simulate("warm", models[k], [2500], wrng).obs, dtype=np.float32)
             for kind in ("viterbi", "posterior_decode"):
-                srv.submit(ids[k], kind, pool[0][2][:64])
-                warm += 1
+                for obs in (long_obs[:64], long_obs):
+                    srv.submit(ids[k], kind, obs)
+                    warm += 1
         while warm > 0:
             warm -= len(srv.poll(256, 100000))
         points = []
