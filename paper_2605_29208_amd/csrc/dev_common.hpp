@@ -233,7 +233,13 @@ __device__ __forceinline__ float flog1p(float x) {
 }
 __device__ __forceinline__ double flog1p(double x) { return log1p(x); }
 __device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
-__device__ __forceinline__ double frcp(double x) { return 1.0 / x; }
+// v_rcp_f64 and one Newton step (r + r (1 - x r)): within an ulp or two for
+// the positive, normal-range sums it is used on, in a third of the
+// instructions of an IEEE division
+__device__ __forceinline__ double frcp(double x) {
+    const double r = __builtin_amdgcn_rcp(x);
+    return fma(r, fma(-x, r, 1.0), r);
+}
 
 template <typename R> __device__ __forceinline__ R neg_inf() { return -__builtin_inf(); }
 
